@@ -1,0 +1,155 @@
+"""Benchmark: quadruped environment steps per second on one MI355X.
+
+One bench "step" = one full rollout of the workload batch: 4096 quadruped
+environments x 1000 environment steps (dt 0.05 s, 10 substeps), seeded
+synthetic reset perturbations and actions, inputs resident in HBM before the
+timed region. `value` is the fused forward rate (env-steps/s). The plain
+per-phase path and the forward+VJP rate are reported beside it, plus the
+roofline of the dominant kernel and the FP64 oracle timed on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+import torch  # noqa: E402
+
+from paper_2106_13281_amd import braxmi, synth  # noqa: E402
+
+PEAK_FP32_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, no packed FP32
+PEAK_FP32_PACKED = 157.3    # with packed FP32 (not generated: disabled at build)
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_flops(name):
+    with open(os.path.join(ROOT, "tests", "golden", "algorithmic_flops.json")) as f:
+        return json.load(f)["workloads"][name]["mean"]
+
+
+def make_inputs(system, wl, seed=0):
+    E = system.n_envs
+    ang, root = synth.reset_noise(seed, E, system.d_max, wl.angle_noise, wl.root_noise)
+    angles = system.default_angles(0)[:, None] + torch.from_numpy(np.ascontiguousarray(ang.T))
+    s0 = system.default_qp(angles.contiguous().cuda(), torch.from_numpy(np.ascontiguousarray(root.T)).cuda())
+    acts = torch.from_numpy(synth.acts_to_device_layout(synth.actions(seed, wl.steps, E, system.a_max,
+                                                                      wl.act_range))).cuda()
+    torch.cuda.synchronize()
+    return s0, acts
+
+
+def time_calls(fn, reps, warmup):
+    """Average ms per call with HIP events on torch's current stream (the one the library uses)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def cpu_baseline(s0, acts, system, budget_s=12.0):
+    """The FP64 oracle on the host cores, on a bounded sample of the same workload."""
+    import oracle
+    o = oracle.Oracle(synth.system_text("quadruped"))
+    E = system.n_envs
+    nb = o.nb
+    X = synth.from_soa(*(t.cpu().numpy() for t in s0.fields()), n_body=nb)
+    A = acts.cpu().numpy().transpose(0, 2, 1)[:, :, :o.na].astype(np.float64)   # [T][E][A]
+    threads = oracle.max_threads()
+    n_env = min(E, 1024)
+    t0 = time.perf_counter()
+    o.rollout(X[:n_env], A[:2, :n_env], threads=threads)
+    per = (time.perf_counter() - t0) / (2 * n_env)
+    T = int(max(2, min(A.shape[0], budget_s / max(per * n_env, 1e-9))))
+    t0 = time.perf_counter()
+    o.rollout(X[:n_env], A[:T, :n_env], threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": n_env * T / dt, "unit": "env-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_env} of the {E} quadruped environments x first {T} of the 1000 steps, FP64, "
+                      f"OpenMP over environments ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--plain-steps", type=int, default=100, help="env steps timed for the plain path")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the environments are independent and need no exchange); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    wl = synth.WORKLOADS["quadruped"]
+    E, T = wl.envs, wl.steps
+    system = braxmi.System(synth.system_text("quadruped"), E, device=0)
+    s0, acts = make_inputs(system, wl)
+    out = system.new_state()
+    log(f"inputs ready: {E} envs x {T} steps")
+    epw, wpb = system.autotune()
+    log(f"autotuned schedule: {epw} envs/wave, {wpb} waves/block")
+
+    # fused forward: the timed region is K full rollouts
+    ms_fused = time_calls(lambda: system.rollout(s0, acts, out=out), args.steps, args.warmup)
+    fused = E * T / (ms_fused / 1e3)
+    log(f"fused forward: {ms_fused:.2f} ms per rollout, {fused:.3e} env-steps/s")
+
+    # plain per-phase path (one launch per phase per substep), shorter horizon
+    Tp = min(args.plain_steps, T)
+    ms_plain = time_calls(lambda: system.rollout(s0, acts[:Tp], out=out, flags=braxmi.BRAX_PLAIN), 1, 1)
+    plain = E * Tp / (ms_plain / 1e3)
+    log(f"plain forward: {ms_plain:.2f} ms per {Tp}-step rollout, {plain:.3e} env-steps/s")
+
+    fpe = algorithmic_flops("quadruped")
+    achieved = fpe * E * T / (ms_fused / 1e3) / 1e12
+    result = {
+        "metric": "quadruped env-steps/s, fwd and fwd+VJP, fused vs plain kernels, 1 MI355X",
+        "value": fused,
+        "unit": "env-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_fused,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"quadruped rollout: {E} environments x {T} steps, dt 0.05 s, 10 substeps, "
+                               f"actions U(-1,1), seed 0", "envs": E, "env_steps": T, "substeps": 10},
+        "fused_fwd_env_steps_per_s": fused,
+        "plain_fwd_env_steps_per_s": plain,
+        "fused_over_plain": fused / plain,
+        "fwd_vjp_env_steps_per_s": None,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "k_fused", "flop_per_env_step": fpe,
+                     "peak_note": "FP32 FMA issue rate without packed FP32 (disabled at build); "
+                                  f"frac vs the packed {PEAK_FP32_PACKED} TFLOP/s = "
+                                  f"{achieved / PEAK_FP32_PACKED:.4f}"},
+    }
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(s0, acts, system)
+        log(f"cpu baseline: {result['cpu_baseline']}")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

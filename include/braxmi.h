@@ -1,0 +1,174 @@
+/* braxmi — batched maximal-coordinate rigid-body step on one MI355X (gfx950).
+ *
+ * The method is the physics step of Brax (arXiv 2106.13281): a scene is a set
+ * of bodies in maximal coordinates whose only changing data are position,
+ * orientation, velocity and angular velocity (Section 3, the QP); one step
+ * `qp' = step(qp, actions)` (Section 3) runs `substeps` repetitions of
+ * Algorithm 1 — kinematic integration, then joint, actuator and collider
+ * updates computed from the same qp, then the potential integrator (joint and
+ * actuator updates, gravity) and the collision integrator (collider updates).
+ * Joints are springs (Section 6.1), contacts are velocity-level impulses with
+ * Baumgarte stabilisation against the ground plane (Section 6.2), systems are
+ * described in the ProtoBuf-like text of Appendix A, and the step is
+ * differentiable (Sections 2 and 5.1.4).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Status: every call returns BRAX_OK (0) or a negative BRAX_E_* code; the
+ *   message of the calling thread's last failure is brax_last_error(). No
+ *   C++ exception crosses this boundary. Arguments are checked on the host
+ *   before anything is launched; a failed check launches nothing.
+ * - Ownership: the caller owns every state, action and gradient buffer (all
+ *   DEVICE pointers, FP32). The brax_sys owns its constant tables, workspace
+ *   and cached HIP graphs and frees them in brax_sys_destroy.
+ * - Streams: `stream` is a hipStream_t (NULL = the legacy default stream).
+ *   Step/rollout/VJP calls are asynchronous on it. A brax_sys is used by one
+ *   stream at a time: its workspace is shared by its calls.
+ * - State layout (structure of arrays, environment index fastest):
+ *     element (c, b, e) of a field = ptr[(c * Bmax + b) * E + e]
+ *   pos, vel, ang: c in [0,3) (x, y, z; world frame, m, m/s, rad/s)
+ *   rot:           c in [0,4) (w, x, y, z; unit quaternion, body to world)
+ *   E = number of environments, Bmax = the largest body count over the
+ *   system types of the batch. Body slots b >= B of a smaller system are
+ *   ignored on input and written as zeros.
+ * - Actions: act[a * E + e], a in [0, Amax); rollouts take acts[t][a][e].
+ *   Each action is clipped to [-1, 1] and drives one joint axis with torque
+ *   gear * action. Action slots beyond a system's own count are ignored.
+ * - Non-finite state is not an error: NaN/Inf propagate. With
+ *   BRAX_NONFINITE_FLAGS a per-environment byte (1 = some output non-finite)
+ *   is written to the buffer brax_sys_query reports.
+ */
+#ifndef BRAXMI_H
+#define BRAXMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct brax_sys brax_sys; /* opaque; owned by the library */
+
+typedef struct {
+  float* pos; /* [3][Bmax][E] */
+  float* rot; /* [4][Bmax][E] */
+  float* vel; /* [3][Bmax][E] */
+  float* ang; /* [3][Bmax][E] */
+} brax_state;
+
+enum {
+  BRAX_OK = 0,
+  BRAX_E_ARG = -1,         /* null pointer, bad size, bad flag, bad index */
+  BRAX_E_PARSE = -2,       /* system text does not parse; message has line:col */
+  BRAX_E_MODEL = -3,       /* parses but is not a valid system (see brax_sys_create) */
+  BRAX_E_DEVICE = -4,      /* a HIP call failed */
+  BRAX_E_NOMEM = -5,       /* device or host allocation failed */
+  BRAX_E_UNSUPPORTED = -6  /* valid request this build does not handle */
+};
+
+enum {
+  BRAX_FUSED = 0,          /* default: one persistent fused kernel */
+  BRAX_PLAIN = 1,          /* one launch per phase per substep (baseline) */
+  BRAX_GRAPH = 4,          /* capture the launch(es) in a HIP graph and replay it */
+  BRAX_NONFINITE_FLAGS = 8 /* also write per-environment non-finite flags */
+};
+
+#define BRAX_MAX_TYPES 8
+#define BRAX_MAX_BODIES 16
+#define BRAX_MAX_JOINTS 16
+#define BRAX_MAX_CONTACTS 96
+#define BRAX_MAX_ACTIONS 48
+
+typedef struct {
+  int32_t n_envs, n_types, b_max, a_max, d_max;
+  int32_t type_envs[BRAX_MAX_TYPES];   /* environments of each type */
+  int32_t n_bodies[BRAX_MAX_TYPES];
+  int32_t n_joints[BRAX_MAX_TYPES];
+  int32_t n_actions[BRAX_MAX_TYPES];
+  int32_t n_dof[BRAX_MAX_TYPES];
+  int32_t n_contacts[BRAX_MAX_TYPES];
+  int32_t substeps[BRAX_MAX_TYPES];
+  float dt[BRAX_MAX_TYPES];
+  int32_t device;                      /* -1 for a host-only (validate) handle */
+  uint8_t* nonfinite;                  /* device [E] flags (BRAX_NONFINITE_FLAGS) */
+} brax_layout;
+
+/* Build a batch of n_envs environments from n_descs system descriptions.
+ * descs: host array of NUL-terminated texts in the Appendix A format
+ *   (substeps, dt, gravity, bodies{name mass inertia frozen colliders position},
+ *   joints{name parent child stiffness damping angular_stiffness
+ *   angular_damping limit_stiffness parent_offset child_offset rotation
+ *   child_rotation angle_limit{min max}...}, actuators{name joint strength},
+ *   baumgarte, elasticity, friction, clearance).
+ * env_desc: host [n_envs] index of each environment's description, or NULL
+ *   (all use descs[0]). Environments of one type need not be contiguous.
+ * device: HIP device ordinal, or -1 to parse and validate only (no device
+ *   work; the handle then only answers brax_sys_query).
+ * Errors: BRAX_E_ARG (null/size), BRAX_E_PARSE (with line:col),
+ *   BRAX_E_MODEL (unknown or repeated body, a body with two parents, a cycle,
+ *   mass <= 0, inertia <= 0, capsule length < 2 radius, angle_limit min > max,
+ *   DOF outside 1..3, a body without inertia or colliders, table limits),
+ *   BRAX_E_DEVICE, BRAX_E_NOMEM. On error *out is NULL. */
+int brax_sys_create(const char* const* descs, int32_t n_descs, const int32_t* env_desc, int32_t n_envs,
+                    int32_t device, brax_sys** out);
+
+/* Free a batch (synchronises its device first). NULL is a no-op. */
+void brax_sys_destroy(brax_sys* sys);
+
+/* Sizes of the batch. */
+int brax_sys_query(const brax_sys* sys, brax_layout* out);
+
+/* Default angle of each DOF of one system type (radians; 0 when inside the
+ * limits, else the mid-range), host out[n_dof[type]]. */
+int brax_default_angles(const brax_sys* sys, int32_t type, float* out);
+
+/* Reset pose (Section 4.1, default_qp): each tree placed in a valid joint
+ * configuration. joint_angles: device [Dmax][E] per-DOF angles in radians, or
+ * NULL for the defaults. root_offset: device [3][E] added to the first body's
+ * position when it is a free root, or NULL. Roots without a given position are
+ * first lifted so their lowest contact point is `clearance` above the ground.
+ * Velocities are zero. */
+int brax_default_qp(const brax_sys* sys, const float* joint_angles, const float* root_offset, brax_state* out,
+                    void* stream);
+
+/* One environment step, qp' = step(qp, act) (Section 3): `substeps`
+ * repetitions of Algorithm 1 with the action held. `out` may alias `in`. */
+int brax_step(const brax_sys* sys, const brax_state* in, const float* act, brax_state* out, int32_t flags,
+              void* stream);
+
+/* Adjoint of brax_step (Sections 2 and 5.1.4: gradients through the step):
+ * given g_out = dL/d(out), writes g_in = dL/d(in) and g_act = dL/d(act)
+ * (overwritten, not accumulated) for the same function brax_step computes.
+ * The forward substeps are recomputed inside. At kinks the one-sided
+ * conventions are: max(0,x)' = [x > 0]; the Coulomb cap is taken when
+ * cap <= stop; clamp' = 1 strictly inside; clip' = 1 on the closed interval;
+ * contact activation and counts have zero derivative. g_in may not alias
+ * in or g_out. */
+int brax_step_vjp(const brax_sys* sys, const brax_state* in, const float* act, const brax_state* g_out,
+                  brax_state* g_in, float* g_act, int32_t flags, void* stream);
+
+/* T consecutive steps with acts [T][Amax][E]. With save_every > 0, the state
+ * after steps save_every, 2*save_every, ... is written to traj (each field
+ * [T/save_every][C][Bmax][E]); traj may be NULL when save_every == 0. The
+ * final state goes to `out` (may alias `in`). T == 0 copies in to out. */
+int brax_rollout(const brax_sys* sys, const brax_state* in, const float* acts, int32_t T, int32_t save_every,
+                 brax_state* traj, brax_state* out, int32_t flags, void* stream);
+
+/* Time the fused kernel's launch shapes on `stream` and keep the fastest
+ * for later calls (the result does not depend on the shape). */
+int brax_autotune(brax_sys* sys, void* stream);
+
+/* Launch shape in use: environments per wavefront and wavefronts per block. */
+int brax_schedule(const brax_sys* sys, int32_t* envs_per_wave, int32_t* waves_per_block);
+
+/* Copy the per-environment non-finite flags written by the last call made
+ * with BRAX_NONFINITE_FLAGS to host out[n_envs] (synchronises the device). */
+int brax_nonfinite(const brax_sys* sys, uint8_t* out);
+
+/* Message of the calling thread's last failure ("" if none). Never NULL. */
+const char* brax_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BRAXMI_H */

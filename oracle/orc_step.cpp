@@ -244,8 +244,8 @@ template <class T> JointFrame<T> joint_frame(const OrcSys& s, int j, const Deriv
 
 // Joint update (Algorithm 1, joint loop; Section 6.1 spring joints).
 template <class T>
-void joint_apply(const OrcSys& s, int j, const Body<T>* B, const Derived<T>* D, V3<T>* f, V3<T>* t,
-                 Margins* mg) {
+void joint_apply(const OrcSys& s, int j, const Body<T>* B, const Derived<T>* D, const JointFrame<T>& fr, V3<T>* f,
+                 V3<T>* t, Margins* mg) {
   const int P = s.j_parent[j], C = s.j_child[j], n = s.j_dof[j];
   V3<T> rP = matvec(D[P].R, const_vec<T>(s.j_anchor_p[j]));
   V3<T> rC = matvec(D[C].R, const_vec<T>(s.j_anchor_c[j]));
@@ -256,7 +256,6 @@ void joint_apply(const OrcSys& s, int j, const Body<T>* B, const Derived<T>* D, 
   // anchor spring and damper: force on the child at its anchor, minus that on the parent
   V3<T> F = add(scale(T(s.j_k_lin[j]), d), scale(T(s.j_c_lin[j]), sub(uP, uC)));
 
-  JointFrame<T> fr = joint_frame(s, j, D[P], D[C]);
   V3<T> e1P = column(fr.AwP, 0), e1C = column(fr.AwC, 0), e2C = column(fr.AwC, 1);
   V3<T> tau = {T(0.0), T(0.0), T(0.0)};
   // alignment spring on the constrained rotational axes
@@ -288,10 +287,10 @@ void joint_apply(const OrcSys& s, int j, const Body<T>* B, const Derived<T>* D, 
 // Actuator update (Algorithm 1, actuator loop): torque gear * a about the
 // joint's Euler axis, on the child and opposite on the parent.
 template <class T>
-void actuator_apply(const OrcSys& s, int k, const T& a, const Derived<T>* D, V3<T>* t) {
+void actuator_apply(const OrcSys& s, int k, const T& a, const JointFrame<T>* frames, V3<T>* t) {
   const int j = s.a_joint[k];
   const int P = s.j_parent[j], C = s.j_child[j];
-  JointFrame<T> fr = joint_frame(s, j, D[P], D[C]);
+  const JointFrame<T>& fr = frames[j];
   V3<T> tau = scale(T(s.a_gear[k]) * a, fr.axis[s.a_axis[k]]);
   t[C] = add(t[C], tau);
   t[P] = sub(t[P], tau);
@@ -353,6 +352,9 @@ void step_env(const OrcSys& s, T* X, const T* act_in, Margins* mg) {
     // qp = kinematic_integrator.apply(qp, dt)
     for (int i = 0; i < nb; ++i) kinematic(s, i, B[i], h);
     for (int i = 0; i < nb; ++i) D[i] = derive(s, i, B[i]);
+    // joint frames and Euler angles, shared by the joint and actuator updates
+    JointFrame<T> fr[MAXJ];
+    for (int j = 0; j < s.nj; ++j) fr[j] = joint_frame(s, j, D[s.j_parent[j]], D[s.j_child[j]]);
     V3<T> fj[MAXB], tj[MAXB], ta[MAXB], dv[MAXB], dw[MAXB];
     int cnt[MAXB];
     for (int i = 0; i < nb; ++i) {
@@ -360,9 +362,9 @@ void step_env(const OrcSys& s, T* X, const T* act_in, Margins* mg) {
       cnt[i] = 0;
     }
     // dp_j += jo.apply(qp)
-    for (int j = 0; j < s.nj; ++j) joint_apply(s, j, B, D, fj, tj, mg);
+    for (int j = 0; j < s.nj; ++j) joint_apply(s, j, B, D, fr[j], fj, tj, mg);
     // dp_a += ac.apply(qp, action)
-    for (int k = 0; k < s.na; ++k) actuator_apply(s, k, a[k], D, ta);
+    for (int k = 0; k < s.na; ++k) actuator_apply(s, k, a[k], fr, ta);
     // dp_c += co.apply(qp)
     for (int c = 0; c < s.nc; ++c) collider_apply(s, c, B, D, h, dv, dw, cnt, mg);
     // qp = potential_integrator.apply(qp, dp_j + dp_a, dt)
@@ -499,8 +501,10 @@ void orc_joint_forces(const OrcSys* s, const double* X, const double* act, doubl
     D[i] = derive(*s, i, B[i]);
     fj[i] = tj[i] = V3<double>{0, 0, 0};
   }
-  for (int j = 0; j < s->nj; ++j) joint_apply(*s, j, B, D, fj, tj, (Margins*)nullptr);
-  for (int k = 0; k < s->na; ++k) actuator_apply(*s, k, clampv(act[k], -1.0, 1.0), D, tj);
+  JointFrame<double> fr[MAXJ];
+  for (int j = 0; j < s->nj; ++j) fr[j] = joint_frame(*s, j, D[s->j_parent[j]], D[s->j_child[j]]);
+  for (int j = 0; j < s->nj; ++j) joint_apply(*s, j, B, D, fr[j], fj, tj, (Margins*)nullptr);
+  for (int k = 0; k < s->na; ++k) actuator_apply(*s, k, clampv(act[k], -1.0, 1.0), fr, tj);
   for (int i = 0; i < s->nb; ++i) {
     f[3 * i + 0] = fj[i].x; f[3 * i + 1] = fj[i].y; f[3 * i + 2] = fj[i].z;
     t[3 * i + 0] = tj[i].x; t[3 * i + 1] = tj[i].y; t[3 * i + 2] = tj[i].z;

@@ -1,0 +1,317 @@
+"""Python binding of the braxmi C ABI (argument marshalling only).
+
+Device memory and streams come from PyTorch (ROCm); every step of the
+physics runs in the HIP library ``libbraxmi.so`` built next to this file.
+There is no fallback: if the library is missing or no GPU is present, the
+calls raise.
+
+State tensors follow the library layout (environment index fastest):
+``pos [3][Bmax][E]``, ``rot [4][Bmax][E]`` (w, x, y, z), ``vel [3][Bmax][E]``,
+``ang [3][Bmax][E]``; actions ``[Amax][E]``, action sequences ``[T][Amax][E]``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbraxmi.so")
+
+BRAX_FUSED, BRAX_PLAIN, BRAX_GRAPH, BRAX_NONFINITE_FLAGS = 0, 1, 4, 8
+MAX_TYPES = 8
+
+ERRORS = {-1: "BRAX_E_ARG", -2: "BRAX_E_PARSE", -3: "BRAX_E_MODEL", -4: "BRAX_E_DEVICE", -5: "BRAX_E_NOMEM",
+          -6: "BRAX_E_UNSUPPORTED"}
+
+
+class BraxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _State(C.Structure):
+    _fields_ = [("pos", C.c_void_p), ("rot", C.c_void_p), ("vel", C.c_void_p), ("ang", C.c_void_p)]
+
+
+class _Layout(C.Structure):
+    _fields_ = [("n_envs", C.c_int32), ("n_types", C.c_int32), ("b_max", C.c_int32), ("a_max", C.c_int32),
+                ("d_max", C.c_int32),
+                ("type_envs", C.c_int32 * MAX_TYPES), ("n_bodies", C.c_int32 * MAX_TYPES),
+                ("n_joints", C.c_int32 * MAX_TYPES), ("n_actions", C.c_int32 * MAX_TYPES),
+                ("n_dof", C.c_int32 * MAX_TYPES), ("n_contacts", C.c_int32 * MAX_TYPES),
+                ("substeps", C.c_int32 * MAX_TYPES), ("dt", C.c_float * MAX_TYPES),
+                ("device", C.c_int32), ("nonfinite", C.c_void_p)]
+
+
+EXPORTS = ("brax_sys_create", "brax_sys_destroy", "brax_sys_query", "brax_default_angles", "brax_default_qp",
+           "brax_step", "brax_step_vjp", "brax_rollout", "brax_autotune", "brax_schedule", "brax_nonfinite",
+           "brax_last_error")
+
+_lib = None
+
+
+def lib():
+    """Load libbraxmi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -m paper_2106_13281_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        L.brax_sys_create.argtypes = [P(C.c_char_p), C.c_int32, P(C.c_int32), C.c_int32, C.c_int32,
+                                      P(C.c_void_p)]
+        L.brax_sys_destroy.argtypes = [C.c_void_p]
+        L.brax_sys_destroy.restype = None
+        L.brax_sys_query.argtypes = [C.c_void_p, P(_Layout)]
+        L.brax_default_angles.argtypes = [C.c_void_p, C.c_int32, P(C.c_float)]
+        L.brax_default_qp.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, P(_State), C.c_void_p]
+        L.brax_step.argtypes = [C.c_void_p, P(_State), C.c_void_p, P(_State), C.c_int32, C.c_void_p]
+        L.brax_step_vjp.argtypes = [C.c_void_p, P(_State), C.c_void_p, P(_State), P(_State), C.c_void_p, C.c_int32,
+                                    C.c_void_p]
+        L.brax_rollout.argtypes = [C.c_void_p, P(_State), C.c_void_p, C.c_int32, C.c_int32, P(_State), P(_State),
+                                   C.c_int32, C.c_void_p]
+        L.brax_autotune.argtypes = [C.c_void_p, C.c_void_p]
+        L.brax_schedule.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32)]
+        L.brax_nonfinite.argtypes = [C.c_void_p, P(C.c_uint8)]
+        L.brax_last_error.restype = C.c_char_p
+        for name in EXPORTS:
+            if name not in ("brax_sys_destroy", "brax_last_error"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise BraxError(rc, lib().brax_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class State:
+    """Structure-of-arrays state: four FP32 CUDA tensors."""
+    pos: torch.Tensor
+    rot: torch.Tensor
+    vel: torch.Tensor
+    ang: torch.Tensor
+
+    @classmethod
+    def empty(cls, b_max, n_envs, device="cuda", lead=()):
+        f = dict(dtype=torch.float32, device=device)
+        return cls(torch.empty(*lead, 3, b_max, n_envs, **f), torch.empty(*lead, 4, b_max, n_envs, **f),
+                   torch.empty(*lead, 3, b_max, n_envs, **f), torch.empty(*lead, 3, b_max, n_envs, **f))
+
+    @classmethod
+    def zeros_like(cls, s):
+        return cls(torch.zeros_like(s.pos), torch.zeros_like(s.rot), torch.zeros_like(s.vel),
+                   torch.zeros_like(s.ang))
+
+    def fields(self):
+        return (self.pos, self.rot, self.vel, self.ang)
+
+    def clone(self):
+        return State(*(t.clone() for t in self.fields()))
+
+    def struct(self):
+        for t in self.fields():
+            if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError("state tensors must be contiguous float32 CUDA tensors")
+        return _State(*(t.data_ptr() for t in self.fields()))
+
+    def __getitem__(self, k):
+        """Snapshot k of a trajectory state (leading save index)."""
+        return State(*(t[k] for t in self.fields()))
+
+
+class System:
+    """A batch of environments of one or several system types on one GPU."""
+
+    def __init__(self, descs, n_envs, env_desc=None, device=0):
+        if isinstance(descs, str):
+            descs = [descs]
+        arr = (C.c_char_p * len(descs))(*[d.encode() for d in descs])
+        ed = None
+        if env_desc is not None:
+            env_desc = list(int(x) for x in env_desc)
+            if len(env_desc) != n_envs:
+                raise ValueError("env_desc must have n_envs entries")
+            ed = (C.c_int32 * n_envs)(*env_desc)
+        h = C.c_void_p()
+        _check(lib().brax_sys_create(arr, len(descs), ed, n_envs, device, C.byref(h)))
+        self._h = h
+        self._L = lib()
+        self.device_index = device
+        lay = _Layout()
+        _check(lib().brax_sys_query(h, C.byref(lay)))
+        self.n_envs, self.n_types = lay.n_envs, lay.n_types
+        self.b_max, self.a_max, self.d_max = lay.b_max, lay.a_max, lay.d_max
+        nt = lay.n_types
+        self.type_envs = list(lay.type_envs[:nt])
+        self.n_bodies = list(lay.n_bodies[:nt])
+        self.n_joints = list(lay.n_joints[:nt])
+        self.n_actions = list(lay.n_actions[:nt])
+        self.n_dof = list(lay.n_dof[:nt])
+        self.n_contacts = list(lay.n_contacts[:nt])
+        self.substeps = list(lay.substeps[:nt])
+        self.dt = list(lay.dt[:nt])
+        self.device = torch.device("cuda", device) if device >= 0 else None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._L.brax_sys_destroy(h)
+            self._h = None
+
+    # ------------------------------------------------------------ helpers
+    def new_state(self, lead=()):
+        return State.empty(self.b_max, self.n_envs, self.device, lead)
+
+    def default_angles(self, t=0):
+        out = (C.c_float * max(self.n_dof[t], 1))()
+        _check(lib().brax_default_angles(self._h, t, out))
+        return torch.tensor(list(out)[: self.n_dof[t]], dtype=torch.float32)
+
+    def _act(self, a, shape):
+        if a is None:
+            if self.a_max == 0:
+                return None
+            raise ValueError("actions required")
+        if a.dtype != torch.float32 or not a.is_contiguous() or not a.is_cuda or tuple(a.shape) != shape:
+            raise ValueError(f"actions must be a contiguous float32 CUDA tensor of shape {shape}")
+        return a
+
+    # ------------------------------------------------------------ calls
+    def default_qp(self, angles=None, root_offset=None, out=None, stream=None):
+        out = self.new_state() if out is None else out
+        if angles is not None:
+            angles = self._act(angles, (self.d_max, self.n_envs)) if self.d_max else None
+        if root_offset is not None:
+            root_offset = self._act(root_offset, (3, self.n_envs))
+        st = out.struct()
+        _check(lib().brax_default_qp(self._h, _ptr(angles), _ptr(root_offset), C.byref(st), _stream(stream)))
+        return out
+
+    def step(self, state, act, out=None, flags=0, stream=None):
+        out = self.new_state() if out is None else out
+        act = self._act(act, (self.a_max, self.n_envs))
+        si, so = state.struct(), out.struct()
+        _check(lib().brax_step(self._h, C.byref(si), _ptr(act), C.byref(so), flags, _stream(stream)))
+        return out
+
+    def step_vjp(self, state, act, g_out, g_in=None, g_act=None, flags=0, stream=None):
+        g_in = self.new_state() if g_in is None else g_in
+        act = self._act(act, (self.a_max, self.n_envs))
+        if g_act is None:
+            g_act = torch.empty(self.a_max, self.n_envs, dtype=torch.float32, device=self.device)
+        si, sg, sgi = state.struct(), g_out.struct(), g_in.struct()
+        _check(lib().brax_step_vjp(self._h, C.byref(si), _ptr(act), C.byref(sg), C.byref(sgi), _ptr(g_act), flags,
+                                   _stream(stream)))
+        return g_in, g_act
+
+    def rollout(self, state, acts, save_every=0, out=None, traj=None, flags=0, stream=None):
+        T = acts.shape[0] if acts is not None else 0
+        out = self.new_state() if out is None else out
+        if T:
+            acts = self._act(acts, (T, self.a_max, self.n_envs))
+        n_save = T // save_every if save_every > 0 else 0
+        if n_save and traj is None:
+            traj = self.new_state(lead=(n_save,))
+        si, so = state.struct(), out.struct()
+        tr = traj.struct() if n_save else None
+        _check(lib().brax_rollout(self._h, C.byref(si), _ptr(acts) if T else None, T, save_every,
+                                  C.byref(tr) if tr is not None else None, C.byref(so), flags, _stream(stream)))
+        return out, (traj if n_save else None)
+
+    def autotune(self, stream=None):
+        _check(lib().brax_autotune(self._h, _stream(stream)))
+        return self.schedule()
+
+    def schedule(self):
+        a, b = C.c_int32(), C.c_int32()
+        _check(lib().brax_schedule(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def nonfinite(self):
+        """Per-environment non-finite flags of the last call made with BRAX_NONFINITE_FLAGS (host copy)."""
+        buf = (C.c_uint8 * max(self.n_envs, 1))()
+        _check(lib().brax_nonfinite(self._h, buf))
+        return torch.tensor(list(buf)[: self.n_envs], dtype=torch.uint8)
+
+
+class RolloutFn(torch.autograd.Function):
+    """Differentiable T-step rollout (final state) with checkpoints every k steps.
+
+    Forward keeps the state every k steps. Backward recomputes each segment
+    from its checkpoint (brax_rollout) and runs brax_step_vjp backwards
+    through it. Inputs: the four initial-state tensors and the action
+    sequence [T][Amax][E]; outputs: the four final-state tensors.
+    """
+
+    @staticmethod
+    def forward(ctx, system, k, pos, rot, vel, ang, acts):
+        T = acts.shape[0]
+        k = max(1, min(int(k), max(T, 1)))
+        s0 = State(pos.detach().contiguous(), rot.detach().contiguous(), vel.detach().contiguous(),
+                   ang.detach().contiguous())
+        acts_d = acts.detach().contiguous()
+        ckpts = [s0]
+        cur = s0
+        t = 0
+        while t < T:
+            n = min(k, T - t)
+            nxt, _ = system.rollout(cur, acts_d[t:t + n])
+            ckpts.append(nxt)
+            cur = nxt
+            t += n
+        ctx.system, ctx.k, ctx.T = system, k, T
+        ctx.save_for_backward(acts_d, *[x for c in ckpts[:-1] for x in c.fields()])
+        return cur.pos, cur.rot, cur.vel, cur.ang
+
+    @staticmethod
+    def backward(ctx, gp, gr, gv, gw):
+        system, k, T = ctx.system, ctx.k, ctx.T
+        saved = ctx.saved_tensors
+        acts = saved[0]
+        ck = [State(*saved[1 + 4 * i: 5 + 4 * i]) for i in range((len(saved) - 1) // 4)]
+
+        def z(g, ref):
+            return torch.zeros_like(ref) if g is None else g.contiguous()
+
+        g = State(z(gp, ck[0].pos), z(gr, ck[0].rot), z(gv, ck[0].vel), z(gw, ck[0].ang))
+        g_acts = torch.zeros_like(acts)
+        seg_starts = list(range(0, T, k))
+        for si in reversed(range(len(seg_starts))):
+            t0 = seg_starts[si]
+            n = min(k, T - t0)
+            # states s_{t0}, ..., s_{t0+n-1}
+            states = [ck[si]]
+            if n > 1:
+                _, traj = system.rollout(ck[si], acts[t0:t0 + n - 1], save_every=1)
+                states += [traj[i] for i in range(n - 1)]
+            for i in reversed(range(n)):
+                g_in, g_a = system.step_vjp(_contig(states[i]), acts[t0 + i], g)
+                g_acts[t0 + i] = g_a
+                g = g_in
+        return None, None, g.pos, g.rot, g.vel, g.ang, g_acts
+
+
+def _contig(s):
+    return State(*(t.contiguous() for t in s.fields()))
+
+
+def rollout_grad(system, state, acts, k=10):
+    """Apply RolloutFn: returns the final State, differentiable w.r.t. state and acts."""
+    p, r, v, w = RolloutFn.apply(system, k, state.pos, state.rot, state.vel, state.ang, acts)
+    return State(p, r, v, w)

@@ -1,0 +1,605 @@
+// C ABI of the library: argument checks, system tables, schedules, graphs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/braxmi.h"
+#include "bx_internal.h"
+#include "bx_vjp.h"
+
+using namespace bx;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t _e = (expr);                                                                \
+    if (_e != hipSuccess) return fail(BRAX_E_DEVICE, "%s: %s", #expr, hipGetErrorString(_e)); \
+  } while (0)
+
+// Keeps the caller's current device and restores it on scope exit.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+struct GraphKey {
+  int kind;  // 0 step, 1 rollout
+  int flags, T, save_every;
+  const void* p[12];
+  bool operator<(const GraphKey& o) const {
+    if (kind != o.kind) return kind < o.kind;
+    if (flags != o.flags) return flags < o.flags;
+    if (T != o.T) return T < o.T;
+    if (save_every != o.save_every) return save_every < o.save_every;
+    return std::memcmp(p, o.p, sizeof p) < 0;
+  }
+};
+
+struct brax_sys {
+  int device = -1;
+  int E = 0, n_types = 0, Bm = 0, Am = 0, Dm = 0;
+  std::vector<SystemDesc> descs;
+  Tables host_tab{};
+  Tables* d_tab = nullptr;
+  std::vector<int32_t> env_type, env_list;
+  int type_off[MAXT] = {0}, type_cnt[MAXT] = {0};
+  int32_t* d_env_type = nullptr;
+  int32_t* d_env_list = nullptr;
+  int32_t* d_type_off = nullptr;
+  // fused schedule
+  int envs_per_wave[MAXT] = {0};
+  int waves_per_block = 1;
+  std::vector<WaveWork> work;
+  WaveWork* d_work = nullptr;
+  // plain scratch per type
+  float* d_jslot[MAXT] = {nullptr};
+  float* d_cslot[MAXT] = {nullptr};
+  // adjoint workspace
+  VjpWork vjp{};
+  uint8_t* d_nonfinite = nullptr;
+  std::map<GraphKey, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+
+  LaunchCtx ctx() const {
+    LaunchCtx c{};
+    c.tab = d_tab;
+    c.host_tab = &host_tab;
+    c.E = E;
+    c.Bm = Bm;
+    c.Am = Am;
+    c.n_types = n_types;
+    c.env_type = d_env_type;
+    c.env_list = d_env_list;
+    c.type_off = d_type_off;
+    for (int t = 0; t < MAXT; ++t) {
+      c.type_off_h[t] = type_off[t];
+      c.type_cnt_h[t] = type_cnt[t];
+    }
+    c.nonfinite = d_nonfinite;
+    return c;
+  }
+};
+
+namespace {
+
+void free_all(brax_sys* s) {
+  if (s->device >= 0) {
+    DeviceGuard g(s->device);
+    (void)hipDeviceSynchronize();
+    for (auto& kv : s->graphs) {
+      (void)hipGraphExecDestroy(kv.second.second);
+      (void)hipGraphDestroy(kv.second.first);
+    }
+    (void)hipFree(s->d_tab);
+    (void)hipFree(s->d_env_type);
+    (void)hipFree(s->d_env_list);
+    (void)hipFree(s->d_type_off);
+    (void)hipFree(s->d_work);
+    (void)hipFree(s->d_nonfinite);
+    for (int t = 0; t < MAXT; ++t) {
+      (void)hipFree(s->d_jslot[t]);
+      (void)hipFree(s->d_cslot[t]);
+    }
+    vjp_free(s->vjp);
+  }
+  delete s;
+}
+
+// Split every type's environments into wavefronts of envs_per_wave[t] and
+// order the wavefronts heaviest first (substeps x per-lane work estimate).
+void build_work(brax_sys* s) {
+  struct Item {
+    double cost;
+    WaveWork w;
+  };
+  std::vector<Item> items;
+  for (int t = 0; t < s->n_types; ++t) {
+    const TypeT& ty = s->host_tab.type[t];
+    int epw = s->envs_per_wave[t];
+    double cost = ty.substeps * (150.0 + (ty.nj > 0 ? 250.0 * ty.max_dof : 0.0) + 130.0 * ty.max_contacts);
+    for (int k0 = 0; k0 < s->type_cnt[t]; k0 += epw)
+      items.push_back(Item{cost, WaveWork{t, k0, std::min(epw, s->type_cnt[t] - k0), 0}});
+  }
+  std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
+  s->work.clear();
+  for (auto& it : items) s->work.push_back(it.w);
+}
+
+int upload_work(brax_sys* s) {
+  (void)hipFree(s->d_work);
+  s->d_work = nullptr;
+  if (s->work.empty()) return BRAX_OK;
+  HIP_TRY(hipMalloc(&s->d_work, sizeof(WaveWork) * s->work.size()));
+  HIP_TRY(hipMemcpy(s->d_work, s->work.data(), sizeof(WaveWork) * s->work.size(), hipMemcpyHostToDevice));
+  return BRAX_OK;
+}
+
+Fields F(const brax_state* st) { return Fields{st->pos, st->rot, st->vel, st->ang}; }
+
+bool state_ok(const brax_state* st) { return st && st->pos && st->rot && st->vel && st->ang; }
+
+// Run `body(stream)` directly, or capture it once per key into a HIP graph
+// and replay that graph.
+template <class Fn>
+int run_maybe_graph(brax_sys* s, bool use_graph, const GraphKey& key, hipStream_t stream, Fn body) {
+  if (!use_graph) return body(stream);
+  auto it = s->graphs.find(key);
+  if (it == s->graphs.end()) {
+    hipStream_t cap = stream;
+    bool own = false;
+    if (cap == nullptr) {  // the legacy default stream cannot be captured
+      HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+      own = true;
+    }
+    HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    int rc = body(cap);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(cap, &g);
+    if (own) (void)hipStreamDestroy(cap);
+    if (rc != BRAX_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(BRAX_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return fail(BRAX_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+    }
+    if (s->graphs.size() >= 16) {  // bounded cache
+      auto old = s->graphs.begin();
+      (void)hipGraphExecDestroy(old->second.second);
+      (void)hipGraphDestroy(old->second.first);
+      s->graphs.erase(old);
+    }
+    it = s->graphs.emplace(key, std::make_pair(g, x)).first;
+  }
+  HIP_TRY(hipGraphLaunch(it->second.second, stream));
+  return BRAX_OK;
+}
+
+int check_flags(int32_t flags) {
+  if (flags & ~(BRAX_PLAIN | BRAX_GRAPH | BRAX_NONFINITE_FLAGS)) return fail(BRAX_E_ARG, "unknown flag bits 0x%x", flags);
+  return BRAX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* brax_last_error(void) { return g_err.c_str(); }
+
+int brax_sys_create(const char* const* descs, int32_t n_descs, const int32_t* env_desc, int32_t n_envs,
+                    int32_t device, brax_sys** out) {
+  g_err.clear();
+  if (!out) return fail(BRAX_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!descs) return fail(BRAX_E_ARG, "descs is NULL");
+  if (n_descs < 1 || n_descs > MAXT) return fail(BRAX_E_ARG, "n_descs must be in 1..%d", MAXT);
+  if (n_envs < 0) return fail(BRAX_E_ARG, "n_envs must be >= 0");
+  if (n_envs > (1 << 24)) return fail(BRAX_E_ARG, "n_envs too large");
+  if (device < -1) return fail(BRAX_E_ARG, "device must be >= -1");
+  std::unique_ptr<brax_sys, void (*)(brax_sys*)> s(new brax_sys(), free_all);
+  s->device = -1;
+  s->n_types = n_descs;
+  s->E = n_envs;
+  s->descs.resize(n_descs);
+  for (int t = 0; t < n_descs; ++t) {
+    if (!descs[t]) return fail(BRAX_E_ARG, "descs[%d] is NULL", t);
+    std::string err;
+    int rc = build_system(descs[t], s->descs[t], err);
+    if (rc != BRAX_OK) return fail(rc, "system %d: %s", t, err.c_str());
+    pack_type(s->descs[t], s->host_tab, t);
+    s->Bm = std::max(s->Bm, s->host_tab.type[t].nb);
+    s->Am = std::max(s->Am, s->host_tab.type[t].na);
+    s->Dm = std::max(s->Dm, s->host_tab.type[t].ndof);
+  }
+  s->env_type.resize(n_envs);
+  for (int e = 0; e < n_envs; ++e) {
+    int t = env_desc ? env_desc[e] : 0;
+    if (t < 0 || t >= n_descs) return fail(BRAX_E_ARG, "env_desc[%d] = %d out of range", e, t);
+    s->env_type[e] = t;
+    s->type_cnt[t]++;
+  }
+  int off = 0;
+  for (int t = 0; t < n_descs; ++t) {
+    s->type_off[t] = off;
+    off += s->type_cnt[t];
+  }
+  s->env_list.resize(n_envs);
+  {
+    int fill[MAXT];
+    for (int t = 0; t < n_descs; ++t) fill[t] = s->type_off[t];
+    for (int e = 0; e < n_envs; ++e) s->env_list[fill[s->env_type[e]]++] = e;
+  }
+  for (int t = 0; t < n_descs; ++t) s->envs_per_wave[t] = std::max(1, 64 / s->host_tab.type[t].nb);
+  s->waves_per_block = 1;
+  build_work(s.get());
+  if (device < 0) {
+    *out = s.release();
+    return BRAX_OK;
+  }
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device >= ndev) return fail(BRAX_E_ARG, "device %d not present (%d devices)", device, ndev);
+  s->device = device;
+  DeviceGuard g(device);
+  if (!g.ok) return fail(BRAX_E_DEVICE, "cannot select device %d", device);
+  auto dmalloc = [&](void** p, size_t n) -> int {
+    if (n == 0) n = 4;
+    hipError_t e = hipMalloc(p, n);
+    if (e == hipErrorOutOfMemory) return fail(BRAX_E_NOMEM, "device allocation of %zu bytes failed", n);
+    if (e != hipSuccess) return fail(BRAX_E_DEVICE, "hipMalloc: %s", hipGetErrorString(e));
+    return BRAX_OK;
+  };
+  int rc;
+  if ((rc = dmalloc((void**)&s->d_tab, sizeof(Tables)))) return rc;
+  HIP_TRY(hipMemcpy(s->d_tab, &s->host_tab, sizeof(Tables), hipMemcpyHostToDevice));
+  if ((rc = dmalloc((void**)&s->d_env_type, sizeof(int32_t) * n_envs))) return rc;
+  if ((rc = dmalloc((void**)&s->d_env_list, sizeof(int32_t) * n_envs))) return rc;
+  if ((rc = dmalloc((void**)&s->d_type_off, sizeof(int32_t) * MAXT))) return rc;
+  if ((rc = dmalloc((void**)&s->d_nonfinite, (size_t)n_envs))) return rc;
+  if (n_envs) {
+    HIP_TRY(hipMemcpy(s->d_env_type, s->env_type.data(), sizeof(int32_t) * n_envs, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(s->d_env_list, s->env_list.data(), sizeof(int32_t) * n_envs, hipMemcpyHostToDevice));
+  }
+  HIP_TRY(hipMemcpy(s->d_type_off, s->type_off, sizeof(int32_t) * MAXT, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemset(s->d_nonfinite, 0, (size_t)std::max(n_envs, 1)));
+  for (int t = 0; t < n_descs; ++t) {
+    const TypeT& ty = s->host_tab.type[t];
+    size_t n = (size_t)s->type_cnt[t];
+    if ((rc = dmalloc((void**)&s->d_jslot[t], sizeof(float) * 12 * std::max(ty.nj, 1) * std::max(n, (size_t)1))))
+      return rc;
+    if ((rc = dmalloc((void**)&s->d_cslot[t], sizeof(float) * 7 * std::max(ty.nc, 1) * std::max(n, (size_t)1))))
+      return rc;
+  }
+  if ((rc = upload_work(s.get()))) return rc;
+  *out = s.release();
+  return BRAX_OK;
+}
+
+void brax_sys_destroy(brax_sys* sys) {
+  if (sys) free_all(sys);
+}
+
+int brax_sys_query(const brax_sys* s, brax_layout* out) {
+  if (!s || !out) return fail(BRAX_E_ARG, "NULL argument");
+  std::memset(out, 0, sizeof *out);
+  out->n_envs = s->E;
+  out->n_types = s->n_types;
+  out->b_max = s->Bm;
+  out->a_max = s->Am;
+  out->d_max = s->Dm;
+  for (int t = 0; t < s->n_types; ++t) {
+    const TypeT& ty = s->host_tab.type[t];
+    out->type_envs[t] = s->type_cnt[t];
+    out->n_bodies[t] = ty.nb;
+    out->n_joints[t] = ty.nj;
+    out->n_actions[t] = ty.na;
+    out->n_dof[t] = ty.ndof;
+    out->n_contacts[t] = ty.nc;
+    out->substeps[t] = ty.substeps;
+    out->dt[t] = ty.dt;
+  }
+  out->device = s->device;
+  out->nonfinite = s->d_nonfinite;
+  return BRAX_OK;
+}
+
+int brax_default_angles(const brax_sys* s, int32_t type, float* out) {
+  if (!s || !out) return fail(BRAX_E_ARG, "NULL argument");
+  if (type < 0 || type >= s->n_types) return fail(BRAX_E_ARG, "type %d out of range", type);
+  const TypeT& ty = s->host_tab.type[type];
+  for (int j = 0; j < ty.nj; ++j) {
+    const JointT& J = s->host_tab.joint[type][j];
+    for (int k = 0; k < J.dof; ++k) out[J.dof0 + k] = J.def_angle[k];
+  }
+  return BRAX_OK;
+}
+
+int brax_default_qp(const brax_sys* sys, const float* joint_angles, const float* root_offset, brax_state* out,
+                    void* stream) {
+  brax_sys* s = const_cast<brax_sys*>(sys);
+  if (!s) return fail(BRAX_E_ARG, "sys is NULL");
+  if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
+  if (s->E == 0) return BRAX_OK;
+  if (!state_ok(out)) return fail(BRAX_E_ARG, "out state has a NULL field");
+  DeviceGuard g(s->device);
+  HIP_TRY(launch_default_qp(s->ctx(), joint_angles, root_offset, F(out), (hipStream_t)stream));
+  return BRAX_OK;
+}
+
+int brax_step(const brax_sys* sys, const brax_state* in, const float* act, brax_state* out, int32_t flags,
+              void* stream) {
+  brax_sys* s = const_cast<brax_sys*>(sys);
+  if (!s) return fail(BRAX_E_ARG, "sys is NULL");
+  if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
+  int rc = check_flags(flags);
+  if (rc) return rc;
+  if (s->E == 0) return BRAX_OK;
+  if (!state_ok(in) || !state_ok(out)) return fail(BRAX_E_ARG, "state has a NULL field");
+  if (!act && s->Am > 0) return fail(BRAX_E_ARG, "act is NULL");
+  DeviceGuard g(s->device);
+  hipStream_t st = (hipStream_t)stream;
+  const bool nf = flags & BRAX_NONFINITE_FLAGS;
+  GraphKey key{};
+  key.kind = 0;
+  key.flags = flags;
+  key.T = 1;
+  const void* ptrs[] = {in->pos, in->rot, in->vel, in->ang, out->pos, out->rot, out->vel, out->ang, act};
+  std::memcpy(key.p, ptrs, sizeof ptrs);
+  return run_maybe_graph(s, flags & BRAX_GRAPH, key, st, [&](hipStream_t cs) -> int {
+    LaunchCtx c = s->ctx();
+    if (flags & BRAX_PLAIN) {
+      if (nf) HIP_TRY(launch_fill_u8(s->d_nonfinite, s->E, 0, cs));
+      HIP_TRY(launch_plain_step(c, F(in), F(out), act, s->d_jslot, s->d_cslot, nf, cs));
+    } else {
+      HIP_TRY(launch_fused(c, s->d_work, (int)s->work.size(), s->waves_per_block, F(in), F(out), act, 1, 0,
+                           Fields{nullptr, nullptr, nullptr, nullptr}, nf, cs));
+    }
+    return BRAX_OK;
+  });
+}
+
+int brax_rollout(const brax_sys* sys, const brax_state* in, const float* acts, int32_t T, int32_t save_every,
+                 brax_state* traj, brax_state* out, int32_t flags, void* stream) {
+  brax_sys* s = const_cast<brax_sys*>(sys);
+  if (!s) return fail(BRAX_E_ARG, "sys is NULL");
+  if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
+  if (T < 0) return fail(BRAX_E_ARG, "T must be >= 0");
+  if (save_every < 0) return fail(BRAX_E_ARG, "save_every must be >= 0");
+  if (s->E == 0) return check_flags(flags);
+  if (!state_ok(in) || !state_ok(out)) return fail(BRAX_E_ARG, "state has a NULL field");
+  if (T > 0 && !acts && s->Am > 0) return fail(BRAX_E_ARG, "acts is NULL");
+  if (save_every > 0 && T / save_every > 0 && !state_ok(traj)) return fail(BRAX_E_ARG, "traj state has a NULL field");
+  int rc = check_flags(flags);
+  if (rc) return rc;
+  DeviceGuard g(s->device);
+  hipStream_t st = (hipStream_t)stream;
+  const bool nf = flags & BRAX_NONFINITE_FLAGS;
+  Fields tr = (save_every > 0 && traj) ? F(traj) : Fields{nullptr, nullptr, nullptr, nullptr};
+  GraphKey key{};
+  key.kind = 1;
+  key.flags = flags;
+  key.T = T;
+  key.save_every = save_every;
+  const void* ptrs[] = {in->pos, in->rot, in->vel, in->ang, out->pos, out->rot, out->vel, out->ang, acts,
+                        tr.pos, tr.rot, tr.vel};
+  std::memcpy(key.p, ptrs, sizeof ptrs);
+  return run_maybe_graph(s, flags & BRAX_GRAPH, key, st, [&](hipStream_t cs) -> int {
+    LaunchCtx c = s->ctx();
+    if (T == 0) {
+      if (in->pos != out->pos) HIP_TRY(launch_copy_state(c, F(in), F(out), cs));
+      if (nf) HIP_TRY(launch_fill_u8(s->d_nonfinite, s->E, 0, cs));
+      return BRAX_OK;
+    }
+    if (flags & BRAX_PLAIN) {
+      if (nf) HIP_TRY(launch_fill_u8(s->d_nonfinite, s->E, 0, cs));
+      const size_t per_step = (size_t)s->Am * s->E;
+      int n_save = 0;
+      for (int t = 0; t < T; ++t) {
+        const bool last = t == T - 1;
+        HIP_TRY(launch_plain_step(c, t == 0 ? F(in) : F(out), F(out), acts ? acts + per_step * t : nullptr,
+                                  s->d_jslot, s->d_cslot, nf && last, cs));
+        if (save_every > 0 && (t + 1) % save_every == 0) {
+          size_t n3 = (size_t)3 * s->Bm * s->E, n4 = (size_t)4 * s->Bm * s->E;
+          Fields dst{tr.pos + n3 * n_save, tr.rot + n4 * n_save, tr.vel + n3 * n_save, tr.ang + n3 * n_save};
+          HIP_TRY(launch_copy_state(c, F(out), dst, cs));
+          ++n_save;
+        }
+      }
+    } else {
+      HIP_TRY(launch_fused(c, s->d_work, (int)s->work.size(), s->waves_per_block, F(in), F(out), acts, T,
+                           save_every, tr, nf, cs));
+    }
+    return BRAX_OK;
+  });
+}
+
+int brax_nonfinite(const brax_sys* s, uint8_t* out) {
+  if (!s || !out) return fail(BRAX_E_ARG, "NULL argument");
+  if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
+  if (s->E == 0) return BRAX_OK;
+  DeviceGuard g(s->device);
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(out, s->d_nonfinite, (size_t)s->E, hipMemcpyDeviceToHost));
+  return BRAX_OK;
+}
+
+int brax_schedule(const brax_sys* s, int32_t* envs_per_wave, int32_t* waves_per_block) {
+  if (!s) return fail(BRAX_E_ARG, "sys is NULL");
+  if (envs_per_wave) *envs_per_wave = s->envs_per_wave[0];
+  if (waves_per_block) *waves_per_block = s->waves_per_block;
+  return BRAX_OK;
+}
+
+int brax_autotune(brax_sys* s, void* stream) {
+  if (!s) return fail(BRAX_E_ARG, "sys is NULL");
+  if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
+  if (s->E == 0) return BRAX_OK;
+  DeviceGuard g(s->device);
+  hipStream_t st = (hipStream_t)stream;
+  // scratch state and zero actions; timing runs use the reset pose
+  const size_t n3 = (size_t)3 * s->Bm * s->E, n4 = (size_t)4 * s->Bm * s->E;
+  const int T = 2;
+  float* buf = nullptr;
+  size_t nbuf = 2 * (3 * n3 + n4) + (size_t)std::max(s->Am, 1) * s->E * T;
+  HIP_TRY(hipMalloc(&buf, sizeof(float) * nbuf));
+  HIP_TRY(hipMemsetAsync(buf, 0, sizeof(float) * nbuf, st));
+  Fields a{buf, buf + n3, buf + n3 + n4, buf + 2 * n3 + n4};
+  float* b0 = buf + 3 * n3 + n4;
+  Fields b{b0, b0 + n3, b0 + n3 + n4, b0 + 2 * n3 + n4};
+  float* acts = buf + 2 * (3 * n3 + n4);
+  LaunchCtx c = s->ctx();
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int rc = BRAX_OK;
+  if (launch_default_qp(c, nullptr, nullptr, a, st) != hipSuccess) rc = fail(BRAX_E_DEVICE, "autotune reset failed");
+  // candidates: environments per wavefront (per type) and wavefronts per block
+  const int wpb_c[] = {1, 2, 4};
+  int best_epw[MAXT];
+  for (int t = 0; t < s->n_types; ++t) best_epw[t] = s->envs_per_wave[t];
+  float best_total = 1e30f;
+  int best_wpb = s->waves_per_block;
+  std::vector<int> epw_c;
+  for (int wpb : wpb_c) {
+    if (rc) break;
+    for (int t = 0; t < s->n_types; ++t) {
+      const int full = std::max(1, 64 / s->host_tab.type[t].nb);
+      epw_c.clear();
+      for (int k = full; k >= 1 && (int)epw_c.size() < 4; k = (k * 3) / 4) {
+        epw_c.push_back(k);
+        if (k == 1) break;
+      }
+      float best_t = 1e30f;
+      for (int epw : epw_c) {
+        // time this type alone with the others at their current best
+        int saved[MAXT];
+        for (int u = 0; u < s->n_types; ++u) saved[u] = s->envs_per_wave[u];
+        for (int u = 0; u < s->n_types; ++u) s->envs_per_wave[u] = best_epw[u];
+        s->envs_per_wave[t] = epw;
+        build_work(s);
+        if ((rc = upload_work(s))) break;
+        float ms = 0, acc = 1e30f;
+        for (int rep = 0; rep < 3 && !rc; ++rep) {
+          if (hipEventRecord(e0, st) != hipSuccess ||
+              launch_fused(c, s->d_work, (int)s->work.size(), wpb, a, b, acts, T, 0, Fields{}, false, st) !=
+                  hipSuccess ||
+              hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+              hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            rc = fail(BRAX_E_DEVICE, "autotune launch failed");
+          acc = std::min(acc, ms);
+        }
+        for (int u = 0; u < s->n_types; ++u) s->envs_per_wave[u] = saved[u];
+        if (acc < best_t) {
+          best_t = acc;
+          best_epw[t] = epw;
+        }
+      }
+      if (rc) break;
+    }
+    if (rc) break;
+    // whole batch at this block shape
+    for (int u = 0; u < s->n_types; ++u) s->envs_per_wave[u] = best_epw[u];
+    build_work(s);
+    if ((rc = upload_work(s))) break;
+    float ms = 0, acc = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+      if (hipEventRecord(e0, st) != hipSuccess ||
+          launch_fused(c, s->d_work, (int)s->work.size(), wpb, a, b, acts, T, 0, Fields{}, false, st) != hipSuccess ||
+          hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        rc = fail(BRAX_E_DEVICE, "autotune launch failed");
+        break;
+      }
+      acc = std::min(acc, ms);
+    }
+    if (!rc && acc < best_total) {
+      best_total = acc;
+      best_wpb = wpb;
+    }
+  }
+  if (!rc) {
+    for (int u = 0; u < s->n_types; ++u) s->envs_per_wave[u] = best_epw[u];
+    s->waves_per_block = best_wpb;
+    build_work(s);
+    rc = upload_work(s);
+  }
+  (void)hipStreamSynchronize(st);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(buf);
+  // cached graphs hold the old schedule
+  for (auto& kv : s->graphs) {
+    (void)hipGraphExecDestroy(kv.second.second);
+    (void)hipGraphDestroy(kv.second.first);
+  }
+  s->graphs.clear();
+  return rc;
+}
+
+int brax_step_vjp(const brax_sys* sys, const brax_state* in, const float* act, const brax_state* g_out,
+                  brax_state* g_in, float* g_act, int32_t flags, void* stream) {
+  brax_sys* s = const_cast<brax_sys*>(sys);
+  if (!s) return fail(BRAX_E_ARG, "sys is NULL");
+  if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
+  if (s->E == 0) return check_flags(flags);
+  if (!state_ok(in) || !state_ok(g_out) || !state_ok(g_in)) return fail(BRAX_E_ARG, "state has a NULL field");
+  if (!act && s->Am > 0) return fail(BRAX_E_ARG, "act is NULL");
+  if (!g_act && s->Am > 0) return fail(BRAX_E_ARG, "g_act is NULL");
+  if (g_in->pos == in->pos || g_in->pos == g_out->pos) return fail(BRAX_E_ARG, "g_in may not alias in or g_out");
+  int rc = check_flags(flags);
+  if (rc) return rc;
+  DeviceGuard g(s->device);
+  hipStream_t st = (hipStream_t)stream;
+  if ((rc = vjp_reserve(s->vjp, s->host_tab, s->n_types, s->type_cnt, s->E, s->Bm)))
+    return fail(BRAX_E_NOMEM, "adjoint workspace allocation failed");
+  GraphKey key{};
+  key.kind = 2;
+  key.flags = flags;
+  key.T = 1;
+  const void* ptrs[] = {in->pos, in->rot, in->vel, in->ang, act, g_out->pos, g_out->rot, g_out->vel, g_out->ang,
+                        g_in->pos, g_in->rot, g_act};
+  std::memcpy(key.p, ptrs, sizeof ptrs);
+  return run_maybe_graph(s, flags & BRAX_GRAPH, key, st, [&](hipStream_t cs) -> int {
+    LaunchCtx c = s->ctx();
+    VjpSched sched{s->d_work, (int)s->work.size(), s->waves_per_block, s->d_jslot, s->d_cslot};
+    HIP_TRY(launch_vjp(c, s->vjp, sched, F(in), act, F(g_out), F(g_in), g_act, (flags & BRAX_PLAIN) != 0, cs));
+    return BRAX_OK;
+  });
+}
+
+}  // extern "C"

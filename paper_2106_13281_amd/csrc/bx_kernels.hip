@@ -1,0 +1,445 @@
+// HIP kernels for gfx950: reset pose, plain per-phase step, fused persistent
+// step/rollout.
+//
+// State layout: structure of arrays, environment index fastest,
+//   field[(c * Bmax + b) * E + e]   (pos/vel/ang c < 3, rot c < 4).
+// Environments of a batch are grouped by system type through `env_list`
+// (the global environment ids of type t are env_list[off_t .. off_t + n_t)).
+#include <hip/hip_runtime.h>
+
+#include "bx_access.h"
+#include "bx_internal.h"
+#include "bx_phys.h"
+
+namespace bx {
+
+// ------------------------------------------------------------------ reset pose
+// One thread per environment. Forward kinematics down each tree (parent
+// before child): R_C = R_P J_P Rx Ry Rz(theta) J_C^T, child anchor on the
+// parent anchor; roots without a given position lifted to the clearance;
+// optional offset of the first body's tree.
+__device__ m3 euler_xyz(float a, float b, float c) {
+  float ca = cosf(a), sa = sinf(a), cb = cosf(b), sb = sinf(b), cc = cosf(c), sc = sinf(c);
+  // Rx(a) Ry(b) Rz(c)
+  m3 M;
+  M.m[0] = cb * cc;                  M.m[1] = -cb * sc;                 M.m[2] = sb;
+  M.m[3] = sa * sb * cc + ca * sc;   M.m[4] = -sa * sb * sc + ca * cc;  M.m[5] = -sa * cb;
+  M.m[6] = -ca * sb * cc + sa * sc;  M.m[7] = ca * sb * sc + sa * cc;   M.m[8] = ca * cb;
+  return M;
+}
+
+__device__ m3 mm(const m3& A, const m3& B) {
+  m3 C;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      C.m[3 * i + j] = A.m[3 * i] * B.m[j] + A.m[3 * i + 1] * B.m[3 + j] + A.m[3 * i + 2] * B.m[6 + j];
+  return C;
+}
+__device__ m3 mmT(const m3& A, const float* B) {  // A * B^T
+  m3 C;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      C.m[3 * i + j] = A.m[3 * i] * B[3 * j] + A.m[3 * i + 1] * B[3 * j + 1] + A.m[3 * i + 2] * B[3 * j + 2];
+  return C;
+}
+
+// Unit quaternion (w >= 0) of a rotation matrix, largest-pivot method.
+__device__ q4 mat_to_quat(const m3& R) {
+  float tr = R.m[0] + R.m[4] + R.m[8];
+  q4 q;
+  if (tr >= R.m[0] && tr >= R.m[4] && tr >= R.m[8]) {
+    float w = 0.5f * sqrtf(1.f + tr);
+    float k = 0.25f / w;
+    q = q4{w, (R.m[7] - R.m[5]) * k, (R.m[2] - R.m[6]) * k, (R.m[3] - R.m[1]) * k};
+  } else if (R.m[0] >= R.m[4] && R.m[0] >= R.m[8]) {
+    float x = 0.5f * sqrtf(1.f + R.m[0] - R.m[4] - R.m[8]);
+    float k = 0.25f / x;
+    q = q4{(R.m[7] - R.m[5]) * k, x, (R.m[1] + R.m[3]) * k, (R.m[2] + R.m[6]) * k};
+  } else if (R.m[4] >= R.m[8]) {
+    float y = 0.5f * sqrtf(1.f - R.m[0] + R.m[4] - R.m[8]);
+    float k = 0.25f / y;
+    q = q4{(R.m[2] - R.m[6]) * k, (R.m[1] + R.m[3]) * k, y, (R.m[5] + R.m[7]) * k};
+  } else {
+    float z = 0.5f * sqrtf(1.f - R.m[0] - R.m[4] + R.m[8]);
+    float k = 0.25f / z;
+    q = q4{(R.m[3] - R.m[1]) * k, (R.m[2] + R.m[6]) * k, (R.m[5] + R.m[7]) * k, z};
+  }
+  float n = 1.f / sqrtf(q.w * q.w + q.x * q.x + q.y * q.y + q.z * q.z);
+  if (q.w < 0.f) n = -n;
+  return q4{q.w * n, q.x * n, q.y * n, q.z * n};
+}
+
+__global__ void k_default_qp(const Tables* __restrict__ tab, const int32_t* __restrict__ env_type, int E, int Bm,
+                             const float* __restrict__ angles, const float* __restrict__ root_off, Fields out) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const int t = env_type[e];
+  const TypeT& ty = tab->type[t];
+  m3 R[MAXB];
+  v3 p[MAXB];
+  for (int i = 0; i < ty.nb; ++i) {
+    const int b = tab->topo[t][i];
+    const BodyT& B = tab->body[t][b];
+    if (B.joint < 0) {
+      R[b] = m3{{1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f}};
+      p[b] = B.has_pos ? ld3(B.pos0) : V(0.f, 0.f, 0.f);
+    } else {
+      const JointT& J = tab->joint[t][B.joint];
+      float th[3] = {0.f, 0.f, 0.f};
+      for (int k = 0; k < J.dof; ++k) th[k] = angles ? angles[(size_t)(J.dof0 + k) * E + e] : J.def_angle[k];
+      m3 RPJ = mul(R[J.parent], J.FP);
+      R[b] = mmT(mm(RPJ, euler_xyz(th[0], th[1], th[2])), J.FC);
+      p[b] = p[J.parent] + mul(R[J.parent], ld3(J.ap)) - mul(R[b], ld3(J.ac));
+    }
+  }
+  // lift every root tree without a given position to the clearance height
+  for (int r = 0; r < ty.nb; ++r) {
+    const BodyT& Br = tab->body[t][r];
+    if (Br.joint >= 0 || Br.has_pos) continue;
+    float low = INFINITY;
+    for (int c = 0; c < ty.nc; ++c) {
+      const ContactT& C = tab->contact[t][c];
+      if (tab->body[t][C.body].root != r) continue;
+      low = fminf(low, (p[C.body] + mul(R[C.body], ld3(C.l))).z - C.rho);
+    }
+    if (low < INFINITY) {
+      for (int b = 0; b < ty.nb; ++b)
+        if (tab->body[t][b].root == r) p[b].z += ty.clearance - low;
+    }
+  }
+  if (root_off) {
+    const BodyT& B0 = tab->body[t][0];
+    if (B0.joint < 0 && (B0.free_p[0] != 0.f || B0.free_p[1] != 0.f || B0.free_p[2] != 0.f)) {
+      v3 off = V(root_off[e], root_off[(size_t)E + e], root_off[(size_t)2 * E + e]);
+      for (int b = 0; b < ty.nb; ++b)
+        if (tab->body[t][b].root == 0) p[b] = p[b] + off;
+    }
+  }
+  for (int b = 0; b < Bm; ++b) {
+    if (b < ty.nb) {
+      Body s;
+      s.p = p[b];
+      s.q = mat_to_quat(R[b]);
+      s.v = s.w = V(0.f, 0.f, 0.f);
+      store_body(out, 0, s, b, e, Bm, E);
+    } else {
+      zero_body(out, b, e, Bm, E);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ plain path
+// One launch per phase per substep, one thread per (item, environment of
+// the type); environment index fastest. Per-joint and per-contact results
+// go to fixed slots and are gathered by the integrators in a fixed order.
+
+// Kinematic phase; on the first substep it reads `in` (and zeroes the padded
+// body slots of `out`), afterwards it updates `out` in place.
+__global__ void k_plain_kinematic(const Tables* __restrict__ tab, int t, const int32_t* __restrict__ envs, int n,
+                                  int E, int Bm, Fields in, Fields out, int zero_pad, float* __restrict__ tape) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = idx / n, k = idx - b * n;
+  if (b >= Bm) return;
+  const int e = envs[k];
+  const TypeT& ty = tab->type[t];
+  if (b >= ty.nb) {
+    if (zero_pad) zero_body(out, b, e, Bm, E);
+    return;
+  }
+  Body s = load_body(in, b, e, Bm, E);
+  if (tape) tape_state(tape, s, b, e, Bm, E);
+  kinematic(tab->body[t][b], s, ty.h);
+  store_body(out, 0, s, b, e, Bm, E);
+}
+
+// Joint and actuator phase: slot j holds (fc, tc, fp, tp) = 12 floats.
+template <int MAXDOF>
+__global__ void k_plain_joint(const Tables* __restrict__ tab, int t, const int32_t* __restrict__ envs, int n,
+                              int E, int Bm, Fields st, const float* __restrict__ act, float* __restrict__ jslot) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = idx / n, k = idx - j * n;
+  const TypeT& ty = tab->type[t];
+  if (j >= ty.nj) return;
+  const int e = envs[k];
+  const JointT& J = tab->joint[t][j];
+  Body P = load_body(st, J.parent, e, Bm, E);
+  Body C = load_body(st, J.child, e, Bm, E);
+  m3 RP = quat_to_mat(P.q), RC = quat_to_mat(C.q);
+  float a[3];
+  for (int x = 0; x < 3; ++x) a[x] = act_of(act, J.act[x], e, E);
+  JointOut o = joint_eval<MAXDOF>(J, P, RP, C, RC, a);
+  const int NJ = ty.nj;
+  float vals[12] = {o.fc.x, o.fc.y, o.fc.z, o.tc.x, o.tc.y, o.tc.z, o.fp.x, o.fp.y, o.fp.z, o.tp.x, o.tp.y, o.tp.z};
+  for (int x = 0; x < 12; ++x) jslot[((size_t)x * NJ + j) * n + k] = vals[x];
+}
+
+// Collider phase: slot c holds (dv, dw, applied) = 7 floats.
+__global__ void k_plain_contact(const Tables* __restrict__ tab, int t, const int32_t* __restrict__ envs, int n,
+                                int E, int Bm, Fields st, float* __restrict__ cslot) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = idx / n, k = idx - c * n;
+  const TypeT& ty = tab->type[t];
+  if (c >= ty.nc) return;
+  const int e = envs[k];
+  const ContactT& C = tab->contact[t][c];
+  const BodyT& B = tab->body[t][C.body];
+  Body s = load_body(st, C.body, e, Bm, E);
+  Frame f = derive(B, s);
+  v3 dv = V(0.f, 0.f, 0.f), dw = V(0.f, 0.f, 0.f);
+  bool on = contact_eval(C, ty, B, s, f, dv, dw);
+  const int NC = ty.nc;
+  float vals[7] = {dv.x, dv.y, dv.z, dw.x, dw.y, dw.z, on ? 1.f : 0.f};
+  for (int x = 0; x < 7; ++x) cslot[((size_t)x * NC + c) * n + k] = vals[x];
+}
+
+// Potential integrator: gathers the body's own joint (as child) then its
+// children's joints (as parent), in that order.
+__global__ void k_plain_potential(const Tables* __restrict__ tab, int t, const int32_t* __restrict__ envs, int n,
+                                  int E, int Bm, Fields st, const float* __restrict__ jslot, float* __restrict__ tape) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = idx / n, k = idx - b * n;
+  const TypeT& ty = tab->type[t];
+  if (b >= ty.nb) return;
+  const int e = envs[k];
+  const BodyT& B = tab->body[t][b];
+  const int NJ = ty.nj;
+  auto slot = [&](int x, int j) { return jslot[((size_t)x * NJ + j) * n + k]; };
+  v3 f = V(0.f, 0.f, 0.f), tq = V(0.f, 0.f, 0.f);
+  if (B.joint >= 0) {
+    f = V(slot(0, B.joint), slot(1, B.joint), slot(2, B.joint));
+    tq = V(slot(3, B.joint), slot(4, B.joint), slot(5, B.joint));
+  }
+  for (int i = 0; i < B.nch; ++i) {
+    const int j = tab->body[t][B.ch[i]].joint;
+    f += V(slot(6, j), slot(7, j), slot(8, j));
+    tq += V(slot(9, j), slot(10, j), slot(11, j));
+  }
+  Body s = load_body(st, b, e, Bm, E);
+  Frame fr = derive(B, s);
+  if (tape) tape_torque(tape, tq, b, e, Bm, E);
+  potential(B, ty, s, fr, f, tq);
+  store_body(st, 0, s, b, e, Bm, E);
+}
+
+// Collision integrator: averages the body's applied contact impulses.
+__global__ void k_plain_collision(const Tables* __restrict__ tab, int t, const int32_t* __restrict__ envs, int n,
+                                  int E, int Bm, Fields st, const float* __restrict__ cslot, uint8_t* nonfinite,
+                                  int last, float* __restrict__ tape) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = idx / n, k = idx - b * n;
+  const TypeT& ty = tab->type[t];
+  if (b >= ty.nb) return;
+  const int e = envs[k];
+  const BodyT& B = tab->body[t][b];
+  const int NC = ty.nc;
+  auto slot = [&](int x, int c) { return cslot[((size_t)x * NC + c) * n + k]; };
+  v3 dv = V(0.f, 0.f, 0.f), dw = V(0.f, 0.f, 0.f);
+  int cnt = 0;
+  for (int c = B.c0; c < B.c1; ++c) {
+    if (slot(6, c) != 0.f) {
+      dv += V(slot(0, c), slot(1, c), slot(2, c));
+      dw += V(slot(3, c), slot(4, c), slot(5, c));
+      ++cnt;
+    }
+  }
+  Body s = load_body(st, b, e, Bm, E);
+  if (tape) tape_count(tape, cnt, b, e, Bm, E);
+  collision(B, s, dv, dw, cnt);
+  store_body(st, 0, s, b, e, Bm, E);
+  if (last && nonfinite && !finite_body(s)) nonfinite[e] = 1;
+}
+
+// ------------------------------------------------------------------ fused path
+// One lane per body, floor(64 / nb) environments per wavefront; the lane of
+// body b also evaluates the joint whose child is b (with its actuators) and
+// b's own contact candidates. Neighbour data moves by cross-lane permutes
+// (ds_bpermute): the child lane fetches its parent's state; the parent lane
+// fetches each child's reaction (fp, tp) in child order. State stays in
+// registers across all substeps and steps; only actions are read per step.
+__device__ __forceinline__ float shfl(float v, int src) { return __shfl(v, src, 64); }
+
+template <int MAXDOF>
+__device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const WaveWork& wk,
+                                          const int32_t* __restrict__ env_list, const int32_t* __restrict__ type_off,
+                                          int E, int Bm, const Fields& in, const Fields& out,
+                                          const float* __restrict__ acts, int Am, int T, int save_every,
+                                          const Fields& traj, uint8_t* nonfinite, float* __restrict__ tape) {
+  const int t = wk.type;
+  const TypeT& ty = tab->type[t];
+  const int nb = ty.nb;
+  const int lane = threadIdx.x & 63;
+  const int slot = lane / nb;
+  const int b = lane - slot * nb;
+  const int base = slot * nb;
+  const bool live = slot < wk.count;
+  const int e = env_list[type_off[t] + wk.k0 + (live ? slot : 0)];
+  const BodyT& B = tab->body[t][b];
+  const bool has_joint = B.joint >= 0;
+  const JointT& J = tab->joint[t][has_joint ? B.joint : 0];
+  const int src_parent = base + (has_joint ? J.parent : b);
+  const float h = ty.h;
+
+  Body s = load_body(in, b, e, Bm, E);
+  int n_save = 0;
+  for (int step = 0; step < T; ++step) {
+    // actions of this step: acts[step][Am][E], held over the substeps
+    float a[3] = {0.f, 0.f, 0.f};
+    if (has_joint)
+      for (int x = 0; x < MAXDOF; ++x) a[x] = act_of(acts + (size_t)step * Am * E, J.act[x], e, E);
+    for (int sub = 0; sub < ty.substeps; ++sub) {
+      float* tp = tape ? tape + (size_t)sub * TAPE_N * Bm * E : nullptr;
+      if (tp && live) tape_state(tp, s, b, e, Bm, E);
+      kinematic(B, s, h);
+      Frame f = derive(B, s);
+      // parent's post-kinematic state
+      Body P;
+      P.p = V(shfl(s.p.x, src_parent), shfl(s.p.y, src_parent), shfl(s.p.z, src_parent));
+      P.q = q4{shfl(s.q.w, src_parent), shfl(s.q.x, src_parent), shfl(s.q.y, src_parent), shfl(s.q.z, src_parent)};
+      P.v = V(shfl(s.v.x, src_parent), shfl(s.v.y, src_parent), shfl(s.v.z, src_parent));
+      P.w = V(shfl(s.w.x, src_parent), shfl(s.w.y, src_parent), shfl(s.w.z, src_parent));
+      JointOut jo;
+      jo.fc = jo.tc = jo.fp = jo.tp = V(0.f, 0.f, 0.f);
+      if (has_joint) jo = joint_eval<MAXDOF>(J, P, quat_to_mat(P.q), s, f.R, a);
+      v3 force = jo.fc, torque = jo.tc;
+      // children's reactions, in child order
+      for (int i = 0; i < ty.max_children; ++i) {
+        const int src = base + (i < B.nch ? B.ch[i] : b);
+        v3 fp = V(shfl(jo.fp.x, src), shfl(jo.fp.y, src), shfl(jo.fp.z, src));
+        v3 tp = V(shfl(jo.tp.x, src), shfl(jo.tp.y, src), shfl(jo.tp.z, src));
+        if (i < B.nch) {
+          force += fp;
+          torque += tp;
+        }
+      }
+      v3 dv = V(0.f, 0.f, 0.f), dw = V(0.f, 0.f, 0.f);
+      int cnt = 0;
+      for (int c = B.c0; c < B.c1; ++c) cnt += contact_eval(tab->contact[t][c], ty, B, s, f, dv, dw) ? 1 : 0;
+      if (tp && live) {
+        tape_torque(tp, torque, b, e, Bm, E);
+        tape_count(tp, cnt, b, e, Bm, E);
+      }
+      potential(B, ty, s, f, force, torque);
+      collision(B, s, dv, dw, cnt);
+    }
+    if (save_every > 0 && (step + 1) % save_every == 0) {
+      if (live) store_snapshot(traj, (size_t)n_save, s, b, e, Bm, E);
+      ++n_save;
+    }
+  }
+  if (live) {
+    store_body(out, 0, s, b, e, Bm, E);
+    // padded body slots of a smaller system are written as zeros
+    for (int pb = nb + b; pb < Bm; pb += nb) zero_body(out, pb, e, Bm, E);
+  }
+  if (nonfinite) {
+    const unsigned long long bad = __ballot(live && !finite_body(s));
+    const unsigned long long group = (nb >= 64) ? ~0ull : ((1ull << nb) - 1ull);
+    if (live && b == 0) nonfinite[e] = ((bad >> base) & group) ? 1 : 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fused(const Tables* __restrict__ tab, const WaveWork* __restrict__ work,
+                                               int n_work, const int32_t* __restrict__ env_list,
+                                               const int32_t* __restrict__ type_off, int E, int Bm, Fields in,
+                                               Fields out, const float* __restrict__ acts, int Am, int T,
+                                               int save_every, Fields traj, uint8_t* nonfinite,
+                                               float* __restrict__ tape) {
+  const int w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (w >= n_work) return;
+  const WaveWork wk = work[w];
+  // wave-uniform: joints of at most one axis take the shorter path
+  if (tab->type[wk.type].max_dof <= 1)
+    fused_run<1>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite, tape);
+  else
+    fused_run<3>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite, tape);
+}
+
+// ------------------------------------------------------------------ small helpers
+__global__ void k_copy_state(int n3, int n4, Fields in, Fields out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n3) {
+    out.pos[i] = in.pos[i];
+    out.vel[i] = in.vel[i];
+    out.ang[i] = in.ang[i];
+  }
+  if (i < n4) out.rot[i] = in.rot[i];
+}
+
+__global__ void k_fill_u8(uint8_t* p, int n, uint8_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ------------------------------------------------------------------ launchers
+static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+hipError_t launch_default_qp(const LaunchCtx& c, const float* angles, const float* root_off, Fields out,
+                             hipStream_t s) {
+  if (c.E == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_default_qp, dim3(cdiv(c.E, 64)), dim3(64), 0, s, c.tab, c.env_type, c.E, c.Bm, angles,
+                     root_off, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused(const LaunchCtx& c, const WaveWork* work, int n_work, int waves_per_block, Fields in,
+                        Fields out, const float* acts, int T, int save_every, Fields traj, bool flags,
+                        hipStream_t s, float* tape) {
+  if (n_work == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fused, dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block), 0, s, c.tab, work,
+                     n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj,
+                     flags ? c.nonfinite : nullptr, tape);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_state(const LaunchCtx& c, Fields in, Fields out, hipStream_t s) {
+  const int n3 = 3 * c.Bm * c.E, n4 = 4 * c.Bm * c.E;
+  if (n4 == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_state, dim3(cdiv(n4, 256)), dim3(256), 0, s, n3, n4, in, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(uint8_t* p, int n, uint8_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u8, dim3(cdiv(n, 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+// One plain step: for every type, `substeps` x (kinematic, joint+actuator,
+// contact, potential, collision) launches. `in` is read by the first
+// kinematic launch only; everything after works in place on `out`.
+hipError_t launch_plain_step(const LaunchCtx& c, Fields in, Fields out, const float* act, float* const* jslot,
+                             float* const* cslot, bool flags, hipStream_t s, float* tape) {
+  const int TB = 256;
+  for (int t = 0; t < c.n_types; ++t) {
+    const int n = c.type_cnt_h[t];
+    if (n == 0) continue;
+    const TypeT& ty = c.host_tab->type[t];
+    const int32_t* envs = c.env_list + c.type_off_h[t];
+    for (int sub = 0; sub < ty.substeps; ++sub) {
+      const bool first = sub == 0;
+      float* tp = tape ? tape + (size_t)sub * TAPE_N * c.Bm * c.E : nullptr;
+      hipLaunchKernelGGL(k_plain_kinematic, dim3(cdiv((long)c.Bm * n, TB)), dim3(TB), 0, s, c.tab, t, envs, n, c.E,
+                         c.Bm, first ? in : out, out, first ? 1 : 0, tp);
+      if (ty.nj > 0) {
+        if (ty.max_dof <= 1)
+          hipLaunchKernelGGL(k_plain_joint<1>, dim3(cdiv((long)ty.nj * n, TB)), dim3(TB), 0, s, c.tab, t, envs, n,
+                             c.E, c.Bm, out, act, jslot[t]);
+        else
+          hipLaunchKernelGGL(k_plain_joint<3>, dim3(cdiv((long)ty.nj * n, TB)), dim3(TB), 0, s, c.tab, t, envs, n,
+                             c.E, c.Bm, out, act, jslot[t]);
+      }
+      if (ty.nc > 0)
+        hipLaunchKernelGGL(k_plain_contact, dim3(cdiv((long)ty.nc * n, TB)), dim3(TB), 0, s, c.tab, t, envs, n, c.E,
+                           c.Bm, out, cslot[t]);
+      hipLaunchKernelGGL(k_plain_potential, dim3(cdiv((long)ty.nb * n, TB)), dim3(TB), 0, s, c.tab, t, envs, n, c.E,
+                         c.Bm, out, jslot[t], tp);
+      hipLaunchKernelGGL(k_plain_collision, dim3(cdiv((long)ty.nb * n, TB)), dim3(TB), 0, s, c.tab, t, envs, n, c.E,
+                         c.Bm, out, cslot[t], flags ? c.nonfinite : nullptr, sub == ty.substeps - 1 ? 1 : 0, tp);
+      hipError_t err = hipGetLastError();
+      if (err != hipSuccess) return err;
+    }
+  }
+  return hipSuccess;
+}
+
+}  // namespace bx

@@ -1,0 +1,294 @@
+// Per-item physics of one substep in FP32 (device code; also compiles for the
+// host). Each function is one item of Algorithm 1 (Section 3): a body's
+// kinematic update, a joint's spring update with its actuators, one
+// ground-contact candidate, a body's potential and collision updates.
+//
+// Frames: world z up, ground plane z = 0. Quaternions (w, x, y, z), Hamilton
+// product, body to world. Velocities and angular velocities in the world frame.
+#pragma once
+#include <math.h>
+
+#include "bx_tables.h"
+
+#define BXF __host__ __device__ __forceinline__
+
+namespace bx {
+
+struct v3 {
+  float x, y, z;
+};
+struct q4 {
+  float w, x, y, z;
+};
+struct m3 {
+  float m[9];  // row-major
+};
+// symmetric 3x3: xx, yy, zz, xy, xz, yz
+struct s3 {
+  float xx, yy, zz, xy, xz, yz;
+};
+
+BXF v3 V(float x, float y, float z) { return v3{x, y, z}; }
+BXF v3 operator+(v3 a, v3 b) { return v3{a.x + b.x, a.y + b.y, a.z + b.z}; }
+BXF v3 operator-(v3 a, v3 b) { return v3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+BXF v3 operator-(v3 a) { return v3{-a.x, -a.y, -a.z}; }
+BXF v3 operator*(float s, v3 a) { return v3{s * a.x, s * a.y, s * a.z}; }
+BXF v3& operator+=(v3& a, v3 b) { a = a + b; return a; }
+BXF float dot(v3 a, v3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+BXF v3 cross(v3 a, v3 b) { return v3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+BXF v3 ld3(const float* p) { return v3{p[0], p[1], p[2]}; }
+
+BXF v3 mul(const m3& A, v3 v) {
+  return v3{A.m[0] * v.x + A.m[1] * v.y + A.m[2] * v.z, A.m[3] * v.x + A.m[4] * v.y + A.m[5] * v.z,
+            A.m[6] * v.x + A.m[7] * v.y + A.m[8] * v.z};
+}
+BXF v3 mul(const s3& S, v3 v) {
+  return v3{S.xx * v.x + S.xy * v.y + S.xz * v.z, S.xy * v.x + S.yy * v.y + S.yz * v.z,
+            S.xz * v.x + S.yz * v.y + S.zz * v.z};
+}
+BXF m3 mul(const m3& A, const float* B) {  // A * B, B row-major constant
+  m3 C;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) C.m[3 * i + j] = A.m[3 * i] * B[j] + A.m[3 * i + 1] * B[3 + j] + A.m[3 * i + 2] * B[6 + j];
+  return C;
+}
+BXF v3 col(const m3& A, int j) { return v3{A.m[j], A.m[3 + j], A.m[6 + j]}; }
+
+BXF q4 qmul(q4 a, q4 b) {
+  return q4{a.w * b.w - a.x * b.x - a.y * b.y - a.z * b.z, a.w * b.x + a.x * b.w + a.y * b.z - a.z * b.y,
+            a.w * b.y - a.x * b.z + a.y * b.w + a.z * b.x, a.w * b.z + a.x * b.y - a.y * b.x + a.z * b.w};
+}
+
+// Rotation matrix of a unit quaternion (body to world).
+BXF m3 quat_to_mat(q4 q) {
+  float xx = q.x * q.x, yy = q.y * q.y, zz = q.z * q.z;
+  float xy = q.x * q.y, xz = q.x * q.z, yz = q.y * q.z;
+  float wx = q.w * q.x, wy = q.w * q.y, wz = q.w * q.z;
+  m3 R;
+  R.m[0] = 1.f - 2.f * (yy + zz); R.m[1] = 2.f * (xy - wz);       R.m[2] = 2.f * (xz + wy);
+  R.m[3] = 2.f * (xy + wz);       R.m[4] = 1.f - 2.f * (xx + zz); R.m[5] = 2.f * (yz - wx);
+  R.m[6] = 2.f * (xz - wy);       R.m[7] = 2.f * (yz + wx);       R.m[8] = 1.f - 2.f * (xx + yy);
+  return R;
+}
+
+// R diag(d) R^T
+BXF s3 rot_diag(const m3& R, const float* d) {
+  float a0 = R.m[0] * d[0], a1 = R.m[1] * d[1], a2 = R.m[2] * d[2];
+  float b0 = R.m[3] * d[0], b1 = R.m[4] * d[1], b2 = R.m[5] * d[2];
+  float c0 = R.m[6] * d[0], c1 = R.m[7] * d[1], c2 = R.m[8] * d[2];
+  s3 S;
+  S.xx = a0 * R.m[0] + a1 * R.m[1] + a2 * R.m[2];
+  S.yy = b0 * R.m[3] + b1 * R.m[4] + b2 * R.m[5];
+  S.zz = c0 * R.m[6] + c1 * R.m[7] + c2 * R.m[8];
+  S.xy = a0 * R.m[3] + a1 * R.m[4] + a2 * R.m[5];
+  S.xz = a0 * R.m[6] + a1 * R.m[7] + a2 * R.m[8];
+  S.yz = b0 * R.m[6] + b1 * R.m[7] + b2 * R.m[8];
+  return S;
+}
+
+// Frozen axes: select (not multiply), so NaN/Inf in a frozen component do
+// not leak and a frozen component is exactly zero.
+BXF v3 keep(v3 a, const float* f) {
+  return v3{f[0] != 0.f ? a.x : 0.f, f[1] != 0.f ? a.y : 0.f, f[2] != 0.f ? a.z : 0.f};
+}
+BXF float clampf(float x, float lo, float hi) { return x < lo ? lo : (x > hi ? hi : x); }
+
+struct Body {
+  v3 p;
+  q4 q;
+  v3 v, w;
+};
+
+// Derived per-body quantities of one substep.
+struct Frame {
+  m3 R;       // orientation
+  s3 Iw;      // world inertia R diag(I) R^T
+  s3 Iwinv;   // its inverse R diag(1/I) R^T
+};
+
+// Kinematic integrator (Algorithm 1, first line): frozen axes hold zero
+// velocity; p += h v; q <- normalize(q + h/2 (0, w) (x) q).
+BXF void kinematic(const BodyT& B, Body& s, float h) {
+  s.v = keep(s.v, B.free_p);
+  s.w = keep(s.w, B.free_r);
+  s.p = s.p + h * s.v;
+  q4 dq = qmul(q4{0.f, s.w.x, s.w.y, s.w.z}, s.q);
+  float hh = 0.5f * h;
+  q4 q{s.q.w + hh * dq.w, s.q.x + hh * dq.x, s.q.y + hh * dq.y, s.q.z + hh * dq.z};
+  float inv = 1.f / sqrtf(q.w * q.w + q.x * q.x + q.y * q.y + q.z * q.z);
+  s.q = q4{q.w * inv, q.x * inv, q.y * inv, q.z * inv};
+}
+
+BXF Frame derive(const BodyT& B, const Body& s) {
+  Frame f;
+  f.R = quat_to_mat(s.q);
+  f.Iw = rot_diag(f.R, B.I);
+  f.Iwinv = rot_diag(f.R, B.Iinv);
+  return f;
+}
+
+// Joint geometry shared by a joint's spring update and its actuators: the
+// anchors relative to each centre of mass, the joint-frame axes in world
+// coordinates, and the intrinsic X-Y-Z Euler angles of the child's joint frame
+// relative to the parent's (M = AwP^T AwC = Rx Ry Rz) with their axes
+// (parent x, intermediate y, child z).
+struct JointGeo {
+  v3 rP, rC;
+  v3 e1P, e2P, e3P, e1C, e2C, e3C;
+  float m12, m22, m01, m00, m02;
+  float c1, s1;
+  float th[3];
+  v3 ax[3];
+};
+
+template <int MAXDOF>
+BXF JointGeo joint_geo(const JointT& J, const m3& RP, const m3& RC) {
+  JointGeo g;
+  g.rP = mul(RP, ld3(J.ap));
+  g.rC = mul(RC, ld3(J.ac));
+  m3 AwP = mul(RP, J.FP);
+  m3 AwC = mul(RC, J.FC);
+  g.e1P = col(AwP, 0);
+  g.e2P = col(AwP, 1);
+  g.e3P = col(AwP, 2);
+  g.e1C = col(AwC, 0);
+  g.e3C = col(AwC, 2);
+  g.m12 = dot(g.e2P, g.e3C);
+  g.m22 = dot(g.e3P, g.e3C);
+  g.th[0] = atan2f(-g.m12, g.m22);
+  float r = sqrtf(g.m12 * g.m12 + g.m22 * g.m22);
+  g.c1 = 1.f;
+  g.s1 = 0.f;
+  if (r > 0.f) {
+    g.c1 = g.m22 / r;
+    g.s1 = -g.m12 / r;
+  }
+  g.ax[0] = g.e1P;
+  g.ax[1] = g.c1 * g.e2P + g.s1 * g.e3P;
+  g.ax[2] = g.e3C;
+  if (MAXDOF > 1) {
+    g.e2C = col(AwC, 1);
+    g.m01 = dot(g.e1P, g.e2C);
+    g.m00 = dot(g.e1P, g.e1C);
+    g.m02 = dot(g.e1P, g.e3C);
+    g.th[1] = asinf(clampf(g.m02, -1.f, 1.f));
+    g.th[2] = atan2f(-g.m01, g.m00);
+  }
+  return g;
+}
+
+// Spring joint (Section 6.1) from the parent's and the child's
+// post-kinematic state. Force/torque on the child (fc, tc) and on the parent
+// (fp, tp):
+//   anchor spring-damper  F = k_lin (xP - xC) + c_lin (uP - uC), at each anchor;
+//   alignment spring      1 DOF: k_ang e1C x e1P; 2 DOF: -k_ang (e1P.e2C) e2C x e1P;
+//   angular damper        c_ang (wP - wC);
+//   limit springs         -k_lim (th_k - clamp(th_k)) about Euler axis k < dof.
+struct JointOut {
+  v3 fc, tc, fp, tp;
+};
+
+template <int MAXDOF>
+BXF v3 joint_spring(const JointT& J, const Body& P, const Body& C, const JointGeo& g, v3& F) {
+  v3 d = (P.p - C.p) + (g.rP - g.rC);
+  v3 uP = P.v + cross(P.w, g.rP);
+  v3 uC = C.v + cross(C.w, g.rC);
+  F = J.k_lin * d + J.c_lin * (uP - uC);
+  v3 tau;
+  if (MAXDOF == 1 || J.dof == 1)
+    tau = J.k_ang * cross(g.e1C, g.e1P);
+  else if (J.dof == 2)
+    tau = (-J.k_ang * g.m01) * cross(g.e2C, g.e1P);
+  else
+    tau = V(0.f, 0.f, 0.f);
+  tau += J.c_ang * (P.w - C.w);
+  for (int k = 0; k < MAXDOF; ++k)
+    if (k < J.dof) tau += (-J.k_lim * (g.th[k] - clampf(g.th[k], J.lo[k], J.hi[k]))) * g.ax[k];
+  return tau;
+}
+
+// Actuators of a joint (Algorithm 1, actuator loop): torque gear_k a_k about
+// Euler axis k, on the child (and its opposite on the parent).
+template <int MAXDOF>
+BXF v3 joint_actuator(const JointT& J, const JointGeo& g, const float* a) {
+  v3 tau = V(0.f, 0.f, 0.f);
+  for (int k = 0; k < MAXDOF; ++k)
+    if (k < J.dof) tau += (J.gear[k] * a[k]) * g.ax[k];
+  return tau;
+}
+
+// Spring and actuators together (the fused path).
+template <int MAXDOF>
+BXF JointOut joint_eval(const JointT& J, const Body& P, const m3& RP, const Body& C, const m3& RC,
+                        const float* a /* clipped actions per axis, 0 if none */) {
+  JointGeo g = joint_geo<MAXDOF>(J, RP, RC);
+  v3 F;
+  v3 tau = joint_spring<MAXDOF>(J, P, C, g, F) + joint_actuator<MAXDOF>(J, g, a);
+  JointOut o;
+  o.fc = F;
+  o.tc = cross(g.rC, F) + tau;
+  o.fp = -F;
+  o.tp = -(cross(g.rP, F) + tau);
+  return o;
+}
+
+// One ground-contact candidate (Section 6.2): velocity-level normal impulse
+// with restitution and Baumgarte term, jn = max(0, -(1+e) vn + beta depth / h)
+// / kn, and a Coulomb friction impulse from the same pre-impulse state,
+// jt = min(mu jn, s / kt). Adds the velocity changes to dv, dw and returns
+// whether an impulse was applied.
+BXF bool contact_eval(const ContactT& c, const TypeT& ty, const BodyT& B, const Body& s, const Frame& f, v3& dv,
+                      v3& dw) {
+  v3 rl = mul(f.R, ld3(c.l));
+  float depth = c.rho - (s.p.z + rl.z);
+  if (!(depth > 0.f)) return false;
+  v3 r = V(rl.x, rl.y, rl.z - c.rho);  // lowest point relative to the centre of mass
+  v3 u = s.v + cross(s.w, r);
+  v3 a = mul(f.Iwinv, V(r.y, -r.x, 0.f));       // Iwinv (r x z)
+  float kn = B.inv_m + (a.x * r.y - a.y * r.x);  // z . ((Iwinv (r x z)) x r)
+  float num = ty.beta_h * depth - ty.one_plus_e * u.z;
+  if (!(num > 0.f)) return false;
+  float jn = num / kn;
+  v3 J = V(0.f, 0.f, jn);
+  float sp = sqrtf(u.x * u.x + u.y * u.y);
+  if (sp > 0.f) {
+    float isp = 1.f / sp;
+    v3 t = V(u.x * isp, u.y * isp, 0.f);
+    v3 b = mul(f.Iwinv, cross(r, t));
+    float kt = B.inv_m + dot(t, cross(b, r));
+    float stop = sp / kt;
+    float cap = ty.mu * jn;
+    float jt = cap <= stop ? cap : stop;
+    J.x = -jt * t.x;
+    J.y = -jt * t.y;
+  }
+  dv += B.inv_m * J;
+  dw += mul(f.Iwinv, cross(r, J));
+  return true;
+}
+
+// Potential integrator: v += h (g + f/m); w += h Iwinv (t - w x (Iw w)).
+BXF void potential(const BodyT& B, const TypeT& ty, Body& s, const Frame& f, v3 force, v3 torque) {
+  v3 acc = ld3(ty.g) + B.inv_m * force;
+  s.v += keep(ty.h * acc, B.free_p);
+  v3 gyro = cross(s.w, mul(f.Iw, s.w));
+  v3 alpha = mul(f.Iwinv, torque - gyro);
+  s.w += keep(ty.h * alpha, B.free_r);
+}
+
+// Collision integrator: the body's contact impulses averaged over the n
+// candidates that applied one.
+BXF void collision(const BodyT& B, Body& s, v3 dv, v3 dw, int n) {
+  if (n > 0) {
+    float inv = 1.f / (float)n;
+    s.v += keep(inv * dv, B.free_p);
+    s.w += keep(inv * dw, B.free_r);
+  }
+}
+
+BXF bool finite_body(const Body& s) {
+  float acc = s.p.x + s.p.y + s.p.z + s.q.w + s.q.x + s.q.y + s.q.z + s.v.x + s.v.y + s.v.z + s.w.x + s.w.y + s.w.z;
+  return isfinite(acc) && !isnan(acc);
+}
+
+}  // namespace bx

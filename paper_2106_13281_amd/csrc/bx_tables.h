@@ -1,0 +1,78 @@
+// Per-system constant tables, packed on the host and read by the kernels.
+//
+// One table set per system type of a batch; a type is one system
+// description (bodies, joints, actuators, colliders of Appendix A plus the
+// engine constants). Everything here is immutable during stepping.
+#pragma once
+#include <cstdint>
+
+namespace bx {
+
+constexpr int MAXT = 8;    // system types per batch
+constexpr int MAXB = 16;   // bodies per system
+constexpr int MAXJ = 16;   // joints per system
+constexpr int MAXC = 96;   // ground-contact candidates per system
+constexpr int MAXA = 48;   // actions per system
+constexpr int MAXCH = 8;   // children per body
+
+struct TypeT {
+  int32_t nb, nj, nc, na, ndof, substeps;
+  int32_t max_dof;         // largest joint DOF (1..3; 0 without joints)
+  int32_t max_children;    // largest child count of a body
+  int32_t max_contacts;    // largest contact-candidate count of a body
+  int32_t pad0;
+  float dt, h;             // step and substep length (s)
+  float beta_h;            // Baumgarte factor over h (1/s)
+  float one_plus_e;        // 1 + restitution
+  float mu;                // Coulomb friction
+  float clearance;         // reset height of the lowest contact point (m)
+  float g[3];              // gravity (m/s^2)
+  float pad1;
+};
+
+struct BodyT {
+  float m, inv_m;
+  float I[3], Iinv[3];     // principal moments, body frame
+  float free_p[3], free_r[3];  // 1 = world axis integrates, 0 = frozen
+  int32_t joint;           // joint whose child this body is; -1 for a root
+  int32_t parent;          // parent body; -1 for a root
+  int32_t c0, c1;          // contact candidates [c0, c1) belong to this body
+  int32_t nch;             // number of child bodies
+  int32_t ch[MAXCH];       // child bodies (ascending joint order)
+  int32_t root;            // root body of this body's tree
+  int32_t has_pos;         // root with a given reset position
+  float pos0[3];           // that position
+};
+
+struct JointT {
+  int32_t parent, child, dof, dof0;  // dof0: first DOF index of this joint
+  float ap[3], ac[3];      // anchor in parent / child body frame
+  float FP[9], FC[9];      // joint frame (row-major rotation) in parent / child body frame
+  float k_lin, c_lin, k_ang, c_ang, k_lim;
+  float lo[3], hi[3];      // angle limits (rad)
+  float gear[3];           // actuator strength per axis (0 = not actuated)
+  int32_t act[3];          // action index per axis (-1 = not actuated)
+  float def_angle[3];      // reset angle per axis
+};
+
+struct ContactT {
+  int32_t body;
+  float l[3];              // centre in the body frame
+  float rho;               // radius (0 for box corners)
+};
+
+struct Tables {
+  TypeT type[MAXT];
+  BodyT body[MAXT][MAXB];
+  JointT joint[MAXT][MAXJ];
+  ContactT contact[MAXT][MAXC];
+  int32_t topo[MAXT][MAXB];  // bodies, every parent before its children
+};
+
+// One wavefront's share of the fused launch: `count` environments of one
+// type, taken from that type's environment list starting at `k0`.
+struct WaveWork {
+  int32_t type, k0, count, pad;
+};
+
+}  // namespace bx

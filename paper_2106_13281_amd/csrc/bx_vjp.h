@@ -1,0 +1,31 @@
+// Adjoint (vector-Jacobian product) of one step: workspace and launcher.
+#pragma once
+#include "bx_internal.h"
+
+namespace bx {
+
+// Device workspace of the adjoint: forward tape, per-body partial
+// cotangents and per-joint/contact slots. Grown on demand, owned by the sys.
+struct VjpWork {
+  size_t bytes = 0;
+  float* buf = nullptr;
+};
+
+// What the forward recompute needs from the sys: the fused schedule and the
+// plain path's per-type slots.
+struct VjpSched {
+  const WaveWork* work;
+  int n_work;
+  int waves_per_block;
+  float* const* jslot;
+  float* const* cslot;
+};
+
+// 0 or BRAX_E_NOMEM.
+int vjp_reserve(VjpWork& w, const Tables& tab, int n_types, const int* type_cnt, int E, int Bm);
+void vjp_free(VjpWork& w);
+// g_in <- d(step)/d(in)^T g_out, g_act <- d(step)/d(act)^T g_out (both overwritten).
+hipError_t launch_vjp(const LaunchCtx& c, VjpWork& w, const VjpSched& sched, Fields in, const float* act,
+                      Fields g_out, Fields g_in, float* g_act, bool plain, hipStream_t s);
+
+}  // namespace bx

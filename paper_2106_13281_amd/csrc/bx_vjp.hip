@@ -1,0 +1,327 @@
+// Adjoint of one step on the GPU (vector-Jacobian product of brax_step).
+//
+// 1. Forward recompute of the step's substeps, writing a tape per substep:
+//    each body's state before the kinematic update, the total torque it
+//    received and its count of applied contacts.
+// 2. Reverse over the substeps, one launch per phase (Algorithm 1 reversed):
+//      integrate  collision + potential integrators -> cotangents of the
+//                 body's post-kinematic state, of its force/torque sums and
+//                 of its contact sums
+//      joint      spring joints           -> parent/child state cotangents
+//      actuator   torque actuators        -> rotation cotangents, action cotangents
+//      contact    ground contacts         -> body state cotangents
+//      kinematic  gathers all of the above in a fixed order, then the
+//                 kinematic integrator's adjoint -> cotangent of the
+//                 substep's input state
+//    Per-joint/contact results go to fixed slots; the gather order is fixed,
+//    so the result is deterministic.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "bx_access.h"
+#include "bx_adj.h"
+#include "bx_vjp.h"
+
+namespace bx {
+
+namespace {
+
+constexpr int TB = 256;
+inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+__device__ __forceinline__ Bar load_bar(const Fields& f, int b, int e, int Bm, int E) {
+  Body s = load_body(f, b, e, Bm, E);
+  Bar r;
+  r.p = s.p;
+  r.q = s.q;
+  r.v = s.v;
+  r.w = s.w;
+  return r;
+}
+__device__ __forceinline__ void store_bar(const Fields& f, const Bar& r, int b, int e, int Bm, int E) {
+  Body s;
+  s.p = r.p;
+  s.q = r.q;
+  s.v = r.v;
+  s.w = r.w;
+  store_body(f, 0, s, b, e, Bm, E);
+}
+// 13-float bar in a [13 * N][n] slot array at item i, environment slot k
+__device__ __forceinline__ void slot_store_bar(float* sl, int x0, int N, int i, int n, int k, const Bar& r) {
+  const float v[13] = {r.p.x, r.p.y, r.p.z, r.q.w, r.q.x, r.q.y, r.q.z, r.v.x, r.v.y, r.v.z, r.w.x, r.w.y, r.w.z};
+  for (int x = 0; x < 13; ++x) sl[((size_t)(x0 + x) * N + i) * n + k] = v[x];
+}
+__device__ __forceinline__ void slot_add_bar(const float* sl, int x0, int N, int i, int n, int k, Bar& r) {
+  float v[13];
+  for (int x = 0; x < 13; ++x) v[x] = sl[((size_t)(x0 + x) * N + i) * n + k];
+  Bar a;
+  a.p = V(v[0], v[1], v[2]);
+  a.q = q4{v[3], v[4], v[5], v[6]};
+  a.v = V(v[7], v[8], v[9]);
+  a.w = V(v[10], v[11], v[12]);
+  bar_add(r, a);
+}
+// per-body vectors [6][Bm][E]
+__device__ __forceinline__ void store2(float* p, v3 a, v3 b, int bb, int e, int Bm, int E) {
+  const float v[6] = {a.x, a.y, a.z, b.x, b.y, b.z};
+  for (int x = 0; x < 6; ++x) p[((size_t)x * Bm + bb) * E + e] = v[x];
+}
+__device__ __forceinline__ void load2(const float* p, v3& a, v3& b, int bb, int e, int Bm, int E) {
+  float v[6];
+  for (int x = 0; x < 6; ++x) v[x] = p[((size_t)x * Bm + bb) * E + e];
+  a = V(v[0], v[1], v[2]);
+  b = V(v[3], v[4], v[5]);
+}
+__device__ __forceinline__ Body post_kin(const Tables* tab, int t, const float* tape_s, int b, int e, int Bm, int E) {
+  Body s = tape_load_state(tape_s, b, e, Bm, E);
+  kinematic(tab->body[t][b], s, tab->type[t].h);
+  return s;
+}
+
+// g_in <- g_out on real bodies, 0 on padded body slots.
+__global__ void k_adj_init(const Tables* __restrict__ tab, int t, const int32_t* __restrict__ envs, int n, int E,
+                           int Bm, Fields g_out, Fields g_in) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = idx / n, k = idx - b * n;
+  if (b >= Bm) return;
+  const int e = envs[k];
+  if (b < tab->type[t].nb) {
+    store_body(g_in, 0, load_body(g_out, b, e, Bm, E), b, e, Bm, E);
+  } else {
+    Body z;
+    z.p = z.v = z.w = V(0.f, 0.f, 0.f);
+    z.q = q4{0.f, 0.f, 0.f, 0.f};
+    store_body(g_in, 0, z, b, e, Bm, E);
+  }
+}
+
+__global__ void k_fill_f32(float* p, size_t n, float v) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Integrate phase adjoint (collision then potential integrator).
+__global__ void k_adj_integrate(const Tables* __restrict__ tab, int t, const int32_t* __restrict__ envs, int n,
+                                int E, int Bm, const float* __restrict__ tape_s, Fields G, float* __restrict__ bpart,
+                                float* __restrict__ ftb, float* __restrict__ dvw) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = idx / n, k = idx - b * n;
+  const TypeT& ty = tab->type[t];
+  if (b >= ty.nb) return;
+  const int e = envs[k];
+  const BodyT& B = tab->body[t][b];
+  Body post = post_kin(tab, t, tape_s, b, e, Bm, E);
+  Frame f = derive(B, post);
+  Bar ob = load_bar(G, b, e, Bm, E);
+  v3 fb, tb, dvb, dwb;
+  Bar part = integrate_adj(B, ty, post, f, tape_load_torque(tape_s, b, e, Bm, E), tape_load_count(tape_s, b, e, Bm, E),
+                           ob, fb, tb, dvb, dwb);
+  store_bar(Fields{bpart, bpart + 3 * Bm * E, bpart + 7 * Bm * E, bpart + 10 * Bm * E}, part, b, e, Bm, E);
+  store2(ftb, fb, tb, b, e, Bm, E);
+  store2(dvw, dvb, dwb, b, e, Bm, E);
+}
+
+// Joint (spring) phase adjoint: slot j holds (parent bar, child bar).
+template <int MAXDOF>
+__global__ void k_adj_joint(const Tables* __restrict__ tab, int t, const int32_t* __restrict__ envs, int n, int E,
+                            int Bm, const float* __restrict__ tape_s, const float* __restrict__ ftb,
+                            float* __restrict__ jbar) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = idx / n, k = idx - j * n;
+  const TypeT& ty = tab->type[t];
+  if (j >= ty.nj) return;
+  const int e = envs[k];
+  const JointT& J = tab->joint[t][j];
+  Body P = post_kin(tab, t, tape_s, J.parent, e, Bm, E);
+  Body C = post_kin(tab, t, tape_s, J.child, e, Bm, E);
+  m3 RP = quat_to_mat(P.q), RC = quat_to_mat(C.q);
+  v3 fcb, tcb, fpb, tpb;
+  load2(ftb, fcb, tcb, J.child, e, Bm, E);
+  load2(ftb, fpb, tpb, J.parent, e, Bm, E);
+  Bar bP = bar_zero(), bC = bar_zero();
+  joint_spring_adj<MAXDOF>(J, P, RP, C, RC, fcb, tcb, fpb, tpb, bP, bC);
+  slot_store_bar(jbar, 0, ty.nj, j, n, k, bP);
+  slot_store_bar(jbar, 13, ty.nj, j, n, k, bC);
+}
+
+// Actuator phase adjoint: slot j holds (parent bar, child bar); the action
+// cotangents are accumulated into g_act (one writer per action and
+// environment per substep; substeps run in order).
+template <int MAXDOF>
+__global__ void k_adj_actuator(const Tables* __restrict__ tab, int t, const int32_t* __restrict__ envs, int n, int E,
+                               int Bm, const float* __restrict__ tape_s, const float* __restrict__ ftb,
+                               const float* __restrict__ act, float* __restrict__ abar, float* __restrict__ g_act) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = idx / n, k = idx - j * n;
+  const TypeT& ty = tab->type[t];
+  if (j >= ty.nj) return;
+  const int e = envs[k];
+  const JointT& J = tab->joint[t][j];
+  Body P = post_kin(tab, t, tape_s, J.parent, e, Bm, E);
+  Body C = post_kin(tab, t, tape_s, J.child, e, Bm, E);
+  m3 RP = quat_to_mat(P.q), RC = quat_to_mat(C.q);
+  v3 fcb, tcb, fpb, tpb;
+  load2(ftb, fcb, tcb, J.child, e, Bm, E);
+  load2(ftb, fpb, tpb, J.parent, e, Bm, E);
+  float a[3], raw[3], ab[3];
+  for (int x = 0; x < 3; ++x) {
+    raw[x] = J.act[x] >= 0 ? act[(size_t)J.act[x] * E + e] : 0.f;
+    a[x] = clampf(raw[x], -1.f, 1.f);
+  }
+  Bar bP = bar_zero(), bC = bar_zero();
+  joint_actuator_adj<MAXDOF>(J, P, RP, C, RC, a, tcb, tpb, bP, bC, ab);
+  slot_store_bar(abar, 0, ty.nj, j, n, k, bP);
+  slot_store_bar(abar, 13, ty.nj, j, n, k, bC);
+  for (int x = 0; x < MAXDOF; ++x)
+    if (x < J.dof && J.act[x] >= 0 && raw[x] >= -1.f && raw[x] <= 1.f) g_act[(size_t)J.act[x] * E + e] += ab[x];
+}
+
+// Contact phase adjoint: slot c holds the body bar (zero when no impulse).
+__global__ void k_adj_contact(const Tables* __restrict__ tab, int t, const int32_t* __restrict__ envs, int n, int E,
+                              int Bm, const float* __restrict__ tape_s, const float* __restrict__ dvw,
+                              float* __restrict__ cbar) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = idx / n, k = idx - c * n;
+  const TypeT& ty = tab->type[t];
+  if (c >= ty.nc) return;
+  const int e = envs[k];
+  const ContactT& Cc = tab->contact[t][c];
+  const BodyT& B = tab->body[t][Cc.body];
+  Body s = post_kin(tab, t, tape_s, Cc.body, e, Bm, E);
+  Frame f = derive(B, s);
+  v3 dvb, dwb;
+  load2(dvw, dvb, dwb, Cc.body, e, Bm, E);
+  bool applied;
+  Bar r = contact_adj(Cc, ty, B, s, f, dvb, dwb, applied);
+  if (!applied) r = bar_zero();
+  slot_store_bar(cbar, 0, ty.nc, c, n, k, r);
+}
+
+// Gather and kinematic adjoint: G <- cotangent of the substep's input state.
+__global__ void k_adj_kinematic(const Tables* __restrict__ tab, int t, const int32_t* __restrict__ envs, int n,
+                                int E, int Bm, const float* __restrict__ tape_s, const float* __restrict__ bpart,
+                                const float* __restrict__ jbar, const float* __restrict__ abar,
+                                const float* __restrict__ cbar, Fields G) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = idx / n, k = idx - b * n;
+  const TypeT& ty = tab->type[t];
+  if (b >= ty.nb) return;
+  const int e = envs[k];
+  const BodyT& B = tab->body[t][b];
+  Bar tot = load_bar(Fields{const_cast<float*>(bpart), const_cast<float*>(bpart) + 3 * Bm * E,
+                            const_cast<float*>(bpart) + 7 * Bm * E, const_cast<float*>(bpart) + 10 * Bm * E},
+                     b, e, Bm, E);
+  if (B.joint >= 0) {
+    slot_add_bar(jbar, 13, ty.nj, B.joint, n, k, tot);
+    slot_add_bar(abar, 13, ty.nj, B.joint, n, k, tot);
+  }
+  for (int i = 0; i < B.nch; ++i) {
+    const int j = tab->body[t][B.ch[i]].joint;
+    slot_add_bar(jbar, 0, ty.nj, j, n, k, tot);
+    slot_add_bar(abar, 0, ty.nj, j, n, k, tot);
+  }
+  for (int c = B.c0; c < B.c1; ++c) slot_add_bar(cbar, 0, ty.nc, c, n, k, tot);
+  Body pre = tape_load_state(tape_s, b, e, Bm, E);
+  store_bar(G, kinematic_adj(B, pre, ty.h, tot), b, e, Bm, E);
+}
+
+}  // namespace
+
+int vjp_reserve(VjpWork& w, const Tables& tab, int n_types, const int* type_cnt, int E, int Bm) {
+  size_t smax = 1;
+  size_t per_type = 0;
+  for (int t = 0; t < n_types; ++t) {
+    smax = std::max(smax, (size_t)tab.type[t].substeps);
+    size_t nt = std::max(type_cnt[t], 1);
+    per_type += nt * (26 * (size_t)std::max(tab.type[t].nj, 1) * 2 + 13 * (size_t)std::max(tab.type[t].nc, 1));
+  }
+  const size_t nbe = (size_t)Bm * std::max(E, 1);
+  const size_t need = (smax * TAPE_N + 13 + 13 + 6 + 6) * nbe + per_type + 64;
+  if (w.buf && w.bytes >= need * sizeof(float)) return 0;
+  vjp_free(w);
+  if (hipMalloc(&w.buf, need * sizeof(float)) != hipSuccess) {
+    w.buf = nullptr;
+    w.bytes = 0;
+    return -5;
+  }
+  w.bytes = need * sizeof(float);
+  return 0;
+}
+
+void vjp_free(VjpWork& w) {
+  if (w.buf) (void)hipFree(w.buf);
+  w.buf = nullptr;
+  w.bytes = 0;
+}
+
+hipError_t launch_vjp(const LaunchCtx& c, VjpWork& w, const VjpSched& sched, Fields in, const float* act,
+                      Fields g_out, Fields g_in, float* g_act, bool plain, hipStream_t s) {
+  const int E = c.E, Bm = c.Bm;
+  const size_t nbe = (size_t)Bm * E;
+  size_t smax = 1;
+  for (int t = 0; t < c.n_types; ++t) smax = std::max(smax, (size_t)c.host_tab->type[t].substeps);
+  float* tape = w.buf;
+  float* p = tape + smax * TAPE_N * nbe;
+  Fields fout{p, p + 3 * nbe, p + 7 * nbe, p + 10 * nbe};
+  p += 13 * nbe;
+  float* bpart = p;
+  p += 13 * nbe;
+  float* ftb = p;
+  p += 6 * nbe;
+  float* dvw = p;
+  p += 6 * nbe;
+  if (c.Am > 0) {
+    const size_t na = (size_t)c.Am * E;
+    hipLaunchKernelGGL(k_fill_f32, dim3(cdiv((long)na, TB)), dim3(TB), 0, s, g_act, na, 0.f);
+  }
+  // 1. forward with tape
+  hipError_t err;
+  if (plain)
+    err = launch_plain_step(c, in, fout, act, sched.jslot, sched.cslot, false, s, tape);
+  else
+    err = launch_fused(c, sched.work, sched.n_work, sched.waves_per_block, in, fout, act, 1, 0,
+                       Fields{nullptr, nullptr, nullptr, nullptr}, false, s, tape);
+  if (err != hipSuccess) return err;
+  // 2. reverse, type by type
+  for (int t = 0; t < c.n_types; ++t) {
+    const int n = c.type_cnt_h[t];
+    if (n == 0) continue;
+    const TypeT& ty = c.host_tab->type[t];
+    const int32_t* envs = c.env_list + c.type_off_h[t];
+    const size_t nj = std::max(ty.nj, 1), nc = std::max(ty.nc, 1);
+    float* jbar = p;
+    float* abar = jbar + 26 * nj * n;
+    float* cbar = abar + 26 * nj * n;
+    p = cbar + 13 * nc * n;
+    hipLaunchKernelGGL(k_adj_init, dim3(cdiv((long)Bm * n, TB)), dim3(TB), 0, s, c.tab, t, envs, n, E, Bm, g_out,
+                       g_in);
+    for (int sub = ty.substeps - 1; sub >= 0; --sub) {
+      const float* tape_s = tape + (size_t)sub * TAPE_N * nbe;
+      hipLaunchKernelGGL(k_adj_integrate, dim3(cdiv((long)ty.nb * n, TB)), dim3(TB), 0, s, c.tab, t, envs, n, E, Bm,
+                         tape_s, g_in, bpart, ftb, dvw);
+      if (ty.nj > 0) {
+        if (ty.max_dof <= 1) {
+          hipLaunchKernelGGL(k_adj_joint<1>, dim3(cdiv((long)ty.nj * n, TB)), dim3(TB), 0, s, c.tab, t, envs, n, E,
+                             Bm, tape_s, ftb, jbar);
+          hipLaunchKernelGGL(k_adj_actuator<1>, dim3(cdiv((long)ty.nj * n, TB)), dim3(TB), 0, s, c.tab, t, envs, n,
+                             E, Bm, tape_s, ftb, act, abar, g_act);
+        } else {
+          hipLaunchKernelGGL(k_adj_joint<3>, dim3(cdiv((long)ty.nj * n, TB)), dim3(TB), 0, s, c.tab, t, envs, n, E,
+                             Bm, tape_s, ftb, jbar);
+          hipLaunchKernelGGL(k_adj_actuator<3>, dim3(cdiv((long)ty.nj * n, TB)), dim3(TB), 0, s, c.tab, t, envs, n,
+                             E, Bm, tape_s, ftb, act, abar, g_act);
+        }
+      }
+      if (ty.nc > 0)
+        hipLaunchKernelGGL(k_adj_contact, dim3(cdiv((long)ty.nc * n, TB)), dim3(TB), 0, s, c.tab, t, envs, n, E, Bm,
+                           tape_s, dvw, cbar);
+      hipLaunchKernelGGL(k_adj_kinematic, dim3(cdiv((long)ty.nb * n, TB)), dim3(TB), 0, s, c.tab, t, envs, n, E, Bm,
+                         tape_s, bpart, jbar, abar, cbar, g_in);
+      if ((err = hipGetLastError()) != hipSuccess) return err;
+    }
+  }
+  return hipGetLastError();
+}
+
+}  // namespace bx

@@ -1,0 +1,140 @@
+"""The C-ABI library: exports, host-side validation and parser agreement.
+
+No GPU needed: a handle created with device -1 parses and validates only.
+"""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import oracle
+from paper_2106_13281_amd import braxmi, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "braxmi.h")
+SYSTEMS = ("chain", "quadruped", "biped", "manipulator")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(brax_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    L = braxmi.lib()
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(braxmi.EXPORTS)
+
+
+def host(descs, n=4, env_desc=None):
+    return braxmi.System(descs, n, env_desc=env_desc, device=-1)
+
+
+@pytest.mark.parametrize("name", SYSTEMS)
+def test_library_and_oracle_parsers_agree(name):
+    """Two independent parsers (C++ library, Python oracle) read the same sizes."""
+    text = synth.system_text(name)
+    s = host(text)
+    o = oracle.Oracle(text).system
+    assert s.n_bodies == [o.nb]
+    assert s.n_joints == [o.nj]
+    assert s.n_actions == [o.na]
+    assert s.n_dof == [o.ndof]
+    assert s.n_contacts == [o.nc]
+    assert s.substeps == [o.substeps]
+    assert abs(s.dt[0] - o.dt) < 1e-7
+    ang = s.default_angles(0).numpy()
+    assert abs(ang - o.default_angles()).max() < 1e-6
+
+
+def test_mixed_batch_layout():
+    descs = [synth.system_text(n) for n in SYSTEMS]
+    env = synth.mixed_assignment(0)
+    s = host(descs, len(env), env_desc=env)
+    assert s.type_envs == list(synth.MIXED_COUNTS)
+    assert s.b_max == 11 and s.a_max == 17 and s.d_max == 17
+
+
+def expect(code, descs, n=1, env_desc=None, match=None):
+    with pytest.raises(braxmi.BraxError) as ei:
+        host(descs, n, env_desc)
+    assert ei.value.code == code, str(ei.value)
+    if match:
+        assert re.search(match, str(ei.value)), str(ei.value)
+
+
+BODY = 'bodies {{ name: "{n}" mass: 1 inertia {{ x: 1 y: 1 z: 1 }} }}\n'
+
+
+def joint(p, c, lims=1, extra=""):
+    return (f'joints {{ name: "{p}{c}" parent: "{p}" child: "{c}" stiffness: 100 {extra}'
+            + "angle_limit { min: -10 max: 10 } " * lims + "}\n")
+
+
+def test_parse_errors_carry_line_and_column():
+    expect(-2, "bodies { name: \"a\" mass: 1\n  foo: 3 }", match=r"2:3: unknown field 'foo'")
+    expect(-2, "bodies { name: \"a\" mass: 1 ", match=r"missing '}'")
+    expect(-2, "substeps: }", match=r"1:11")
+    expect(-2, 'bodies { name: "a" mass: 1 inertia { x: 1 w: 2 } }', match=r"unknown field 'w'")
+    expect(-2, "dt: 0.01 $", match=r"unexpected character")
+
+
+def test_model_errors():
+    two = BODY.format(n="a") + BODY.format(n="b")
+    expect(-3, 'bodies { name: "a" mass: 0 inertia { x: 1 y: 1 z: 1 } }', match="mass")
+    expect(-3, 'bodies { name: "a" mass: 1 inertia { x: 1 y: 0 z: 1 } }', match="inertia")
+    expect(-3, 'bodies { name: "a" mass: 1 }', match="no inertia")
+    expect(-3, 'bodies { name: "a" mass: 1 colliders { capsule { radius: 0.2 length: 0.3 } } }', match="2 radius")
+    expect(-3, two + joint("a", "c"), match="unknown child")
+    expect(-3, two + joint("a", "b") + joint("b", "a"), match="two parents|cycle")
+    three = two + BODY.format(n="c")
+    expect(-3, three + joint("a", "c") + joint("b", "c"), match="two parents")
+    expect(-3, three + joint("a", "b") + joint("b", "c") + joint("c", "a"), match="two parents|cycle")
+    expect(-3, two + joint("a", "b", lims=4), match="1 to 3")
+    expect(-3, two + 'joints { name: "j" parent: "a" child: "b" angle_limit { min: 10 max: -10 } }', match="min > max")
+    expect(-3, BODY.format(n="a") + BODY.format(n="a"), match="twice")
+    expect(-3, two + joint("a", "b") + 'actuators { name: "x" joint: "nope" strength: 1 }', match="unknown joint")
+    expect(-3, "", match="no bodies")
+    expect(-3, "substeps: 0\n" + BODY.format(n="a"), match="substeps")
+
+
+def test_argument_errors():
+    L = braxmi.lib()
+    h = C.c_void_p()
+    assert L.brax_sys_create(None, 1, None, 1, -1, C.byref(h)) == -1
+    arr = (C.c_char_p * 1)(BODY.format(n="a").encode())
+    assert L.brax_sys_create(arr, 0, None, 1, -1, C.byref(h)) == -1
+    assert L.brax_sys_create(arr, 1, None, -1, -1, C.byref(h)) == -1
+    assert L.brax_sys_create(arr, 1, None, 1, -1, None) == -1
+    bad = (C.c_int32 * 2)(0, 1)
+    assert L.brax_sys_create(arr, 1, bad, 2, -1, C.byref(h)) == -1
+    assert b"out of range" in L.brax_last_error()
+    assert not h.value
+    # a host-only handle refuses device work with BRAX_E_ARG
+    s = host(BODY.format(n="a"), 3)
+    st = braxmi._State()
+    assert L.brax_step(s._h, C.byref(st), None, C.byref(st), 0, None) == -1
+    assert L.brax_rollout(s._h, C.byref(st), None, -1, 0, None, C.byref(st), 0, None) == -1
+    assert L.brax_sys_query(None, None) == -1
+    L.brax_sys_destroy(None)  # no-op
+
+
+def test_last_error_is_thread_local():
+    import threading
+    L = braxmi.lib()
+    L.brax_sys_query(None, None)
+    seen = []
+
+    def worker():
+        seen.append(L.brax_last_error())
+
+    th = threading.Thread(target=worker)
+    th.start()
+    th.join()
+    assert seen == [b""]
+    assert L.brax_last_error() != b""

@@ -1,0 +1,202 @@
+"""GPU parity of the forward path (reset pose, step, rollout) against the oracle.
+
+All calls go through the C ABI (libbraxmi.so) via the Python binding; inputs
+are seeded synthetic states and actions shared with the oracle as FP32 arrays.
+Tolerances: 1e-4 relative per step from identical state, 1e-3 over 20-step
+rollouts, for environments that are not branch-ambiguous (see helpers).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2106_13281_amd import braxmi, synth
+from tests.helpers import ambiguous, make_states, rel_err
+
+pytestmark = pytest.mark.gpu
+SYSTEMS = ("chain", "quadruped", "biped", "manipulator")
+STEP_TOL, ROLL_TOL = 1e-4, 1e-3
+STEP_AMB, ROLL_AMB = 1e-6, 1e-5
+
+
+def to_dev(X, b_max=None):
+    return braxmi.State(*(torch.from_numpy(a).cuda() for a in synth.to_soa(X, b_max)))
+
+
+def from_dev(st, nb):
+    torch.cuda.synchronize()
+    return synth.from_soa(*(t.cpu().numpy() for t in st.fields()), n_body=nb)
+
+
+def acts_dev(acts, a_max=None):
+    return torch.from_numpy(synth.acts_to_device_layout(acts, a_max)).cuda()
+
+
+def report(tag, r, amb):
+    print(f"{tag}: envs {len(r)}, ambiguous {int(amb.sum())}, max rel err (pos, rot, vel, ang) "
+          f"all {r.max(0)} non-ambiguous {r[~amb].max(0) if (~amb).any() else 'n/a'}", flush=True)
+
+
+def check(r, amb, tol, frac=0.02):
+    """Every environment meets `tol` unless it is branch-ambiguous; those
+    excused must be at most `frac` of the batch."""
+    bad = r.max(1) >= tol
+    assert not (bad & ~amb).any(), r[bad & ~amb].max(0)
+    assert bad.mean() <= frac, (bad.sum(), len(bad))
+
+
+@pytest.mark.parametrize("name", SYSTEMS)
+def test_default_qp_matches_oracle(name):
+    wl = synth.WORKLOADS[name]
+    o = oracle.Oracle(synth.system_text(wl.system))
+    s = o.system
+    E = 37
+    ang, root = synth.reset_noise(3, E, s.ndof, wl.angle_noise, max(wl.root_noise, 0.1))
+    full = (s.default_angles()[None, :] + ang.astype(np.float64)).astype(np.float32)
+    Xo = np.stack([o.default_qp(full[e].astype(np.float64), root[e].astype(np.float64)) for e in range(E)])
+    sysg = braxmi.System(synth.system_text(wl.system), E)
+    st = sysg.default_qp(torch.from_numpy(np.ascontiguousarray(full.T)).cuda(),
+                         torch.from_numpy(np.ascontiguousarray(root.T)).cuda())
+    Xg = from_dev(st, s.nb)
+    r = rel_err(Xg, Xo)
+    assert r.max() < 2e-6, r.max(0)
+    # default angles path (NULL angles, NULL offset)
+    st0 = sysg.default_qp()
+    Xo0 = o.default_qp()
+    assert rel_err(from_dev(st0, s.nb), np.broadcast_to(Xo0, (E,) + Xo0.shape)).max() < 2e-6
+
+
+@pytest.mark.parametrize("flags", [braxmi.BRAX_FUSED, braxmi.BRAX_PLAIN])
+@pytest.mark.parametrize("name", SYSTEMS)
+def test_step_matches_oracle(name, flags):
+    E = 157  # several wavefronts and a ragged tail
+    o, X, acts = make_states(name, E, seed=1, warm=25)
+    a = acts[0]
+    Xo, mg = o.step(X, a.astype(np.float64), margins=True)
+    sysg = braxmi.System(synth.system_text(synth.WORKLOADS[name].system), E)
+    out = sysg.step(to_dev(X), acts_dev(a[None])[0].contiguous(), flags=flags)
+    r = rel_err(from_dev(out, o.nb), Xo)
+    amb = ambiguous(mg, STEP_AMB)
+    report(f"step {name} flags={flags}", r, amb)
+    check(r, amb, STEP_TOL)
+
+
+@pytest.mark.parametrize("name", SYSTEMS)
+def test_rollout_20_steps_matches_oracle(name):
+    E = 96
+    o, X, acts = make_states(name, E, seed=2, warm=20)
+    T = 20
+    Xo, _, mg = o.rollout(X, acts[:T].astype(np.float64), margins=True)
+    sysg = braxmi.System(synth.system_text(synth.WORKLOADS[name].system), E)
+    out, _ = sysg.rollout(to_dev(X), acts_dev(acts[:T]))
+    r = rel_err(from_dev(out, o.nb), Xo)
+    amb = ambiguous(mg, ROLL_AMB)
+    report(f"rollout20 {name}", r, amb)
+    check(r, amb, ROLL_TOL)
+
+
+@pytest.mark.parametrize("name", SYSTEMS)
+def test_plain_and_fused_agree(name):
+    E = 64
+    o, X, acts = make_states(name, E, seed=4, warm=10)
+    sysg = braxmi.System(synth.system_text(synth.WORKLOADS[name].system), E)
+    a = acts_dev(acts[:5])
+    f, _ = sysg.rollout(to_dev(X), a)
+    p, _ = sysg.rollout(to_dev(X), a, flags=braxmi.BRAX_PLAIN)
+    r = rel_err(from_dev(f, o.nb), from_dev(p, o.nb))
+    print(f"plain vs fused {name}: max {r.max(0)}", flush=True)
+    assert r.max() < 1e-5
+
+
+def test_rollout_saves_match_single_steps_and_are_deterministic():
+    E = 50
+    o, X, acts = make_states("quadruped", E, seed=5, warm=5)
+    sysg = braxmi.System(synth.system_text("quadruped"), E)
+    a = acts_dev(acts[:6])
+    out, traj = sysg.rollout(to_dev(X), a, save_every=2)
+    assert traj.pos.shape[0] == 3
+    s = to_dev(X)
+    for t in range(6):
+        s = sysg.step(s, a[t].contiguous())
+        if (t + 1) % 2 == 0:
+            for f1, f2 in zip(traj[(t + 1) // 2 - 1].fields(), s.fields()):
+                assert torch.equal(f1, f2)
+    for f1, f2 in zip(out.fields(), s.fields()):
+        assert torch.equal(f1, f2)
+    out2, _ = sysg.rollout(to_dev(X), a)
+    for f1, f2 in zip(out.fields(), out2.fields()):
+        assert torch.equal(f1, f2)
+
+
+def test_in_place_step_and_zero_steps():
+    E = 20
+    o, X, acts = make_states("chain", E, seed=6, warm=3)
+    sysg = braxmi.System(synth.system_text("chain"), E)
+    ref = sysg.step(to_dev(X), acts_dev(acts[:1])[0].contiguous())
+    s = to_dev(X)
+    sysg.step(s, acts_dev(acts[:1])[0].contiguous(), out=s)
+    for f1, f2 in zip(ref.fields(), s.fields()):
+        assert torch.equal(f1, f2)
+    out, _ = sysg.rollout(to_dev(X), torch.zeros(0, sysg.a_max, E, device="cuda"))
+    Xg = from_dev(out, o.nb)
+    assert np.array_equal(Xg.astype(np.float32), X.astype(np.float32))
+
+
+@pytest.mark.parametrize("E", [1, 7, 8, 63, 65])
+def test_ragged_env_counts(E):
+    o, X, acts = make_states("quadruped", E, seed=7, warm=10)
+    Xo, mg = o.step(X, acts[0].astype(np.float64), margins=True)
+    sysg = braxmi.System(synth.system_text("quadruped"), E)
+    out = sysg.step(to_dev(X), acts_dev(acts[:1])[0].contiguous())
+    r = rel_err(from_dev(out, o.nb), Xo)
+    check(r, ambiguous(mg, STEP_AMB), STEP_TOL, frac=1.0 if E < 50 else 0.02)
+
+
+def test_zero_envs():
+    sysg = braxmi.System(synth.system_text("chain"), 0)
+    s = sysg.new_state()
+    sysg.step(s, torch.zeros(sysg.a_max, 0, device="cuda"))
+    torch.cuda.synchronize()
+
+
+def test_nonfinite_flags_and_isolation():
+    E = 30
+    o, X, acts = make_states("biped", E, seed=8, warm=5)
+    X[11, 3, 8] = np.nan
+    sysg = braxmi.System(synth.system_text("biped"), E)
+    for flags in (braxmi.BRAX_FUSED, braxmi.BRAX_PLAIN):
+        out = sysg.step(to_dev(X), acts_dev(acts[:1])[0].contiguous(), flags=flags | braxmi.BRAX_NONFINITE_FLAGS)
+        nf = sysg.nonfinite().numpy()
+        assert nf[11] == 1 and nf.sum() == 1
+        Xg = from_dev(out, o.nb)
+        assert np.isnan(Xg[11]).any()
+        assert np.isfinite(np.delete(Xg, 11, axis=0)).all()
+
+
+def test_graph_replay_matches_eager():
+    E = 48
+    o, X, acts = make_states("quadruped", E, seed=9, warm=5)
+    sysg = braxmi.System(synth.system_text("quadruped"), E)
+    for flags in (braxmi.BRAX_FUSED, braxmi.BRAX_PLAIN):
+        a = acts_dev(acts[:3])
+        ref, _ = sysg.rollout(to_dev(X), a, flags=flags)
+        inp = to_dev(X)
+        out = sysg.new_state()
+        for rep in range(3):  # replays interleaved with eager work
+            sysg.rollout(inp, a, out=out, flags=flags | braxmi.BRAX_GRAPH)
+            torch.cuda.synchronize()
+            for f1, f2 in zip(ref.fields(), out.fields()):
+                assert torch.equal(f1, f2), (flags, rep)
+            junk = torch.randn(1000, device="cuda").sum()
+            del junk
+
+
+def test_padded_bodies_written_as_zero():
+    descs = [synth.system_text("chain"), synth.system_text("quadruped")]
+    env = [0, 1, 0, 1, 1]
+    sysg = braxmi.System(descs, 5, env_desc=env)
+    s = sysg.default_qp()
+    out = sysg.step(s, torch.zeros(sysg.a_max, 5, device="cuda"))
+    torch.cuda.synchronize()
+    for f in out.fields():
+        assert torch.all(f[:, 3:, 0] == 0) and torch.all(f[:, 3:, 2] == 0)
