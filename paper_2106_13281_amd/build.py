@@ -16,6 +16,11 @@ FLAGS = [
     # no packed-FP32 instructions (v_pk_*_f32) anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-ffp-contract=fast", "-fno-math-errno",
+    # FP32 divide and sqrt without the correctly-rounded sequences (about
+    # 2.5 ulp); the parity budget against the FP64 checker is 1e-4
+    "-fno-hip-fp32-correctly-rounded-divide-sqrt",
+    # FP32 denormals flushed to zero (no range scaling around reciprocals)
+    "-fgpu-flush-denormals-to-zero",
     "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
 ]
 

@@ -62,8 +62,21 @@ __device__ __forceinline__ float act_of(const float* act, int a, int e, int E) {
 // kinematic update (13), the total torque it received (3), its count of
 // applied contacts (1).
 __device__ __forceinline__ void tape_state(float* tp, const Body& s, int b, int e, int Bm, int E) {
-  const float v[13] = {s.p.x, s.p.y, s.p.z, s.q.w, s.q.x, s.q.y, s.q.z, s.v.x, s.v.y, s.v.z, s.w.x, s.w.y, s.w.z};
-  for (int c = 0; c < 13; ++c) tp[((size_t)c * Bm + b) * E + e] = v[c];
+  const size_t st = (size_t)Bm * E;
+  float* q = tp + (size_t)b * E + e;
+  q[0] = s.p.x;
+  q[st] = s.p.y;
+  q[2 * st] = s.p.z;
+  q[3 * st] = s.q.w;
+  q[4 * st] = s.q.x;
+  q[5 * st] = s.q.y;
+  q[6 * st] = s.q.z;
+  q[7 * st] = s.v.x;
+  q[8 * st] = s.v.y;
+  q[9 * st] = s.v.z;
+  q[10 * st] = s.w.x;
+  q[11 * st] = s.w.y;
+  q[12 * st] = s.w.z;
 }
 __device__ __forceinline__ void tape_torque(float* tp, v3 t, int b, int e, int Bm, int E) {
   tp[((size_t)13 * Bm + b) * E + e] = t.x;
@@ -74,13 +87,13 @@ __device__ __forceinline__ void tape_count(float* tp, int n, int b, int e, int B
   tp[((size_t)16 * Bm + b) * E + e] = (float)n;
 }
 __device__ __forceinline__ Body tape_load_state(const float* tp, int b, int e, int Bm, int E) {
-  float v[13];
-  for (int c = 0; c < 13; ++c) v[c] = tp[((size_t)c * Bm + b) * E + e];
+  const size_t st = (size_t)Bm * E;
+  const float* q = tp + (size_t)b * E + e;
   Body s;
-  s.p = V(v[0], v[1], v[2]);
-  s.q = q4{v[3], v[4], v[5], v[6]};
-  s.v = V(v[7], v[8], v[9]);
-  s.w = V(v[10], v[11], v[12]);
+  s.p = V(q[0], q[st], q[2 * st]);
+  s.q = q4{q[3 * st], q[4 * st], q[5 * st], q[6 * st]};
+  s.v = V(q[7 * st], q[8 * st], q[9 * st]);
+  s.w = V(q[10 * st], q[11 * st], q[12 * st]);
   return s;
 }
 __device__ __forceinline__ v3 tape_load_torque(const float* tp, int b, int e, int Bm, int E) {
@@ -89,5 +102,53 @@ __device__ __forceinline__ v3 tape_load_torque(const float* tp, int b, int e, in
 __device__ __forceinline__ int tape_load_count(const float* tp, int b, int e, int Bm, int E) {
   return (int)tp[((size_t)16 * Bm + b) * E + e];
 }
+
+// Cross-lane read within the wavefront (ds_bpermute).
+__device__ __forceinline__ float shfl(float v, int src) { return __shfl(v, src, 64); }
+
+// Keeps a value in a VGPR: the empty asm makes it opaque, so the compiler
+// cannot re-load it from the constant tables inside the hot loop.
+__device__ __forceinline__ void pin(float& x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void pin(int& x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void pin3(float* x) {
+  pin(x[0]);
+  pin(x[1]);
+  pin(x[2]);
+}
+
+// Per-lane constants copied once into registers.
+template <int MAXDOF>
+__device__ __forceinline__ void pin_consts(BodyT& B, JointT& J, bool has_joint, ContactT* C, int nc) {
+  pin(B.inv_m);
+  pin3(B.I);
+  pin3(B.Iinv);
+  pin3(B.free_p);
+  pin3(B.free_r);
+  if (has_joint) {
+    pin3(J.ap);
+    pin3(J.ac);
+    for (int k = 0; k < 9; ++k) {
+      pin(J.FP[k]);
+      pin(J.FC[k]);
+    }
+    pin(J.k_lin);
+    pin(J.c_lin);
+    pin(J.k_ang);
+    pin(J.c_ang);
+    pin(J.k_lim);
+    for (int k = 0; k < MAXDOF; ++k) {
+      pin(J.lo[k]);
+      pin(J.hi[k]);
+      pin(J.gear[k]);
+    }
+  }
+  for (int c = 0; c < nc; ++c) {
+    pin3(C[c].l);
+    pin(C[c].rho);
+  }
+}
+
+// Contact candidates of a body kept in registers (more are read from the table).
+constexpr int REG_CONTACTS = 2;
 
 }  // namespace bx

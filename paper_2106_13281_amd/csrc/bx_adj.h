@@ -332,15 +332,13 @@ BXF void joint_geo_adj(const JointT& J, const Body& P, const m3& RP, const Body&
   quat_to_mat_adj(C.q, RbC, qbC);
 }
 
-// Spring joint adjoint: given the cotangents of (fc, tc, fp, tp), accumulate
-// into the parent's and child's post-kinematic state cotangents.
+// Spring part of a joint's adjoint on given geometry: accumulates into the
+// state cotangents (bP, bC) and the geometry cotangents (gb).
 template <int MAXDOF>
-BXF void joint_spring_adj(const JointT& J, const Body& P, const m3& RP, const Body& C, const m3& RC, v3 fcb, v3 tcb,
-                          v3 fpb, v3 tpb, Bar& bP, Bar& bC) {
-  JointGeo g = joint_geo<MAXDOF>(J, RP, RC);
+BXF void spring_adj_core(const JointT& J, const Body& P, const Body& C, const JointGeo& g, v3 fcb, v3 tcb, v3 fpb,
+                         v3 tpb, Bar& bP, Bar& bC, GeoBar& gb) {
   v3 F;
   (void)joint_spring<MAXDOF>(J, P, C, g, F);
-  GeoBar gb = geobar_zero();
   // fc = F, tc = rC x F + tau, fp = -F, tp = -(rP x F) - tau
   v3 Fb = fcb - fpb;
   v3 taub = tcb - tpb;
@@ -382,17 +380,12 @@ BXF void joint_spring_adj(const JointT& J, const Body& P, const m3& RP, const Bo
   bC.p += -db;
   gb.rP += db;
   gb.rC += -db;
-  joint_geo_adj<MAXDOF>(J, P, RP, C, RC, g, gb, bP.q, bC.q);
 }
 
-// Actuator adjoint: given the cotangent tb of the child's torque (the parent
-// gets the opposite torque, cotangent tpb), accumulate into both rotations and
-// return the cotangents of the clipped actions.
+// Actuator part on given geometry: child torque cotangent tcb, parent tpb.
 template <int MAXDOF>
-BXF void joint_actuator_adj(const JointT& J, const Body& P, const m3& RP, const Body& C, const m3& RC, const float* a,
-                            v3 tcb, v3 tpb, Bar& bP, Bar& bC, float* ab) {
-  JointGeo g = joint_geo<MAXDOF>(J, RP, RC);
-  GeoBar gb = geobar_zero();
+BXF void actuator_adj_core(const JointT& J, const JointGeo& g, const float* a, v3 tcb, v3 tpb, GeoBar& gb,
+                           float* ab) {
   v3 taub = tcb - tpb;
   for (int k = 0; k < 3; ++k) ab[k] = 0.f;
   for (int k = 0; k < MAXDOF; ++k) {
@@ -401,6 +394,39 @@ BXF void joint_actuator_adj(const JointT& J, const Body& P, const m3& RP, const 
       ab[k] = J.gear[k] * dot(g.ax[k], taub);
     }
   }
+}
+
+// Spring joint adjoint: given the cotangents of (fc, tc, fp, tp), accumulate
+// into the parent's and child's post-kinematic state cotangents.
+template <int MAXDOF>
+BXF void joint_spring_adj(const JointT& J, const Body& P, const m3& RP, const Body& C, const m3& RC, v3 fcb, v3 tcb,
+                          v3 fpb, v3 tpb, Bar& bP, Bar& bC) {
+  JointGeo g = joint_geo<MAXDOF>(J, RP, RC);
+  GeoBar gb = geobar_zero();
+  spring_adj_core<MAXDOF>(J, P, C, g, fcb, tcb, fpb, tpb, bP, bC, gb);
+  joint_geo_adj<MAXDOF>(J, P, RP, C, RC, g, gb, bP.q, bC.q);
+}
+
+// Actuator adjoint: given the cotangent of the child's torque (the parent
+// gets the opposite torque), accumulate into both rotations and return the
+// cotangents of the clipped actions.
+template <int MAXDOF>
+BXF void joint_actuator_adj(const JointT& J, const Body& P, const m3& RP, const Body& C, const m3& RC, const float* a,
+                            v3 tcb, v3 tpb, Bar& bP, Bar& bC, float* ab) {
+  JointGeo g = joint_geo<MAXDOF>(J, RP, RC);
+  GeoBar gb = geobar_zero();
+  actuator_adj_core<MAXDOF>(J, g, a, tcb, tpb, gb, ab);
+  joint_geo_adj<MAXDOF>(J, P, RP, C, RC, g, gb, bP.q, bC.q);
+}
+
+// Spring and actuators together (the fused path): geometry computed once.
+template <int MAXDOF>
+BXF void joint_eval_adj(const JointT& J, const Body& P, const m3& RP, const Body& C, const m3& RC, const float* a,
+                        v3 fcb, v3 tcb, v3 fpb, v3 tpb, Bar& bP, Bar& bC, float* ab) {
+  JointGeo g = joint_geo<MAXDOF>(J, RP, RC);
+  GeoBar gb = geobar_zero();
+  spring_adj_core<MAXDOF>(J, P, C, g, fcb, tcb, fpb, tpb, bP, bC, gb);
+  actuator_adj_core<MAXDOF>(J, g, a, tcb, tpb, gb, ab);
   joint_geo_adj<MAXDOF>(J, P, RP, C, RC, g, gb, bP.q, bC.q);
 }
 

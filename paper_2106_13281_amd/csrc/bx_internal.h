@@ -86,12 +86,11 @@ struct LaunchCtx {
 
 hipError_t launch_default_qp(const LaunchCtx& c, const float* angles, const float* root_off, Fields out,
                              hipStream_t s);
-// tape (nullable, T == 1 only): per substep [TAPE_N][Bm][E], see bx_access.h.
 hipError_t launch_fused(const LaunchCtx& c, const WaveWork* work, int n_work, int waves_per_block, Fields in,
-                        Fields out, const float* acts, int T, int save_every, Fields traj, bool flags, hipStream_t s,
-                        float* tape = nullptr);
+                        Fields out, const float* acts, int T, int save_every, Fields traj, bool flags, hipStream_t s);
 // Plain path: one step (all substeps) of every type; acts points at this
-// step's [Am][E] actions. jslot/cslot: per-type scratch.
+// step's [Am][E] actions. jslot/cslot: per-type scratch. tape (nullable):
+// per substep [TAPE_N][Bm][E] records for the adjoint, see bx_access.h.
 hipError_t launch_plain_step(const LaunchCtx& c, Fields in, Fields out, const float* act, float* const* jslot,
                              float* const* cslot, bool flags, hipStream_t s, float* tape = nullptr);
 hipError_t launch_copy_state(const LaunchCtx& c, Fields in, Fields out, hipStream_t s);

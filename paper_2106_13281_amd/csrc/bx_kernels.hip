@@ -256,16 +256,15 @@ __global__ void k_plain_collision(const Tables* __restrict__ tab, int t, const i
 // (ds_bpermute): the child lane fetches its parent's state; the parent lane
 // fetches each child's reaction (fp, tp) in child order. State stays in
 // registers across all substeps and steps; only actions are read per step.
-__device__ __forceinline__ float shfl(float v, int src) { return __shfl(v, src, 64); }
 
 template <int MAXDOF>
 __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const WaveWork& wk,
                                           const int32_t* __restrict__ env_list, const int32_t* __restrict__ type_off,
                                           int E, int Bm, const Fields& in, const Fields& out,
                                           const float* __restrict__ acts, int Am, int T, int save_every,
-                                          const Fields& traj, uint8_t* nonfinite, float* __restrict__ tape) {
+                                          const Fields& traj, uint8_t* nonfinite) {
   const int t = wk.type;
-  const TypeT& ty = tab->type[t];
+  const TypeT ty = tab->type[t];
   const int nb = ty.nb;
   const int lane = threadIdx.x & 63;
   const int slot = lane / nb;
@@ -273,10 +272,15 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
   const int base = slot * nb;
   const bool live = slot < wk.count;
   const int e = env_list[type_off[t] + wk.k0 + (live ? slot : 0)];
-  const BodyT& B = tab->body[t][b];
+  BodyT B = tab->body[t][b];
   const bool has_joint = B.joint >= 0;
-  const JointT& J = tab->joint[t][has_joint ? B.joint : 0];
+  JointT J = tab->joint[t][has_joint ? B.joint : 0];
   const int src_parent = base + (has_joint ? J.parent : b);
+  const int n_con = B.c1 - B.c0;
+  ContactT Creg[REG_CONTACTS];
+  Creg[0] = tab->contact[t][B.c0];
+  Creg[1] = tab->contact[t][B.c0 + (n_con > 1 ? 1 : 0)];
+  pin_consts<MAXDOF>(B, J, has_joint, Creg, REG_CONTACTS);
   const float h = ty.h;
 
   Body s = load_body(in, b, e, Bm, E);
@@ -287,8 +291,6 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
     if (has_joint)
       for (int x = 0; x < MAXDOF; ++x) a[x] = act_of(acts + (size_t)step * Am * E, J.act[x], e, E);
     for (int sub = 0; sub < ty.substeps; ++sub) {
-      float* tp = tape ? tape + (size_t)sub * TAPE_N * Bm * E : nullptr;
-      if (tp && live) tape_state(tp, s, b, e, Bm, E);
       kinematic(B, s, h);
       Frame f = derive(B, s);
       // parent's post-kinematic state
@@ -303,21 +305,20 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
       v3 force = jo.fc, torque = jo.tc;
       // children's reactions, in child order
       for (int i = 0; i < ty.max_children; ++i) {
-        const int src = base + (i < B.nch ? B.ch[i] : b);
+        const int src = base + (i < B.nch ? (int)((B.ch_packed >> (4 * i)) & 15u) : b);
         v3 fp = V(shfl(jo.fp.x, src), shfl(jo.fp.y, src), shfl(jo.fp.z, src));
-        v3 tp = V(shfl(jo.tp.x, src), shfl(jo.tp.y, src), shfl(jo.tp.z, src));
+        v3 tp2 = V(shfl(jo.tp.x, src), shfl(jo.tp.y, src), shfl(jo.tp.z, src));
         if (i < B.nch) {
           force += fp;
-          torque += tp;
+          torque += tp2;
         }
       }
       v3 dv = V(0.f, 0.f, 0.f), dw = V(0.f, 0.f, 0.f);
       int cnt = 0;
-      for (int c = B.c0; c < B.c1; ++c) cnt += contact_eval(tab->contact[t][c], ty, B, s, f, dv, dw) ? 1 : 0;
-      if (tp && live) {
-        tape_torque(tp, torque, b, e, Bm, E);
-        tape_count(tp, cnt, b, e, Bm, E);
-      }
+      // the first REG_CONTACTS candidates from registers (no dynamic indexing), the rest from the table
+      if (n_con > 0) cnt += contact_eval(Creg[0], ty, B, s, f, dv, dw) ? 1 : 0;
+      if (n_con > 1) cnt += contact_eval(Creg[1], ty, B, s, f, dv, dw) ? 1 : 0;
+      for (int c = REG_CONTACTS; c < n_con; ++c) cnt += contact_eval(tab->contact[t][B.c0 + c], ty, B, s, f, dv, dw) ? 1 : 0;
       potential(B, ty, s, f, force, torque);
       collision(B, s, dv, dw, cnt);
     }
@@ -342,16 +343,15 @@ __global__ __launch_bounds__(256) void k_fused(const Tables* __restrict__ tab, c
                                                int n_work, const int32_t* __restrict__ env_list,
                                                const int32_t* __restrict__ type_off, int E, int Bm, Fields in,
                                                Fields out, const float* __restrict__ acts, int Am, int T,
-                                               int save_every, Fields traj, uint8_t* nonfinite,
-                                               float* __restrict__ tape) {
+                                               int save_every, Fields traj, uint8_t* nonfinite) {
   const int w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (w >= n_work) return;
   const WaveWork wk = work[w];
   // wave-uniform: joints of at most one axis take the shorter path
   if (tab->type[wk.type].max_dof <= 1)
-    fused_run<1>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite, tape);
+    fused_run<1>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite);
   else
-    fused_run<3>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite, tape);
+    fused_run<3>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite);
 }
 
 // ------------------------------------------------------------------ small helpers
@@ -383,11 +383,11 @@ hipError_t launch_default_qp(const LaunchCtx& c, const float* angles, const floa
 
 hipError_t launch_fused(const LaunchCtx& c, const WaveWork* work, int n_work, int waves_per_block, Fields in,
                         Fields out, const float* acts, int T, int save_every, Fields traj, bool flags,
-                        hipStream_t s, float* tape) {
+                        hipStream_t s) {
   if (n_work == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fused, dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block), 0, s, c.tab, work,
                      n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj,
-                     flags ? c.nonfinite : nullptr, tape);
+                     flags ? c.nonfinite : nullptr);
   return hipGetLastError();
 }
 

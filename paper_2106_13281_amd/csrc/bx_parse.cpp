@@ -527,6 +527,7 @@ void pack_type(const SystemDesc& d, Tables& tab, int t) {
   }
   for (int j = 0; j < ty.nj; ++j) {
     BodyT& P = tab.body[t][d.joints[j].parent];
+    P.ch_packed |= (uint32_t)d.joints[j].child << (4 * P.nch);
     P.ch[P.nch++] = d.joints[j].child;
   }
   for (int b = 0; b < ty.nb; ++b) {

@@ -39,6 +39,7 @@ struct BodyT {
   int32_t c0, c1;          // contact candidates [c0, c1) belong to this body
   int32_t nch;             // number of child bodies
   int32_t ch[MAXCH];       // child bodies (ascending joint order)
+  uint32_t ch_packed;      // the same, 4 bits per child (child i in bits 4i..4i+3)
   int32_t root;            // root body of this body's tree
   int32_t has_pos;         // root with a given reset position
   float pos0[3];           // that position

@@ -226,6 +226,168 @@ __global__ void k_adj_kinematic(const Tables* __restrict__ tab, int t, const int
   store_bar(G, kinematic_adj(B, pre, ty.h, tot), b, e, Bm, E);
 }
 
+// ------------------------------------------------------------ fused adjoint
+// One lane per body as in the fused forward kernel. The forward substeps run
+// first with their tape in LDS ([substep][TAPE_N][64 lanes] per wavefront,
+// lane fastest); then the substeps run backwards, each lane computing its
+// body's integrate, joint (+ actuator) and contact adjoints. The parent's
+// post-kinematic state and force/torque cotangents come by cross-lane reads;
+// each child's cotangent for its parent is read by the parent lane in child
+// order.
+__device__ __forceinline__ Body shfl_body(const Body& s, int src) {
+  Body r;
+  r.p = V(shfl(s.p.x, src), shfl(s.p.y, src), shfl(s.p.z, src));
+  r.q = q4{shfl(s.q.w, src), shfl(s.q.x, src), shfl(s.q.y, src), shfl(s.q.z, src)};
+  r.v = V(shfl(s.v.x, src), shfl(s.v.y, src), shfl(s.v.z, src));
+  r.w = V(shfl(s.w.x, src), shfl(s.w.y, src), shfl(s.w.z, src));
+  return r;
+}
+__device__ __forceinline__ Bar shfl_bar(const Bar& s, int src) {
+  Bar r;
+  r.p = V(shfl(s.p.x, src), shfl(s.p.y, src), shfl(s.p.z, src));
+  r.q = q4{shfl(s.q.w, src), shfl(s.q.x, src), shfl(s.q.y, src), shfl(s.q.z, src)};
+  r.v = V(shfl(s.v.x, src), shfl(s.v.y, src), shfl(s.v.z, src));
+  r.w = V(shfl(s.w.x, src), shfl(s.w.y, src), shfl(s.w.z, src));
+  return r;
+}
+__device__ __forceinline__ v3 shfl3(v3 a, int src) { return V(shfl(a.x, src), shfl(a.y, src), shfl(a.z, src)); }
+
+template <int MAXDOF>
+__device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, const WaveWork& wk,
+                                              const int32_t* __restrict__ env_list,
+                                              const int32_t* __restrict__ type_off, int E, int Bm, int Am,
+                                              const Fields& in, const float* __restrict__ act, const Fields& g_out,
+                                              const Fields& g_in, float* __restrict__ g_act, float* lds) {
+  const int t = wk.type;
+  const TypeT ty = tab->type[t];
+  const int nb = ty.nb;
+  const int lane = threadIdx.x & 63;
+  const int slot = lane / nb;
+  const int b = lane - slot * nb;
+  const int base = slot * nb;
+  const bool live = slot < wk.count;
+  const int e = env_list[type_off[t] + wk.k0 + (live ? slot : 0)];
+  BodyT B = tab->body[t][b];
+  const bool has_joint = B.joint >= 0;
+  JointT J = tab->joint[t][has_joint ? B.joint : 0];
+  const int src_parent = base + (has_joint ? J.parent : b);
+  const int n_con = B.c1 - B.c0;
+  ContactT Creg[REG_CONTACTS];
+  Creg[0] = tab->contact[t][B.c0];
+  Creg[1] = tab->contact[t][B.c0 + (n_con > 1 ? 1 : 0)];
+  pin_consts<MAXDOF>(B, J, has_joint, Creg, REG_CONTACTS);
+  const float h = ty.h;
+  float a[3] = {0.f, 0.f, 0.f}, raw[3] = {0.f, 0.f, 0.f};
+  if (has_joint)
+    for (int x = 0; x < MAXDOF; ++x) {
+      raw[x] = J.act[x] >= 0 ? act[(size_t)J.act[x] * E + e] : 0.f;
+      a[x] = clampf(raw[x], -1.f, 1.f);
+    }
+
+  // forward substeps with their tape in LDS
+  Body s = load_body(in, b, e, Bm, E);
+  for (int sub = 0; sub < ty.substeps; ++sub) {
+    float* tp = lds + sub * TAPE_N * 64 + lane;
+    tp[0] = s.p.x; tp[64] = s.p.y; tp[128] = s.p.z;
+    tp[192] = s.q.w; tp[256] = s.q.x; tp[320] = s.q.y; tp[384] = s.q.z;
+    tp[448] = s.v.x; tp[512] = s.v.y; tp[576] = s.v.z;
+    tp[640] = s.w.x; tp[704] = s.w.y; tp[768] = s.w.z;
+    kinematic(B, s, h);
+    Frame f = derive(B, s);
+    Body P = shfl_body(s, src_parent);
+    JointOut jo;
+    jo.fc = jo.tc = jo.fp = jo.tp = V(0.f, 0.f, 0.f);
+    if (has_joint) jo = joint_eval<MAXDOF>(J, P, quat_to_mat(P.q), s, f.R, a);
+    v3 force = jo.fc, torque = jo.tc;
+    for (int i = 0; i < ty.max_children; ++i) {
+      const int src = base + (i < B.nch ? (int)((B.ch_packed >> (4 * i)) & 15u) : b);
+      v3 fp = shfl3(jo.fp, src), tq = shfl3(jo.tp, src);
+      if (i < B.nch) {
+        force += fp;
+        torque += tq;
+      }
+    }
+    v3 dv = V(0.f, 0.f, 0.f), dw = V(0.f, 0.f, 0.f);
+    int cnt = 0;
+    if (n_con > 0) cnt += contact_eval(Creg[0], ty, B, s, f, dv, dw) ? 1 : 0;
+    if (n_con > 1) cnt += contact_eval(Creg[1], ty, B, s, f, dv, dw) ? 1 : 0;
+    for (int c = REG_CONTACTS; c < n_con; ++c) cnt += contact_eval(tab->contact[t][B.c0 + c], ty, B, s, f, dv, dw) ? 1 : 0;
+    tp[832] = torque.x; tp[896] = torque.y; tp[960] = torque.z;
+    tp[1024] = (float)cnt;
+    potential(B, ty, s, f, force, torque);
+    collision(B, s, dv, dw, cnt);
+  }
+
+  // reverse substeps
+  Bar G = live ? load_bar(g_out, b, e, Bm, E) : bar_zero();
+  float ga[3] = {0.f, 0.f, 0.f};
+  for (int sub = ty.substeps - 1; sub >= 0; --sub) {
+    const float* tp = lds + sub * TAPE_N * 64 + lane;
+    Body pre;
+    pre.p = V(tp[0], tp[64], tp[128]);
+    pre.q = q4{tp[192], tp[256], tp[320], tp[384]};
+    pre.v = V(tp[448], tp[512], tp[576]);
+    pre.w = V(tp[640], tp[704], tp[768]);
+    const v3 ttot = V(tp[832], tp[896], tp[960]);
+    const int n = (int)tp[1024];
+    Body post = pre;
+    kinematic(B, post, h);
+    Frame f = derive(B, post);
+    v3 fb, tb, dvb, dwb;
+    Bar tot = integrate_adj(B, ty, post, f, ttot, n, G, fb, tb, dvb, dwb);
+    Body P = shfl_body(post, src_parent);
+    v3 fbP = shfl3(fb, src_parent), tbP = shfl3(tb, src_parent);
+    Bar bP = bar_zero(), bC = bar_zero();
+    if (has_joint) {
+      float ab[3];
+      joint_eval_adj<MAXDOF>(J, P, quat_to_mat(P.q), post, f.R, a, fb, tb, fbP, tbP, bP, bC, ab);
+      for (int x = 0; x < MAXDOF; ++x) ga[x] += ab[x];
+    }
+    bar_add(tot, bC);
+    for (int i = 0; i < ty.max_children; ++i) {
+      const int src = base + (i < B.nch ? (int)((B.ch_packed >> (4 * i)) & 15u) : b);
+      Bar x = shfl_bar(bP, src);
+      if (i < B.nch) bar_add(tot, x);
+    }
+    auto contact_back = [&](const ContactT& C) {
+      bool applied;
+      Bar bc = contact_adj(C, ty, B, post, f, dvb, dwb, applied);
+      if (applied) bar_add(tot, bc);
+    };
+    if (n_con > 0) contact_back(Creg[0]);
+    if (n_con > 1) contact_back(Creg[1]);
+    for (int c = REG_CONTACTS; c < n_con; ++c) contact_back(tab->contact[t][B.c0 + c]);
+    G = kinematic_adj(B, pre, h, tot);
+  }
+  if (live) {
+    store_bar(g_in, G, b, e, Bm, E);
+    for (int pb = nb + b; pb < Bm; pb += nb) zero_body(g_in, pb, e, Bm, E);
+    if (has_joint)
+      for (int x = 0; x < MAXDOF; ++x)
+        if (x < J.dof && J.act[x] >= 0)
+          g_act[(size_t)J.act[x] * E + e] = (raw[x] >= -1.f && raw[x] <= 1.f) ? ga[x] : 0.f;
+    if (b == 0)
+      for (int x = ty.na; x < Am; ++x) g_act[(size_t)x * E + e] = 0.f;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_fused_vjp(const Tables* __restrict__ tab, const WaveWork* __restrict__ work,
+                                                  int n_work, const int32_t* __restrict__ env_list,
+                                                  const int32_t* __restrict__ type_off, int E, int Bm, int Am,
+                                                  int smax, Fields in, const float* __restrict__ act, Fields g_out,
+                                                  Fields g_in, float* __restrict__ g_act) {
+  extern __shared__ float lds_tape[];
+  const int w = blockIdx.x;
+  if (w >= n_work) return;
+  const WaveWork wk = work[w];
+  float* lds = lds_tape;
+  (void)smax;
+  if (tab->type[wk.type].max_dof <= 1)
+    fused_vjp_run<1>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds);
+  else
+    fused_vjp_run<3>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds);
+}
+
 }  // namespace
 
 int vjp_reserve(VjpWork& w, const Tables& tab, int n_types, const int* type_cnt, int E, int Bm) {
@@ -271,17 +433,20 @@ hipError_t launch_vjp(const LaunchCtx& c, VjpWork& w, const VjpSched& sched, Fie
   p += 6 * nbe;
   float* dvw = p;
   p += 6 * nbe;
+  if (!plain) {
+    // one wavefront per block; its tape lives in LDS
+    const size_t lds = smax * TAPE_N * 64 * sizeof(float);
+    if (sched.n_work == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fused_vjp, dim3(sched.n_work), dim3(64), lds, s, c.tab, sched.work, sched.n_work, c.env_list,
+                       c.type_off, E, Bm, c.Am, (int)smax, in, act, g_out, g_in, g_act);
+    return hipGetLastError();
+  }
   if (c.Am > 0) {
     const size_t na = (size_t)c.Am * E;
     hipLaunchKernelGGL(k_fill_f32, dim3(cdiv((long)na, TB)), dim3(TB), 0, s, g_act, na, 0.f);
   }
-  // 1. forward with tape
-  hipError_t err;
-  if (plain)
-    err = launch_plain_step(c, in, fout, act, sched.jslot, sched.cslot, false, s, tape);
-  else
-    err = launch_fused(c, sched.work, sched.n_work, sched.waves_per_block, in, fout, act, 1, 0,
-                       Fields{nullptr, nullptr, nullptr, nullptr}, false, s, tape);
+  // 1. forward with tape (plain per-phase kernels)
+  hipError_t err = launch_plain_step(c, in, fout, act, sched.jslot, sched.cslot, false, s, tape);
   if (err != hipSuccess) return err;
   // 2. reverse, type by type
   for (int t = 0; t < c.n_types; ++t) {

@@ -1,0 +1,198 @@
+"""GPU parity of the adjoint (brax_step_vjp) and of gradients through rollouts.
+
+The oracle's adjoint is J^T g with J from forward-mode dual numbers through
+the FP64 stepper (itself checked against central differences on the CPU).
+Tolerance: 1e-3 relative (normwise per environment) for gradients.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2106_13281_amd import braxmi, synth
+from tests.helpers import make_states
+
+pytestmark = pytest.mark.gpu
+SYSTEMS = ("chain", "quadruped", "biped", "manipulator")
+GRAD_TOL = 1e-3
+
+
+def to_dev(X, b_max=None):
+    return braxmi.State(*(torch.from_numpy(a).cuda() for a in synth.to_soa(X, b_max)))
+
+
+def from_dev(st, nb):
+    torch.cuda.synchronize()
+    return synth.from_soa(*(t.cpu().numpy() for t in st.fields()), n_body=nb)
+
+
+def acts_dev(a, a_max=None):
+    return torch.from_numpy(synth.acts_to_device_layout(a, a_max)).cuda()
+
+
+def normwise(got, ref):
+    got = got.reshape(len(got), -1)
+    ref = ref.reshape(len(ref), -1)
+    return np.linalg.norm(got - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), 1e-30)
+
+
+@pytest.mark.parametrize("flags", [braxmi.BRAX_FUSED, braxmi.BRAX_PLAIN])
+@pytest.mark.parametrize("name", SYSTEMS)
+def test_step_vjp_matches_oracle(name, flags):
+    E = 40
+    o, X, acts = make_states(name, E, seed=11, warm=15)
+    a = acts[0]
+    g = np.random.default_rng(12).normal(size=X.shape).astype(np.float32).astype(np.float64)
+    gi_o, ga_o = o.step_vjp(X, a.astype(np.float64), g)
+    _, mg = o.step(X, a.astype(np.float64), margins=True)
+    sysg = braxmi.System(synth.system_text(synth.WORKLOADS[name].system), E)
+    g_in, g_act = sysg.step_vjp(to_dev(X), acts_dev(a[None])[0].contiguous(), to_dev(g), flags=flags)
+    gi = from_dev(g_in, o.nb)
+    ga = g_act.cpu().numpy().T[:, :o.na]
+    err = normwise(np.concatenate([gi.reshape(E, -1), ga], 1), np.concatenate([gi_o.reshape(E, -1), ga_o], 1))
+    amb = mg.min(1) < 1e-6          # jumps or kinks within rounding reach
+    print(f"vjp {name} flags={flags}: max err {err.max():.2e} non-ambiguous {err[~amb].max() if (~amb).any() else 0:.2e} "
+          f"ambiguous {int(amb.sum())}/{E}", flush=True)
+    bad = err >= GRAD_TOL
+    assert not (bad & ~amb).any(), err[bad & ~amb]
+    assert bad.mean() <= 0.05
+
+
+def test_vjp_plain_and_fused_tapes_agree_and_are_deterministic():
+    E = 64
+    o, X, acts = make_states("biped", E, seed=13, warm=10)
+    g = np.random.default_rng(14).normal(size=X.shape)
+    sysg = braxmi.System(synth.system_text("biped"), E)
+    a = acts_dev(acts[:1])[0].contiguous()
+    gf, af = sysg.step_vjp(to_dev(X), a, to_dev(g))
+    gp, ap = sysg.step_vjp(to_dev(X), a, to_dev(g), flags=braxmi.BRAX_PLAIN)
+    gf2, af2 = sysg.step_vjp(to_dev(X), a, to_dev(g))
+    for x, y in zip(gf.fields(), gf2.fields()):
+        assert torch.equal(x, y)
+    assert torch.equal(af, af2)
+    ref = np.concatenate([from_dev(gf, o.nb).reshape(E, -1), af.cpu().numpy().T], 1)
+    got = np.concatenate([from_dev(gp, o.nb).reshape(E, -1), ap.cpu().numpy().T], 1)
+    assert normwise(got, ref).max() < 1e-4
+
+
+def test_vjp_graph_replay_matches_eager():
+    E = 32
+    o, X, acts = make_states("quadruped", E, seed=15, warm=5)
+    g = np.random.default_rng(16).normal(size=X.shape)
+    sysg = braxmi.System(synth.system_text("quadruped"), E)
+    a = acts_dev(acts[:1])[0].contiguous()
+    ref_g, ref_a = sysg.step_vjp(to_dev(X), a, to_dev(g))
+    st, go = to_dev(X), to_dev(g)
+    gi = sysg.new_state()
+    ga = torch.empty_like(ref_a)
+    for rep in range(3):
+        sysg.step_vjp(st, a, go, g_in=gi, g_act=ga, flags=braxmi.BRAX_GRAPH)
+        torch.cuda.synchronize()
+        for x, y in zip(ref_g.fields(), gi.fields()):
+            assert torch.equal(x, y), rep
+        assert torch.equal(ref_a, ga)
+        _ = torch.randn(1000, device="cuda").sum()
+
+
+def _loss_grad_oracle(o, X0, acts, states=None):
+    """d/da of -(x_torso(T) - x_torso(0)) + 1e-3 sum |a|^2 by chained oracle VJPs,
+    along the oracle's own trajectory or along the given `states` (s_0..s_{T-1})."""
+    T, E, _ = acts.shape
+    if states is None:
+        _, tr, _ = o.rollout(X0, acts.astype(np.float64), traj=True)
+        states = [X0] + [tr[t] for t in range(T - 1)]
+    g = np.zeros_like(X0)
+    g[:, 0, 0] = -1.0
+    ga = np.zeros(acts.shape)
+    for t in reversed(range(T)):
+        gi, gat = o.step_vjp(states[t], acts[t].astype(np.float64), g)
+        ga[t] = gat + 2e-3 * acts[t]
+        g = gi
+    return ga
+
+
+def test_rollout_gradient_differentiation_workload():
+    """Quadruped, 100-step rollout, checkpoints every 10 steps, 8 environments:
+    gradient of -(torso x displacement) + 1e-3 sum |a|^2 w.r.t. the actions.
+
+    (a) Along the GPU's own FP32 trajectory, the GPU adjoint equals the chain
+        of the oracle's FP64 step adjoints within 1e-3 for every environment.
+    (b) Against the oracle end to end (its own FP64 trajectory), within 1e-3
+        for every environment whose FP64 gradient is stable under input
+        perturbations at FP32 rounding level (relative 6e-8); an environment
+        whose FP64 gradient itself moves by more than the tolerance there is
+        ill-conditioned and only reported.
+    """
+    name, E, T, k = "quadruped", 8, 100, 10
+    wl = synth.WORKLOADS["quadruped_diff"]
+    o = oracle.Oracle(synth.system_text(name))
+    s = o.system
+    ang, root = synth.reset_noise(0, E, s.ndof, wl.angle_noise, wl.root_noise)
+    X0 = np.stack([o.default_qp(s.default_angles() + ang[e].astype(np.float64), root[e]) for e in range(E)])
+    X0 = X0.astype(np.float32).astype(np.float64)
+    acts = synth.actions(0, T, E, s.na, wl.act_range)
+    ga_o = _loss_grad_oracle(o, X0, acts)
+    Xp = X0 * (1 + 6e-8 * np.random.default_rng(22).choice([-1.0, 1.0], size=X0.shape))
+    ga_p = _loss_grad_oracle(o, Xp, acts)
+    cond = normwise(ga_p.transpose(1, 0, 2), ga_o.transpose(1, 0, 2))
+    stable = cond < GRAD_TOL
+
+    sysg = braxmi.System(synth.system_text(name), E)
+    s0 = to_dev(X0)
+    A = acts_dev(acts).requires_grad_(True)
+    out = braxmi.rollout_grad(sysg, s0, A, k=k)
+    loss = -(out.pos[0, 0] - s0.pos[0, 0]).sum() + 1e-3 * (A ** 2).sum()
+    loss.backward()
+    ga = A.grad.cpu().numpy().transpose(0, 2, 1)[:, :, :s.na]      # [T][E][A]
+    err = normwise(ga.transpose(1, 0, 2), ga_o.transpose(1, 0, 2))
+
+    # the GPU's own forward trajectory (FP32), then the oracle adjoint along it
+    _, traj = sysg.rollout(s0, acts_dev(acts[:T - 1]), save_every=1)
+    states = [X0] + [from_dev(traj[i], s.nb) for i in range(T - 1)]
+    ga_along = _loss_grad_oracle(o, X0, acts, states=states)
+    err_along = normwise(ga.transpose(1, 0, 2), ga_along.transpose(1, 0, 2))
+    print(f"rollout gradient T={T} k={k}: vs oracle {np.array2string(err, precision=2)}; "
+          f"FP64 sensitivity {np.array2string(cond, precision=2)}; "
+          f"vs oracle adjoint along GPU trajectory {np.array2string(err_along, precision=2)}", flush=True)
+    assert err_along.max() < GRAD_TOL
+    assert (err[stable] < GRAD_TOL).all()
+    assert stable.sum() >= E // 2
+
+    # checkpoint spacing changes memory, not the result
+    A2 = acts_dev(acts).requires_grad_(True)
+    out2 = braxmi.rollout_grad(sysg, s0, A2, k=1)
+    (-(out2.pos[0, 0] - s0.pos[0, 0]).sum() + 1e-3 * (A2 ** 2).sum()).backward()
+    assert torch.equal(A.grad, A2.grad)
+
+
+def test_mixed_batch_vjp_equals_homogeneous():
+    descs = [synth.system_text(n) for n in SYSTEMS]
+    per = {n: make_states(n, 6, seed=17, warm=5) for n in SYSTEMS}
+    env = [k % 4 for k in range(24)]
+    bm = 11
+    am = 17
+    Xmix = np.zeros((24, bm, 13))
+    amix = np.zeros((1, 24, am), np.float32)
+    gmix = np.zeros((24, bm, 13))
+    rng = np.random.default_rng(18)
+    gs = {}
+    for t, n in enumerate(SYSTEMS):
+        o, X, acts = per[n]
+        gs[n] = rng.normal(size=X.shape)
+        idx = [i for i in range(24) if env[i] == t]
+        Xmix[idx, :o.nb] = X
+        amix[0, idx, :o.na] = acts[0]
+        gmix[idx, :o.nb] = gs[n]
+    Xmix[:, :, 3] = np.where(Xmix[:, :, 3] == 0, 1.0, Xmix[:, :, 3])   # padded slots: any finite value
+    mixed = braxmi.System(descs, 24, env_desc=env)
+    gi, ga = mixed.step_vjp(to_dev(Xmix, bm), acts_dev(amix, am)[0].contiguous(), to_dev(gmix, bm))
+    gim = from_dev(gi, bm)
+    gam = ga.cpu().numpy().T
+    for t, n in enumerate(SYSTEMS):
+        o, X, acts = per[n]
+        one = braxmi.System(descs[t], 6)
+        g1, a1 = one.step_vjp(to_dev(X), acts_dev(acts[:1])[0].contiguous(), to_dev(gs[n]))
+        idx = [i for i in range(24) if env[i] == t]
+        assert np.array_equal(gim[idx, :o.nb], from_dev(g1, o.nb)), n
+        assert np.array_equal(gam[idx, :o.na], a1.cpu().numpy().T), n
+        assert not gim[idx, o.nb:].any()
