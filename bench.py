@@ -114,9 +114,11 @@ def main():
         # kernel, to scale the profiler's FETCH_SIZE / WRITE_SIZE readings
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
+        flush = torch.empty(160 << 20, dtype=torch.float32, device="cuda")
+        flush.fill_(2.0)          # 640 MiB written: evicts the 256 MiB last-level cache
         dst.copy_(src)
         torch.cuda.synchronize()
-        del src, dst
+        del src, dst, flush
 
     # fused forward: the timed region is K full rollouts
     ms_fused = time_calls(lambda: system.rollout(s0, acts, out=out), args.steps, args.warmup)
@@ -148,6 +150,52 @@ def main():
     fwd_vjp = wd.envs * wd.steps / (ms_vjp / 1e3)
     log(f"forward+VJP: {ms_vjp:.2f} ms per {wd.envs}x{wd.steps} rollout gradient, {fwd_vjp:.3e} env-steps/s")
 
+    # the other workloads: biped forward; mixed batch (one persistent launch
+    # over 8192 environments of four system types), direct and graph-replayed,
+    # forward and forward+VJP
+    extra = {}
+    wb = synth.WORKLOADS["biped"]
+    bsys = braxmi.System(synth.system_text("biped"), wb.envs, device=0)
+    bsys.autotune()
+    b0, bacts = make_inputs(bsys, wb)
+    bout = bsys.new_state()
+    ms_b = time_calls(lambda: bsys.rollout(b0, bacts, out=bout), args.steps, args.warmup)
+    extra["biped_fwd_env_steps_per_s"] = wb.envs * wb.steps / (ms_b / 1e3)
+    log(f"biped forward: {ms_b:.2f} ms per {wb.envs}x{wb.steps} rollout")
+
+    types = synth.mixed_assignment(0)
+    msys = braxmi.System([synth.system_text(n) for n in synth.MIXED_TYPES], len(types), env_desc=types, device=0)
+    msys.autotune()
+    m0 = msys.default_qp(None, None)
+    Tm = 1000
+    macts = torch.from_numpy(synth.acts_to_device_layout(
+        synth.actions(0, Tm, len(types), msys.a_max, 1.0))).cuda()
+    mout = msys.new_state()
+    ms_m = time_calls(lambda: msys.rollout(m0, macts, out=mout), args.steps, args.warmup)
+    ms_mg = time_calls(lambda: msys.rollout(m0, macts, out=mout, flags=braxmi.BRAX_GRAPH), args.steps,
+                       args.warmup)
+    extra["mixed_fwd_env_steps_per_s"] = len(types) * Tm / (ms_m / 1e3)
+    extra["mixed_fwd_graph_env_steps_per_s"] = len(types) * Tm / (ms_mg / 1e3)
+    # single steps, launched one by one vs replayed from a captured graph
+    ms_ms = time_calls(lambda: msys.step(m0, macts[0], out=mout), 50, 5)
+    ms_msg = time_calls(lambda: msys.step(m0, macts[0], out=mout, flags=braxmi.BRAX_GRAPH), 50, 5)
+    extra["mixed_step_us"] = ms_ms * 1e3
+    extra["mixed_step_graph_us"] = ms_msg * 1e3
+    Tv = 100
+
+    def mixed_fwd_bwd():
+        A = macts[:Tv].detach().clone().requires_grad_(True)
+        o2 = braxmi.rollout_grad(msys, m0, A, k=10)
+        (o2.pos.sum() + 1e-3 * (A ** 2).sum()).backward()
+        return A.grad
+    ms_mv = time_calls(mixed_fwd_bwd, 1, 1)
+    extra["mixed_fwd_vjp_env_steps_per_s"] = len(types) * Tv / (ms_mv / 1e3)
+    extra["mixed_workload"] = ("8192 environments: 2048 chains, 3277 quadrupeds, 2048 bipeds, 819 manipulators "
+                               "(seeded permutation), reset pose, actions U(-1,1); forward 1000 steps, "
+                               "forward+VJP 100 steps with checkpoints every 10")
+    log(f"mixed forward: {ms_m:.2f} ms ({ms_mg:.2f} ms graph); step {ms_ms * 1e3:.1f} us "
+        f"({ms_msg * 1e3:.1f} us graph); forward+VJP {ms_mv:.2f} ms")
+
     fpe = algorithmic_flops("quadruped")
     achieved = fpe * E * T / (ms_fused / 1e3) / 1e12
     result = {
@@ -170,6 +218,7 @@ def main():
         "fused_over_plain": fused / plain,
         "fwd_vjp_env_steps_per_s": fwd_vjp,
         "fwd_vjp_workload": f"quadruped {wd.envs} environments x {wd.steps} steps, checkpoints every 10 steps",
+        **extra,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
                      "kernel": "k_fused", "flop_per_env_step": fpe,

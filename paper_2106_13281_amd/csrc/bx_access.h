@@ -150,5 +150,7 @@ __device__ __forceinline__ void pin_consts(BodyT& B, JointT& J, bool has_joint, 
 
 // Contact candidates of a body kept in registers (more are read from the table).
 constexpr int REG_CONTACTS = 2;
+// Children whose reactions are gathered with all cross-lane reads in flight at once.
+constexpr int GATHER = 4;
 
 }  // namespace bx

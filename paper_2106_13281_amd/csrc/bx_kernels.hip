@@ -292,25 +292,26 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
       for (int x = 0; x < MAXDOF; ++x) a[x] = act_of(acts + (size_t)step * Am * E, J.act[x], e, E);
     for (int sub = 0; sub < ty.substeps; ++sub) {
       kinematic(B, s, h);
-      Frame f = derive(B, s);
-      // parent's post-kinematic state
+      // parent's post-kinematic state: issue the cross-lane reads first, then
+      // derive this body's frame while they are in flight
       Body P;
       P.p = V(shfl(s.p.x, src_parent), shfl(s.p.y, src_parent), shfl(s.p.z, src_parent));
       P.q = q4{shfl(s.q.w, src_parent), shfl(s.q.x, src_parent), shfl(s.q.y, src_parent), shfl(s.q.z, src_parent)};
       P.v = V(shfl(s.v.x, src_parent), shfl(s.v.y, src_parent), shfl(s.v.z, src_parent));
       P.w = V(shfl(s.w.x, src_parent), shfl(s.w.y, src_parent), shfl(s.w.z, src_parent));
+      Frame f = derive(B, s);
       JointOut jo;
       jo.fc = jo.tc = jo.fp = jo.tp = V(0.f, 0.f, 0.f);
       if (has_joint) jo = joint_eval<MAXDOF>(J, P, quat_to_mat(P.q), s, f.R, a);
-      v3 force = jo.fc, torque = jo.tc;
-      // children's reactions, in child order
-      for (int i = 0; i < ty.max_children; ++i) {
-        const int src = base + (i < B.nch ? (int)((B.ch_packed >> (4 * i)) & 15u) : b);
-        v3 fp = V(shfl(jo.fp.x, src), shfl(jo.fp.y, src), shfl(jo.fp.z, src));
-        v3 tp2 = V(shfl(jo.tp.x, src), shfl(jo.tp.y, src), shfl(jo.tp.z, src));
-        if (i < B.nch) {
-          force += fp;
-          torque += tp2;
+      // children's reactions: all cross-lane reads issued before the contact
+      // phase and consumed after it (child order)
+      v3 cf[GATHER], ct[GATHER];
+#pragma unroll
+      for (int i = 0; i < GATHER; ++i) {
+        if (i < ty.max_children) {
+          const int src = base + (i < B.nch ? (int)((B.ch_packed >> (4 * i)) & 15u) : b);
+          cf[i] = V(shfl(jo.fp.x, src), shfl(jo.fp.y, src), shfl(jo.fp.z, src));
+          ct[i] = V(shfl(jo.tp.x, src), shfl(jo.tp.y, src), shfl(jo.tp.z, src));
         }
       }
       v3 dv = V(0.f, 0.f, 0.f), dw = V(0.f, 0.f, 0.f);
@@ -319,6 +320,23 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
       if (n_con > 0) cnt += contact_eval(Creg[0], ty, B, s, f, dv, dw) ? 1 : 0;
       if (n_con > 1) cnt += contact_eval(Creg[1], ty, B, s, f, dv, dw) ? 1 : 0;
       for (int c = REG_CONTACTS; c < n_con; ++c) cnt += contact_eval(tab->contact[t][B.c0 + c], ty, B, s, f, dv, dw) ? 1 : 0;
+      v3 force = jo.fc, torque = jo.tc;
+#pragma unroll
+      for (int i = 0; i < GATHER; ++i) {
+        if (i < B.nch) {
+          force += cf[i];
+          torque += ct[i];
+        }
+      }
+      for (int i = GATHER; i < ty.max_children; ++i) {
+        const int src = base + (i < B.nch ? (int)((B.ch_packed >> (4 * i)) & 15u) : b);
+        v3 fp = V(shfl(jo.fp.x, src), shfl(jo.fp.y, src), shfl(jo.fp.z, src));
+        v3 tq = V(shfl(jo.tp.x, src), shfl(jo.tp.y, src), shfl(jo.tp.z, src));
+        if (i < B.nch) {
+          force += fp;
+          torque += tq;
+        }
+      }
       potential(B, ty, s, f, force, torque);
       collision(B, s, dv, dw, cnt);
     }

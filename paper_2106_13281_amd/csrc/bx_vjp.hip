@@ -293,18 +293,18 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
     tp[448] = s.v.x; tp[512] = s.v.y; tp[576] = s.v.z;
     tp[640] = s.w.x; tp[704] = s.w.y; tp[768] = s.w.z;
     kinematic(B, s, h);
-    Frame f = derive(B, s);
     Body P = shfl_body(s, src_parent);
+    Frame f = derive(B, s);
     JointOut jo;
     jo.fc = jo.tc = jo.fp = jo.tp = V(0.f, 0.f, 0.f);
     if (has_joint) jo = joint_eval<MAXDOF>(J, P, quat_to_mat(P.q), s, f.R, a);
-    v3 force = jo.fc, torque = jo.tc;
-    for (int i = 0; i < ty.max_children; ++i) {
-      const int src = base + (i < B.nch ? (int)((B.ch_packed >> (4 * i)) & 15u) : b);
-      v3 fp = shfl3(jo.fp, src), tq = shfl3(jo.tp, src);
-      if (i < B.nch) {
-        force += fp;
-        torque += tq;
+    v3 cf[GATHER], ct[GATHER];
+#pragma unroll
+    for (int i = 0; i < GATHER; ++i) {
+      if (i < ty.max_children) {
+        const int src = base + (i < B.nch ? (int)((B.ch_packed >> (4 * i)) & 15u) : b);
+        cf[i] = shfl3(jo.fp, src);
+        ct[i] = shfl3(jo.tp, src);
       }
     }
     v3 dv = V(0.f, 0.f, 0.f), dw = V(0.f, 0.f, 0.f);
@@ -312,6 +312,22 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
     if (n_con > 0) cnt += contact_eval(Creg[0], ty, B, s, f, dv, dw) ? 1 : 0;
     if (n_con > 1) cnt += contact_eval(Creg[1], ty, B, s, f, dv, dw) ? 1 : 0;
     for (int c = REG_CONTACTS; c < n_con; ++c) cnt += contact_eval(tab->contact[t][B.c0 + c], ty, B, s, f, dv, dw) ? 1 : 0;
+    v3 force = jo.fc, torque = jo.tc;
+#pragma unroll
+    for (int i = 0; i < GATHER; ++i) {
+      if (i < B.nch) {
+        force += cf[i];
+        torque += ct[i];
+      }
+    }
+    for (int i = GATHER; i < ty.max_children; ++i) {
+      const int src = base + (i < B.nch ? (int)((B.ch_packed >> (4 * i)) & 15u) : b);
+      v3 fp = shfl3(jo.fp, src), tq = shfl3(jo.tp, src);
+      if (i < B.nch) {
+        force += fp;
+        torque += tq;
+      }
+    }
     tp[832] = torque.x; tp[896] = torque.y; tp[960] = torque.z;
     tp[1024] = (float)cnt;
     potential(B, ty, s, f, force, torque);
@@ -332,10 +348,10 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
     const int n = (int)tp[1024];
     Body post = pre;
     kinematic(B, post, h);
+    Body P = shfl_body(post, src_parent);
     Frame f = derive(B, post);
     v3 fb, tb, dvb, dwb;
     Bar tot = integrate_adj(B, ty, post, f, ttot, n, G, fb, tb, dvb, dwb);
-    Body P = shfl_body(post, src_parent);
     v3 fbP = shfl3(fb, src_parent), tbP = shfl3(tb, src_parent);
     Bar bP = bar_zero(), bC = bar_zero();
     if (has_joint) {
@@ -343,11 +359,14 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
       joint_eval_adj<MAXDOF>(J, P, quat_to_mat(P.q), post, f.R, a, fb, tb, fbP, tbP, bP, bC, ab);
       for (int x = 0; x < MAXDOF; ++x) ga[x] += ab[x];
     }
-    bar_add(tot, bC);
-    for (int i = 0; i < ty.max_children; ++i) {
-      const int src = base + (i < B.nch ? (int)((B.ch_packed >> (4 * i)) & 15u) : b);
-      Bar x = shfl_bar(bP, src);
-      if (i < B.nch) bar_add(tot, x);
+    // children's cotangents for this body: reads in flight during the contact adjoints
+    Bar cb[GATHER];
+#pragma unroll
+    for (int i = 0; i < GATHER; ++i) {
+      if (i < ty.max_children) {
+        const int src = base + (i < B.nch ? (int)((B.ch_packed >> (4 * i)) & 15u) : b);
+        cb[i] = shfl_bar(bP, src);
+      }
     }
     auto contact_back = [&](const ContactT& C) {
       bool applied;
@@ -357,6 +376,15 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
     if (n_con > 0) contact_back(Creg[0]);
     if (n_con > 1) contact_back(Creg[1]);
     for (int c = REG_CONTACTS; c < n_con; ++c) contact_back(tab->contact[t][B.c0 + c]);
+    bar_add(tot, bC);
+#pragma unroll
+    for (int i = 0; i < GATHER; ++i)
+      if (i < B.nch) bar_add(tot, cb[i]);
+    for (int i = GATHER; i < ty.max_children; ++i) {
+      const int src = base + (i < B.nch ? (int)((B.ch_packed >> (4 * i)) & 15u) : b);
+      Bar x = shfl_bar(bP, src);
+      if (i < B.nch) bar_add(tot, x);
+    }
     G = kinematic_adj(B, pre, h, tot);
   }
   if (live) {

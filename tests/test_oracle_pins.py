@@ -647,3 +647,39 @@ def test_flop_count_of_a_free_body_substep():
     X = np.zeros((1, 13))
     X[0, 3] = 1
     assert o.count_flops(X, np.zeros(0)) == 54 + 39 + 144 + 63
+
+
+def test_rollout_loss_gradient_matches_central_differences():
+    """Differentiation workload (quadruped): the chained oracle adjoint of
+    L = -(x_torso(T) - x_torso(0)) + 1e-3 sum |a|^2 against FP64 central
+    differences (h = 1e-6) of L along random action directions."""
+    wl = synth.WORKLOADS["quadruped_diff"]
+    o = oracle.Oracle(synth.system_text("quadruped"))
+    s = o.system
+    E, T = 3, 30
+    ang, root = synth.reset_noise(5, E, s.ndof, wl.angle_noise, wl.root_noise)
+    X0 = np.stack([o.default_qp(s.default_angles() + ang[e].astype(np.float64), root[e]) for e in range(E)])
+    acts = synth.actions(5, T, E, s.na, wl.act_range).astype(np.float64)
+
+    def loss(A):
+        XT, _, _ = o.rollout(X0, A)
+        return -(XT[:, 0, 0] - X0[:, 0, 0]) + 1e-3 * (A ** 2).sum(axis=(0, 2))
+
+    _, tr, mg = o.rollout(X0, acts, traj=True, margins=True)
+    states = [X0] + [tr[t] for t in range(T - 1)]
+    g = np.zeros_like(X0)
+    g[:, 0, 0] = -1.0
+    grad = np.zeros_like(acts)
+    for t in reversed(range(T)):
+        gi, gat = o.step_vjp(states[t], acts[t], g)
+        grad[t] = gat + 2e-3 * acts[t]
+        g = gi
+    rng = np.random.default_rng(6)
+    h = 1e-6
+    for _ in range(4):
+        d = rng.normal(size=acts.shape)
+        fd = (loss(acts + h * d) - loss(acts - h * d)) / (2 * h)
+        an = (grad * d).sum(axis=(0, 2))
+        ok = mg[:, :3].min(1) > 1e-5       # no jump of the step within reach of the perturbation
+        assert ok.any()
+        assert np.all(np.abs(fd - an)[ok] <= 1e-5 * np.maximum(np.abs(an[ok]), 1.0)), (fd, an)
