@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=100, help="env steps timed for the plain path")
+    ap.add_argument("--schedule", default="auto",
+                    help="fused launch shape 'ENVS_PER_WAVE,WAVES_PER_BLOCK' for the quadruped batch, or 'auto'")
     ap.add_argument("--only", choices=["all", "fused"], default="all",
                     help="fused: time only the fused forward rollout (for profiler runs), after a 256 MiB "
                          "device copy that calibrates the HBM byte counters")
@@ -106,8 +108,11 @@ def main():
     s0, acts = make_inputs(system, wl)
     out = system.new_state()
     log(f"inputs ready: {E} envs x {T} steps")
-    epw, wpb = system.autotune()
-    log(f"autotuned schedule: {epw} envs/wave, {wpb} waves/block")
+    if args.schedule == "auto":
+        epw, wpb = system.autotune()
+    else:
+        epw, wpb = system.set_schedule(*(int(x) for x in args.schedule.split(",")))
+    log(f"schedule ({args.schedule}): {epw} envs/wave, {wpb} waves/block")
 
     if args.only == "fused":
         # a plain copy of known size (256 MiB read + 256 MiB written) next to the
@@ -212,7 +217,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"quadruped rollout: {E} environments x {T} steps, dt 0.05 s, 10 substeps, "
-                               f"actions U(-1,1), seed 0", "envs": E, "env_steps": T, "substeps": 10},
+                               f"actions U(-1,1), seed 0", "envs": E, "env_steps": T, "substeps": 10,
+                   "schedule": {"envs_per_wave": epw, "waves_per_block": wpb}},
         "fused_fwd_env_steps_per_s": fused,
         "plain_fwd_env_steps_per_s": plain,
         "fused_over_plain": fused / plain,

@@ -158,8 +158,15 @@ int brax_rollout(const brax_sys* sys, const brax_state* in, const float* acts, i
  * for later calls (the result does not depend on the shape). */
 int brax_autotune(brax_sys* sys, void* stream);
 
-/* Launch shape in use: environments per wavefront and wavefronts per block. */
+/* Launch shape in use: environments per wavefront (of the first system type)
+ * and wavefronts per block. */
 int brax_schedule(const brax_sys* sys, int32_t* envs_per_wave, int32_t* waves_per_block);
+
+/* Set the launch shape: envs_per_wave environments per wavefront for every
+ * type (clamped to each type's maximum floor(64 / bodies); <= 0 keeps the
+ * maximum) and waves_per_block in {1, 2, 4}. Results do not depend on it.
+ * BRAX_E_ARG for other block shapes. */
+int brax_set_schedule(brax_sys* sys, int32_t envs_per_wave, int32_t waves_per_block);
 
 /* Copy the per-environment non-finite flags written by the last call made
  * with BRAX_NONFINITE_FLAGS to host out[n_envs] (synchronises the device). */

@@ -48,8 +48,8 @@ class _Layout(C.Structure):
 
 
 EXPORTS = ("brax_sys_create", "brax_sys_destroy", "brax_sys_query", "brax_default_angles", "brax_default_qp",
-           "brax_step", "brax_step_vjp", "brax_rollout", "brax_autotune", "brax_schedule", "brax_nonfinite",
-           "brax_last_error")
+           "brax_step", "brax_step_vjp", "brax_rollout", "brax_autotune", "brax_schedule", "brax_set_schedule",
+           "brax_nonfinite", "brax_last_error")
 
 _lib = None
 
@@ -76,6 +76,7 @@ def lib():
                                    C.c_int32, C.c_void_p]
         L.brax_autotune.argtypes = [C.c_void_p, C.c_void_p]
         L.brax_schedule.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32)]
+        L.brax_set_schedule.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
         L.brax_nonfinite.argtypes = [C.c_void_p, P(C.c_uint8)]
         L.brax_last_error.restype = C.c_char_p
         for name in EXPORTS:
@@ -242,6 +243,10 @@ class System:
         a, b = C.c_int32(), C.c_int32()
         _check(lib().brax_schedule(self._h, C.byref(a), C.byref(b)))
         return a.value, b.value
+
+    def set_schedule(self, envs_per_wave, waves_per_block):
+        _check(lib().brax_set_schedule(self._h, envs_per_wave, waves_per_block))
+        return self.schedule()
 
     def nonfinite(self):
         """Per-environment non-finite flags of the last call made with BRAX_NONFINITE_FLAGS (host copy)."""

@@ -252,6 +252,97 @@ BXF Bar contact_adj(const ContactT& c, const TypeT& ty, const BodyT& B, const Bo
   return r;
 }
 
+// The same adjoint without branches (the contact's result is kept by
+// selection), so that independent contacts and the joint interleave.
+BXF Bar contact_adj_sel(const ContactT& c, const TypeT& ty, const BodyT& B, const Body& s, const Frame& f, v3 dvb, v3 dwb,
+                    bool& applied) {
+  Bar r = bar_zero();
+  applied = false;
+  v3 l = ld3(c.l);
+  v3 rl = mul(f.R, l);
+  float depth = c.rho - (s.p.z + rl.z);
+  v3 rr = V(rl.x, rl.y, rl.z - c.rho);
+  v3 u = s.v + cross(s.w, rr);
+  v3 zz = V(rr.y, -rr.x, 0.f);
+  v3 a = mul(f.Iwinv, zz);
+  float kn = B.inv_m + (a.x * rr.y - a.y * rr.x);
+  float num = ty.beta_h * depth - ty.one_plus_e * u.z;
+  const bool on = (depth > 0.f) && (num > 0.f);
+  applied = on;
+  float jn = num / kn;
+  v3 J = V(0.f, 0.f, jn);
+  float sp = sqrtf(u.x * u.x + u.y * u.y);
+  v3 t = V(0.f, 0.f, 0.f), zt = V(0.f, 0.f, 0.f), b = V(0.f, 0.f, 0.f), m = V(0.f, 0.f, 0.f);
+  float kt = 0.f, stop = 0.f, cap = 0.f, jt = 0.f, isp = 0.f;
+  bool use_cap = false;
+  {
+    isp = sp > 0.f ? 1.f / sp : 0.f;
+    t = V(u.x * isp, u.y * isp, 0.f);
+    zt = cross(rr, t);
+    b = mul(f.Iwinv, zt);
+    m = cross(b, rr);
+    kt = B.inv_m + dot(t, m);
+    stop = sp / kt;
+    cap = ty.mu * jn;
+    use_cap = cap <= stop;
+    jt = use_cap ? cap : stop;
+    J.x = -jt * t.x;
+    J.y = -jt * t.y;
+  }
+  // outputs: dv = inv_m J; dw = Iwinv (r x J)
+  s3 Iwinvb = s3_zero();
+  v3 y = cross(rr, J);
+  sym_outer_add(Iwinvb, dwb, y);
+  v3 yb = mul(f.Iwinv, dwb);
+  v3 rb = V(0.f, 0.f, 0.f), Jb = B.inv_m * dvb;
+  cross_adj(rr, J, yb, rb, Jb);
+  float jnb = Jb.z;
+  v3 ub = V(0.f, 0.f, 0.f);
+  {
+    float jtb = -(Jb.x * t.x + Jb.y * t.y);
+    v3 tb = V(-jt * Jb.x, -jt * Jb.y, 0.f);
+    float capb = use_cap ? jtb : 0.f, stopb = use_cap ? 0.f : jtb;
+    jnb += ty.mu * capb;
+    float spb = stopb / kt;
+    float ktb = -stopb * sp / (kt * kt);
+    // kt = inv_m + t . m, m = b x r, b = Iwinv zt, zt = r x t
+    tb += ktb * m;
+    v3 mb = ktb * t, bb = V(0.f, 0.f, 0.f);
+    cross_adj(b, rr, mb, bb, rb);
+    sym_outer_add(Iwinvb, bb, zt);
+    v3 ztb = mul(f.Iwinv, bb);
+    cross_adj(rr, t, ztb, rb, tb);
+    // t = u_xy / sp, sp = |u_xy|
+    float tdot = tb.x * t.x + tb.y * t.y;
+    ub.x += (tb.x - t.x * tdot) * isp + spb * t.x;
+    ub.y += (tb.y - t.y * tdot) * isp + spb * t.y;
+  }
+  // jn = num / kn
+  float numb = jnb / kn;
+  float knb = -jnb * jn / kn;
+  float depthb = ty.beta_h * numb;
+  ub.z += -ty.one_plus_e * numb;
+  // kn = inv_m + a.x r.y - a.y r.x, a = Iwinv zz, zz = (r.y, -r.x, 0)
+  v3 abar = V(knb * rr.y, -knb * rr.x, 0.f);
+  rb.y += knb * a.x;
+  rb.x += -knb * a.y;
+  sym_outer_add(Iwinvb, abar, zz);
+  v3 zzb = mul(f.Iwinv, abar);
+  rb.y += zzb.x;
+  rb.x += -zzb.y;
+  // u = v + w x r
+  r.v += ub;
+  cross_adj(s.w, rr, ub, r.w, rb);
+  // r = R l - rho z; depth = rho - p.z - (R l).z
+  v3 rlb = rb;
+  r.p.z -= depthb;
+  rlb.z -= depthb;
+  m3 Rb = m3_zero();
+  outer_add(Rb, rlb, l);
+  frame_adj(B, s, f, Rb, s3_zero(), Iwinvb, r.q);
+  return on ? r : bar_zero();
+}
+
 // ------------------------------------------------------------ joint geometry
 struct GeoBar {
   v3 rP, rC;

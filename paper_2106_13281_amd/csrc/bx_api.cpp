@@ -465,6 +465,29 @@ int brax_schedule(const brax_sys* s, int32_t* envs_per_wave, int32_t* waves_per_
   return BRAX_OK;
 }
 
+int brax_set_schedule(brax_sys* s, int32_t envs_per_wave, int32_t waves_per_block) {
+  if (!s) return fail(BRAX_E_ARG, "sys is NULL");
+  if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
+    return fail(BRAX_E_ARG, "waves_per_block must be 1, 2 or 4");
+  for (int t = 0; t < s->n_types; ++t) {
+    const int full = std::max(1, 64 / s->host_tab.type[t].nb);
+    s->envs_per_wave[t] = envs_per_wave <= 0 ? full : std::min(envs_per_wave, full);
+  }
+  s->waves_per_block = waves_per_block;
+  build_work(s);
+  if (s->device >= 0) {
+    DeviceGuard g(s->device);
+    int rc = upload_work(s);
+    if (rc) return rc;
+  }
+  for (auto& kv : s->graphs) {
+    (void)hipGraphExecDestroy(kv.second.second);
+    (void)hipGraphDestroy(kv.second.first);
+  }
+  s->graphs.clear();
+  return BRAX_OK;
+}
+
 int brax_autotune(brax_sys* s, void* stream) {
   if (!s) return fail(BRAX_E_ARG, "sys is NULL");
   if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");

@@ -300,9 +300,12 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
       P.v = V(shfl(s.v.x, src_parent), shfl(s.v.y, src_parent), shfl(s.v.z, src_parent));
       P.w = V(shfl(s.w.x, src_parent), shfl(s.w.y, src_parent), shfl(s.w.z, src_parent));
       Frame f = derive(B, s);
-      JointOut jo;
-      jo.fc = jo.tc = jo.fp = jo.tp = V(0.f, 0.f, 0.f);
-      if (has_joint) jo = joint_eval<MAXDOF>(J, P, quat_to_mat(P.q), s, f.R, a);
+      // joint evaluated on every lane (a root uses its own state as the
+      // parent and its result is discarded), so that it interleaves with the
+      // contacts below
+      JointOut jo = joint_eval<MAXDOF>(J, P, quat_to_mat(P.q), s, f.R, a);
+      const v3 z3 = V(0.f, 0.f, 0.f);
+      if (!has_joint) jo.fc = jo.tc = jo.fp = jo.tp = z3;
       // children's reactions: all cross-lane reads issued before the contact
       // phase and consumed after it (child order)
       v3 cf[GATHER], ct[GATHER];
@@ -316,9 +319,21 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
       }
       v3 dv = V(0.f, 0.f, 0.f), dw = V(0.f, 0.f, 0.f);
       int cnt = 0;
-      // the first REG_CONTACTS candidates from registers (no dynamic indexing), the rest from the table
-      if (n_con > 0) cnt += contact_eval(Creg[0], ty, B, s, f, dv, dw) ? 1 : 0;
-      if (n_con > 1) cnt += contact_eval(Creg[1], ty, B, s, f, dv, dw) ? 1 : 0;
+      // the first REG_CONTACTS candidates from registers, without branches
+      // (a lane without a second candidate repeats its first and drops it);
+      // the rest from the table
+      {
+        v3 dv1 = z3, dw1 = z3;
+        int c0 = contact_eval_sel(Creg[0], ty, B, s, f, dv, dw);
+        int c1 = contact_eval_sel(Creg[1], ty, B, s, f, dv1, dw1);
+        if (n_con > 0) cnt += c0;
+        if (n_con > 1) {
+          dv += dv1;
+          dw += dw1;
+          cnt += c1;
+        }
+        if (n_con == 0) dv = dw = z3;
+      }
       for (int c = REG_CONTACTS; c < n_con; ++c) cnt += contact_eval(tab->contact[t][B.c0 + c], ty, B, s, f, dv, dw) ? 1 : 0;
       v3 force = jo.fc, torque = jo.tc;
 #pragma unroll

@@ -267,6 +267,41 @@ BXF bool contact_eval(const ContactT& c, const TypeT& ty, const BodyT& B, const 
   return true;
 }
 
+// The same contact as contact_eval without branches: every quantity is
+// computed and the impulse is kept by selection, so that independent contacts
+// (and the joint) can be interleaved by the scheduler. Returns 1 if an
+// impulse was applied, else 0.
+BXF int contact_eval_sel(const ContactT& c, const TypeT& ty, const BodyT& B, const Body& s, const Frame& f, v3& dv,
+                         v3& dw) {
+  v3 rl = mul(f.R, ld3(c.l));
+  float depth = c.rho - (s.p.z + rl.z);
+  v3 r = V(rl.x, rl.y, rl.z - c.rho);
+  v3 u = s.v + cross(s.w, r);
+  v3 a = mul(f.Iwinv, V(r.y, -r.x, 0.f));
+  float kn = B.inv_m + (a.x * r.y - a.y * r.x);
+  float num = ty.beta_h * depth - ty.one_plus_e * u.z;
+  const bool on = (depth > 0.f) && (num > 0.f);
+  float jn = num / kn;
+  float sp = sqrtf(u.x * u.x + u.y * u.y);
+  float isp = sp > 0.f ? 1.f / sp : 0.f;
+  v3 t = V(u.x * isp, u.y * isp, 0.f);
+  v3 b = mul(f.Iwinv, cross(r, t));
+  float kt = B.inv_m + dot(t, cross(b, r));
+  float stop = sp / kt;
+  float cap = ty.mu * jn;
+  float jt = cap <= stop ? cap : stop;
+  v3 J = V(-jt * t.x, -jt * t.y, jn);
+  v3 ddv = B.inv_m * J;
+  v3 ddw = mul(f.Iwinv, cross(r, J));
+  dv.x += on ? ddv.x : 0.f;
+  dv.y += on ? ddv.y : 0.f;
+  dv.z += on ? ddv.z : 0.f;
+  dw.x += on ? ddw.x : 0.f;
+  dw.y += on ? ddw.y : 0.f;
+  dw.z += on ? ddw.z : 0.f;
+  return on ? 1 : 0;
+}
+
 // Potential integrator: v += h (g + f/m); w += h Iwinv (t - w x (Iw w)).
 BXF void potential(const BodyT& B, const TypeT& ty, Body& s, const Frame& f, v3 force, v3 torque) {
   v3 acc = ld3(ty.g) + B.inv_m * force;

@@ -295,9 +295,9 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
     kinematic(B, s, h);
     Body P = shfl_body(s, src_parent);
     Frame f = derive(B, s);
-    JointOut jo;
-    jo.fc = jo.tc = jo.fp = jo.tp = V(0.f, 0.f, 0.f);
-    if (has_joint) jo = joint_eval<MAXDOF>(J, P, quat_to_mat(P.q), s, f.R, a);
+    const v3 z3 = V(0.f, 0.f, 0.f);
+    JointOut jo = joint_eval<MAXDOF>(J, P, quat_to_mat(P.q), s, f.R, a);
+    if (!has_joint) jo.fc = jo.tc = jo.fp = jo.tp = z3;
     v3 cf[GATHER], ct[GATHER];
 #pragma unroll
     for (int i = 0; i < GATHER; ++i) {
@@ -307,10 +307,20 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
         ct[i] = shfl3(jo.tp, src);
       }
     }
-    v3 dv = V(0.f, 0.f, 0.f), dw = V(0.f, 0.f, 0.f);
+    v3 dv = z3, dw = z3;
     int cnt = 0;
-    if (n_con > 0) cnt += contact_eval(Creg[0], ty, B, s, f, dv, dw) ? 1 : 0;
-    if (n_con > 1) cnt += contact_eval(Creg[1], ty, B, s, f, dv, dw) ? 1 : 0;
+    {
+      v3 dv1 = z3, dw1 = z3;
+      int c0 = contact_eval_sel(Creg[0], ty, B, s, f, dv, dw);
+      int c1 = contact_eval_sel(Creg[1], ty, B, s, f, dv1, dw1);
+      if (n_con > 0) cnt += c0;
+      if (n_con > 1) {
+        dv += dv1;
+        dw += dw1;
+        cnt += c1;
+      }
+      if (n_con == 0) dv = dw = z3;
+    }
     for (int c = REG_CONTACTS; c < n_con; ++c) cnt += contact_eval(tab->contact[t][B.c0 + c], ty, B, s, f, dv, dw) ? 1 : 0;
     v3 force = jo.fc, torque = jo.tc;
 #pragma unroll
@@ -354,10 +364,15 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
     Bar tot = integrate_adj(B, ty, post, f, ttot, n, G, fb, tb, dvb, dwb);
     v3 fbP = shfl3(fb, src_parent), tbP = shfl3(tb, src_parent);
     Bar bP = bar_zero(), bC = bar_zero();
-    if (has_joint) {
+    {
+      // evaluated on every lane (roots drop it) so that it interleaves with the contacts
       float ab[3];
       joint_eval_adj<MAXDOF>(J, P, quat_to_mat(P.q), post, f.R, a, fb, tb, fbP, tbP, bP, bC, ab);
-      for (int x = 0; x < MAXDOF; ++x) ga[x] += ab[x];
+      if (has_joint) {
+        for (int x = 0; x < MAXDOF; ++x) ga[x] += ab[x];
+      } else {
+        bP = bC = bar_zero();
+      }
     }
     // children's cotangents for this body: reads in flight during the contact adjoints
     Bar cb[GATHER];
@@ -368,14 +383,18 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
         cb[i] = shfl_bar(bP, src);
       }
     }
-    auto contact_back = [&](const ContactT& C) {
+    {
+      bool ap0, ap1;
+      Bar b0 = contact_adj_sel(Creg[0], ty, B, post, f, dvb, dwb, ap0);
+      Bar b1 = contact_adj_sel(Creg[1], ty, B, post, f, dvb, dwb, ap1);
+      if (n_con > 0 && ap0) bar_add(tot, b0);
+      if (n_con > 1 && ap1) bar_add(tot, b1);
+    }
+    for (int c = REG_CONTACTS; c < n_con; ++c) {
       bool applied;
-      Bar bc = contact_adj(C, ty, B, post, f, dvb, dwb, applied);
+      Bar bc = contact_adj(tab->contact[t][B.c0 + c], ty, B, post, f, dvb, dwb, applied);
       if (applied) bar_add(tot, bc);
-    };
-    if (n_con > 0) contact_back(Creg[0]);
-    if (n_con > 1) contact_back(Creg[1]);
-    for (int c = REG_CONTACTS; c < n_con; ++c) contact_back(tab->contact[t][B.c0 + c]);
+    }
     bar_add(tot, bC);
 #pragma unroll
     for (int i = 0; i < GATHER; ++i)
