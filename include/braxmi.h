@@ -141,7 +141,7 @@ int brax_step(const brax_sys* sys, const brax_state* in, const float* act, brax_
  * (overwritten, not accumulated) for the same function brax_step computes.
  * The forward substeps are recomputed inside. At kinks the one-sided
  * conventions are: max(0,x)' = [x > 0]; the Coulomb cap is taken when
- * cap <= stop; clamp' = 1 strictly inside; clip' = 1 on the closed interval;
+ * cap <= stop; clamp' = 1 and clip' = 1 on the closed interval;
  * contact activation and counts have zero derivative. g_in may not alias
  * in or g_out. */
 int brax_step_vjp(const brax_sys* sys, const brax_state* in, const float* act, const brax_state* g_out,

@@ -38,11 +38,6 @@ BXF void outer_add(m3& A, v3 yb, v3 v) {
   A.m[3] += yb.y * v.x; A.m[4] += yb.y * v.y; A.m[5] += yb.y * v.z;
   A.m[6] += yb.z * v.x; A.m[7] += yb.z * v.y; A.m[8] += yb.z * v.z;
 }
-// A^T y
-BXF v3 mulT(const m3& A, v3 y) {
-  return v3{A.m[0] * y.x + A.m[3] * y.y + A.m[6] * y.z, A.m[1] * y.x + A.m[4] * y.y + A.m[7] * y.z,
-            A.m[2] * y.x + A.m[5] * y.y + A.m[8] * y.z};
-}
 // y = S v for a symmetric S stored once per off-diagonal pair
 BXF void sym_outer_add(s3& S, v3 yb, v3 v) {
   S.xx += yb.x * v.x;
@@ -81,6 +76,17 @@ BXF void frame_adj(const BodyT& B, const Body& s, const Frame& f, const m3& Rb_i
   rot_diag_adj(f.R, B.I, Iwb, Rb);
   rot_diag_adj(f.R, B.Iinv, Iwinvb, Rb);
   quat_to_mat_adj(s.q, Rb, qb);
+}
+// Cotangents of a body's frame (R, Iw, Iwinv), summed over the items of a
+// substep that read it; frame_adj is linear in them, so one conversion to
+// q_bar per body and substep serves every item.
+struct FrameBar {
+  m3 Rb;
+  s3 Iwb, Iwinvb;
+};
+BXF FrameBar framebar_zero() { return FrameBar{m3_zero(), s3_zero(), s3_zero()}; }
+BXF void frame_adj(const BodyT& B, const Body& s, const Frame& f, const FrameBar& fr, q4& qb) {
+  frame_adj(B, s, f, fr.Rb, fr.Iwb, fr.Iwinvb, qb);
 }
 // c = a x b  ->  a_bar += b x c_bar, b_bar += c_bar x a
 BXF void cross_adj(v3 a, v3 b, v3 cb, v3& ab, v3& bb) {
@@ -128,7 +134,7 @@ BXF Bar kinematic_adj(const BodyT& B, const Body& pre, float h, const Bar& ob) {
 // of the post-kinematic state and the cotangents of f_tot, t_tot and of the
 // contact sums (dvb, dwb; zero when n == 0).
 BXF Bar integrate_adj(const BodyT& B, const TypeT& ty, const Body& post, const Frame& f, v3 t_tot, int n,
-                      const Bar& ob, v3& fb, v3& tb, v3& dvb, v3& dwb) {
+                      const Bar& ob, v3& fb, v3& tb, v3& dvb, v3& dwb, FrameBar& fr) {
   const float h = ty.h;
   Bar r;
   r.p = ob.p;
@@ -146,16 +152,21 @@ BXF Bar integrate_adj(const BodyT& B, const TypeT& ty, const Body& post, const F
   v3 ab = h * keep(ob.w, B.free_r);           // cotangent of alpha = Iwinv x
   v3 u = mul(f.Iw, post.w);
   v3 x = t_tot - cross(post.w, u);
-  s3 Iwinvb = s3_zero(), Iwb = s3_zero();
-  sym_outer_add(Iwinvb, ab, x);
+  sym_outer_add(fr.Iwinvb, ab, x);
   v3 xb = mul(f.Iwinv, ab);
   tb = xb;
   v3 gb = -xb;                               // gyro = w' x u
   v3 ub = V(0.f, 0.f, 0.f);
   cross_adj(post.w, u, gb, r.w, ub);
   r.w += mul(f.Iw, ub);
-  sym_outer_add(Iwb, ub, post.w);
-  frame_adj(B, post, f, m3_zero(), Iwb, Iwinvb, r.q);
+  sym_outer_add(fr.Iwb, ub, post.w);
+  return r;
+}
+BXF Bar integrate_adj(const BodyT& B, const TypeT& ty, const Body& post, const Frame& f, v3 t_tot, int n,
+                      const Bar& ob, v3& fb, v3& tb, v3& dvb, v3& dwb) {
+  FrameBar fr = framebar_zero();
+  Bar r = integrate_adj(B, ty, post, f, t_tot, n, ob, fb, tb, dvb, dwb, fr);
+  frame_adj(B, post, f, fr, r.q);
   return r;
 }
 
@@ -163,7 +174,7 @@ BXF Bar integrate_adj(const BodyT& B, const TypeT& ty, const Body& post, const F
 // Cotangent of the body's post-kinematic state from one applied contact,
 // given the cotangents of the body's contact sums (dvb, dwb).
 BXF Bar contact_adj(const ContactT& c, const TypeT& ty, const BodyT& B, const Body& s, const Frame& f, v3 dvb, v3 dwb,
-                    bool& applied) {
+                    bool& applied, FrameBar& fr) {
   Bar r = bar_zero();
   applied = false;
   v3 l = ld3(c.l);
@@ -181,7 +192,7 @@ BXF Bar contact_adj(const ContactT& c, const TypeT& ty, const BodyT& B, const Bo
   float jn = num / kn;
   v3 J = V(0.f, 0.f, jn);
   float sp = sqrtf(u.x * u.x + u.y * u.y);
-  v3 t = V(0.f, 0.f, 0.f), zt = V(0.f, 0.f, 0.f), b = V(0.f, 0.f, 0.f), m = V(0.f, 0.f, 0.f);
+  v3 t = V(0.f, 0.f, 0.f), zt = V(0.f, 0.f, 0.f), b = V(0.f, 0.f, 0.f);
   float kt = 0.f, stop = 0.f, cap = 0.f, jt = 0.f, isp = 0.f;
   bool use_cap = false;
   if (sp > 0.f) {
@@ -189,8 +200,7 @@ BXF Bar contact_adj(const ContactT& c, const TypeT& ty, const BodyT& B, const Bo
     t = V(u.x * isp, u.y * isp, 0.f);
     zt = cross(rr, t);
     b = mul(f.Iwinv, zt);
-    m = cross(b, rr);
-    kt = B.inv_m + dot(t, m);
+    kt = B.inv_m + dot(zt, b);
     stop = sp / kt;
     cap = ty.mu * jn;
     use_cap = cap <= stop;
@@ -199,9 +209,8 @@ BXF Bar contact_adj(const ContactT& c, const TypeT& ty, const BodyT& B, const Bo
     J.y = -jt * t.y;
   }
   // outputs: dv = inv_m J; dw = Iwinv (r x J)
-  s3 Iwinvb = s3_zero();
   v3 y = cross(rr, J);
-  sym_outer_add(Iwinvb, dwb, y);
+  sym_outer_add(fr.Iwinvb, dwb, y);
   v3 yb = mul(f.Iwinv, dwb);
   v3 rb = V(0.f, 0.f, 0.f), Jb = B.inv_m * dvb;
   cross_adj(rr, J, yb, rb, Jb);
@@ -214,12 +223,9 @@ BXF Bar contact_adj(const ContactT& c, const TypeT& ty, const BodyT& B, const Bo
     jnb += ty.mu * capb;
     float spb = stopb / kt;
     float ktb = -stopb * sp / (kt * kt);
-    // kt = inv_m + t . m, m = b x r, b = Iwinv zt, zt = r x t
-    tb += ktb * m;
-    v3 mb = ktb * t, bb = V(0.f, 0.f, 0.f);
-    cross_adj(b, rr, mb, bb, rb);
-    sym_outer_add(Iwinvb, bb, zt);
-    v3 ztb = mul(f.Iwinv, bb);
+    // kt = inv_m + zt . Iwinv zt, zt = r x t (Iwinv symmetric)
+    sym_outer_add(fr.Iwinvb, ktb * zt, zt);
+    v3 ztb = (2.f * ktb) * b;
     cross_adj(rr, t, ztb, rb, tb);
     // t = u_xy / sp, sp = |u_xy|
     float tdot = tb.x * t.x + tb.y * t.y;
@@ -235,7 +241,7 @@ BXF Bar contact_adj(const ContactT& c, const TypeT& ty, const BodyT& B, const Bo
   v3 abar = V(knb * rr.y, -knb * rr.x, 0.f);
   rb.y += knb * a.x;
   rb.x += -knb * a.y;
-  sym_outer_add(Iwinvb, abar, zz);
+  sym_outer_add(fr.Iwinvb, abar, zz);
   v3 zzb = mul(f.Iwinv, abar);
   rb.y += zzb.x;
   rb.x += -zzb.y;
@@ -246,101 +252,15 @@ BXF Bar contact_adj(const ContactT& c, const TypeT& ty, const BodyT& B, const Bo
   v3 rlb = rb;
   r.p.z -= depthb;
   rlb.z -= depthb;
-  m3 Rb = m3_zero();
-  outer_add(Rb, rlb, l);
-  frame_adj(B, s, f, Rb, s3_zero(), Iwinvb, r.q);
+  outer_add(fr.Rb, rlb, l);
   return r;
 }
-
-// The same adjoint without branches (the contact's result is kept by
-// selection), so that independent contacts and the joint interleave.
-BXF Bar contact_adj_sel(const ContactT& c, const TypeT& ty, const BodyT& B, const Body& s, const Frame& f, v3 dvb, v3 dwb,
+BXF Bar contact_adj(const ContactT& c, const TypeT& ty, const BodyT& B, const Body& s, const Frame& f, v3 dvb, v3 dwb,
                     bool& applied) {
-  Bar r = bar_zero();
-  applied = false;
-  v3 l = ld3(c.l);
-  v3 rl = mul(f.R, l);
-  float depth = c.rho - (s.p.z + rl.z);
-  v3 rr = V(rl.x, rl.y, rl.z - c.rho);
-  v3 u = s.v + cross(s.w, rr);
-  v3 zz = V(rr.y, -rr.x, 0.f);
-  v3 a = mul(f.Iwinv, zz);
-  float kn = B.inv_m + (a.x * rr.y - a.y * rr.x);
-  float num = ty.beta_h * depth - ty.one_plus_e * u.z;
-  const bool on = (depth > 0.f) && (num > 0.f);
-  applied = on;
-  float jn = num / kn;
-  v3 J = V(0.f, 0.f, jn);
-  float sp = sqrtf(u.x * u.x + u.y * u.y);
-  v3 t = V(0.f, 0.f, 0.f), zt = V(0.f, 0.f, 0.f), b = V(0.f, 0.f, 0.f), m = V(0.f, 0.f, 0.f);
-  float kt = 0.f, stop = 0.f, cap = 0.f, jt = 0.f, isp = 0.f;
-  bool use_cap = false;
-  {
-    isp = sp > 0.f ? 1.f / sp : 0.f;
-    t = V(u.x * isp, u.y * isp, 0.f);
-    zt = cross(rr, t);
-    b = mul(f.Iwinv, zt);
-    m = cross(b, rr);
-    kt = B.inv_m + dot(t, m);
-    stop = sp / kt;
-    cap = ty.mu * jn;
-    use_cap = cap <= stop;
-    jt = use_cap ? cap : stop;
-    J.x = -jt * t.x;
-    J.y = -jt * t.y;
-  }
-  // outputs: dv = inv_m J; dw = Iwinv (r x J)
-  s3 Iwinvb = s3_zero();
-  v3 y = cross(rr, J);
-  sym_outer_add(Iwinvb, dwb, y);
-  v3 yb = mul(f.Iwinv, dwb);
-  v3 rb = V(0.f, 0.f, 0.f), Jb = B.inv_m * dvb;
-  cross_adj(rr, J, yb, rb, Jb);
-  float jnb = Jb.z;
-  v3 ub = V(0.f, 0.f, 0.f);
-  {
-    float jtb = -(Jb.x * t.x + Jb.y * t.y);
-    v3 tb = V(-jt * Jb.x, -jt * Jb.y, 0.f);
-    float capb = use_cap ? jtb : 0.f, stopb = use_cap ? 0.f : jtb;
-    jnb += ty.mu * capb;
-    float spb = stopb / kt;
-    float ktb = -stopb * sp / (kt * kt);
-    // kt = inv_m + t . m, m = b x r, b = Iwinv zt, zt = r x t
-    tb += ktb * m;
-    v3 mb = ktb * t, bb = V(0.f, 0.f, 0.f);
-    cross_adj(b, rr, mb, bb, rb);
-    sym_outer_add(Iwinvb, bb, zt);
-    v3 ztb = mul(f.Iwinv, bb);
-    cross_adj(rr, t, ztb, rb, tb);
-    // t = u_xy / sp, sp = |u_xy|
-    float tdot = tb.x * t.x + tb.y * t.y;
-    ub.x += (tb.x - t.x * tdot) * isp + spb * t.x;
-    ub.y += (tb.y - t.y * tdot) * isp + spb * t.y;
-  }
-  // jn = num / kn
-  float numb = jnb / kn;
-  float knb = -jnb * jn / kn;
-  float depthb = ty.beta_h * numb;
-  ub.z += -ty.one_plus_e * numb;
-  // kn = inv_m + a.x r.y - a.y r.x, a = Iwinv zz, zz = (r.y, -r.x, 0)
-  v3 abar = V(knb * rr.y, -knb * rr.x, 0.f);
-  rb.y += knb * a.x;
-  rb.x += -knb * a.y;
-  sym_outer_add(Iwinvb, abar, zz);
-  v3 zzb = mul(f.Iwinv, abar);
-  rb.y += zzb.x;
-  rb.x += -zzb.y;
-  // u = v + w x r
-  r.v += ub;
-  cross_adj(s.w, rr, ub, r.w, rb);
-  // r = R l - rho z; depth = rho - p.z - (R l).z
-  v3 rlb = rb;
-  r.p.z -= depthb;
-  rlb.z -= depthb;
-  m3 Rb = m3_zero();
-  outer_add(Rb, rlb, l);
-  frame_adj(B, s, f, Rb, s3_zero(), Iwinvb, r.q);
-  return on ? r : bar_zero();
+  FrameBar fr = framebar_zero();
+  Bar r = contact_adj(c, ty, B, s, f, dvb, dwb, applied, fr);
+  if (applied) frame_adj(B, s, f, fr, r.q);
+  return r;
 }
 
 // ------------------------------------------------------------ joint geometry
@@ -359,9 +279,10 @@ BXF GeoBar geobar_zero() {
 }
 
 // Geometry cotangents -> q_bar of parent and child.
+// The child's rotation cotangent is added to RbC (its frame_adj follows
+// later); the parent's is turned into q_bar here.
 template <int MAXDOF>
-BXF void joint_geo_adj(const JointT& J, const Body& P, const m3& RP, const Body& C, const m3& RC, const JointGeo& g,
-                       GeoBar gb, q4& qbP, q4& qbC) {
+BXF void joint_geo_adj(const JointT& J, const Body& P, const JointGeo& g, GeoBar gb, q4& qbP, m3& RbC_acc) {
   float m12b = 0.f, m22b = 0.f, m01b = 0.f, m00b = 0.f, m02b = 0.f;
   // axes: ax0 = e1P, ax1 = c1 e2P + s1 e3P, ax2 = e3C
   gb.e1P += gb.ax[0];
@@ -406,7 +327,7 @@ BXF void joint_geo_adj(const JointT& J, const Body& P, const m3& RP, const Body&
       AbP.m[3 * i + k] = i == 0 ? cP[k].x : (i == 1 ? cP[k].y : cP[k].z);
       AbC.m[3 * i + k] = i == 0 ? cC[k].x : (i == 1 ? cC[k].y : cC[k].z);
     }
-  m3 RbP = m3_zero(), RbC = m3_zero();
+  m3 RbP = m3_zero();
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) {
       float sp = 0.f, sc = 0.f;
@@ -415,11 +336,17 @@ BXF void joint_geo_adj(const JointT& J, const Body& P, const m3& RP, const Body&
         sc += AbC.m[3 * i + k] * J.FC[3 * j + k];
       }
       RbP.m[3 * i + j] = sp;
-      RbC.m[3 * i + j] = sc;
+      RbC_acc.m[3 * i + j] += sc;
     }
   outer_add(RbP, gb.rP, ld3(J.ap));
-  outer_add(RbC, gb.rC, ld3(J.ac));
+  outer_add(RbC_acc, gb.rC, ld3(J.ac));
   quat_to_mat_adj(P.q, RbP, qbP);
+}
+template <int MAXDOF>
+BXF void joint_geo_adj(const JointT& J, const Body& P, const Body& C, const JointGeo& g, const GeoBar& gb, q4& qbP,
+                       q4& qbC) {
+  m3 RbC = m3_zero();
+  joint_geo_adj<MAXDOF>(J, P, g, gb, qbP, RbC);
   quat_to_mat_adj(C.q, RbC, qbC);
 }
 
@@ -495,7 +422,7 @@ BXF void joint_spring_adj(const JointT& J, const Body& P, const m3& RP, const Bo
   JointGeo g = joint_geo<MAXDOF>(J, RP, RC);
   GeoBar gb = geobar_zero();
   spring_adj_core<MAXDOF>(J, P, C, g, fcb, tcb, fpb, tpb, bP, bC, gb);
-  joint_geo_adj<MAXDOF>(J, P, RP, C, RC, g, gb, bP.q, bC.q);
+  joint_geo_adj<MAXDOF>(J, P, C, g, gb, bP.q, bC.q);
 }
 
 // Actuator adjoint: given the cotangent of the child's torque (the parent
@@ -507,18 +434,19 @@ BXF void joint_actuator_adj(const JointT& J, const Body& P, const m3& RP, const 
   JointGeo g = joint_geo<MAXDOF>(J, RP, RC);
   GeoBar gb = geobar_zero();
   actuator_adj_core<MAXDOF>(J, g, a, tcb, tpb, gb, ab);
-  joint_geo_adj<MAXDOF>(J, P, RP, C, RC, g, gb, bP.q, bC.q);
+  joint_geo_adj<MAXDOF>(J, P, C, g, gb, bP.q, bC.q);
 }
 
-// Spring and actuators together (the fused path): geometry computed once.
+// Spring and actuators together (the fused path): geometry computed once;
+// the child's rotation cotangent is added to its frame cotangents fr.
 template <int MAXDOF>
 BXF void joint_eval_adj(const JointT& J, const Body& P, const m3& RP, const Body& C, const m3& RC, const float* a,
-                        v3 fcb, v3 tcb, v3 fpb, v3 tpb, Bar& bP, Bar& bC, float* ab) {
+                        v3 fcb, v3 tcb, v3 fpb, v3 tpb, Bar& bP, Bar& bC, float* ab, FrameBar& fr) {
   JointGeo g = joint_geo<MAXDOF>(J, RP, RC);
   GeoBar gb = geobar_zero();
   spring_adj_core<MAXDOF>(J, P, C, g, fcb, tcb, fpb, tpb, bP, bC, gb);
   actuator_adj_core<MAXDOF>(J, g, a, tcb, tpb, gb, ab);
-  joint_geo_adj<MAXDOF>(J, P, RP, C, RC, g, gb, bP.q, bC.q);
+  joint_geo_adj<MAXDOF>(J, P, g, gb, bP.q, fr.Rb);
 }
 
 }  // namespace bx

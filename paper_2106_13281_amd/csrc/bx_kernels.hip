@@ -284,6 +284,9 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
   const float h = ty.h;
 
   Body s = load_body(in, b, e, Bm, E);
+  // frozen velocity components zeroed once; every update below keeps them zero
+  s.v = keep(s.v, B.free_p);
+  s.w = keep(s.w, B.free_r);
   int n_save = 0;
   for (int step = 0; step < T; ++step) {
     // actions of this step: acts[step][Am][E], held over the substeps
@@ -291,21 +294,26 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
     if (has_joint)
       for (int x = 0; x < MAXDOF; ++x) a[x] = act_of(acts + (size_t)step * Am * E, J.act[x], e, E);
     for (int sub = 0; sub < ty.substeps; ++sub) {
-      kinematic(B, s, h);
-      // parent's post-kinematic state: issue the cross-lane reads first, then
-      // derive this body's frame while they are in flight
+      kinematic_unmasked(s, h);
+      // parent's post-kinematic state: the cross-lane reads are issued first
+      // and this body's rotation is formed while they are in flight; the
+      // parent's rotation matrix is read from the parent lane's own
       Body P;
       P.p = V(shfl(s.p.x, src_parent), shfl(s.p.y, src_parent), shfl(s.p.z, src_parent));
-      P.q = q4{shfl(s.q.w, src_parent), shfl(s.q.x, src_parent), shfl(s.q.y, src_parent), shfl(s.q.z, src_parent)};
+      P.q = s.q;  // unused: the joint reads the parent's orientation as RP
       P.v = V(shfl(s.v.x, src_parent), shfl(s.v.y, src_parent), shfl(s.v.z, src_parent));
       P.w = V(shfl(s.w.x, src_parent), shfl(s.w.y, src_parent), shfl(s.w.z, src_parent));
-      Frame f = derive(B, s);
+      const m3 R = quat_to_mat(s.q);
+      m3 RP;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) RP.m[i] = shfl(R.m[i], src_parent);
+      Frame f = derive_inv(B, R);
+      JointChild jc = joint_child<MAXDOF>(J, s, R);
       // joint evaluated on every lane (a root uses its own state as the
       // parent and its result is discarded), so that it interleaves with the
       // contacts below
-      JointOut jo = joint_eval<MAXDOF>(J, P, quat_to_mat(P.q), s, f.R, a);
-      const v3 z3 = V(0.f, 0.f, 0.f);
-      if (!has_joint) jo.fc = jo.tc = jo.fp = jo.tp = z3;
+      // (a root's fp, tp are never read: its parent gather has no such child)
+      JointOut jo = joint_eval<MAXDOF>(J, P, RP, s, jc, a);
       // children's reactions: all cross-lane reads issued before the contact
       // phase and consumed after it (child order)
       v3 cf[GATHER], ct[GATHER];
@@ -319,23 +327,13 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
       }
       v3 dv = V(0.f, 0.f, 0.f), dw = V(0.f, 0.f, 0.f);
       int cnt = 0;
-      // the first REG_CONTACTS candidates from registers, without branches
-      // (a lane without a second candidate repeats its first and drops it);
-      // the rest from the table
-      {
-        v3 dv1 = z3, dw1 = z3;
-        int c0 = contact_eval_sel(Creg[0], ty, B, s, f, dv, dw);
-        int c1 = contact_eval_sel(Creg[1], ty, B, s, f, dv1, dw1);
-        if (n_con > 0) cnt += c0;
-        if (n_con > 1) {
-          dv += dv1;
-          dw += dw1;
-          cnt += c1;
-        }
-        if (n_con == 0) dv = dw = z3;
-      }
+      // the first REG_CONTACTS candidates from registers (no dynamic indexing), the rest from the table;
+      // a candidate is skipped by the whole wave when it touches the ground on no lane
+      if (n_con > 0) cnt += contact_eval(Creg[0], ty, B, s, f, dv, dw) ? 1 : 0;
+      if (n_con > 1) cnt += contact_eval(Creg[1], ty, B, s, f, dv, dw) ? 1 : 0;
       for (int c = REG_CONTACTS; c < n_con; ++c) cnt += contact_eval(tab->contact[t][B.c0 + c], ty, B, s, f, dv, dw) ? 1 : 0;
-      v3 force = jo.fc, torque = jo.tc;
+      const v3 z3 = V(0.f, 0.f, 0.f);
+      v3 force = has_joint ? jo.fc : z3, torque = has_joint ? jo.tc : z3;
 #pragma unroll
       for (int i = 0; i < GATHER; ++i) {
         if (i < B.nch) {

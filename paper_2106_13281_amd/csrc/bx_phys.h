@@ -42,6 +42,10 @@ BXF v3 mul(const m3& A, v3 v) {
   return v3{A.m[0] * v.x + A.m[1] * v.y + A.m[2] * v.z, A.m[3] * v.x + A.m[4] * v.y + A.m[5] * v.z,
             A.m[6] * v.x + A.m[7] * v.y + A.m[8] * v.z};
 }
+BXF v3 mul_t(const m3& A, v3 y) {  // A^T y
+  return v3{A.m[0] * y.x + A.m[3] * y.y + A.m[6] * y.z, A.m[1] * y.x + A.m[4] * y.y + A.m[7] * y.z,
+            A.m[2] * y.x + A.m[5] * y.y + A.m[8] * y.z};
+}
 BXF v3 mul(const s3& S, v3 v) {
   return v3{S.xx * v.x + S.xy * v.y + S.xz * v.z, S.xy * v.x + S.yy * v.y + S.yz * v.z,
             S.xz * v.x + S.yz * v.y + S.zz * v.z};
@@ -91,7 +95,36 @@ BXF s3 rot_diag(const m3& R, const float* d) {
 BXF v3 keep(v3 a, const float* f) {
   return v3{f[0] != 0.f ? a.x : 0.f, f[1] != 0.f ? a.y : 0.f, f[2] != 0.f ? a.z : 0.f};
 }
+// v + keep(h x) with one rounding: the frozen components keep v exactly.
+BXF v3 keep_fma(v3 v, float h, v3 x, const float* f) {
+  return v3{f[0] != 0.f ? fmaf(h, x.x, v.x) : v.x, f[1] != 0.f ? fmaf(h, x.y, v.y) : v.y,
+            f[2] != 0.f ? fmaf(h, x.z, v.z) : v.z};
+}
 BXF float clampf(float x, float lo, float hi) { return x < lo ? lo : (x > hi ? hi : x); }
+
+// atan2 for the joint angles. The octant reduction t = min(|x|,|y|) /
+// max(|x|,|y|) in [0, 1] is followed by atan t = t P(t^2), P of degree 7 fitted
+// (minimax, in absolute error) to atan on [0, 1], then by the reflections
+// pi/2 - r, pi - r and the sign of y. Absolute error about 1.2e-7 rad in FP32;
+// atan2(+-0, -0) = +-pi and atan2(+-0, +0) = +-0 as in C.
+BXF float atan2_poly(float y, float x) {
+  const float ax = fabsf(x), ay = fabsf(y);
+  const float mn = fminf(ax, ay), mx = fmaxf(ax, ay);
+  const float t = mx > 0.f ? mn * (1.f / mx) : 0.f;
+  const float u = t * t;
+  float p = -4.054381535e-3f;
+  p = p * u + 2.186222805e-2f;
+  p = p * u - 5.591116410e-2f;
+  p = p * u + 9.642101199e-2f;
+  p = p * u - 1.390858575e-1f;
+  p = p * u + 1.994655492e-1f;
+  p = p * u - 3.332985952e-1f;
+  p = p * u + 9.999993351e-1f;
+  float r = p * t;
+  r = ay > ax ? 1.57079637f - r : r;
+  r = signbit(x) ? 3.14159274f - r : r;
+  return copysignf(r, y);
+}
 
 struct Body {
   v3 p;
@@ -108,9 +141,9 @@ struct Frame {
 
 // Kinematic integrator (Algorithm 1, first line): frozen axes hold zero
 // velocity; p += h v; q <- normalize(q + h/2 (0, w) (x) q).
-BXF void kinematic(const BodyT& B, Body& s, float h) {
-  s.v = keep(s.v, B.free_p);
-  s.w = keep(s.w, B.free_r);
+// The kinematic update for a state whose frozen velocity components are
+// already zero (the integrators below keep them zero).
+BXF void kinematic_unmasked(Body& s, float h) {
   s.p = s.p + h * s.v;
   q4 dq = qmul(q4{0.f, s.w.x, s.w.y, s.w.z}, s.q);
   float hh = 0.5f * h;
@@ -118,12 +151,26 @@ BXF void kinematic(const BodyT& B, Body& s, float h) {
   float inv = 1.f / sqrtf(q.w * q.w + q.x * q.x + q.y * q.y + q.z * q.z);
   s.q = q4{q.w * inv, q.x * inv, q.y * inv, q.z * inv};
 }
+BXF void kinematic(const BodyT& B, Body& s, float h) {
+  s.v = keep(s.v, B.free_p);
+  s.w = keep(s.w, B.free_r);
+  kinematic_unmasked(s, h);
+}
 
 BXF Frame derive(const BodyT& B, const Body& s) {
   Frame f;
   f.R = quat_to_mat(s.q);
   f.Iw = rot_diag(f.R, B.I);
   f.Iwinv = rot_diag(f.R, B.Iinv);
+  return f;
+}
+// The frame from a given rotation without the world inertia, which the
+// forward step does not use (Iw is left zero).
+BXF Frame derive_inv(const BodyT& B, const m3& R) {
+  Frame f;
+  f.R = R;
+  f.Iw = s3{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  f.Iwinv = rot_diag(R, B.Iinv);
   return f;
 }
 
@@ -141,21 +188,38 @@ struct JointGeo {
   v3 ax[3];
 };
 
+// The child's side of the geometry, which needs no parent data: its anchor
+// offset, its joint-frame axes and its anchor velocity.
+struct JointChild {
+  v3 rC, uC, e1C, e2C, e3C;
+};
+
 template <int MAXDOF>
-BXF JointGeo joint_geo(const JointT& J, const m3& RP, const m3& RC) {
+BXF JointChild joint_child(const JointT& J, const Body& C, const m3& RC) {
+  JointChild c;
+  c.rC = mul(RC, ld3(J.ac));
+  m3 AwC = mul(RC, J.FC);
+  c.e1C = col(AwC, 0);
+  c.e2C = MAXDOF > 1 ? col(AwC, 1) : V(0.f, 0.f, 0.f);
+  c.e3C = col(AwC, 2);
+  c.uC = C.v + cross(C.w, c.rC);
+  return c;
+}
+
+template <int MAXDOF>
+BXF JointGeo joint_geo(const JointT& J, const m3& RP, const JointChild& c) {
   JointGeo g;
   g.rP = mul(RP, ld3(J.ap));
-  g.rC = mul(RC, ld3(J.ac));
+  g.rC = c.rC;
   m3 AwP = mul(RP, J.FP);
-  m3 AwC = mul(RC, J.FC);
   g.e1P = col(AwP, 0);
   g.e2P = col(AwP, 1);
   g.e3P = col(AwP, 2);
-  g.e1C = col(AwC, 0);
-  g.e3C = col(AwC, 2);
+  g.e1C = c.e1C;
+  g.e3C = c.e3C;
   g.m12 = dot(g.e2P, g.e3C);
   g.m22 = dot(g.e3P, g.e3C);
-  g.th[0] = atan2f(-g.m12, g.m22);
+  g.th[0] = atan2_poly(-g.m12, g.m22);
   float r = sqrtf(g.m12 * g.m12 + g.m22 * g.m22);
   g.c1 = 1.f;
   g.s1 = 0.f;
@@ -167,14 +231,21 @@ BXF JointGeo joint_geo(const JointT& J, const m3& RP, const m3& RC) {
   g.ax[1] = g.c1 * g.e2P + g.s1 * g.e3P;
   g.ax[2] = g.e3C;
   if (MAXDOF > 1) {
-    g.e2C = col(AwC, 1);
+    g.e2C = c.e2C;
     g.m01 = dot(g.e1P, g.e2C);
     g.m00 = dot(g.e1P, g.e1C);
     g.m02 = dot(g.e1P, g.e3C);
     g.th[1] = asinf(clampf(g.m02, -1.f, 1.f));
-    g.th[2] = atan2f(-g.m01, g.m00);
+    g.th[2] = atan2_poly(-g.m01, g.m00);
   }
   return g;
+}
+
+template <int MAXDOF>
+BXF JointGeo joint_geo(const JointT& J, const m3& RP, const m3& RC) {
+  Body none;
+  none.v = none.w = V(0.f, 0.f, 0.f);
+  return joint_geo<MAXDOF>(J, RP, joint_child<MAXDOF>(J, none, RC));
 }
 
 // Spring joint (Section 6.1) from the parent's and the child's
@@ -189,10 +260,9 @@ struct JointOut {
 };
 
 template <int MAXDOF>
-BXF v3 joint_spring(const JointT& J, const Body& P, const Body& C, const JointGeo& g, v3& F) {
+BXF v3 joint_spring(const JointT& J, const Body& P, const Body& C, const JointGeo& g, v3 uC, v3& F) {
   v3 d = (P.p - C.p) + (g.rP - g.rC);
   v3 uP = P.v + cross(P.w, g.rP);
-  v3 uC = C.v + cross(C.w, g.rC);
   F = J.k_lin * d + J.c_lin * (uP - uC);
   v3 tau;
   if (MAXDOF == 1 || J.dof == 1)
@@ -206,6 +276,10 @@ BXF v3 joint_spring(const JointT& J, const Body& P, const Body& C, const JointGe
     if (k < J.dof) tau += (-J.k_lim * (g.th[k] - clampf(g.th[k], J.lo[k], J.hi[k]))) * g.ax[k];
   return tau;
 }
+template <int MAXDOF>
+BXF v3 joint_spring(const JointT& J, const Body& P, const Body& C, const JointGeo& g, v3& F) {
+  return joint_spring<MAXDOF>(J, P, C, g, C.v + cross(C.w, g.rC), F);
+}
 
 // Actuators of a joint (Algorithm 1, actuator loop): torque gear_k a_k about
 // Euler axis k, on the child (and its opposite on the parent).
@@ -217,19 +291,24 @@ BXF v3 joint_actuator(const JointT& J, const JointGeo& g, const float* a) {
   return tau;
 }
 
-// Spring and actuators together (the fused path).
+// Spring and actuators together (the fused path), from the child's side
+// computed beforehand.
 template <int MAXDOF>
-BXF JointOut joint_eval(const JointT& J, const Body& P, const m3& RP, const Body& C, const m3& RC,
+BXF JointOut joint_eval(const JointT& J, const Body& P, const m3& RP, const Body& C, const JointChild& c,
                         const float* a /* clipped actions per axis, 0 if none */) {
-  JointGeo g = joint_geo<MAXDOF>(J, RP, RC);
+  JointGeo g = joint_geo<MAXDOF>(J, RP, c);
   v3 F;
-  v3 tau = joint_spring<MAXDOF>(J, P, C, g, F) + joint_actuator<MAXDOF>(J, g, a);
+  v3 tau = joint_spring<MAXDOF>(J, P, C, g, c.uC, F) + joint_actuator<MAXDOF>(J, g, a);
   JointOut o;
   o.fc = F;
   o.tc = cross(g.rC, F) + tau;
   o.fp = -F;
   o.tp = -(cross(g.rP, F) + tau);
   return o;
+}
+template <int MAXDOF>
+BXF JointOut joint_eval(const JointT& J, const Body& P, const m3& RP, const Body& C, const m3& RC, const float* a) {
+  return joint_eval<MAXDOF>(J, P, RP, C, joint_child<MAXDOF>(J, C, RC), a);
 }
 
 // One ground-contact candidate (Section 6.2): velocity-level normal impulse
@@ -254,8 +333,8 @@ BXF bool contact_eval(const ContactT& c, const TypeT& ty, const BodyT& B, const 
   if (sp > 0.f) {
     float isp = 1.f / sp;
     v3 t = V(u.x * isp, u.y * isp, 0.f);
-    v3 b = mul(f.Iwinv, cross(r, t));
-    float kt = B.inv_m + dot(t, cross(b, r));
+    v3 z = cross(r, t);
+    float kt = B.inv_m + dot(z, mul(f.Iwinv, z));  // t.((Iwinv (r x t)) x r) = (r x t).Iwinv (r x t)
     float stop = sp / kt;
     float cap = ty.mu * jn;
     float jt = cap <= stop ? cap : stop;
@@ -267,48 +346,16 @@ BXF bool contact_eval(const ContactT& c, const TypeT& ty, const BodyT& B, const 
   return true;
 }
 
-// The same contact as contact_eval without branches: every quantity is
-// computed and the impulse is kept by selection, so that independent contacts
-// (and the joint) can be interleaved by the scheduler. Returns 1 if an
-// impulse was applied, else 0.
-BXF int contact_eval_sel(const ContactT& c, const TypeT& ty, const BodyT& B, const Body& s, const Frame& f, v3& dv,
-                         v3& dw) {
-  v3 rl = mul(f.R, ld3(c.l));
-  float depth = c.rho - (s.p.z + rl.z);
-  v3 r = V(rl.x, rl.y, rl.z - c.rho);
-  v3 u = s.v + cross(s.w, r);
-  v3 a = mul(f.Iwinv, V(r.y, -r.x, 0.f));
-  float kn = B.inv_m + (a.x * r.y - a.y * r.x);
-  float num = ty.beta_h * depth - ty.one_plus_e * u.z;
-  const bool on = (depth > 0.f) && (num > 0.f);
-  float jn = num / kn;
-  float sp = sqrtf(u.x * u.x + u.y * u.y);
-  float isp = sp > 0.f ? 1.f / sp : 0.f;
-  v3 t = V(u.x * isp, u.y * isp, 0.f);
-  v3 b = mul(f.Iwinv, cross(r, t));
-  float kt = B.inv_m + dot(t, cross(b, r));
-  float stop = sp / kt;
-  float cap = ty.mu * jn;
-  float jt = cap <= stop ? cap : stop;
-  v3 J = V(-jt * t.x, -jt * t.y, jn);
-  v3 ddv = B.inv_m * J;
-  v3 ddw = mul(f.Iwinv, cross(r, J));
-  dv.x += on ? ddv.x : 0.f;
-  dv.y += on ? ddv.y : 0.f;
-  dv.z += on ? ddv.z : 0.f;
-  dw.x += on ? ddw.x : 0.f;
-  dw.y += on ? ddw.y : 0.f;
-  dw.z += on ? ddw.z : 0.f;
-  return on ? 1 : 0;
-}
-
 // Potential integrator: v += h (g + f/m); w += h Iwinv (t - w x (Iw w)).
+// Iw w is formed in the body frame, R (I o (R^T w)), which needs no world
+// inertia matrix.
 BXF void potential(const BodyT& B, const TypeT& ty, Body& s, const Frame& f, v3 force, v3 torque) {
   v3 acc = ld3(ty.g) + B.inv_m * force;
-  s.v += keep(ty.h * acc, B.free_p);
-  v3 gyro = cross(s.w, mul(f.Iw, s.w));
+  s.v = keep_fma(s.v, ty.h, acc, B.free_p);
+  v3 wb = mul_t(f.R, s.w);
+  v3 gyro = cross(s.w, mul(f.R, V(B.I[0] * wb.x, B.I[1] * wb.y, B.I[2] * wb.z)));
   v3 alpha = mul(f.Iwinv, torque - gyro);
-  s.w += keep(ty.h * alpha, B.free_r);
+  s.w = keep_fma(s.w, ty.h, alpha, B.free_r);
 }
 
 // Collision integrator: the body's contact impulses averaged over the n
@@ -316,8 +363,8 @@ BXF void potential(const BodyT& B, const TypeT& ty, Body& s, const Frame& f, v3 
 BXF void collision(const BodyT& B, Body& s, v3 dv, v3 dw, int n) {
   if (n > 0) {
     float inv = 1.f / (float)n;
-    s.v += keep(inv * dv, B.free_p);
-    s.w += keep(inv * dw, B.free_r);
+    s.v = keep_fma(s.v, inv, dv, B.free_p);
+    s.w = keep_fma(s.w, inv, dw, B.free_r);
   }
 }
 

@@ -293,10 +293,21 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
     tp[448] = s.v.x; tp[512] = s.v.y; tp[576] = s.v.z;
     tp[640] = s.w.x; tp[704] = s.w.y; tp[768] = s.w.z;
     kinematic(B, s, h);
-    Body P = shfl_body(s, src_parent);
-    Frame f = derive(B, s);
+    // as in the forward kernel: parent reads first, the parent's rotation
+    // matrix read from the parent lane
+    Body P;
+    P.p = shfl3(s.p, src_parent);
+    P.q = s.q;  // unused: the joint reads the parent's orientation as RP
+    P.v = shfl3(s.v, src_parent);
+    P.w = shfl3(s.w, src_parent);
+    const m3 R = quat_to_mat(s.q);
+    m3 RP;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) RP.m[i] = shfl(R.m[i], src_parent);
+    Frame f = derive_inv(B, R);
+    JointChild jc = joint_child<MAXDOF>(J, s, R);
     const v3 z3 = V(0.f, 0.f, 0.f);
-    JointOut jo = joint_eval<MAXDOF>(J, P, quat_to_mat(P.q), s, f.R, a);
+    JointOut jo = joint_eval<MAXDOF>(J, P, RP, s, jc, a);
     if (!has_joint) jo.fc = jo.tc = jo.fp = jo.tp = z3;
     v3 cf[GATHER], ct[GATHER];
 #pragma unroll
@@ -309,18 +320,10 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
     }
     v3 dv = z3, dw = z3;
     int cnt = 0;
-    {
-      v3 dv1 = z3, dw1 = z3;
-      int c0 = contact_eval_sel(Creg[0], ty, B, s, f, dv, dw);
-      int c1 = contact_eval_sel(Creg[1], ty, B, s, f, dv1, dw1);
-      if (n_con > 0) cnt += c0;
-      if (n_con > 1) {
-        dv += dv1;
-        dw += dw1;
-        cnt += c1;
-      }
-      if (n_con == 0) dv = dw = z3;
-    }
+    // the first REG_CONTACTS candidates from registers (no dynamic indexing), the rest from the table;
+    // a candidate is skipped by the whole wave when it touches the ground on no lane
+    if (n_con > 0) cnt += contact_eval(Creg[0], ty, B, s, f, dv, dw) ? 1 : 0;
+    if (n_con > 1) cnt += contact_eval(Creg[1], ty, B, s, f, dv, dw) ? 1 : 0;
     for (int c = REG_CONTACTS; c < n_con; ++c) cnt += contact_eval(tab->contact[t][B.c0 + c], ty, B, s, f, dv, dw) ? 1 : 0;
     v3 force = jo.fc, torque = jo.tc;
 #pragma unroll
@@ -361,18 +364,21 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
     Body P = shfl_body(post, src_parent);
     Frame f = derive(B, post);
     v3 fb, tb, dvb, dwb;
-    Bar tot = integrate_adj(B, ty, post, f, ttot, n, G, fb, tb, dvb, dwb);
+    // this body's frame cotangents from every item of the substep, turned
+    // into its quaternion cotangent once at the end
+    FrameBar fr = framebar_zero();
+    Bar tot = integrate_adj(B, ty, post, f, ttot, n, G, fb, tb, dvb, dwb, fr);
     v3 fbP = shfl3(fb, src_parent), tbP = shfl3(tb, src_parent);
     Bar bP = bar_zero(), bC = bar_zero();
     {
-      // evaluated on every lane (roots drop it) so that it interleaves with the contacts
+      // evaluated on every lane so that it interleaves with the contacts; a
+      // root's joint gets zero cotangents, and the adjoint being linear in
+      // them, every output is then exactly zero
+      const v3 z3 = V(0.f, 0.f, 0.f);
       float ab[3];
-      joint_eval_adj<MAXDOF>(J, P, quat_to_mat(P.q), post, f.R, a, fb, tb, fbP, tbP, bP, bC, ab);
-      if (has_joint) {
-        for (int x = 0; x < MAXDOF; ++x) ga[x] += ab[x];
-      } else {
-        bP = bC = bar_zero();
-      }
+      joint_eval_adj<MAXDOF>(J, P, quat_to_mat(P.q), post, f.R, a, has_joint ? fb : z3, has_joint ? tb : z3,
+                             has_joint ? fbP : z3, has_joint ? tbP : z3, bP, bC, ab, fr);
+      for (int x = 0; x < MAXDOF; ++x) ga[x] += ab[x];
     }
     // children's cotangents for this body: reads in flight during the contact adjoints
     Bar cb[GATHER];
@@ -383,19 +389,16 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
         cb[i] = shfl_bar(bP, src);
       }
     }
-    {
-      bool ap0, ap1;
-      Bar b0 = contact_adj_sel(Creg[0], ty, B, post, f, dvb, dwb, ap0);
-      Bar b1 = contact_adj_sel(Creg[1], ty, B, post, f, dvb, dwb, ap1);
-      if (n_con > 0 && ap0) bar_add(tot, b0);
-      if (n_con > 1 && ap1) bar_add(tot, b1);
-    }
-    for (int c = REG_CONTACTS; c < n_con; ++c) {
+    auto contact_back = [&](const ContactT& C) {
       bool applied;
-      Bar bc = contact_adj(tab->contact[t][B.c0 + c], ty, B, post, f, dvb, dwb, applied);
+      Bar bc = contact_adj(C, ty, B, post, f, dvb, dwb, applied, fr);
       if (applied) bar_add(tot, bc);
-    }
+    };
+    if (n_con > 0) contact_back(Creg[0]);
+    if (n_con > 1) contact_back(Creg[1]);
+    for (int c = REG_CONTACTS; c < n_con; ++c) contact_back(tab->contact[t][B.c0 + c]);
     bar_add(tot, bC);
+    frame_adj(B, post, f, fr, tot.q);
 #pragma unroll
     for (int i = 0; i < GATHER; ++i)
       if (i < B.nch) bar_add(tot, cb[i]);
