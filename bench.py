@@ -62,26 +62,34 @@ def time_calls(fn, reps, warmup):
     return e0.elapsed_time(e1) / reps
 
 
-def cpu_baseline(s0, acts, system, budget_s=12.0):
-    """The FP64 oracle on the host cores, on a bounded sample of the same workload."""
+def cpu_baseline(s0, acts, system, budget_s=12.0, budget_1core_s=4.0):
+    """The FP64 oracle on the host cores, on a bounded sample of the same
+    workload (all environments, as many leading steps as fit the budget), and
+    on one core on a smaller sample."""
     import oracle
     o = oracle.Oracle(synth.system_text("quadruped"))
     E = system.n_envs
-    nb = o.nb
-    X = synth.from_soa(*(t.cpu().numpy() for t in s0.fields()), n_body=nb)
+    X = synth.from_soa(*(t.cpu().numpy() for t in s0.fields()), n_body=o.nb)
     A = acts.cpu().numpy().transpose(0, 2, 1)[:, :, :o.na].astype(np.float64)   # [T][E][A]
     threads = oracle.max_threads()
-    n_env = min(E, 1024)
     t0 = time.perf_counter()
-    o.rollout(X[:n_env], A[:2, :n_env], threads=threads)
-    per = (time.perf_counter() - t0) / (2 * n_env)
-    T = int(max(2, min(A.shape[0], budget_s / max(per * n_env, 1e-9))))
+    o.rollout(X, A[:2], threads=threads)
+    per = (time.perf_counter() - t0) / (2 * E)          # seconds per env-step on all threads
+    T = int(max(2, min(A.shape[0], budget_s / max(per * E, 1e-9))))
     t0 = time.perf_counter()
-    o.rollout(X[:n_env], A[:T, :n_env], threads=threads)
+    o.rollout(X, A[:T], threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": n_env * T / dt, "unit": "env-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n_env} of the {E} quadruped environments x first {T} of the 1000 steps, FP64, "
+    full = {"value": E * T / dt, "unit": "env-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"all {E} quadruped environments x first {T} of the {A.shape[0]} steps, FP64, "
                       f"OpenMP over environments ({dt:.1f} s)"}
+    n1 = min(E, 256)
+    T1 = int(max(2, min(A.shape[0], budget_1core_s / max(per * threads * n1, 1e-9))))
+    t0 = time.perf_counter()
+    o.rollout(X[:n1], A[:T1, :n1], threads=1)
+    dt1 = time.perf_counter() - t0
+    one = {"value": n1 * T1 / dt1, "unit": "env-steps/s", "cores": 1, "kind": "oracle",
+           "sample": f"{n1} of the {E} quadruped environments x first {T1} steps, FP64, one thread ({dt1:.1f} s)"}
+    return full, one
 
 
 def main():
@@ -137,7 +145,11 @@ def main():
     Tp = min(args.plain_steps, T)
     ms_plain = time_calls(lambda: system.rollout(s0, acts[:Tp], out=out, flags=braxmi.BRAX_PLAIN), 1, 1)
     plain = E * Tp / (ms_plain / 1e3)
-    log(f"plain forward: {ms_plain:.2f} ms per {Tp}-step rollout, {plain:.3e} env-steps/s")
+    ms_plain_g = time_calls(lambda: system.rollout(s0, acts[:Tp], out=out, flags=braxmi.BRAX_PLAIN | braxmi.BRAX_GRAPH),
+                            1, 1)
+    plain_g = E * Tp / (ms_plain_g / 1e3)
+    log(f"plain forward: {ms_plain:.2f} ms per {Tp}-step rollout, {plain:.3e} env-steps/s; "
+        f"graph-replayed {ms_plain_g:.2f} ms")
 
     # forward + VJP: the differentiation workload (1024 quadrupeds x 100 steps,
     # checkpoints every 10 steps), gradient of a loss w.r.t. all actions
@@ -166,7 +178,18 @@ def main():
     bout = bsys.new_state()
     ms_b = time_calls(lambda: bsys.rollout(b0, bacts, out=bout), args.steps, args.warmup)
     extra["biped_fwd_env_steps_per_s"] = wb.envs * wb.steps / (ms_b / 1e3)
+    extra["biped_fwd_frac"] = algorithmic_flops("biped") * wb.envs * wb.steps / (ms_b / 1e3) / 1e12 / PEAK_FP32_TFLOPS
     log(f"biped forward: {ms_b:.2f} ms per {wb.envs}x{wb.steps} rollout")
+    # planar runner with target-angle actuators
+    wc = synth.WORKLOADS["cheetah"]
+    csys = braxmi.System(synth.system_text("cheetah"), wc.envs, device=0)
+    csys.autotune()
+    c0, cacts = make_inputs(csys, wc)
+    cout = csys.new_state()
+    ms_c = time_calls(lambda: csys.rollout(c0, cacts, out=cout), args.steps, args.warmup)
+    extra["cheetah_fwd_env_steps_per_s"] = wc.envs * wc.steps / (ms_c / 1e3)
+    extra["cheetah_fwd_frac"] = algorithmic_flops("cheetah") * wc.envs * wc.steps / (ms_c / 1e3) / 1e12 / PEAK_FP32_TFLOPS
+    log(f"cheetah forward: {ms_c:.2f} ms per {wc.envs}x{wc.steps} rollout")
 
     types = synth.mixed_assignment(0)
     msys = braxmi.System([synth.system_text(n) for n in synth.MIXED_TYPES], len(types), env_desc=types, device=0)
@@ -180,6 +203,8 @@ def main():
     ms_mg = time_calls(lambda: msys.rollout(m0, macts, out=mout, flags=braxmi.BRAX_GRAPH), args.steps,
                        args.warmup)
     extra["mixed_fwd_env_steps_per_s"] = len(types) * Tm / (ms_m / 1e3)
+    mixed_flop = sum(algorithmic_flops(n) * int((types == t).sum()) for t, n in enumerate(synth.MIXED_TYPES)) * Tm
+    extra["mixed_fwd_frac"] = mixed_flop / (ms_m / 1e3) / 1e12 / PEAK_FP32_TFLOPS
     extra["mixed_fwd_graph_env_steps_per_s"] = len(types) * Tm / (ms_mg / 1e3)
     # single steps, launched one by one vs replayed from a captured graph
     ms_ms = time_calls(lambda: msys.step(m0, macts[0], out=mout), 50, 5)
@@ -222,6 +247,7 @@ def main():
         "fused_fwd_env_steps_per_s": fused,
         "plain_fwd_env_steps_per_s": plain,
         "fused_over_plain": fused / plain,
+        "plain_fwd_graph_env_steps_per_s": plain_g,
         "fwd_vjp_env_steps_per_s": fwd_vjp,
         "fwd_vjp_workload": f"quadruped {wd.envs} environments x {wd.steps} steps, checkpoints every 10 steps",
         **extra,
@@ -233,8 +259,8 @@ def main():
                                   f"{achieved / PEAK_FP32_PACKED:.4f}"},
     }
     if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(s0, acts, system)
-        log(f"cpu baseline: {result['cpu_baseline']}")
+        result["cpu_baseline"], result["cpu_baseline_1core"] = cpu_baseline(s0, acts, system)
+        log(f"cpu baseline: {result['cpu_baseline']}; one core: {result['cpu_baseline_1core']}")
     print(json.dumps(result), flush=True)
 
 

@@ -63,6 +63,7 @@ class _OrcSys(C.Structure):
         ("j_lo", C.c_double * 3 * MAXJ), ("j_hi", C.c_double * 3 * MAXJ),
         ("a_joint", C.c_int32 * MAXA), ("a_axis", C.c_int32 * MAXA),
         ("a_gear", C.c_double * MAXA),
+        ("a_mode", C.c_int32 * MAXA),
     ]
 
 

@@ -68,6 +68,7 @@ struct OrcSys {
   double j_lo[MAXJ][3], j_hi[MAXJ][3];               // radians
   int32_t a_joint[MAXA], a_axis[MAXA];               // action k drives joint a_joint[k], axis a_axis[k]
   double a_gear[MAXA];
+  int32_t a_mode[MAXA];                              // 0 torque, 1 target angle
 };
 
 // ------------------------------------------------------------ small vectors
@@ -284,14 +285,18 @@ void joint_apply(const OrcSys& s, int j, const Body<T>* B, const Derived<T>* D, 
   t[P] = sub(t[P], add(cross(rP, F), tau));
 }
 
-// Actuator update (Algorithm 1, actuator loop): torque gear * a about the
-// joint's Euler axis, on the child and opposite on the parent.
+// Actuator update (Algorithm 1, actuator loop; Section 3: actions are
+// torques or target angles), about the joint's Euler axis, on the child and
+// opposite on the parent: a torque actuator applies gear * a; a target-angle
+// actuator drives the angle towards a (radians, clamped to the joint's
+// range) with gear * (a - theta).
 template <class T>
 void actuator_apply(const OrcSys& s, int k, const T& a, const JointFrame<T>* frames, V3<T>* t) {
   const int j = s.a_joint[k];
   const int P = s.j_parent[j], C = s.j_child[j];
   const JointFrame<T>& fr = frames[j];
-  V3<T> tau = scale(T(s.a_gear[k]) * a, fr.axis[s.a_axis[k]]);
+  const T drive = s.a_mode[k] == 1 ? a - fr.th[s.a_axis[k]] : a;
+  V3<T> tau = scale(T(s.a_gear[k]) * drive, fr.axis[s.a_axis[k]]);
   t[C] = add(t[C], tau);
   t[P] = sub(t[P], tau);
 }
@@ -342,8 +347,14 @@ void step_env(const OrcSys& s, T* X, const T* act_in, Margins* mg) {
   const double h = s.dt / s.substeps;
   T a[MAXA];
   for (int k = 0; k < s.na; ++k) {
-    a[k] = clampv(act_in[k], -1.0, 1.0);
-    if (mg) mg->clip_gap = std::min(mg->clip_gap, std::fabs(1.0 - std::fabs(val(act_in[k]))));
+    // torque actions are clipped to [-1, 1], target angles to the joint's range
+    double lo = -1.0, hi = 1.0;
+    if (s.a_mode[k] == 1) {
+      lo = s.j_lo[s.a_joint[k]][s.a_axis[k]];
+      hi = s.j_hi[s.a_joint[k]][s.a_axis[k]];
+    }
+    a[k] = clampv(act_in[k], lo, hi);
+    if (mg) mg->clip_gap = std::min(mg->clip_gap, std::min(std::fabs(val(act_in[k]) - lo), std::fabs(val(act_in[k]) - hi)));
   }
   Body<T> B[MAXB];
   Derived<T> D[MAXB];

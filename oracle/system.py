@@ -333,15 +333,21 @@ class System:
                 x = parent_of[x]
         self.parent_of = parent_of
 
-        self.actions = []  # (joint, axis, gear)
+        # (joint, axis, gear, mode): mode 0 = torque gear * clip(a, -1, 1);
+        # mode 1 = target angle: gear * (clamp(a, lo, hi) - theta), a in radians
+        self.actions = []
         for am in cfg.get("actuators", []):
             jn = _one(am, "joint")
             if jn not in jnames:
                 raise ValueError(f"actuator on unknown joint {jn}")
             j = jnames[jn]
             gear = float(_one(am, "strength", 0.0))
+            kinds = [k for k in ("torque", "angle") if k in am]
+            if len(kinds) > 1:
+                raise ValueError(f"actuator {jn}: both torque and angle")
+            mode = 1 if kinds == ["angle"] else 0
             for ax in range(self.joints[j]["dof"]):
-                self.actions.append((j, ax, gear))
+                self.actions.append((j, ax, gear, mode))
         self.na = len(self.actions)
         if self.na > MAXA:
             raise ValueError("too many actions")
@@ -458,4 +464,5 @@ class System:
         f["a_joint"] = [a[0] for a in self.actions]
         f["a_axis"] = [a[1] for a in self.actions]
         f["a_gear"] = [a[2] for a in self.actions]
+        f["a_mode"] = [a[3] for a in self.actions]
         return f

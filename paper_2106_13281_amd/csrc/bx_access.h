@@ -54,8 +54,26 @@ __device__ __forceinline__ void zero_body(const Fields& f, int b, int e, int Bm,
   store_body(f, 0, z, b, e, Bm, E);
 }
 
-__device__ __forceinline__ float act_of(const float* act, int a, int e, int E) {
-  return a >= 0 ? clampf(act[(size_t)a * E + e], -1.f, 1.f) : 0.f;
+// Blocks are dispatched round-robin over the 8 XCDs (each with its own L2):
+// block b runs on XCD b % 8. Wavefronts of neighbouring environments share
+// cache lines of the environment-fastest arrays (actions, state), so the
+// block index is permuted to give each XCD one contiguous range of work
+// items; the map is a bijection on [0, n) whatever the dispatch order is.
+__device__ __forceinline__ int xcd_block(int b, int n) {
+  constexpr int NXCD = 8;
+  const int q = n / NXCD, r = n % NXCD, x = b % NXCD;
+  return x * q + (x < r ? x : r) + b / NXCD;
+}
+
+// Action of joint axis x, clipped to its range ([-1, 1] for a torque,
+// the joint's range for a target angle); 0 for an axis without actuator.
+__device__ __forceinline__ float act_of(const float* act, const JointT& J, int x, int e, int E) {
+  return J.act[x] >= 0 ? clampf(act[(size_t)J.act[x] * E + e], J.act_lo[x], J.act_hi[x]) : 0.f;
+}
+// The same action unclipped (0 for an axis without actuator), for loads
+// issued ahead of their use.
+__device__ __forceinline__ float act_raw(const float* act, const JointT& J, int x, int e, int E) {
+  return J.act[x] >= 0 ? act[(size_t)J.act[x] * E + e] : 0.f;
 }
 
 // Forward tape of one substep, [TAPE_N][Bmax][E]: the body's state before the

@@ -364,7 +364,7 @@ BXF void spring_adj_core(const JointT& J, const Body& P, const Body& C, const Jo
   cross_adj(g.rP, F, -tpb, gb.rP, Fb);
   // limits: tau += -k_lim ex_k ax_k, ex = th - clamp(th)
   for (int k = 0; k < MAXDOF; ++k) {
-    if (k < J.dof) {
+    if (MAXDOF == 1 || k < J.dof) {
       float ex = g.th[k] - clampf(g.th[k], J.lo[k], J.hi[k]);
       gb.ax[k] += (-J.k_lim * ex) * taub;
       float exb = -J.k_lim * dot(g.ax[k], taub);
@@ -407,9 +407,11 @@ BXF void actuator_adj_core(const JointT& J, const JointGeo& g, const float* a, v
   v3 taub = tcb - tpb;
   for (int k = 0; k < 3; ++k) ab[k] = 0.f;
   for (int k = 0; k < MAXDOF; ++k) {
-    if (k < J.dof) {
-      gb.ax[k] += (J.gear[k] * a[k]) * taub;
+    if (MAXDOF == 1 || k < J.dof) {
+      // tau += gear (a - pd theta) ax
+      gb.ax[k] += (J.gear[k] * (a[k] - J.act_pd[k] * g.th[k])) * taub;
       ab[k] = J.gear[k] * dot(g.ax[k], taub);
+      gb.th[k] -= J.act_pd[k] * ab[k];
     }
   }
 }

@@ -47,6 +47,7 @@ struct JointD {
 struct ActD {
   int joint, axis;
   double gear;
+  int mode;  // 0 torque, 1 target angle
 };
 struct ContactD {
   int body;

@@ -166,7 +166,7 @@ __global__ void k_plain_joint(const Tables* __restrict__ tab, int t, const int32
   Body C = load_body(st, J.child, e, Bm, E);
   m3 RP = quat_to_mat(P.q), RC = quat_to_mat(C.q);
   float a[3];
-  for (int x = 0; x < 3; ++x) a[x] = act_of(act, J.act[x], e, E);
+  for (int x = 0; x < 3; ++x) a[x] = act_of(act, J, x, e, E);
   JointOut o = joint_eval<MAXDOF>(J, P, RP, C, RC, a);
   const int NJ = ty.nj;
   float vals[12] = {o.fc.x, o.fc.y, o.fc.z, o.tc.x, o.tc.y, o.tc.z, o.fp.x, o.fp.y, o.fp.z, o.tp.x, o.tp.y, o.tp.z};
@@ -288,11 +288,16 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
   s.v = keep(s.v, B.free_p);
   s.w = keep(s.w, B.free_r);
   int n_save = 0;
+  // actions acts[step][Am][E], held over the substeps of a step; each step's
+  // are loaded one step ahead so that the loads' latency is hidden
+  float raw_next[3] = {0.f, 0.f, 0.f};
+  if (has_joint && T > 0)
+    for (int x = 0; x < MAXDOF; ++x) raw_next[x] = act_raw(acts, J, x, e, E);
   for (int step = 0; step < T; ++step) {
-    // actions of this step: acts[step][Am][E], held over the substeps
     float a[3] = {0.f, 0.f, 0.f};
-    if (has_joint)
-      for (int x = 0; x < MAXDOF; ++x) a[x] = act_of(acts + (size_t)step * Am * E, J.act[x], e, E);
+    for (int x = 0; x < MAXDOF; ++x) a[x] = clampf(raw_next[x], J.act_lo[x], J.act_hi[x]);
+    if (has_joint && step + 1 < T)
+      for (int x = 0; x < MAXDOF; ++x) raw_next[x] = act_raw(acts + (size_t)(step + 1) * Am * E, J, x, e, E);
     for (int sub = 0; sub < ty.substeps; ++sub) {
       kinematic_unmasked(s, h);
       // parent's post-kinematic state: the cross-lane reads are issued first
@@ -375,7 +380,7 @@ __global__ __launch_bounds__(256) void k_fused(const Tables* __restrict__ tab, c
                                                const int32_t* __restrict__ type_off, int E, int Bm, Fields in,
                                                Fields out, const float* __restrict__ acts, int Am, int T,
                                                int save_every, Fields traj, uint8_t* nonfinite) {
-  const int w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int w = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (w >= n_work) return;
   const WaveWork wk = work[w];
   // wave-uniform: joints of at most one axis take the shorter path

@@ -442,14 +442,17 @@ int build_system(const char* text, SystemDesc& d, std::string& err) {
     std::set<int> actuated;
     for (const Val* av : top.all("actuators")) {
       View a = top.sub(av);
-      a.check({"name", "joint", "strength"});
+      a.check({"name", "joint", "strength", "torque", "angle"});
       std::string jn = a.str("joint");
       if (!jidx.count(jn)) throw MErr{"actuator '" + a.str("name") + "': unknown joint '" + jn + "'"};
       int j = jidx[jn];
       if (actuated.count(j)) throw MErr{"joint '" + jn + "' has two actuators"};
       actuated.insert(j);
       double gear = a.num("strength", 0);
-      for (int k = 0; k < d.joints[j].dof; ++k) d.actions.push_back(ActD{j, k, gear});
+      if (a.has("torque") && a.has("angle"))
+        throw MErr{"actuator '" + a.str("name") + "': both torque and angle"};
+      const int mode = a.has("angle") ? 1 : 0;
+      for (int k = 0; k < d.joints[j].dof; ++k) d.actions.push_back(ActD{j, k, gear, mode});
     }
     if ((int)d.actions.size() > MAXA) throw MErr{"more than 48 actions"};
 
@@ -571,6 +574,9 @@ void pack_type(const SystemDesc& d, Tables& tab, int t) {
       J.hi[k] = (float)S.hi[k];
       J.act[k] = -1;
       J.gear[k] = 0.f;
+      J.act_lo[k] = -1.f;
+      J.act_hi[k] = 1.f;
+      J.act_pd[k] = 0.f;
       double def = (k < S.dof && !(S.lo[k] <= 0.0 && 0.0 <= S.hi[k])) ? 0.5 * (S.lo[k] + S.hi[k]) : 0.0;
       J.def_angle[k] = (float)def;
     }
@@ -587,8 +593,14 @@ void pack_type(const SystemDesc& d, Tables& tab, int t) {
   }
   for (int a = 0; a < ty.na; ++a) {
     JointT& J = tab.joint[t][d.actions[a].joint];
-    J.act[d.actions[a].axis] = a;
-    J.gear[d.actions[a].axis] = (float)d.actions[a].gear;
+    const int k = d.actions[a].axis;
+    J.act[k] = a;
+    J.gear[k] = (float)d.actions[a].gear;
+    if (d.actions[a].mode == 1) {  // target angle: clamped to the joint's range, drives theta towards it
+      J.act_lo[k] = J.lo[k];
+      J.act_hi[k] = J.hi[k];
+      J.act_pd[k] = 1.f;
+    }
   }
   // parent-before-child order
   int n = 0;

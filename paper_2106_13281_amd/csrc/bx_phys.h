@@ -273,7 +273,7 @@ BXF v3 joint_spring(const JointT& J, const Body& P, const Body& C, const JointGe
     tau = V(0.f, 0.f, 0.f);
   tau += J.c_ang * (P.w - C.w);
   for (int k = 0; k < MAXDOF; ++k)
-    if (k < J.dof) tau += (-J.k_lim * (g.th[k] - clampf(g.th[k], J.lo[k], J.hi[k]))) * g.ax[k];
+    if (MAXDOF == 1 || k < J.dof) tau += (-J.k_lim * (g.th[k] - clampf(g.th[k], J.lo[k], J.hi[k]))) * g.ax[k];
   return tau;
 }
 template <int MAXDOF>
@@ -281,13 +281,14 @@ BXF v3 joint_spring(const JointT& J, const Body& P, const Body& C, const JointGe
   return joint_spring<MAXDOF>(J, P, C, g, C.v + cross(C.w, g.rC), F);
 }
 
-// Actuators of a joint (Algorithm 1, actuator loop): torque gear_k a_k about
-// Euler axis k, on the child (and its opposite on the parent).
+// Actuators of a joint (Algorithm 1, actuator loop): about Euler axis k, on
+// the child (and its opposite on the parent), a torque gear_k a_k, or for a
+// target-angle actuator gear_k (a_k - theta_k); act_pd selects the second.
 template <int MAXDOF>
 BXF v3 joint_actuator(const JointT& J, const JointGeo& g, const float* a) {
   v3 tau = V(0.f, 0.f, 0.f);
   for (int k = 0; k < MAXDOF; ++k)
-    if (k < J.dof) tau += (J.gear[k] * a[k]) * g.ax[k];
+    if (MAXDOF == 1 || k < J.dof) tau += (J.gear[k] * (a[k] - J.act_pd[k] * g.th[k])) * g.ax[k];
   return tau;
 }
 

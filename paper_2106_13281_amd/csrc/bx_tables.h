@@ -53,6 +53,8 @@ struct JointT {
   float lo[3], hi[3];      // angle limits (rad)
   float gear[3];           // actuator strength per axis (0 = not actuated)
   int32_t act[3];          // action index per axis (-1 = not actuated)
+  float act_lo[3], act_hi[3];  // action clip range: [-1, 1] (torque) or the joint's range (target angle)
+  float act_pd[3];         // 1 for a target-angle actuator (torque gear (a - theta)), 0 for torque (gear a)
   float def_angle[3];      // reset angle per axis
 };
 

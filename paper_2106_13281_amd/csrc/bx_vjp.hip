@@ -167,14 +167,14 @@ __global__ void k_adj_actuator(const Tables* __restrict__ tab, int t, const int3
   float a[3], raw[3], ab[3];
   for (int x = 0; x < 3; ++x) {
     raw[x] = J.act[x] >= 0 ? act[(size_t)J.act[x] * E + e] : 0.f;
-    a[x] = clampf(raw[x], -1.f, 1.f);
+    a[x] = clampf(raw[x], J.act_lo[x], J.act_hi[x]);
   }
   Bar bP = bar_zero(), bC = bar_zero();
   joint_actuator_adj<MAXDOF>(J, P, RP, C, RC, a, tcb, tpb, bP, bC, ab);
   slot_store_bar(abar, 0, ty.nj, j, n, k, bP);
   slot_store_bar(abar, 13, ty.nj, j, n, k, bC);
   for (int x = 0; x < MAXDOF; ++x)
-    if (x < J.dof && J.act[x] >= 0 && raw[x] >= -1.f && raw[x] <= 1.f) g_act[(size_t)J.act[x] * E + e] += ab[x];
+    if (x < J.dof && J.act[x] >= 0 && raw[x] >= J.act_lo[x] && raw[x] <= J.act_hi[x]) g_act[(size_t)J.act[x] * E + e] += ab[x];
 }
 
 // Contact phase adjoint: slot c holds the body bar (zero when no impulse).
@@ -281,7 +281,7 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
   if (has_joint)
     for (int x = 0; x < MAXDOF; ++x) {
       raw[x] = J.act[x] >= 0 ? act[(size_t)J.act[x] * E + e] : 0.f;
-      a[x] = clampf(raw[x], -1.f, 1.f);
+      a[x] = clampf(raw[x], J.act_lo[x], J.act_hi[x]);
     }
 
   // forward substeps with their tape in LDS
@@ -415,7 +415,7 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
     if (has_joint)
       for (int x = 0; x < MAXDOF; ++x)
         if (x < J.dof && J.act[x] >= 0)
-          g_act[(size_t)J.act[x] * E + e] = (raw[x] >= -1.f && raw[x] <= 1.f) ? ga[x] : 0.f;
+          g_act[(size_t)J.act[x] * E + e] = (raw[x] >= J.act_lo[x] && raw[x] <= J.act_hi[x]) ? ga[x] : 0.f;
     if (b == 0)
       for (int x = ty.na; x < Am; ++x) g_act[(size_t)x * E + e] = 0.f;
   }
@@ -427,7 +427,7 @@ __global__ __launch_bounds__(64) void k_fused_vjp(const Tables* __restrict__ tab
                                                   int smax, Fields in, const float* __restrict__ act, Fields g_out,
                                                   Fields g_in, float* __restrict__ g_act) {
   extern __shared__ float lds_tape[];
-  const int w = blockIdx.x;
+  const int w = xcd_block(blockIdx.x, gridDim.x);
   if (w >= n_work) return;
   const WaveWork wk = work[w];
   float* lds = lds_tape;

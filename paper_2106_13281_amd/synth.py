@@ -39,14 +39,17 @@ class Workload:
     root_noise: float       # root x, y ~ U(-x, x); drop height ~ U(0, x) m
 
 
-# The five workload shapes (small chain, quadruped, biped, differentiation,
-# mixed batch). Sizes: environments x steps.
+# The workload shapes (small chain, quadruped, biped, differentiation,
+# manipulator, planar runner; the mixed batch below). Sizes: environments x
+# steps.
 WORKLOADS = {
     "chain": Workload("chain", 64, 200, 1.0, 0.2, 0.0),
     "quadruped": Workload("quadruped", 4096, 1000, 1.0, 0.1, 0.1),
     "biped": Workload("biped", 2048, 1000, 0.4, 0.1, 0.0),
     "quadruped_diff": Workload("quadruped", 1024, 100, 1.0, 0.1, 0.1),
     "manipulator": Workload("manipulator", 819, 1000, 1.0, 0.1, 0.0),
+    # planar runner with target-angle actuators: actions are joint angles (rad)
+    "cheetah": Workload("cheetah", 2048, 1000, 0.6, 0.1, 0.1),
 }
 
 # Mixed batch: 8192 environments, 25% chains, 40% quadrupeds, 25% bipeds,

@@ -13,7 +13,8 @@ from paper_2106_13281_amd import braxmi, synth
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "braxmi.h")
-SYSTEMS = ("chain", "quadruped", "biped", "manipulator")
+SYSTEMS = ("chain", "quadruped", "biped", "manipulator", "cheetah")
+MIXED = synth.MIXED_TYPES      # the four types of the mixed batch
 
 
 def declared_functions():
@@ -53,7 +54,7 @@ def test_library_and_oracle_parsers_agree(name):
 
 
 def test_mixed_batch_layout():
-    descs = [synth.system_text(n) for n in SYSTEMS]
+    descs = [synth.system_text(n) for n in MIXED]
     env = synth.mixed_assignment(0)
     s = host(descs, len(env), env_desc=env)
     assert s.type_envs == list(synth.MIXED_COUNTS)

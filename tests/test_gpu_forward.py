@@ -14,7 +14,8 @@ from paper_2106_13281_amd import braxmi, synth
 from tests.helpers import ambiguous, make_states, rel_err
 
 pytestmark = pytest.mark.gpu
-SYSTEMS = ("chain", "quadruped", "biped", "manipulator")
+SYSTEMS = ("chain", "quadruped", "biped", "manipulator", "cheetah")
+MIXED = synth.MIXED_TYPES      # the four types of the mixed batch
 STEP_TOL, ROLL_TOL = 1e-4, 1e-3
 STEP_AMB, ROLL_AMB = 1e-6, 1e-5
 
@@ -208,13 +209,13 @@ def test_padded_bodies_written_as_zero():
 def test_mixed_batch_equals_homogeneous_runs():
     """One launch over interleaved system types gives, bit for bit, what each
     type gives on its own (same per-lane arithmetic, independent environments)."""
-    descs = [synth.system_text(n) for n in SYSTEMS]
-    per = {n: make_states(n, 9, seed=19, warm=5) for n in SYSTEMS}
+    descs = [synth.system_text(n) for n in MIXED]
+    per = {n: make_states(n, 9, seed=19, warm=5) for n in MIXED}
     env = list(np.random.default_rng(20).permutation([k % 4 for k in range(36)]))
     bm, am = 11, 17
     Xmix = np.zeros((36, bm, 13))
     amix = np.zeros((4, 36, am), np.float32)
-    for t, n in enumerate(SYSTEMS):
+    for t, n in enumerate(MIXED):
         o, X, acts = per[n]
         idx = [i for i in range(36) if env[i] == t]
         Xmix[idx, :o.nb] = X
@@ -223,7 +224,7 @@ def test_mixed_batch_equals_homogeneous_runs():
     for flags in (braxmi.BRAX_FUSED, braxmi.BRAX_FUSED | braxmi.BRAX_GRAPH, braxmi.BRAX_PLAIN):
         out, _ = mixed.rollout(to_dev(Xmix, bm), acts_dev(amix, am), flags=flags)
         Xg = from_dev(out, bm)
-        for t, n in enumerate(SYSTEMS):
+        for t, n in enumerate(MIXED):
             o, X, acts = per[n]
             one = braxmi.System(descs[t], 9)
             ref, _ = one.rollout(to_dev(X), acts_dev(acts[:4]), flags=flags & braxmi.BRAX_PLAIN)

@@ -13,7 +13,8 @@ from paper_2106_13281_amd import braxmi, synth
 from tests.helpers import make_states
 
 pytestmark = pytest.mark.gpu
-SYSTEMS = ("chain", "quadruped", "biped", "manipulator")
+SYSTEMS = ("chain", "quadruped", "biped", "manipulator", "cheetah")
+MIXED = synth.MIXED_TYPES      # the four types of the mixed batch
 GRAD_TOL = 1e-3
 
 
@@ -195,8 +196,8 @@ def test_rollout_gradient_differentiation_workload():
 
 
 def test_mixed_batch_vjp_equals_homogeneous():
-    descs = [synth.system_text(n) for n in SYSTEMS]
-    per = {n: make_states(n, 6, seed=17, warm=5) for n in SYSTEMS}
+    descs = [synth.system_text(n) for n in MIXED]
+    per = {n: make_states(n, 6, seed=17, warm=5) for n in MIXED}
     env = [k % 4 for k in range(24)]
     bm = 11
     am = 17
@@ -205,7 +206,7 @@ def test_mixed_batch_vjp_equals_homogeneous():
     gmix = np.zeros((24, bm, 13))
     rng = np.random.default_rng(18)
     gs = {}
-    for t, n in enumerate(SYSTEMS):
+    for t, n in enumerate(MIXED):
         o, X, acts = per[n]
         gs[n] = rng.normal(size=X.shape)
         idx = [i for i in range(24) if env[i] == t]
@@ -217,7 +218,7 @@ def test_mixed_batch_vjp_equals_homogeneous():
     gi, ga = mixed.step_vjp(to_dev(Xmix, bm), acts_dev(amix, am)[0].contiguous(), to_dev(gmix, bm))
     gim = from_dev(gi, bm)
     gam = ga.cpu().numpy().T
-    for t, n in enumerate(SYSTEMS):
+    for t, n in enumerate(MIXED):
         o, X, acts = per[n]
         one = braxmi.System(descs[t], 6)
         g1, a1 = one.step_vjp(to_dev(X), acts_dev(acts[:1])[0].contiguous(), to_dev(gs[n]))

@@ -413,6 +413,68 @@ actuators {{ name: "j" joint: "j" strength: {gear} }}
     assert abs(th[0, 0] - (math.radians(30) + gear * a / k_lim)) < 1e-9
 
 
+# ------------------------------------------------------------ target-angle actuator
+ANGLE_HINGE = """substeps: {S}
+dt: {dt}
+bodies {{ name: "p" mass: 1 inertia {{ x: 1 y: 1 z: 1 }} frozen {{ position {{ x: 1 y: 1 z: 1 }} rotation {{ x: 1 y: 1 z: 1 }} }} }}
+bodies {{ name: "c" mass: 1 inertia {{ x: {I} y: {I} z: {I} }} }}
+joints {{
+  name: "j" parent: "p" child: "c" stiffness: 5000 damping: 0
+  angular_stiffness: 300 angular_damping: 0 limit_stiffness: 1000
+  angle_limit {{ min: -50 max: 40 }}
+}}
+actuators {{ name: "j" joint: "j" strength: {gear} angle {{}} }}
+"""
+
+
+@pytest.mark.parametrize("target", [0.3, -0.6, 1.2])
+def test_target_angle_actuator_discrete_oscillator(target):
+    """A child centred on a hinge about the frozen parent's x axis, no gravity,
+    no damping: only the actuator and the limit spring act about the axis, so
+    per substep theta <- theta + 2 atan(h w / 2) (the quaternion update's exact
+    rotation) and w <- w + h / I (gear (clamp(target, lo, hi) - theta)
+    - k_lim (theta - clamp(theta, lo, hi))). A target beyond the 40 degree
+    limit is clamped to it."""
+    S, dt, I, gear = 4, 0.01, 0.05, 3.0
+    o = oracle.Oracle(ANGLE_HINGE.format(S=S, dt=dt, I=I, gear=gear))
+    X = o.default_qp()[None]
+    T = 150
+    _, tr, _ = o.rollout(X, np.full((T, 1, 1), target), traj=True)
+    lo, hi, k_lim = math.radians(-50), math.radians(40), 1000.0
+    ts = min(max(target, lo), hi)
+    h = dt / S
+    th, w = 0.0, 0.0
+    for t in range(T):
+        for _ in range(S):
+            th += 2 * math.atan(h * w / 2)
+            w += h / I * (gear * (ts - th) - k_lim * (th - min(max(th, lo), hi)))
+        ang, _ = o.joint_angles(tr[t])
+        assert abs(ang[0, 0] - th) < 1e-11, t
+        assert abs(tr[t, 0, 1, 10] - w) < 1e-10 and abs(tr[t, 0, 1, 11]) < 1e-12 and abs(tr[t, 0, 1, 12]) < 1e-12
+
+
+def test_planar_masking_keeps_motion_in_the_plane():
+    """Planar runner: every body has y translation and x, z rotation frozen
+    (world axes), so y, v_y, w_x, w_z stay exactly at their reset values and
+    the quaternions stay rotations about y (q_x = q_z = 0 up to the reset
+    pose's rounding) under joints,
+    target-angle actuators, gravity and contacts."""
+    wl = synth.WORKLOADS["cheetah"]
+    o = oracle.Oracle(synth.system_text("cheetah"))
+    s = o.system
+    E = 16
+    ang, root = synth.reset_noise(3, E, s.ndof, wl.angle_noise, wl.root_noise)
+    X = np.stack([o.default_qp(s.default_angles() + ang[e], root[e] * np.array([1.0, 0.0, 1.0])) for e in range(E)])
+    _, tr, _ = o.rollout(X, synth.actions(3, 300, E, s.na, wl.act_range), traj=True)
+    assert np.isfinite(tr).all()
+    assert np.abs(tr[..., 1] - X[None, ..., 1]).max() == 0
+    assert np.abs(tr[..., [8, 10, 12]]).max() == 0
+    # q_x, q_z start at the rounding level of the reset pose and stay there
+    assert np.abs(X[..., [4, 6]]).max() < 1e-16 and np.abs(tr[..., [4, 6]]).max() < 1e-15
+    assert np.abs(tr[..., [0, 2]] - X[None, ..., [0, 2]]).max() > 0.05       # it does move in the plane
+    assert np.abs(tr[..., 11]).max() > 1.0
+
+
 # ------------------------------------------------------------ P10 / P11 conservation
 def _astronaut(name, damping_off=True, isotropic=True):
     text = synth.system_text(name)
@@ -575,7 +637,7 @@ def test_default_pose_realises_joint_angles():
 
 
 # ------------------------------------------------------------ P13 adjoint
-@pytest.mark.parametrize("name", ["chain", "quadruped", "biped", "manipulator"])
+@pytest.mark.parametrize("name", ["chain", "quadruped", "biped", "manipulator", "cheetah"])
 def test_dual_jacobian_matches_central_differences(name):
     wl = synth.WORKLOADS[name]
     o = oracle.Oracle(synth.system_text(name))
@@ -611,7 +673,7 @@ def test_dual_jacobian_matches_central_differences(name):
 
 
 # ------------------------------------------------------------ stability + work
-@pytest.mark.parametrize("name", ["chain", "quadruped", "biped", "manipulator"])
+@pytest.mark.parametrize("name", ["chain", "quadruped", "biped", "manipulator", "cheetah"])
 def test_workloads_stay_finite_and_joints_hold(name):
     wl = synth.WORKLOADS[name]
     o = oracle.Oracle(synth.system_text(name))
