@@ -10,8 +10,10 @@ roofline of the dominant kernel and the FP64 oracle timed on the host cores.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -35,6 +37,25 @@ def log(msg):
 def algorithmic_flops(name):
     with open(os.path.join(ROOT, "tests", "golden", "algorithmic_flops.json")) as f:
         return json.load(f)["workloads"][name]["mean"]
+
+
+def measured_traffic():
+    """HBM bytes per k_fused launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a 256 MiB copy), or None
+    when the kernel sources differ from the ones the counters were taken on."""
+    path = os.path.join(ROOT, "profiles", "k_fused_quadruped_4096x1000_counters.md")
+    try:
+        with open(path) as f:
+            text = f.read()
+        want = re.search(r"kernel_source_sha256: ([0-9a-f]{64})", text).group(1)
+        nbytes = int(re.search(r"hbm_bytes_per_launch: (\d+)", text).group(1))
+    except (OSError, AttributeError):
+        return None
+    h = hashlib.sha256()
+    for name in ("bx_kernels.hip", "bx_phys.h", "bx_access.h", "bx_tables.h", "bx_internal.h"):
+        with open(os.path.join(ROOT, "paper_2106_13281_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return nbytes if h.hexdigest() == want else None
 
 
 def make_inputs(system, wl, seed=0):
@@ -252,7 +273,7 @@ def main():
         "fwd_vjp_workload": f"quadruped {wd.envs} environments x {wd.steps} steps, checkpoints every 10 steps",
         **extra,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
                      "kernel": "k_fused", "flop_per_env_step": fpe,
                      "peak_note": "FP32 FMA issue rate without packed FP32 (disabled at build); "
                                   f"frac vs the packed {PEAK_FP32_PACKED} TFLOP/s = "

@@ -154,6 +154,25 @@ int brax_step_vjp(const brax_sys* sys, const brax_state* in, const float* act, c
 int brax_rollout(const brax_sys* sys, const brax_state* in, const float* acts, int32_t T, int32_t save_every,
                  brax_state* traj, brax_state* out, int32_t flags, void* stream);
 
+/* brax_rollout (save_every 0) that also records what the adjoint needs of
+ * every substep (Sections 3 and 5.1.4: the backward pass through the steps
+ * of Algorithm 1): tape, device, caller-owned, T * Smax * 17 * Bmax * E
+ * floats laid out [T][Smax][17][Bmax][E], Smax = the largest substep count of
+ * the batch's systems; per body and substep: the state before the kinematic
+ * update (pos 3, rot 4, vel 3, ang 3), the total joint and actuator torque
+ * (3) and the number of contacts that applied an impulse (1). Substeps beyond
+ * a system's own count are not written. Fused path only: BRAX_PLAIN gives
+ * BRAX_E_UNSUPPORTED. The state results equal brax_rollout's. */
+int brax_rollout_tape(const brax_sys* sys, const brax_state* in, const float* acts, int32_t T, float* tape,
+                      brax_state* out, int32_t flags, void* stream);
+
+/* Adjoint of one step from its tape (one [Smax][17][Bmax][E] slice written
+ * by brax_rollout_tape for that step, with the same actions) instead of
+ * recomputing the forward substeps: same outputs and kink conventions as
+ * brax_step_vjp. g_in may not alias g_out. Fused path only. */
+int brax_step_vjp_tape(const brax_sys* sys, const float* tape, const float* act, const brax_state* g_out,
+                       brax_state* g_in, float* g_act, int32_t flags, void* stream);
+
 /* Time the fused kernel's launch shapes on `stream` and keep the fastest
  * for later calls (the result does not depend on the shape). */
 int brax_autotune(brax_sys* sys, void* stream);

@@ -48,8 +48,9 @@ class _Layout(C.Structure):
 
 
 EXPORTS = ("brax_sys_create", "brax_sys_destroy", "brax_sys_query", "brax_default_angles", "brax_default_qp",
-           "brax_step", "brax_step_vjp", "brax_rollout", "brax_autotune", "brax_schedule", "brax_set_schedule",
-           "brax_nonfinite", "brax_last_error")
+           "brax_step", "brax_step_vjp", "brax_rollout", "brax_rollout_tape", "brax_step_vjp_tape", "brax_autotune",
+           "brax_schedule", "brax_set_schedule", "brax_nonfinite", "brax_last_error")
+TAPE_N = 17  # floats per body per substep in a forward tape
 
 _lib = None
 
@@ -74,6 +75,10 @@ def lib():
                                     C.c_void_p]
         L.brax_rollout.argtypes = [C.c_void_p, P(_State), C.c_void_p, C.c_int32, C.c_int32, P(_State), P(_State),
                                    C.c_int32, C.c_void_p]
+        L.brax_rollout_tape.argtypes = [C.c_void_p, P(_State), C.c_void_p, C.c_int32, C.c_void_p, P(_State),
+                                        C.c_int32, C.c_void_p]
+        L.brax_step_vjp_tape.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, P(_State), P(_State), C.c_void_p,
+                                         C.c_int32, C.c_void_p]
         L.brax_autotune.argtypes = [C.c_void_p, C.c_void_p]
         L.brax_schedule.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32)]
         L.brax_set_schedule.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
@@ -166,6 +171,7 @@ class System:
         self.n_dof = list(lay.n_dof[:nt])
         self.n_contacts = list(lay.n_contacts[:nt])
         self.substeps = list(lay.substeps[:nt])
+        self.s_max = max(self.substeps) if self.substeps else 1   # tape stride (substeps per step)
         self.dt = list(lay.dt[:nt])
         self.device = torch.device("cuda", device) if device >= 0 else None
 
@@ -235,6 +241,36 @@ class System:
                                   C.byref(tr) if tr is not None else None, C.byref(so), flags, _stream(stream)))
         return out, (traj if n_save else None)
 
+    def rollout_tape(self, state, acts, tape=None, out=None, flags=0, stream=None):
+        """rollout that also writes the forward tape [T][Smax][17][Bmax][E] for step_vjp_tape."""
+        T = acts.shape[0] if acts is not None else 0
+        out = self.new_state() if out is None else out
+        if T:
+            acts = self._act(acts, (T, self.a_max, self.n_envs))
+        shape = (T, self.s_max, TAPE_N, self.b_max, self.n_envs)
+        if tape is None:
+            tape = torch.empty(shape, dtype=torch.float32, device=self.device)
+        if tuple(tape.shape) != shape or tape.dtype != torch.float32 or not tape.is_contiguous():
+            raise ValueError(f"tape must be a contiguous float32 tensor of shape {shape}")
+        si, so = state.struct(), out.struct()
+        _check(lib().brax_rollout_tape(self._h, C.byref(si), _ptr(acts) if T else None, T, _ptr(tape) if T else None,
+                                       C.byref(so), flags, _stream(stream)))
+        return out, tape
+
+    def step_vjp_tape(self, tape, act, g_out, g_in=None, g_act=None, flags=0, stream=None):
+        """step_vjp from one step's tape slice [Smax][17][Bmax][E] instead of recomputing the step."""
+        shape = (self.s_max, TAPE_N, self.b_max, self.n_envs)
+        if tuple(tape.shape) != shape or tape.dtype != torch.float32 or not tape.is_contiguous():
+            raise ValueError(f"tape must be a contiguous float32 tensor of shape {shape}")
+        g_in = self.new_state() if g_in is None else g_in
+        act = self._act(act, (self.a_max, self.n_envs))
+        if g_act is None:
+            g_act = torch.empty(self.a_max, self.n_envs, dtype=torch.float32, device=self.device)
+        sg, sgi = g_out.struct(), g_in.struct()
+        _check(lib().brax_step_vjp_tape(self._h, _ptr(tape), _ptr(act), C.byref(sg), C.byref(sgi), _ptr(g_act),
+                                        flags, _stream(stream)))
+        return g_in, g_act
+
     def autotune(self, stream=None):
         _check(lib().brax_autotune(self._h, _stream(stream)))
         return self.schedule()
@@ -259,13 +295,17 @@ class RolloutFn(torch.autograd.Function):
     """Differentiable T-step rollout (final state) with checkpoints every k steps.
 
     Forward keeps the state every k steps. Backward recomputes each segment
-    from its checkpoint (brax_rollout) and runs brax_step_vjp backwards
-    through it. Inputs: the four initial-state tensors and the action
-    sequence [T][Amax][E]; outputs: the four final-state tensors.
+    from its checkpoint and runs the step adjoint backwards through it: with
+    tape=True the recompute writes every substep's tape (brax_rollout_tape,
+    one segment at a time) and the adjoint reads it (brax_step_vjp_tape);
+    with tape=False the recompute keeps the step states (brax_rollout) and
+    brax_step_vjp recomputes each step's substeps itself. Inputs: the four
+    initial-state tensors and the action sequence [T][Amax][E]; outputs: the
+    four final-state tensors.
     """
 
     @staticmethod
-    def forward(ctx, system, k, pos, rot, vel, ang, acts):
+    def forward(ctx, system, k, tape, pos, rot, vel, ang, acts):
         T = acts.shape[0]
         k = max(1, min(int(k), max(T, 1)))
         s0 = State(pos.detach().contiguous(), rot.detach().contiguous(), vel.detach().contiguous(),
@@ -280,13 +320,13 @@ class RolloutFn(torch.autograd.Function):
             ckpts.append(nxt)
             cur = nxt
             t += n
-        ctx.system, ctx.k, ctx.T = system, k, T
+        ctx.system, ctx.k, ctx.T, ctx.tape = system, k, T, bool(tape)
         ctx.save_for_backward(acts_d, *[x for c in ckpts[:-1] for x in c.fields()])
         return cur.pos, cur.rot, cur.vel, cur.ang
 
     @staticmethod
     def backward(ctx, gp, gr, gv, gw):
-        system, k, T = ctx.system, ctx.k, ctx.T
+        system, k, T, use_tape = ctx.system, ctx.k, ctx.T, ctx.tape
         saved = ctx.saved_tensors
         acts = saved[0]
         ck = [State(*saved[1 + 4 * i: 5 + 4 * i]) for i in range((len(saved) - 1) // 4)]
@@ -297,9 +337,20 @@ class RolloutFn(torch.autograd.Function):
         g = State(z(gp, ck[0].pos), z(gr, ck[0].rot), z(gv, ck[0].vel), z(gw, ck[0].ang))
         g_acts = torch.zeros_like(acts)
         seg_starts = list(range(0, T, k))
+        tape = None
         for si in reversed(range(len(seg_starts))):
             t0 = seg_starts[si]
             n = min(k, T - t0)
+            if use_tape:
+                if tape is None or tape.shape[0] < n:
+                    tape = torch.empty((n, system.s_max, TAPE_N, system.b_max, system.n_envs), dtype=torch.float32,
+                                       device=acts.device)
+                system.rollout_tape(ck[si], acts[t0:t0 + n], tape=tape[:n])
+                for i in reversed(range(n)):
+                    g_in, g_a = system.step_vjp_tape(tape[i], acts[t0 + i], g)
+                    g_acts[t0 + i] = g_a
+                    g = g_in
+                continue
             # states s_{t0}, ..., s_{t0+n-1}
             states = [ck[si]]
             if n > 1:
@@ -309,14 +360,14 @@ class RolloutFn(torch.autograd.Function):
                 g_in, g_a = system.step_vjp(_contig(states[i]), acts[t0 + i], g)
                 g_acts[t0 + i] = g_a
                 g = g_in
-        return None, None, g.pos, g.rot, g.vel, g.ang, g_acts
+        return None, None, None, g.pos, g.rot, g.vel, g.ang, g_acts
 
 
 def _contig(s):
     return State(*(t.contiguous() for t in s.fields()))
 
 
-def rollout_grad(system, state, acts, k=10):
+def rollout_grad(system, state, acts, k=10, tape=True):
     """Apply RolloutFn: returns the final State, differentiable w.r.t. state and acts."""
-    p, r, v, w = RolloutFn.apply(system, k, state.pos, state.rot, state.vel, state.ang, acts)
+    p, r, v, w = RolloutFn.apply(system, k, tape, state.pos, state.rot, state.vel, state.ang, acts)
     return State(p, r, v, w)

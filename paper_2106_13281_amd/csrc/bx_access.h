@@ -55,14 +55,19 @@ __device__ __forceinline__ void zero_body(const Fields& f, int b, int e, int Bm,
 }
 
 // Blocks are dispatched round-robin over the 8 XCDs (each with its own L2):
-// block b runs on XCD b % 8. Wavefronts of neighbouring environments share
-// cache lines of the environment-fastest arrays (actions, state), so the
-// block index is permuted to give each XCD one contiguous range of work
-// items; the map is a bijection on [0, n) whatever the dispatch order is.
+// block b runs on XCD b % 8. Neighbouring work items (environments) share the
+// 128-byte lines of the environment-fastest arrays (actions, state), so the
+// block index is permuted in groups of 64 blocks: within a group, XCD x takes
+// the 8 consecutive items 8x..8x+7. Dispatch order (heaviest work first in a
+// mixed batch) is kept at the granularity of a group; a last partial group
+// gives each XCD one contiguous range. A bijection on [0, n) whatever the
+// dispatch order is.
 __device__ __forceinline__ int xcd_block(int b, int n) {
-  constexpr int NXCD = 8;
-  const int q = n / NXCD, r = n % NXCD, x = b % NXCD;
-  return x * q + (x < r ? x : r) + b / NXCD;
+  constexpr int NXCD = 8, RUN = 8, G = NXCD * RUN;
+  const int g0 = (b / G) * G, i = b - g0, m = n - g0 < G ? n - g0 : G;
+  if (m == G) return g0 + (i % NXCD) * RUN + i / NXCD;
+  const int q = m / NXCD, r = m % NXCD, x = i % NXCD;
+  return g0 + x * q + (x < r ? x : r) + i / NXCD;
 }
 
 // Action of joint axis x, clipped to its range ([-1, 1] for a torque,

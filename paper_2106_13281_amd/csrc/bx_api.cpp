@@ -55,7 +55,7 @@ struct DeviceGuard {
 }  // namespace
 
 struct GraphKey {
-  int kind;  // 0 step, 1 rollout
+  int kind;  // 0 step, 1 rollout, 2 adjoint, 3 rollout with tape, 4 adjoint from a tape
   int flags, T, save_every;
   const void* p[12];
   bool operator<(const GraphKey& o) const {
@@ -83,6 +83,11 @@ struct brax_sys {
   int waves_per_block = 1;
   std::vector<WaveWork> work;
   WaveWork* d_work = nullptr;
+  // adjoint schedule: full wavefronts (its launch holds a tape in LDS, so
+  // fewer wavefronts mean fewer rounds), fixed at creation
+  std::vector<WaveWork> vjp_work;
+  WaveWork* d_vjp_work = nullptr;
+  int smax = 1;  // largest substep count of the batch's types (tape stride)
   // plain scratch per type
   float* d_jslot[MAXT] = {nullptr};
   float* d_cslot[MAXT] = {nullptr};
@@ -126,6 +131,7 @@ void free_all(brax_sys* s) {
     (void)hipFree(s->d_env_list);
     (void)hipFree(s->d_type_off);
     (void)hipFree(s->d_work);
+    (void)hipFree(s->d_vjp_work);
     (void)hipFree(s->d_nonfinite);
     for (int t = 0; t < MAXT; ++t) {
       (void)hipFree(s->d_jslot[t]);
@@ -138,7 +144,7 @@ void free_all(brax_sys* s) {
 
 // Split every type's environments into wavefronts of envs_per_wave[t] and
 // order the wavefronts heaviest first (substeps x per-lane work estimate).
-void build_work(brax_sys* s) {
+std::vector<WaveWork> make_work(const brax_sys* s, const int* envs_per_wave) {
   struct Item {
     double cost;
     WaveWork w;
@@ -146,15 +152,18 @@ void build_work(brax_sys* s) {
   std::vector<Item> items;
   for (int t = 0; t < s->n_types; ++t) {
     const TypeT& ty = s->host_tab.type[t];
-    int epw = s->envs_per_wave[t];
+    int epw = envs_per_wave[t];
     double cost = ty.substeps * (150.0 + (ty.nj > 0 ? 250.0 * ty.max_dof : 0.0) + 130.0 * ty.max_contacts);
     for (int k0 = 0; k0 < s->type_cnt[t]; k0 += epw)
       items.push_back(Item{cost, WaveWork{t, k0, std::min(epw, s->type_cnt[t] - k0), 0}});
   }
   std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
-  s->work.clear();
-  for (auto& it : items) s->work.push_back(it.w);
+  std::vector<WaveWork> out;
+  for (auto& it : items) out.push_back(it.w);
+  return out;
 }
+
+void build_work(brax_sys* s) { s->work = make_work(s, s->envs_per_wave); }
 
 int upload_work(brax_sys* s) {
   (void)hipFree(s->d_work);
@@ -265,6 +274,7 @@ int brax_sys_create(const char* const* descs, int32_t n_descs, const int32_t* en
     for (int e = 0; e < n_envs; ++e) s->env_list[fill[s->env_type[e]]++] = e;
   }
   for (int t = 0; t < n_descs; ++t) s->envs_per_wave[t] = std::max(1, 64 / s->host_tab.type[t].nb);
+  for (int t = 0; t < n_descs; ++t) s->smax = std::max(s->smax, s->host_tab.type[t].substeps);
   s->waves_per_block = 1;
   build_work(s.get());
   if (device < 0) {
@@ -306,6 +316,16 @@ int brax_sys_create(const char* const* descs, int32_t n_descs, const int32_t* en
       return rc;
   }
   if ((rc = upload_work(s.get()))) return rc;
+  {
+    int full[MAXT];
+    for (int t = 0; t < n_descs; ++t) full[t] = std::max(1, 64 / s->host_tab.type[t].nb);
+    s->vjp_work = make_work(s.get(), full);
+    if (!s->vjp_work.empty()) {
+      if ((rc = dmalloc((void**)&s->d_vjp_work, sizeof(WaveWork) * s->vjp_work.size()))) return rc;
+      HIP_TRY(hipMemcpy(s->d_vjp_work, s->vjp_work.data(), sizeof(WaveWork) * s->vjp_work.size(),
+                        hipMemcpyHostToDevice));
+    }
+  }
   *out = s.release();
   return BRAX_OK;
 }
@@ -448,6 +468,41 @@ int brax_rollout(const brax_sys* sys, const brax_state* in, const float* acts, i
   });
 }
 
+int brax_rollout_tape(const brax_sys* sys, const brax_state* in, const float* acts, int32_t T, float* tape,
+                      brax_state* out, int32_t flags, void* stream) {
+  brax_sys* s = const_cast<brax_sys*>(sys);
+  if (!s) return fail(BRAX_E_ARG, "sys is NULL");
+  if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
+  if (T < 0) return fail(BRAX_E_ARG, "T must be >= 0");
+  if (flags & BRAX_PLAIN) return fail(BRAX_E_UNSUPPORTED, "the tape is written by the fused path only");
+  if (s->E == 0) return check_flags(flags);
+  if (!state_ok(in) || !state_ok(out)) return fail(BRAX_E_ARG, "state has a NULL field");
+  if (T > 0 && !acts && s->Am > 0) return fail(BRAX_E_ARG, "acts is NULL");
+  if (T > 0 && !tape) return fail(BRAX_E_ARG, "tape is NULL");
+  int rc = check_flags(flags);
+  if (rc) return rc;
+  DeviceGuard g(s->device);
+  hipStream_t st = (hipStream_t)stream;
+  const bool nf = flags & BRAX_NONFINITE_FLAGS;
+  GraphKey key{};
+  key.kind = 3;
+  key.flags = flags;
+  key.T = T;
+  const void* ptrs[] = {in->pos, in->rot, in->vel, in->ang, out->pos, out->rot, out->vel, out->ang, acts, tape};
+  std::memcpy(key.p, ptrs, sizeof ptrs);
+  return run_maybe_graph(s, flags & BRAX_GRAPH, key, st, [&](hipStream_t cs) -> int {
+    LaunchCtx c = s->ctx();
+    if (T == 0) {
+      if (in->pos != out->pos) HIP_TRY(launch_copy_state(c, F(in), F(out), cs));
+      if (nf) HIP_TRY(launch_fill_u8(s->d_nonfinite, s->E, 0, cs));
+      return BRAX_OK;
+    }
+    HIP_TRY(launch_fused(c, s->d_work, (int)s->work.size(), s->waves_per_block, F(in), F(out), acts, T, 0,
+                         Fields{nullptr, nullptr, nullptr, nullptr}, nf, cs, tape, s->smax));
+    return BRAX_OK;
+  });
+}
+
 int brax_nonfinite(const brax_sys* s, uint8_t* out) {
   if (!s || !out) return fail(BRAX_E_ARG, "NULL argument");
   if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
@@ -496,7 +551,7 @@ int brax_autotune(brax_sys* s, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   // scratch state and zero actions; timing runs use the reset pose
   const size_t n3 = (size_t)3 * s->Bm * s->E, n4 = (size_t)4 * s->Bm * s->E;
-  const int T = 2;
+  const int T = 8;
   float* buf = nullptr;
   size_t nbuf = 2 * (3 * n3 + n4) + (size_t)std::max(s->Am, 1) * s->E * T;
   HIP_TRY(hipMalloc(&buf, sizeof(float) * nbuf));
@@ -510,7 +565,20 @@ int brax_autotune(brax_sys* s, void* stream) {
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   int rc = BRAX_OK;
-  if (launch_default_qp(c, nullptr, nullptr, a, st) != hipSuccess) rc = fail(BRAX_E_DEVICE, "autotune reset failed");
+  // timing state: the reset pose after 32 steps of zero actions, so that the
+  // bodies have dropped onto the ground and contacts are active as in use
+  if (launch_default_qp(c, nullptr, nullptr, b, st) != hipSuccess ||
+      launch_fused(c, s->d_work, (int)s->work.size(), s->waves_per_block, b, a, acts, 1, 0, Fields{}, false, st) !=
+          hipSuccess)
+    rc = fail(BRAX_E_DEVICE, "autotune reset failed");
+  for (int k = 1; k < 32 && !rc; ++k)
+    if (launch_fused(c, s->d_work, (int)s->work.size(), s->waves_per_block, a, a, acts, 1, 0, Fields{}, false, st) !=
+        hipSuccess)
+      rc = fail(BRAX_E_DEVICE, "autotune reset failed");
+  int n_cu = 0;
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, s->device) != hipSuccess || n_cu <= 0)
+    n_cu = 256;
+  const int n_simd = 4 * n_cu;  // four SIMDs per compute unit
   // candidates: environments per wavefront (per type) and wavefronts per block
   const int wpb_c[] = {1, 2, 4};
   int best_epw[MAXT];
@@ -521,12 +589,15 @@ int brax_autotune(brax_sys* s, void* stream) {
   for (int wpb : wpb_c) {
     if (rc) break;
     for (int t = 0; t < s->n_types; ++t) {
+      // from a full wavefront down to half of one, at most 6 values evenly
+      // spaced, plus the value that gives about one wavefront per SIMD
       const int full = std::max(1, 64 / s->host_tab.type[t].nb);
+      const int low = std::max(1, full / 2);
       epw_c.clear();
-      for (int k = full; k >= 1 && (int)epw_c.size() < 4; k = (k * 3) / 4) {
-        epw_c.push_back(k);
-        if (k == 1) break;
-      }
+      const int span = full - low + 1, nc = std::min(span, 6);
+      for (int i = 0; i < nc; ++i) epw_c.push_back(full - (nc > 1 ? (i * (span - 1)) / (nc - 1) : 0));
+      const int fill = std::min(full, std::max(1, (s->type_cnt[t] + n_simd - 1) / n_simd));
+      if (std::find(epw_c.begin(), epw_c.end(), fill) == epw_c.end()) epw_c.push_back(fill);
       float best_t = 1e30f;
       for (int epw : epw_c) {
         // time this type alone with the others at their current best
@@ -619,8 +690,38 @@ int brax_step_vjp(const brax_sys* sys, const brax_state* in, const float* act, c
   std::memcpy(key.p, ptrs, sizeof ptrs);
   return run_maybe_graph(s, flags & BRAX_GRAPH, key, st, [&](hipStream_t cs) -> int {
     LaunchCtx c = s->ctx();
-    VjpSched sched{s->d_work, (int)s->work.size(), s->waves_per_block, s->d_jslot, s->d_cslot};
+    VjpSched sched{s->d_vjp_work, (int)s->vjp_work.size(), 1, s->d_jslot, s->d_cslot};
     HIP_TRY(launch_vjp(c, s->vjp, sched, F(in), act, F(g_out), F(g_in), g_act, (flags & BRAX_PLAIN) != 0, cs));
+    return BRAX_OK;
+  });
+}
+
+int brax_step_vjp_tape(const brax_sys* sys, const float* tape, const float* act, const brax_state* g_out,
+                       brax_state* g_in, float* g_act, int32_t flags, void* stream) {
+  brax_sys* s = const_cast<brax_sys*>(sys);
+  if (!s) return fail(BRAX_E_ARG, "sys is NULL");
+  if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
+  if (flags & BRAX_PLAIN) return fail(BRAX_E_UNSUPPORTED, "the tape adjoint runs on the fused path only");
+  if (s->E == 0) return check_flags(flags);
+  if (!tape) return fail(BRAX_E_ARG, "tape is NULL");
+  if (!state_ok(g_out) || !state_ok(g_in)) return fail(BRAX_E_ARG, "state has a NULL field");
+  if (!act && s->Am > 0) return fail(BRAX_E_ARG, "act is NULL");
+  if (!g_act && s->Am > 0) return fail(BRAX_E_ARG, "g_act is NULL");
+  if (g_in->pos == g_out->pos) return fail(BRAX_E_ARG, "g_in may not alias g_out");
+  int rc = check_flags(flags);
+  if (rc) return rc;
+  DeviceGuard g(s->device);
+  hipStream_t st = (hipStream_t)stream;
+  GraphKey key{};
+  key.kind = 4;
+  key.flags = flags;
+  key.T = 1;
+  const void* ptrs[] = {tape, act, g_out->pos, g_out->rot, g_out->vel, g_out->ang, g_in->pos, g_in->rot, g_act};
+  std::memcpy(key.p, ptrs, sizeof ptrs);
+  return run_maybe_graph(s, flags & BRAX_GRAPH, key, st, [&](hipStream_t cs) -> int {
+    LaunchCtx c = s->ctx();
+    VjpSched sched{s->d_vjp_work, (int)s->vjp_work.size(), 1, s->d_jslot, s->d_cslot};
+    HIP_TRY(launch_vjp_tape(c, sched, tape, act, F(g_out), F(g_in), g_act, cs));
     return BRAX_OK;
   });
 }

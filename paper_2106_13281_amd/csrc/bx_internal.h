@@ -87,8 +87,10 @@ struct LaunchCtx {
 
 hipError_t launch_default_qp(const LaunchCtx& c, const float* angles, const float* root_off, Fields out,
                              hipStream_t s);
+// tape (nullable): also write tape[T][smax][TAPE_N][Bm][E] (see bx_access.h).
 hipError_t launch_fused(const LaunchCtx& c, const WaveWork* work, int n_work, int waves_per_block, Fields in,
-                        Fields out, const float* acts, int T, int save_every, Fields traj, bool flags, hipStream_t s);
+                        Fields out, const float* acts, int T, int save_every, Fields traj, bool flags, hipStream_t s,
+                        float* tape = nullptr, int smax = 0);
 // Plain path: one step (all substeps) of every type; acts points at this
 // step's [Am][E] actions. jslot/cslot: per-type scratch. tape (nullable):
 // per substep [TAPE_N][Bm][E] records for the adjoint, see bx_access.h.

@@ -257,12 +257,17 @@ __global__ void k_plain_collision(const Tables* __restrict__ tab, int t, const i
 // fetches each child's reaction (fp, tp) in child order. State stays in
 // registers across all substeps and steps; only actions are read per step.
 
-template <int MAXDOF>
+// TAPE: also write each substep's tape record (state before the kinematic
+// update, total torque, count of applied contacts) to
+// tape[step][sub][TAPE_N][Bm][E], for the adjoint that reads it instead of
+// recomputing the step.
+template <int MAXDOF, bool TAPE>
 __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const WaveWork& wk,
                                           const int32_t* __restrict__ env_list, const int32_t* __restrict__ type_off,
                                           int E, int Bm, const Fields& in, const Fields& out,
                                           const float* __restrict__ acts, int Am, int T, int save_every,
-                                          const Fields& traj, uint8_t* nonfinite) {
+                                          const Fields& traj, uint8_t* nonfinite, float* __restrict__ tape,
+                                          int smax) {
   const int t = wk.type;
   const TypeT ty = tab->type[t];
   const int nb = ty.nb;
@@ -299,6 +304,8 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
     if (has_joint && step + 1 < T)
       for (int x = 0; x < MAXDOF; ++x) raw_next[x] = act_raw(acts + (size_t)(step + 1) * Am * E, J, x, e, E);
     for (int sub = 0; sub < ty.substeps; ++sub) {
+      float* tp = TAPE ? tape + ((size_t)step * smax + sub) * TAPE_N * Bm * E : nullptr;
+      if (TAPE && live) tape_state(tp, s, b, e, Bm, E);
       kinematic_unmasked(s, h);
       // parent's post-kinematic state: the cross-lane reads are issued first
       // and this body's rotation is formed while they are in flight; the
@@ -355,6 +362,10 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
           torque += tq;
         }
       }
+      if (TAPE && live) {
+        tape_torque(tp, torque, b, e, Bm, E);
+        tape_count(tp, cnt, b, e, Bm, E);
+      }
       potential(B, ty, s, f, force, torque);
       collision(B, s, dv, dw, cnt);
     }
@@ -379,15 +390,28 @@ __global__ __launch_bounds__(256) void k_fused(const Tables* __restrict__ tab, c
                                                int n_work, const int32_t* __restrict__ env_list,
                                                const int32_t* __restrict__ type_off, int E, int Bm, Fields in,
                                                Fields out, const float* __restrict__ acts, int Am, int T,
-                                               int save_every, Fields traj, uint8_t* nonfinite) {
+                                               int save_every, Fields traj, uint8_t* nonfinite, float* tape,
+                                               int smax) {
   const int w = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (w >= n_work) return;
   const WaveWork wk = work[w];
   // wave-uniform: joints of at most one axis take the shorter path
-  if (tab->type[wk.type].max_dof <= 1)
-    fused_run<1>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite);
-  else
-    fused_run<3>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite);
+  const bool one = tab->type[wk.type].max_dof <= 1;
+  if (tape == nullptr) {
+    if (one)
+      fused_run<1, false>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
+                          nullptr, 0);
+    else
+      fused_run<3, false>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
+                          nullptr, 0);
+  } else {
+    if (one)
+      fused_run<1, true>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
+                         tape, smax);
+    else
+      fused_run<3, true>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
+                         tape, smax);
+  }
 }
 
 // ------------------------------------------------------------------ small helpers
@@ -419,11 +443,11 @@ hipError_t launch_default_qp(const LaunchCtx& c, const float* angles, const floa
 
 hipError_t launch_fused(const LaunchCtx& c, const WaveWork* work, int n_work, int waves_per_block, Fields in,
                         Fields out, const float* acts, int T, int save_every, Fields traj, bool flags,
-                        hipStream_t s) {
+                        hipStream_t s, float* tape, int smax) {
   if (n_work == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fused, dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block), 0, s, c.tab, work,
                      n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj,
-                     flags ? c.nonfinite : nullptr);
+                     flags ? c.nonfinite : nullptr, tape, smax);
   return hipGetLastError();
 }
 

@@ -252,12 +252,16 @@ __device__ __forceinline__ Bar shfl_bar(const Bar& s, int src) {
 }
 __device__ __forceinline__ v3 shfl3(v3 a, int src) { return V(shfl(a.x, src), shfl(a.y, src), shfl(a.z, src)); }
 
-template <int MAXDOF>
+// FROM_TAPE: the forward substeps are not recomputed; their tape records are
+// read from hbm_tape[sub][TAPE_N][Bm][E] (written by the fused forward with
+// a tape) instead of the LDS tape.
+template <int MAXDOF, bool FROM_TAPE>
 __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, const WaveWork& wk,
                                               const int32_t* __restrict__ env_list,
                                               const int32_t* __restrict__ type_off, int E, int Bm, int Am,
                                               const Fields& in, const float* __restrict__ act, const Fields& g_out,
-                                              const Fields& g_in, float* __restrict__ g_act, float* lds) {
+                                              const Fields& g_in, float* __restrict__ g_act, float* lds,
+                                              const float* __restrict__ hbm_tape) {
   const int t = wk.type;
   const TypeT ty = tab->type[t];
   const int nb = ty.nb;
@@ -285,8 +289,8 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
     }
 
   // forward substeps with their tape in LDS
-  Body s = load_body(in, b, e, Bm, E);
-  for (int sub = 0; sub < ty.substeps; ++sub) {
+  Body s = FROM_TAPE ? Body{} : load_body(in, b, e, Bm, E);
+  for (int sub = 0; sub < (FROM_TAPE ? 0 : ty.substeps); ++sub) {
     float* tp = lds + sub * TAPE_N * 64 + lane;
     tp[0] = s.p.x; tp[64] = s.p.y; tp[128] = s.p.z;
     tp[192] = s.q.w; tp[256] = s.q.x; tp[320] = s.q.y; tp[384] = s.q.z;
@@ -351,14 +355,23 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
   Bar G = live ? load_bar(g_out, b, e, Bm, E) : bar_zero();
   float ga[3] = {0.f, 0.f, 0.f};
   for (int sub = ty.substeps - 1; sub >= 0; --sub) {
-    const float* tp = lds + sub * TAPE_N * 64 + lane;
     Body pre;
-    pre.p = V(tp[0], tp[64], tp[128]);
-    pre.q = q4{tp[192], tp[256], tp[320], tp[384]};
-    pre.v = V(tp[448], tp[512], tp[576]);
-    pre.w = V(tp[640], tp[704], tp[768]);
-    const v3 ttot = V(tp[832], tp[896], tp[960]);
-    const int n = (int)tp[1024];
+    v3 ttot;
+    int n;
+    if (FROM_TAPE) {
+      const float* tp = hbm_tape + (size_t)sub * TAPE_N * Bm * E;
+      pre = tape_load_state(tp, b, e, Bm, E);
+      ttot = tape_load_torque(tp, b, e, Bm, E);
+      n = tape_load_count(tp, b, e, Bm, E);
+    } else {
+      const float* tp = lds + sub * TAPE_N * 64 + lane;
+      pre.p = V(tp[0], tp[64], tp[128]);
+      pre.q = q4{tp[192], tp[256], tp[320], tp[384]};
+      pre.v = V(tp[448], tp[512], tp[576]);
+      pre.w = V(tp[640], tp[704], tp[768]);
+      ttot = V(tp[832], tp[896], tp[960]);
+      n = (int)tp[1024];
+    }
     Body post = pre;
     kinematic(B, post, h);
     Body P = shfl_body(post, src_parent);
@@ -433,9 +446,26 @@ __global__ __launch_bounds__(64) void k_fused_vjp(const Tables* __restrict__ tab
   float* lds = lds_tape;
   (void)smax;
   if (tab->type[wk.type].max_dof <= 1)
-    fused_vjp_run<1>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds);
+    fused_vjp_run<1, false>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds, nullptr);
   else
-    fused_vjp_run<3>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds);
+    fused_vjp_run<3, false>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds, nullptr);
+}
+
+// The adjoint of one step from its forward tape in HBM (no recompute, no LDS).
+__global__ __launch_bounds__(64) void k_fused_vjp_tape(const Tables* __restrict__ tab,
+                                                       const WaveWork* __restrict__ work, int n_work,
+                                                       const int32_t* __restrict__ env_list,
+                                                       const int32_t* __restrict__ type_off, int E, int Bm, int Am,
+                                                       const float* __restrict__ tape, const float* __restrict__ act,
+                                                       Fields g_out, Fields g_in, float* __restrict__ g_act) {
+  const int w = xcd_block(blockIdx.x, gridDim.x);
+  if (w >= n_work) return;
+  const WaveWork wk = work[w];
+  const Fields none{nullptr, nullptr, nullptr, nullptr};
+  if (tab->type[wk.type].max_dof <= 1)
+    fused_vjp_run<1, true>(tab, wk, env_list, type_off, E, Bm, Am, none, act, g_out, g_in, g_act, nullptr, tape);
+  else
+    fused_vjp_run<3, true>(tab, wk, env_list, type_off, E, Bm, Am, none, act, g_out, g_in, g_act, nullptr, tape);
 }
 
 }  // namespace
@@ -465,6 +495,14 @@ void vjp_free(VjpWork& w) {
   if (w.buf) (void)hipFree(w.buf);
   w.buf = nullptr;
   w.bytes = 0;
+}
+
+hipError_t launch_vjp_tape(const LaunchCtx& c, const VjpSched& sched, const float* tape, const float* act,
+                           Fields g_out, Fields g_in, float* g_act, hipStream_t s) {
+  if (sched.n_work == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fused_vjp_tape, dim3(sched.n_work), dim3(64), 0, s, c.tab, sched.work, sched.n_work,
+                     c.env_list, c.type_off, c.E, c.Bm, c.Am, tape, act, g_out, g_in, g_act);
+  return hipGetLastError();
 }
 
 hipError_t launch_vjp(const LaunchCtx& c, VjpWork& w, const VjpSched& sched, Fields in, const float* act,

@@ -59,6 +59,56 @@ def test_step_vjp_matches_oracle(name, flags):
     assert bad.mean() <= 0.05
 
 
+@pytest.mark.parametrize("name", SYSTEMS)
+def test_step_vjp_from_tape_matches_oracle_and_recompute(name):
+    """brax_rollout_tape writes the substep tape; brax_step_vjp_tape on it
+    gives the oracle's adjoint (same bar as the recomputing adjoint) and agrees
+    with brax_step_vjp; the tape rollout's state equals brax_rollout's."""
+    E = 40
+    o, X, acts = make_states(name, E, seed=11, warm=15)
+    a = acts[0]
+    g = np.random.default_rng(12).normal(size=X.shape).astype(np.float32).astype(np.float64)
+    gi_o, ga_o = o.step_vjp(X, a.astype(np.float64), g)
+    _, mg = o.step(X, a.astype(np.float64), margins=True)
+    sysg = braxmi.System(synth.system_text(synth.WORKLOADS[name].system), E)
+    A = acts_dev(a[None])
+    out_t, tape = sysg.rollout_tape(to_dev(X), A)
+    out_r, _ = sysg.rollout(to_dev(X), A)
+    for x, y in zip(out_t.fields(), out_r.fields()):
+        assert torch.allclose(x, y, rtol=1e-6, atol=1e-6)
+    g_in, g_act = sysg.step_vjp_tape(tape[0], A[0].contiguous(), to_dev(g))
+    gi = from_dev(g_in, o.nb)
+    ga = g_act.cpu().numpy().T[:, :o.na]
+    err = normwise(np.concatenate([gi.reshape(E, -1), ga], 1), np.concatenate([gi_o.reshape(E, -1), ga_o], 1))
+    amb = mg.min(1) < 1e-6
+    print(f"vjp from tape {name}: max err {err.max():.2e} ambiguous {int(amb.sum())}/{E}", flush=True)
+    bad = err >= GRAD_TOL
+    assert not (bad & ~amb).any(), err[bad & ~amb]
+    assert bad.mean() <= 0.05
+    g_in2, g_act2 = sysg.step_vjp(to_dev(X), A[0].contiguous(), to_dev(g))
+    ref = np.concatenate([from_dev(g_in2, o.nb).reshape(E, -1), g_act2.cpu().numpy().T], 1)
+    got = np.concatenate([gi.reshape(E, -1), g_act.cpu().numpy().T], 1)
+    assert (normwise(got, ref)[~amb] < 1e-4).all()
+
+
+def test_rollout_gradient_tape_and_recompute_agree():
+    """RolloutFn with the segment tape and with per-step recompute: the same
+    gradient (both are the adjoint of the same FP32 forward)."""
+    name, E, T = "biped", 16, 30
+    o, X, _ = make_states(name, E, seed=23, warm=5)
+    acts = synth.actions(23, T, E, o.na, synth.WORKLOADS[name].act_range)
+    sysg = braxmi.System(synth.system_text(name), E)
+    grads = []
+    for tape in (True, False):
+        A = acts_dev(acts).requires_grad_(True)
+        out = braxmi.rollout_grad(sysg, to_dev(X), A, k=7, tape=tape)
+        (out.pos[0].sum() + 0.1 * out.vel.sum()).backward()
+        grads.append(A.grad.cpu().numpy().transpose(1, 0, 2).reshape(sysg.n_envs, -1))
+    err = normwise(grads[0], grads[1])
+    print(f"rollout gradient tape vs recompute: max {err.max():.2e}", flush=True)
+    assert err.max() < 1e-4
+
+
 def test_vjp_plain_and_fused_tapes_agree_and_are_deterministic():
     E = 64
     o, X, acts = make_states("biped", E, seed=13, warm=10)
@@ -226,3 +276,17 @@ def test_mixed_batch_vjp_equals_homogeneous():
         assert np.array_equal(gim[idx, :o.nb], from_dev(g1, o.nb)), n
         assert np.array_equal(gam[idx, :o.na], a1.cpu().numpy().T), n
         assert not gim[idx, o.nb:].any()
+    # the same from the tape of the mixed launch, against each type's own tape adjoint
+    A = acts_dev(amix, am)
+    _, tape = mixed.rollout_tape(to_dev(Xmix, bm), A)
+    gi_t, ga_t = mixed.step_vjp_tape(tape[0], A[0].contiguous(), to_dev(gmix, bm))
+    gim_t, gam_t = from_dev(gi_t, bm), ga_t.cpu().numpy().T
+    for t, n in enumerate(MIXED):
+        o, X, acts = per[n]
+        one = braxmi.System(descs[t], 6)
+        A1 = acts_dev(acts[:1])
+        _, tape1 = one.rollout_tape(to_dev(X), A1)
+        g1, a1 = one.step_vjp_tape(tape1[0], A1[0].contiguous(), to_dev(gs[n]))
+        idx = [i for i in range(24) if env[i] == t]
+        assert np.array_equal(gim_t[idx, :o.nb], from_dev(g1, o.nb)), n
+        assert np.array_equal(gam_t[idx, :o.na], a1.cpu().numpy().T), n
