@@ -172,6 +172,25 @@ def main():
     log(f"plain forward: {ms_plain:.2f} ms per {Tp}-step rollout, {plain:.3e} env-steps/s; "
         f"graph-replayed {ms_plain_g:.2f} ms")
 
+    # environment layer after the step (reward, termination, auto-reset,
+    # observation), single steps graph-replayed, ant-like parameters
+    system.env_configure([dict(root=0, forward_weight=1.0, healthy_reward=1.0, ctrl_cost=0.5, z_min=0.2, z_max=1.0)])
+    est = system.new_state()
+    for x, y in zip(est.fields(), s0.fields()):
+        x.copy_(y)
+    eobs = torch.empty(system.obs_dim, E, device="cuda")
+    erew = torch.empty(E, device="cuda")
+    edone = torch.empty(E, dtype=torch.uint8, device="cuda")
+    n_env_steps = 100
+    eact = acts[0].clone()      # the policy's action buffer (fixed address, as a replayed graph wants)
+
+    def env_loop():
+        for _ in range(n_env_steps):
+            system.env_step(est, eact, s0, out=est, obs=eobs, reward=erew, done=edone, flags=braxmi.BRAX_GRAPH)
+    ms_env = time_calls(env_loop, 1, 1)
+    env_rate = E * n_env_steps / (ms_env / 1e3)
+    log(f"environment step: {ms_env / n_env_steps * 1e3:.1f} us per step of {E} environments")
+
     # forward + VJP: the differentiation workload (1024 quadrupeds x 100 steps,
     # checkpoints every 10 steps), gradient of a loss w.r.t. all actions
     wd = synth.WORKLOADS["quadruped_diff"]
@@ -269,6 +288,9 @@ def main():
         "plain_fwd_env_steps_per_s": plain,
         "fused_over_plain": fused / plain,
         "plain_fwd_graph_env_steps_per_s": plain_g,
+        "env_step_env_steps_per_s": env_rate,
+        "env_step_workload": f"quadruped {E} environments, single environment steps (step, reward, termination, "
+                             f"auto-reset, observation) graph-replayed, {n_env_steps} steps",
         "fwd_vjp_env_steps_per_s": fwd_vjp,
         "fwd_vjp_workload": f"quadruped {wd.envs} environments x {wd.steps} steps, checkpoints every 10 steps",
         **extra,

@@ -91,6 +91,9 @@ typedef struct {
   float dt[BRAX_MAX_TYPES];
   int32_t device;                      /* -1 for a host-only (validate) handle */
   uint8_t* nonfinite;                  /* device [E] flags (BRAX_NONFINITE_FLAGS) */
+  int64_t tape_step_floats;            /* floats per step of a brax_rollout_tape tape */
+  int32_t n_params[BRAX_MAX_TYPES];    /* system parameters per type (brax_step_vjp_params) */
+  int32_t p_max;                       /* the largest of n_params */
 } brax_layout;
 
 /* Build a batch of n_envs environments from n_descs system descriptions.
@@ -156,22 +159,68 @@ int brax_rollout(const brax_sys* sys, const brax_state* in, const float* acts, i
 
 /* brax_rollout (save_every 0) that also records what the adjoint needs of
  * every substep (Sections 3 and 5.1.4: the backward pass through the steps
- * of Algorithm 1): tape, device, caller-owned, T * Smax * 17 * Bmax * E
- * floats laid out [T][Smax][17][Bmax][E], Smax = the largest substep count of
- * the batch's systems; per body and substep: the state before the kinematic
- * update (pos 3, rot 4, vel 3, ang 3), the total joint and actuator torque
- * (3) and the number of contacts that applied an impulse (1). Substeps beyond
- * a system's own count are not written. Fused path only: BRAX_PLAIN gives
+ * of Algorithm 1): per body and substep, the state before the kinematic
+ * update (13 floats), the total joint and actuator torque (3) and the number
+ * of contacts that applied an impulse (1). tape: device, caller-owned,
+ * T * brax_layout.tape_step_floats floats, step t at offset
+ * t * tape_step_floats; its layout inside a step is the library's own
+ * (wavefront-major, for coalesced access) and is read only by
+ * brax_step_vjp_tape of the same sys. Fused path only: BRAX_PLAIN gives
  * BRAX_E_UNSUPPORTED. The state results equal brax_rollout's. */
 int brax_rollout_tape(const brax_sys* sys, const brax_state* in, const float* acts, int32_t T, float* tape,
                       brax_state* out, int32_t flags, void* stream);
 
-/* Adjoint of one step from its tape (one [Smax][17][Bmax][E] slice written
- * by brax_rollout_tape for that step, with the same actions) instead of
- * recomputing the forward substeps: same outputs and kink conventions as
- * brax_step_vjp. g_in may not alias g_out. Fused path only. */
+/* brax_step_vjp that also writes the cotangents of the system parameters
+ * (Section 2: gradients through the simulation; here with respect to the
+ * constants of the system description), per environment: g_params
+ * [p_max][E] (device, caller-owned, overwritten), for each system type in
+ * this order: mass of every body (nb), principal inertia of every body (x,
+ * y, z; 3 nb), then per joint (nj each) the anchor stiffness, anchor
+ * damping, angular stiffness, angular damping and limit stiffness, then the
+ * strength of every action (na), then the friction coefficient (1): n_params
+ * = 4 nb + 5 nj + na + 1 entries; rows beyond them are zero. The gradient of
+ * a loss summed over environments sharing the parameters is the sum over
+ * E. Fused path only. */
+int brax_step_vjp_params(const brax_sys* sys, const brax_state* in, const float* act, const brax_state* g_out,
+                         brax_state* g_in, float* g_act, float* g_params, int32_t flags, void* stream);
+
+/* Adjoint of one step from its tape (the tape_step_floats written by
+ * brax_rollout_tape of the same sys for that step, with the same actions)
+ * instead of recomputing the forward substeps: same outputs and kink
+ * conventions as brax_step_vjp. g_in may not alias g_out. Fused path only. */
 int brax_step_vjp_tape(const brax_sys* sys, const float* tape, const float* act, const brax_state* g_out,
                        brax_state* g_in, float* g_act, int32_t flags, void* stream);
+
+/* Environment layer (Section 4.2: gym-like environments; App. E: rewards
+ * close to the MuJoCo gym ones without a contact cost, termination on the
+ * torso height leaving a range). Per system type: */
+typedef struct {
+  int32_t root;          /* body whose x progress is rewarded and whose height decides termination */
+  float forward_weight;  /* reward per m/s of root x velocity over the step */
+  float healthy_reward;  /* reward while z_min <= root z <= z_max after the step */
+  float ctrl_cost;       /* cost per unit of sum_k a_k^2 (the actions as passed) */
+  float z_min, z_max;    /* healthy root heights, metres (use +-inf for none) */
+} brax_env_params;
+
+/* Set the environment-layer parameters, one entry per system type (host
+ * array of n_types). Synchronous; BRAX_E_ARG for a root out of range or
+ * z_min > z_max. */
+int brax_env_configure(brax_sys* sys, const brax_env_params* params);
+
+/* One environment step of every environment, on `stream`: brax_step from
+ * `in` to `out`, then
+ *   reward[e] = forward_weight (x_root' - x_root) / dt
+ *               + healthy_reward [healthy] - ctrl_cost sum_k a_k^2,
+ *   done[e]   = !healthy, healthy = z_min <= z_root' <= z_max (after the step),
+ * then every finished environment's `out` state is replaced by its `reset`
+ * state (all Bmax bodies), and obs [Omax][E] (Omax = 11 + 2 * d_max) is the
+ * observation of `out`: z_root, q_root (4), v_root (3), w_root (3), the joint
+ * angles (D, joint order, as in the joint law) and the relative angular
+ * velocity (w_child - w_parent) projected on each Euler axis (D), zero-padded.
+ * `out` may alias `in`; `reset` may not alias `out`. Device pointers, caller
+ * owned; done is uint8. Fused path only. */
+int brax_env_step(const brax_sys* sys, const brax_state* in, const float* act, const brax_state* reset,
+                  brax_state* out, float* obs, float* reward, uint8_t* done, int32_t flags, void* stream);
 
 /* Time the fused kernel's launch shapes on `stream` and keep the fastest
  * for later calls (the result does not depend on the shape). */

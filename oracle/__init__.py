@@ -187,6 +187,49 @@ class Oracle:
         g = np.einsum("eo,eoi->ei", np.asarray(g_out, dtype=np.float64).reshape(E, self.ns), J)
         return g[:, :self.ns].reshape(E, self.nb, 13), g[:, self.ns:]
 
+    # ---------------------------------------------------------------- parameters
+    def param_names(self):
+        """System parameters in the library's order: mass per body, principal
+        inertia per body (x, y, z), per joint k_lin, c_lin, k_ang, c_ang, k_lim,
+        actuator strength per action, friction."""
+        names = [("mass", (b,)) for b in range(self.nb)]
+        names += [("inertia", (b, k)) for b in range(self.nb) for k in range(3)]
+        for f in ("j_k_lin", "j_c_lin", "j_k_ang", "j_c_ang", "j_k_lim"):
+            names += [(f, (j,)) for j in range(self.nj)]
+        names += [("a_gear", (k,)) for k in range(self.na)]
+        names += [("friction", ())]
+        return names
+
+    def _param(self, name, idx, value=None):
+        field = getattr(self._s, name)
+        if not idx:
+            if value is not None:
+                setattr(self._s, name, value)
+            return getattr(self._s, name)
+        arr = field if len(idx) == 1 else field[idx[0]]
+        if value is not None:
+            arr[idx[-1]] = value
+        return arr[idx[-1]]
+
+    def param_vjp(self, X, act, g_out, rel=1e-6):
+        """g_out . d(step)/d(parameter) for every parameter (param_names order),
+        by central differences of the FP64 step: [E][P]."""
+        X = np.asarray(X, dtype=np.float64)
+        g = np.asarray(g_out, dtype=np.float64).reshape(len(X), -1)
+        out = []
+        for name, idx in self.param_names():
+            v = float(self._param(name, idx))
+            eps = rel * max(abs(v), 1.0)
+            try:
+                self._param(name, idx, v + eps)
+                fp = self.step(X, act)
+                self._param(name, idx, v - eps)
+                fm = self.step(X, act)
+            finally:
+                self._param(name, idx, v)
+            out.append(((fp - fm).reshape(len(X), -1) * g).sum(1) / (2 * eps))
+        return np.stack(out, 1)
+
     def count_flops(self, X, act):
         """Algorithmic floating-point operations of one step of one environment."""
         X = np.ascontiguousarray(X, dtype=np.float64).reshape(self.nb, 13)

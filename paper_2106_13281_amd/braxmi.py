@@ -12,6 +12,7 @@ State tensors follow the library layout (environment index fastest):
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 from dataclasses import dataclass
 
@@ -37,6 +38,11 @@ class _State(C.Structure):
     _fields_ = [("pos", C.c_void_p), ("rot", C.c_void_p), ("vel", C.c_void_p), ("ang", C.c_void_p)]
 
 
+class _EnvParams(C.Structure):
+    _fields_ = [("root", C.c_int32), ("forward_weight", C.c_float), ("healthy_reward", C.c_float),
+                ("ctrl_cost", C.c_float), ("z_min", C.c_float), ("z_max", C.c_float)]
+
+
 class _Layout(C.Structure):
     _fields_ = [("n_envs", C.c_int32), ("n_types", C.c_int32), ("b_max", C.c_int32), ("a_max", C.c_int32),
                 ("d_max", C.c_int32),
@@ -44,13 +50,15 @@ class _Layout(C.Structure):
                 ("n_joints", C.c_int32 * MAX_TYPES), ("n_actions", C.c_int32 * MAX_TYPES),
                 ("n_dof", C.c_int32 * MAX_TYPES), ("n_contacts", C.c_int32 * MAX_TYPES),
                 ("substeps", C.c_int32 * MAX_TYPES), ("dt", C.c_float * MAX_TYPES),
-                ("device", C.c_int32), ("nonfinite", C.c_void_p)]
+                ("device", C.c_int32), ("nonfinite", C.c_void_p), ("tape_step_floats", C.c_int64),
+                ("n_params", C.c_int32 * MAX_TYPES), ("p_max", C.c_int32)]
 
 
 EXPORTS = ("brax_sys_create", "brax_sys_destroy", "brax_sys_query", "brax_default_angles", "brax_default_qp",
-           "brax_step", "brax_step_vjp", "brax_rollout", "brax_rollout_tape", "brax_step_vjp_tape", "brax_autotune",
-           "brax_schedule", "brax_set_schedule", "brax_nonfinite", "brax_last_error")
-TAPE_N = 17  # floats per body per substep in a forward tape
+           "brax_step", "brax_step_vjp", "brax_step_vjp_params", "brax_rollout", "brax_rollout_tape",
+           "brax_step_vjp_tape",
+           "brax_env_configure", "brax_env_step", "brax_autotune", "brax_schedule", "brax_set_schedule",
+           "brax_nonfinite", "brax_last_error")
 
 _lib = None
 
@@ -75,10 +83,15 @@ def lib():
                                     C.c_void_p]
         L.brax_rollout.argtypes = [C.c_void_p, P(_State), C.c_void_p, C.c_int32, C.c_int32, P(_State), P(_State),
                                    C.c_int32, C.c_void_p]
+        L.brax_step_vjp_params.argtypes = [C.c_void_p, P(_State), C.c_void_p, P(_State), P(_State), C.c_void_p,
+                                           C.c_void_p, C.c_int32, C.c_void_p]
         L.brax_rollout_tape.argtypes = [C.c_void_p, P(_State), C.c_void_p, C.c_int32, C.c_void_p, P(_State),
                                         C.c_int32, C.c_void_p]
         L.brax_step_vjp_tape.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, P(_State), P(_State), C.c_void_p,
                                          C.c_int32, C.c_void_p]
+        L.brax_env_configure.argtypes = [C.c_void_p, P(_EnvParams)]
+        L.brax_env_step.argtypes = [C.c_void_p, P(_State), C.c_void_p, P(_State), P(_State), C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_int32, C.c_void_p]
         L.brax_autotune.argtypes = [C.c_void_p, C.c_void_p]
         L.brax_schedule.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32)]
         L.brax_set_schedule.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
@@ -171,7 +184,9 @@ class System:
         self.n_dof = list(lay.n_dof[:nt])
         self.n_contacts = list(lay.n_contacts[:nt])
         self.substeps = list(lay.substeps[:nt])
-        self.s_max = max(self.substeps) if self.substeps else 1   # tape stride (substeps per step)
+        self.tape_step_floats = lay.tape_step_floats               # floats per step of a forward tape
+        self.n_params = list(lay.n_params[:nt])
+        self.p_max = lay.p_max
         self.dt = list(lay.dt[:nt])
         self.device = torch.device("cuda", device) if device >= 0 else None
 
@@ -227,6 +242,19 @@ class System:
                                    _stream(stream)))
         return g_in, g_act
 
+    def step_vjp_params(self, state, act, g_out, g_in=None, g_act=None, g_params=None, flags=0, stream=None):
+        """step_vjp plus the per-environment cotangents of the system parameters [p_max][E]."""
+        g_in = self.new_state() if g_in is None else g_in
+        act = self._act(act, (self.a_max, self.n_envs))
+        if g_act is None:
+            g_act = torch.empty(self.a_max, self.n_envs, dtype=torch.float32, device=self.device)
+        if g_params is None:
+            g_params = torch.empty(self.p_max, self.n_envs, dtype=torch.float32, device=self.device)
+        si, sg, sgi = state.struct(), g_out.struct(), g_in.struct()
+        _check(lib().brax_step_vjp_params(self._h, C.byref(si), _ptr(act), C.byref(sg), C.byref(sgi), _ptr(g_act),
+                                          _ptr(g_params), flags, _stream(stream)))
+        return g_in, g_act, g_params
+
     def rollout(self, state, acts, save_every=0, out=None, traj=None, flags=0, stream=None):
         T = acts.shape[0] if acts is not None else 0
         out = self.new_state() if out is None else out
@@ -242,12 +270,12 @@ class System:
         return out, (traj if n_save else None)
 
     def rollout_tape(self, state, acts, tape=None, out=None, flags=0, stream=None):
-        """rollout that also writes the forward tape [T][Smax][17][Bmax][E] for step_vjp_tape."""
+        """rollout that also writes the forward tape [T][tape_step_floats] for step_vjp_tape."""
         T = acts.shape[0] if acts is not None else 0
         out = self.new_state() if out is None else out
         if T:
             acts = self._act(acts, (T, self.a_max, self.n_envs))
-        shape = (T, self.s_max, TAPE_N, self.b_max, self.n_envs)
+        shape = (T, self.tape_step_floats)
         if tape is None:
             tape = torch.empty(shape, dtype=torch.float32, device=self.device)
         if tuple(tape.shape) != shape or tape.dtype != torch.float32 or not tape.is_contiguous():
@@ -258,8 +286,8 @@ class System:
         return out, tape
 
     def step_vjp_tape(self, tape, act, g_out, g_in=None, g_act=None, flags=0, stream=None):
-        """step_vjp from one step's tape slice [Smax][17][Bmax][E] instead of recomputing the step."""
-        shape = (self.s_max, TAPE_N, self.b_max, self.n_envs)
+        """step_vjp from one step's tape slice [tape_step_floats] instead of recomputing the step."""
+        shape = (self.tape_step_floats,)
         if tuple(tape.shape) != shape or tape.dtype != torch.float32 or not tape.is_contiguous():
             raise ValueError(f"tape must be a contiguous float32 tensor of shape {shape}")
         g_in = self.new_state() if g_in is None else g_in
@@ -270,6 +298,35 @@ class System:
         _check(lib().brax_step_vjp_tape(self._h, _ptr(tape), _ptr(act), C.byref(sg), C.byref(sgi), _ptr(g_act),
                                         flags, _stream(stream)))
         return g_in, g_act
+
+    def env_configure(self, params):
+        """Environment-layer parameters, one dict per system type with keys root,
+        forward_weight, healthy_reward, ctrl_cost, z_min, z_max."""
+        if len(params) != self.n_types:
+            raise ValueError(f"{self.n_types} parameter sets expected")
+        arr = (_EnvParams * self.n_types)()
+        for i, p in enumerate(params):
+            arr[i] = _EnvParams(int(p.get("root", 0)), float(p.get("forward_weight", 1.0)),
+                                float(p.get("healthy_reward", 1.0)), float(p.get("ctrl_cost", 0.5)),
+                                float(p.get("z_min", -math.inf)), float(p.get("z_max", math.inf)))
+        _check(lib().brax_env_configure(self._h, arr))
+
+    @property
+    def obs_dim(self):
+        return 11 + 2 * self.d_max
+
+    def env_step(self, state, act, reset, out=None, obs=None, reward=None, done=None, flags=0, stream=None):
+        """(out, obs [Omax][E], reward [E], done [E] uint8) of one environment step."""
+        out = self.new_state() if out is None else out
+        act = self._act(act, (self.a_max, self.n_envs))
+        dev = self.device
+        obs = torch.empty(self.obs_dim, self.n_envs, dtype=torch.float32, device=dev) if obs is None else obs
+        reward = torch.empty(self.n_envs, dtype=torch.float32, device=dev) if reward is None else reward
+        done = torch.empty(self.n_envs, dtype=torch.uint8, device=dev) if done is None else done
+        si, sr, so = state.struct(), reset.struct(), out.struct()
+        _check(lib().brax_env_step(self._h, C.byref(si), _ptr(act), C.byref(sr), C.byref(so), _ptr(obs),
+                                   _ptr(reward), _ptr(done), flags, _stream(stream)))
+        return out, obs, reward, done
 
     def autotune(self, stream=None):
         _check(lib().brax_autotune(self._h, _stream(stream)))
@@ -343,8 +400,7 @@ class RolloutFn(torch.autograd.Function):
             n = min(k, T - t0)
             if use_tape:
                 if tape is None or tape.shape[0] < n:
-                    tape = torch.empty((n, system.s_max, TAPE_N, system.b_max, system.n_envs), dtype=torch.float32,
-                                       device=acts.device)
+                    tape = torch.empty((n, system.tape_step_floats), dtype=torch.float32, device=acts.device)
                 system.rollout_tape(ck[si], acts[t0:t0 + n], tape=tape[:n])
                 for i in reversed(range(n)):
                     g_in, g_a = system.step_vjp_tape(tape[i], acts[t0 + i], g)

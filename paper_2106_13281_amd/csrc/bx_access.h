@@ -54,6 +54,33 @@ __device__ __forceinline__ void zero_body(const Fields& f, int b, int e, int Bm,
   store_body(f, 0, z, b, e, Bm, E);
 }
 
+// Tape of the fused path, wavefront-major: per substep and work item, TAPE_N
+// rows of 64 floats (one per lane; rows 0-12 the state before the kinematic
+// update, 13-15 the total torque, 16 the applied-contact count), so that
+// every store and load of a row is 256 contiguous bytes.
+__device__ __forceinline__ void wtape_state(float* tp, const Body& s, int lane) {
+  const float v[13] = {s.p.x, s.p.y, s.p.z, s.q.w, s.q.x, s.q.y, s.q.z, s.v.x, s.v.y, s.v.z, s.w.x, s.w.y, s.w.z};
+#pragma unroll
+  for (int k = 0; k < 13; ++k) tp[k * 64 + lane] = v[k];
+}
+__device__ __forceinline__ void wtape_rest(float* tp, v3 torque, int cnt, int lane) {
+  tp[13 * 64 + lane] = torque.x;
+  tp[14 * 64 + lane] = torque.y;
+  tp[15 * 64 + lane] = torque.z;
+  tp[16 * 64 + lane] = (float)cnt;
+}
+__device__ __forceinline__ void wtape_load(const float* tp, int lane, Body& s, v3& torque, int& cnt) {
+  float v[17];
+#pragma unroll
+  for (int k = 0; k < 17; ++k) v[k] = tp[k * 64 + lane];
+  s.p = V(v[0], v[1], v[2]);
+  s.q = q4{v[3], v[4], v[5], v[6]};
+  s.v = V(v[7], v[8], v[9]);
+  s.w = V(v[10], v[11], v[12]);
+  torque = V(v[13], v[14], v[15]);
+  cnt = (int)v[16];
+}
+
 // Blocks are dispatched round-robin over the 8 XCDs (each with its own L2):
 // block b runs on XCD b % 8. Neighbouring work items (environments) share the
 // 128-byte lines of the environment-fastest arrays (actions, state), so the

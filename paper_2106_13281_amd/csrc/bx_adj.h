@@ -133,8 +133,9 @@ BXF Bar kinematic_adj(const BodyT& B, const Body& pre, float h, const Bar& ob) {
 // Given the cotangent of (p1, q1, v3, w3) (ob), returns the partial cotangent
 // of the post-kinematic state and the cotangents of f_tot, t_tot and of the
 // contact sums (dvb, dwb; zero when n == 0).
+// invm_bar accumulates the cotangent of 1/m given the total force f_tot.
 BXF Bar integrate_adj(const BodyT& B, const TypeT& ty, const Body& post, const Frame& f, v3 t_tot, int n,
-                      const Bar& ob, v3& fb, v3& tb, v3& dvb, v3& dwb, FrameBar& fr) {
+                      const Bar& ob, v3& fb, v3& tb, v3& dvb, v3& dwb, FrameBar& fr, v3 f_tot, float& invm_bar) {
   const float h = ty.h;
   Bar r;
   r.p = ob.p;
@@ -149,6 +150,7 @@ BXF Bar integrate_adj(const BodyT& B, const TypeT& ty, const Body& post, const F
     dvb = dwb = V(0.f, 0.f, 0.f);
   }
   fb = (h * B.inv_m) * keep(ob.v, B.free_p);
+  invm_bar += h * dot(keep(ob.v, B.free_p), f_tot);
   v3 ab = h * keep(ob.w, B.free_r);           // cotangent of alpha = Iwinv x
   v3 u = mul(f.Iw, post.w);
   v3 x = t_tot - cross(post.w, u);
@@ -165,7 +167,8 @@ BXF Bar integrate_adj(const BodyT& B, const TypeT& ty, const Body& post, const F
 BXF Bar integrate_adj(const BodyT& B, const TypeT& ty, const Body& post, const Frame& f, v3 t_tot, int n,
                       const Bar& ob, v3& fb, v3& tb, v3& dvb, v3& dwb) {
   FrameBar fr = framebar_zero();
-  Bar r = integrate_adj(B, ty, post, f, t_tot, n, ob, fb, tb, dvb, dwb, fr);
+  float unused = 0.f;
+  Bar r = integrate_adj(B, ty, post, f, t_tot, n, ob, fb, tb, dvb, dwb, fr, V(0.f, 0.f, 0.f), unused);
   frame_adj(B, post, f, fr, r.q);
   return r;
 }
@@ -173,8 +176,10 @@ BXF Bar integrate_adj(const BodyT& B, const TypeT& ty, const Body& post, const F
 // ------------------------------------------------------------ contact
 // Cotangent of the body's post-kinematic state from one applied contact,
 // given the cotangents of the body's contact sums (dvb, dwb).
+// invm_bar / mu_bar accumulate the cotangents of 1/m and of the friction
+// coefficient.
 BXF Bar contact_adj(const ContactT& c, const TypeT& ty, const BodyT& B, const Body& s, const Frame& f, v3 dvb, v3 dwb,
-                    bool& applied, FrameBar& fr) {
+                    bool& applied, FrameBar& fr, float& invm_bar, float& mu_bar) {
   Bar r = bar_zero();
   applied = false;
   v3 l = ld3(c.l);
@@ -213,6 +218,7 @@ BXF Bar contact_adj(const ContactT& c, const TypeT& ty, const BodyT& B, const Bo
   sym_outer_add(fr.Iwinvb, dwb, y);
   v3 yb = mul(f.Iwinv, dwb);
   v3 rb = V(0.f, 0.f, 0.f), Jb = B.inv_m * dvb;
+  invm_bar += dot(dvb, J);                   // dv = inv_m J
   cross_adj(rr, J, yb, rb, Jb);
   float jnb = Jb.z;
   v3 ub = V(0.f, 0.f, 0.f);
@@ -221,8 +227,10 @@ BXF Bar contact_adj(const ContactT& c, const TypeT& ty, const BodyT& B, const Bo
     v3 tb = V(-jt * Jb.x, -jt * Jb.y, 0.f);
     float capb = use_cap ? jtb : 0.f, stopb = use_cap ? 0.f : jtb;
     jnb += ty.mu * capb;
+    mu_bar += capb * jn;                     // cap = mu jn
     float spb = stopb / kt;
     float ktb = -stopb * sp / (kt * kt);
+    invm_bar += ktb;
     // kt = inv_m + zt . Iwinv zt, zt = r x t (Iwinv symmetric)
     sym_outer_add(fr.Iwinvb, ktb * zt, zt);
     v3 ztb = (2.f * ktb) * b;
@@ -235,6 +243,7 @@ BXF Bar contact_adj(const ContactT& c, const TypeT& ty, const BodyT& B, const Bo
   // jn = num / kn
   float numb = jnb / kn;
   float knb = -jnb * jn / kn;
+  invm_bar += knb;                           // kn = inv_m + ...
   float depthb = ty.beta_h * numb;
   ub.z += -ty.one_plus_e * numb;
   // kn = inv_m + a.x r.y - a.y r.x, a = Iwinv zz, zz = (r.y, -r.x, 0)
@@ -258,7 +267,8 @@ BXF Bar contact_adj(const ContactT& c, const TypeT& ty, const BodyT& B, const Bo
 BXF Bar contact_adj(const ContactT& c, const TypeT& ty, const BodyT& B, const Body& s, const Frame& f, v3 dvb, v3 dwb,
                     bool& applied) {
   FrameBar fr = framebar_zero();
-  Bar r = contact_adj(c, ty, B, s, f, dvb, dwb, applied, fr);
+  float u0 = 0.f, u1 = 0.f;
+  Bar r = contact_adj(c, ty, B, s, f, dvb, dwb, applied, fr, u0, u1);
   if (applied) frame_adj(B, s, f, fr, r.q);
   return r;
 }
@@ -353,8 +363,9 @@ BXF void joint_geo_adj(const JointT& J, const Body& P, const Body& C, const Join
 // Spring part of a joint's adjoint on given geometry: accumulates into the
 // state cotangents (bP, bC) and the geometry cotangents (gb).
 template <int MAXDOF>
+// jbar (nullable) accumulates the cotangents of k_lin, c_lin, k_ang, c_ang, k_lim.
 BXF void spring_adj_core(const JointT& J, const Body& P, const Body& C, const JointGeo& g, v3 fcb, v3 tcb, v3 fpb,
-                         v3 tpb, Bar& bP, Bar& bC, GeoBar& gb) {
+                         v3 tpb, Bar& bP, Bar& bC, GeoBar& gb, float* jbar = nullptr) {
   v3 F;
   (void)joint_spring<MAXDOF>(J, P, C, g, F);
   // fc = F, tc = rC x F + tau, fp = -F, tp = -(rP x F) - tau
@@ -368,6 +379,7 @@ BXF void spring_adj_core(const JointT& J, const Body& P, const Body& C, const Jo
       float ex = g.th[k] - clampf(g.th[k], J.lo[k], J.hi[k]);
       gb.ax[k] += (-J.k_lim * ex) * taub;
       float exb = -J.k_lim * dot(g.ax[k], taub);
+      if (jbar) jbar[4] += -ex * dot(g.ax[k], taub);
       bool inside = g.th[k] >= J.lo[k] && g.th[k] <= J.hi[k];
       gb.th[k] += inside ? 0.f : exb;
     }
@@ -375,14 +387,17 @@ BXF void spring_adj_core(const JointT& J, const Body& P, const Body& C, const Jo
   // damper
   bP.w += J.c_ang * taub;
   bC.w += -J.c_ang * taub;
+  if (jbar) jbar[3] += dot(P.w - C.w, taub);
   // alignment
   if (MAXDOF == 1 || J.dof == 1) {
     v3 a = J.k_ang * taub;  // tau = k (e1C x e1P)
     cross_adj(g.e1C, g.e1P, a, gb.e1C, gb.e1P);
+    if (jbar) jbar[2] += dot(cross(g.e1C, g.e1P), taub);
   } else if (J.dof == 2) {
     v3 wv = cross(g.e2C, g.e1P);  // tau = (-k m01) wv
     float m01b = -J.k_ang * dot(wv, taub);
     v3 wb = (-J.k_ang * g.m01) * taub;
+    if (jbar) jbar[2] += -g.m01 * dot(wv, taub);
     cross_adj(g.e2C, g.e1P, wb, gb.e2C, gb.e1P);
     gb.e1P += m01b * g.e2C;
     gb.e2C += m01b * g.e1P;
@@ -390,6 +405,12 @@ BXF void spring_adj_core(const JointT& J, const Body& P, const Body& C, const Jo
   // anchor spring-damper: F = k d + c (uP - uC)
   v3 db = J.k_lin * Fb;
   v3 uPb = J.c_lin * Fb, uCb = -J.c_lin * Fb;
+  if (jbar) {
+    const v3 d = (P.p - C.p) + (g.rP - g.rC);
+    const v3 du = (P.v + cross(P.w, g.rP)) - (C.v + cross(C.w, g.rC));
+    jbar[0] += dot(d, Fb);
+    jbar[1] += dot(du, Fb);
+  }
   bP.v += uPb;
   cross_adj(P.w, g.rP, uPb, bP.w, gb.rP);
   bC.v += uCb;
@@ -402,8 +423,9 @@ BXF void spring_adj_core(const JointT& J, const Body& P, const Body& C, const Jo
 
 // Actuator part on given geometry: child torque cotangent tcb, parent tpb.
 template <int MAXDOF>
+// gbar (nullable) accumulates the cotangents of the actuator strengths per axis.
 BXF void actuator_adj_core(const JointT& J, const JointGeo& g, const float* a, v3 tcb, v3 tpb, GeoBar& gb,
-                           float* ab) {
+                           float* ab, float* gbar = nullptr) {
   v3 taub = tcb - tpb;
   for (int k = 0; k < 3; ++k) ab[k] = 0.f;
   for (int k = 0; k < MAXDOF; ++k) {
@@ -412,6 +434,7 @@ BXF void actuator_adj_core(const JointT& J, const JointGeo& g, const float* a, v
       gb.ax[k] += (J.gear[k] * (a[k] - J.act_pd[k] * g.th[k])) * taub;
       ab[k] = J.gear[k] * dot(g.ax[k], taub);
       gb.th[k] -= J.act_pd[k] * ab[k];
+      if (gbar) gbar[k] += (a[k] - J.act_pd[k] * g.th[k]) * dot(g.ax[k], taub);
     }
   }
 }
@@ -443,11 +466,12 @@ BXF void joint_actuator_adj(const JointT& J, const Body& P, const m3& RP, const 
 // the child's rotation cotangent is added to its frame cotangents fr.
 template <int MAXDOF>
 BXF void joint_eval_adj(const JointT& J, const Body& P, const m3& RP, const Body& C, const m3& RC, const float* a,
-                        v3 fcb, v3 tcb, v3 fpb, v3 tpb, Bar& bP, Bar& bC, float* ab, FrameBar& fr) {
+                        v3 fcb, v3 tcb, v3 fpb, v3 tpb, Bar& bP, Bar& bC, float* ab, FrameBar& fr,
+                        float* jbar = nullptr, float* gbar = nullptr) {
   JointGeo g = joint_geo<MAXDOF>(J, RP, RC);
   GeoBar gb = geobar_zero();
-  spring_adj_core<MAXDOF>(J, P, C, g, fcb, tcb, fpb, tpb, bP, bC, gb);
-  actuator_adj_core<MAXDOF>(J, g, a, tcb, tpb, gb, ab);
+  spring_adj_core<MAXDOF>(J, P, C, g, fcb, tcb, fpb, tpb, bP, bC, gb, jbar);
+  actuator_adj_core<MAXDOF>(J, g, a, tcb, tpb, gb, ab, gbar);
   joint_geo_adj<MAXDOF>(J, P, g, gb, bP.q, fr.Rb);
 }
 

@@ -88,6 +88,10 @@ struct brax_sys {
   std::vector<WaveWork> vjp_work;
   WaveWork* d_vjp_work = nullptr;
   int smax = 1;  // largest substep count of the batch's types (tape stride)
+  // environment layer (brax_env_configure)
+  bool env_ready = false;
+  EnvT* d_env = nullptr;
+  float* d_env_x0 = nullptr;
   // plain scratch per type
   float* d_jslot[MAXT] = {nullptr};
   float* d_cslot[MAXT] = {nullptr};
@@ -132,6 +136,8 @@ void free_all(brax_sys* s) {
     (void)hipFree(s->d_type_off);
     (void)hipFree(s->d_work);
     (void)hipFree(s->d_vjp_work);
+    (void)hipFree(s->d_env);
+    (void)hipFree(s->d_env_x0);
     (void)hipFree(s->d_nonfinite);
     for (int t = 0; t < MAXT; ++t) {
       (void)hipFree(s->d_jslot[t]);
@@ -342,6 +348,13 @@ int brax_sys_query(const brax_sys* s, brax_layout* out) {
   out->b_max = s->Bm;
   out->a_max = s->Am;
   out->d_max = s->Dm;
+  out->tape_step_floats = (int64_t)s->smax * (int64_t)s->vjp_work.size() * TAPE_N * 64;
+  out->p_max = 0;
+  for (int t = 0; t < s->n_types; ++t) {
+    const TypeT& ty = s->host_tab.type[t];
+    out->n_params[t] = 4 * ty.nb + 5 * ty.nj + ty.na + 1;
+    out->p_max = std::max(out->p_max, out->n_params[t]);
+  }
   for (int t = 0; t < s->n_types; ++t) {
     const TypeT& ty = s->host_tab.type[t];
     out->type_envs[t] = s->type_cnt[t];
@@ -497,8 +510,65 @@ int brax_rollout_tape(const brax_sys* sys, const brax_state* in, const float* ac
       if (nf) HIP_TRY(launch_fill_u8(s->d_nonfinite, s->E, 0, cs));
       return BRAX_OK;
     }
-    HIP_TRY(launch_fused(c, s->d_work, (int)s->work.size(), s->waves_per_block, F(in), F(out), acts, T, 0,
+    // the adjoint's work list, so that both sides index the tape by the same wavefronts
+    HIP_TRY(launch_fused(c, s->d_vjp_work, (int)s->vjp_work.size(), 1, F(in), F(out), acts, T, 0,
                          Fields{nullptr, nullptr, nullptr, nullptr}, nf, cs, tape, s->smax));
+    return BRAX_OK;
+  });
+}
+
+int brax_env_configure(brax_sys* s, const brax_env_params* params) {
+  if (!s || !params) return fail(BRAX_E_ARG, "NULL argument");
+  if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
+  EnvT h[MAXT] = {};
+  for (int t = 0; t < s->n_types; ++t) {
+    const brax_env_params& p = params[t];
+    if (p.root < 0 || p.root >= s->host_tab.type[t].nb)
+      return fail(BRAX_E_ARG, "type %d: root body %d out of range [0, %d)", t, p.root, s->host_tab.type[t].nb);
+    if (!(p.z_min <= p.z_max)) return fail(BRAX_E_ARG, "type %d: z_min > z_max", t);
+    h[t] = EnvT{p.root, p.forward_weight, p.healthy_reward, p.ctrl_cost, p.z_min, p.z_max};
+  }
+  DeviceGuard g(s->device);
+  HIP_TRY(hipDeviceSynchronize());  // a running call may read the old parameters
+  if (!s->d_env) {
+    hipError_t e1 = hipMalloc(&s->d_env, sizeof(EnvT) * MAXT);
+    hipError_t e2 = hipMalloc(&s->d_env_x0, sizeof(float) * std::max(s->E, 1));
+    if (e1 != hipSuccess || e2 != hipSuccess) return fail(BRAX_E_NOMEM, "environment-layer allocation failed");
+  }
+  HIP_TRY(hipMemcpy(s->d_env, h, sizeof(EnvT) * MAXT, hipMemcpyHostToDevice));
+  s->env_ready = true;
+  return BRAX_OK;
+}
+
+int brax_env_step(const brax_sys* sys, const brax_state* in, const float* act, const brax_state* reset,
+                  brax_state* out, float* obs, float* reward, uint8_t* done, int32_t flags, void* stream) {
+  brax_sys* s = const_cast<brax_sys*>(sys);
+  if (!s) return fail(BRAX_E_ARG, "sys is NULL");
+  if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
+  if (!s->env_ready) return fail(BRAX_E_ARG, "brax_env_configure has not been called");
+  if (flags & BRAX_PLAIN) return fail(BRAX_E_UNSUPPORTED, "the environment step runs on the fused path only");
+  if (s->E == 0) return check_flags(flags);
+  if (!state_ok(in) || !state_ok(out) || !state_ok(reset)) return fail(BRAX_E_ARG, "state has a NULL field");
+  if (!act && s->Am > 0) return fail(BRAX_E_ARG, "act is NULL");
+  if (!obs || !reward || !done) return fail(BRAX_E_ARG, "obs, reward or done is NULL");
+  if (reset->pos == out->pos) return fail(BRAX_E_ARG, "reset may not alias out");
+  int rc = check_flags(flags);
+  if (rc) return rc;
+  DeviceGuard g(s->device);
+  hipStream_t st = (hipStream_t)stream;
+  const int omax = 11 + 2 * s->Dm;
+  GraphKey key{};
+  key.kind = 5;
+  key.flags = flags;
+  key.T = 1;
+  const void* ptrs[] = {in->pos, in->rot, act, reset->pos, reset->rot, out->pos, out->rot, obs, reward, done};
+  std::memcpy(key.p, ptrs, sizeof ptrs);
+  return run_maybe_graph(s, flags & BRAX_GRAPH, key, st, [&](hipStream_t cs) -> int {
+    LaunchCtx c = s->ctx();
+    HIP_TRY(launch_env_pre(c, s->d_env, F(in), s->d_env_x0, cs));
+    HIP_TRY(launch_fused(c, s->d_work, (int)s->work.size(), s->waves_per_block, F(in), F(out), act, 1, 0,
+                         Fields{nullptr, nullptr, nullptr, nullptr}, (flags & BRAX_NONFINITE_FLAGS) != 0, cs));
+    HIP_TRY(launch_env(c, s->d_env, omax, s->d_env_x0, F(out), act, F(reset), obs, reward, done, cs));
     return BRAX_OK;
   });
 }
@@ -692,6 +762,40 @@ int brax_step_vjp(const brax_sys* sys, const brax_state* in, const float* act, c
     LaunchCtx c = s->ctx();
     VjpSched sched{s->d_vjp_work, (int)s->vjp_work.size(), 1, s->d_jslot, s->d_cslot};
     HIP_TRY(launch_vjp(c, s->vjp, sched, F(in), act, F(g_out), F(g_in), g_act, (flags & BRAX_PLAIN) != 0, cs));
+    return BRAX_OK;
+  });
+}
+
+int brax_step_vjp_params(const brax_sys* sys, const brax_state* in, const float* act, const brax_state* g_out,
+                         brax_state* g_in, float* g_act, float* g_params, int32_t flags, void* stream) {
+  brax_sys* s = const_cast<brax_sys*>(sys);
+  if (!s) return fail(BRAX_E_ARG, "sys is NULL");
+  if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
+  if (flags & BRAX_PLAIN) return fail(BRAX_E_UNSUPPORTED, "parameter cotangents are computed on the fused path only");
+  if (s->E == 0) return check_flags(flags);
+  if (!state_ok(in) || !state_ok(g_out) || !state_ok(g_in)) return fail(BRAX_E_ARG, "state has a NULL field");
+  if (!act && s->Am > 0) return fail(BRAX_E_ARG, "act is NULL");
+  if (!g_act && s->Am > 0) return fail(BRAX_E_ARG, "g_act is NULL");
+  if (!g_params) return fail(BRAX_E_ARG, "g_params is NULL");
+  if (g_in->pos == in->pos || g_in->pos == g_out->pos) return fail(BRAX_E_ARG, "g_in may not alias in or g_out");
+  int rc = check_flags(flags);
+  if (rc) return rc;
+  int p_max = 0;
+  for (int t = 0; t < s->n_types; ++t)
+    p_max = std::max(p_max, 4 * s->host_tab.type[t].nb + 5 * s->host_tab.type[t].nj + s->host_tab.type[t].na + 1);
+  DeviceGuard g(s->device);
+  hipStream_t st = (hipStream_t)stream;
+  GraphKey key{};
+  key.kind = 6;
+  key.flags = flags;
+  key.T = 1;
+  const void* ptrs[] = {in->pos, in->rot, act, g_out->pos, g_out->rot, g_out->vel, g_out->ang, g_in->pos, g_in->rot,
+                        g_act, g_params};
+  std::memcpy(key.p, ptrs, sizeof ptrs);
+  return run_maybe_graph(s, flags & BRAX_GRAPH, key, st, [&](hipStream_t cs) -> int {
+    LaunchCtx c = s->ctx();
+    VjpSched sched{s->d_vjp_work, (int)s->vjp_work.size(), 1, s->d_jslot, s->d_cslot};
+    HIP_TRY(launch_vjp_params(c, sched, F(in), act, F(g_out), F(g_in), g_act, g_params, p_max, cs));
     return BRAX_OK;
   });
 }

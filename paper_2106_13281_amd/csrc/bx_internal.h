@@ -87,7 +87,8 @@ struct LaunchCtx {
 
 hipError_t launch_default_qp(const LaunchCtx& c, const float* angles, const float* root_off, Fields out,
                              hipStream_t s);
-// tape (nullable): also write tape[T][smax][TAPE_N][Bm][E] (see bx_access.h).
+// tape (nullable): also write the wavefront-major tape
+// [T][smax][n_work][TAPE_N][64] (see bx_access.h).
 hipError_t launch_fused(const LaunchCtx& c, const WaveWork* work, int n_work, int waves_per_block, Fields in,
                         Fields out, const float* acts, int T, int save_every, Fields traj, bool flags, hipStream_t s,
                         float* tape = nullptr, int smax = 0);
@@ -97,6 +98,12 @@ hipError_t launch_fused(const LaunchCtx& c, const WaveWork* work, int n_work, in
 hipError_t launch_plain_step(const LaunchCtx& c, Fields in, Fields out, const float* act, float* const* jslot,
                              float* const* cslot, bool flags, hipStream_t s, float* tape = nullptr);
 hipError_t launch_copy_state(const LaunchCtx& c, Fields in, Fields out, hipStream_t s);
+// Environment layer: k_env_pre keeps each environment's root x before the
+// step (x0 [E]); k_env, after the step, writes reward, done and (after the
+// reset of finished environments) the observations [Omax][E].
+hipError_t launch_env_pre(const LaunchCtx& c, const EnvT* env, Fields in, float* x0, hipStream_t s);
+hipError_t launch_env(const LaunchCtx& c, const EnvT* env, int Omax, const float* x0, Fields out,
+                      const float* act, Fields reset, float* obs, float* reward, uint8_t* done, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, int n, uint8_t v, hipStream_t s);
 
 }  // namespace bx

@@ -258,16 +258,16 @@ __global__ void k_plain_collision(const Tables* __restrict__ tab, int t, const i
 // registers across all substeps and steps; only actions are read per step.
 
 // TAPE: also write each substep's tape record (state before the kinematic
-// update, total torque, count of applied contacts) to
-// tape[step][sub][TAPE_N][Bm][E], for the adjoint that reads it instead of
-// recomputing the step.
+// update, total torque, count of applied contacts) to the wavefront-major
+// tape[step][sub][work item w of n_work][TAPE_N][64], for the adjoint that
+// reads it instead of recomputing the step.
 template <int MAXDOF, bool TAPE>
 __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const WaveWork& wk,
                                           const int32_t* __restrict__ env_list, const int32_t* __restrict__ type_off,
                                           int E, int Bm, const Fields& in, const Fields& out,
                                           const float* __restrict__ acts, int Am, int T, int save_every,
                                           const Fields& traj, uint8_t* nonfinite, float* __restrict__ tape,
-                                          int smax) {
+                                          int smax, int w, int n_work) {
   const int t = wk.type;
   const TypeT ty = tab->type[t];
   const int nb = ty.nb;
@@ -304,8 +304,8 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
     if (has_joint && step + 1 < T)
       for (int x = 0; x < MAXDOF; ++x) raw_next[x] = act_raw(acts + (size_t)(step + 1) * Am * E, J, x, e, E);
     for (int sub = 0; sub < ty.substeps; ++sub) {
-      float* tp = TAPE ? tape + ((size_t)step * smax + sub) * TAPE_N * Bm * E : nullptr;
-      if (TAPE && live) tape_state(tp, s, b, e, Bm, E);
+      float* tp = TAPE ? tape + (((size_t)step * smax + sub) * n_work + w) * TAPE_N * 64 : nullptr;
+      if (TAPE) wtape_state(tp, s, lane);
       kinematic_unmasked(s, h);
       // parent's post-kinematic state: the cross-lane reads are issued first
       // and this body's rotation is formed while they are in flight; the
@@ -362,10 +362,7 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
           torque += tq;
         }
       }
-      if (TAPE && live) {
-        tape_torque(tp, torque, b, e, Bm, E);
-        tape_count(tp, cnt, b, e, Bm, E);
-      }
+      if (TAPE) wtape_rest(tp, torque, cnt, lane);
       potential(B, ty, s, f, force, torque);
       collision(B, s, dv, dw, cnt);
     }
@@ -400,17 +397,17 @@ __global__ __launch_bounds__(256) void k_fused(const Tables* __restrict__ tab, c
   if (tape == nullptr) {
     if (one)
       fused_run<1, false>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
-                          nullptr, 0);
+                          nullptr, 0, w, n_work);
     else
       fused_run<3, false>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
-                          nullptr, 0);
+                          nullptr, 0, w, n_work);
   } else {
     if (one)
       fused_run<1, true>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
-                         tape, smax);
+                         tape, smax, w, n_work);
     else
       fused_run<3, true>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
-                         tape, smax);
+                         tape, smax, w, n_work);
   }
 }
 
@@ -425,13 +422,101 @@ __global__ void k_copy_state(int n3, int n4, Fields in, Fields out) {
   if (i < n4) out.rot[i] = in.rot[i];
 }
 
+static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+// ------------------------------------------------------------------ environment layer
+// One thread per environment (SoA reads coalesce over environments).
+__global__ void k_env_pre(const Tables* __restrict__ tab, const EnvT* __restrict__ env,
+                          const int32_t* __restrict__ env_type, int E, int Bm, Fields in, float* __restrict__ x0) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const int root = env[env_type[e]].root;
+  x0[e] = in.pos[(size_t)root * E + e];
+}
+
+// Locomotion reward, termination, reset and observation (Section 4.2):
+//   reward = forward_weight (x_root' - x_root) / dt + healthy_reward [healthy]
+//            - ctrl_cost sum_k a_k^2,  healthy = z_min <= z_root' <= z_max,
+//   done = not healthy; a finished environment takes its reset state; the
+//   observation of the (reset) state is [z_root, q_root, v_root, w_root,
+//   joint angles (D), (w_child - w_parent) . Euler axis (D)], zero-padded.
+__global__ void k_env(const Tables* __restrict__ tab, const EnvT* __restrict__ env,
+                      const int32_t* __restrict__ env_type, int E, int Bm, int Am, int Omax,
+                      const float* __restrict__ x0, Fields out, const float* __restrict__ act, Fields reset,
+                      float* __restrict__ obs, float* __restrict__ reward, uint8_t* __restrict__ done) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const int t = env_type[e];
+  const TypeT& ty = tab->type[t];
+  const EnvT P = env[t];
+  const size_t BE = (size_t)Bm * E;
+  const float x1 = out.pos[(size_t)P.root * E + e];
+  const float z1 = out.pos[2 * BE + (size_t)P.root * E + e];
+  const bool healthy = z1 >= P.z_min && z1 <= P.z_max;
+  float ctrl = 0.f;
+  for (int k = 0; k < ty.na; ++k) {
+    const float a = act[(size_t)k * E + e];
+    ctrl += a * a;
+  }
+  reward[e] = P.forward_weight * (x1 - x0[e]) / ty.dt + (healthy ? P.healthy_reward : 0.f) - P.ctrl_cost * ctrl;
+  done[e] = healthy ? 0 : 1;
+  if (!healthy) {
+    for (int b = 0; b < Bm; ++b) {
+      const size_t i = (size_t)b * E + e;
+      for (int c = 0; c < 3; ++c) {
+        out.pos[c * BE + i] = reset.pos[c * BE + i];
+        out.vel[c * BE + i] = reset.vel[c * BE + i];
+        out.ang[c * BE + i] = reset.ang[c * BE + i];
+      }
+      for (int c = 0; c < 4; ++c) out.rot[c * BE + i] = reset.rot[c * BE + i];
+    }
+  }
+  auto load = [&](int b) {
+    const size_t i = (size_t)b * E + e;
+    Body s;
+    s.p = V(out.pos[i], out.pos[BE + i], out.pos[2 * BE + i]);
+    s.q = q4{out.rot[i], out.rot[BE + i], out.rot[2 * BE + i], out.rot[3 * BE + i]};
+    s.v = V(out.vel[i], out.vel[BE + i], out.vel[2 * BE + i]);
+    s.w = V(out.ang[i], out.ang[BE + i], out.ang[2 * BE + i]);
+    return s;
+  };
+  const Body r = load(P.root);
+  const float head[11] = {r.p.z, r.q.w, r.q.x, r.q.y, r.q.z, r.v.x, r.v.y, r.v.z, r.w.x, r.w.y, r.w.z};
+  for (int k = 0; k < 11; ++k) obs[(size_t)k * E + e] = head[k];
+  const int D = ty.ndof;
+  for (int j = 0; j < ty.nj; ++j) {
+    const JointT& J = tab->joint[t][j];
+    const Body Pb = load(J.parent), Cb = load(J.child);
+    const JointGeo g = joint_geo<3>(J, quat_to_mat(Pb.q), quat_to_mat(Cb.q));
+    const v3 wrel = Cb.w - Pb.w;
+    for (int k = 0; k < J.dof; ++k) {
+      obs[(size_t)(11 + J.dof0 + k) * E + e] = g.th[k];
+      obs[(size_t)(11 + D + J.dof0 + k) * E + e] = dot(wrel, g.ax[k]);
+    }
+  }
+  for (int k = 11 + 2 * D; k < Omax; ++k) obs[(size_t)k * E + e] = 0.f;
+}
+
+hipError_t launch_env_pre(const LaunchCtx& c, const EnvT* env, Fields in, float* x0, hipStream_t s) {
+  if (c.E == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_env_pre, dim3(cdiv(c.E, 256)), dim3(256), 0, s, c.tab, env, c.env_type, c.E, c.Bm, in, x0);
+  return hipGetLastError();
+}
+
+hipError_t launch_env(const LaunchCtx& c, const EnvT* env, int Omax, const float* x0, Fields out, const float* act,
+                      Fields reset, float* obs, float* reward, uint8_t* done, hipStream_t s) {
+  if (c.E == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_env, dim3(cdiv(c.E, 256)), dim3(256), 0, s, c.tab, env, c.env_type, c.E, c.Bm, c.Am, Omax,
+                     x0, out, act, reset, obs, reward, done);
+  return hipGetLastError();
+}
+
 __global__ void k_fill_u8(uint8_t* p, int n, uint8_t v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }
 
 // ------------------------------------------------------------------ launchers
-static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
 hipError_t launch_default_qp(const LaunchCtx& c, const float* angles, const float* root_off, Fields out,
                              hipStream_t s) {

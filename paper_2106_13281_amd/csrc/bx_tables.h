@@ -72,6 +72,15 @@ struct Tables {
   int32_t topo[MAXT][MAXB];  // bodies, every parent before its children
 };
 
+// Environment-layer parameters of one system type (reward, termination).
+struct EnvT {
+  int32_t root;            // body whose x progress is rewarded and whose height decides termination
+  float forward_weight;    // reward per m/s of root x velocity over the step
+  float healthy_reward;    // reward while the root height is within [z_min, z_max]
+  float ctrl_cost;         // cost per unit of sum_k a_k^2 (actions as given)
+  float z_min, z_max;      // healthy root heights (m)
+};
+
 // One wavefront's share of the fused launch: `count` environments of one
 // type, taken from that type's environment list starting at `k0`.
 struct WaveWork {

@@ -27,8 +27,13 @@ void vjp_free(VjpWork& w);
 // g_in <- d(step)/d(in)^T g_out, g_act <- d(step)/d(act)^T g_out (both overwritten).
 hipError_t launch_vjp(const LaunchCtx& c, VjpWork& w, const VjpSched& sched, Fields in, const float* act,
                       Fields g_out, Fields g_in, float* g_act, bool plain, hipStream_t s);
-// The same adjoint from the step's forward tape tape[Smax][TAPE_N][Bm][E]
-// (written by the fused forward), without recomputing the step.
+// The adjoint with the cotangents of the system parameters, per environment,
+// g_params[p_max][E] (see brax_step_vjp_params for the order).
+hipError_t launch_vjp_params(const LaunchCtx& c, const VjpSched& sched, Fields in, const float* act, Fields g_out,
+                             Fields g_in, float* g_act, float* g_params, int p_max, hipStream_t s);
+// The same adjoint from the step's wavefront-major forward tape
+// [Smax][n_work][TAPE_N][64] (written by the fused forward with the same
+// work list), without recomputing the step.
 hipError_t launch_vjp_tape(const LaunchCtx& c, const VjpSched& sched, const float* tape, const float* act,
                            Fields g_out, Fields g_in, float* g_act, hipStream_t s);
 

@@ -253,15 +253,22 @@ __device__ __forceinline__ Bar shfl_bar(const Bar& s, int src) {
 __device__ __forceinline__ v3 shfl3(v3 a, int src) { return V(shfl(a.x, src), shfl(a.y, src), shfl(a.z, src)); }
 
 // FROM_TAPE: the forward substeps are not recomputed; their tape records are
-// read from hbm_tape[sub][TAPE_N][Bm][E] (written by the fused forward with
-// a tape) instead of the LDS tape.
-template <int MAXDOF, bool FROM_TAPE>
+// read from the wavefront-major hbm_tape[sub][work item w of n_work][TAPE_N][64]
+// (written by the fused forward with a tape, same work list) instead of the
+// LDS tape.
+// PARAMS: also the cotangents of the system parameters, per environment,
+// into g_params[P_max][E] (order: mass per body, inertia per body x, y, z,
+// per joint k_lin, c_lin, k_ang, c_ang, k_lim, strength per action,
+// friction); the LDS tape then also keeps each body's total force.
+template <int MAXDOF, bool FROM_TAPE, bool PARAMS = false>
 __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, const WaveWork& wk,
                                               const int32_t* __restrict__ env_list,
                                               const int32_t* __restrict__ type_off, int E, int Bm, int Am,
                                               const Fields& in, const float* __restrict__ act, const Fields& g_out,
                                               const Fields& g_in, float* __restrict__ g_act, float* lds,
-                                              const float* __restrict__ hbm_tape) {
+                                              const float* __restrict__ hbm_tape, int w, int n_work,
+                                              float* __restrict__ g_params = nullptr, int p_max = 0) {
+  constexpr int TN = PARAMS ? TAPE_N + 3 : TAPE_N;  // LDS tape rows per substep
   const int t = wk.type;
   const TypeT ty = tab->type[t];
   const int nb = ty.nb;
@@ -291,7 +298,7 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
   // forward substeps with their tape in LDS
   Body s = FROM_TAPE ? Body{} : load_body(in, b, e, Bm, E);
   for (int sub = 0; sub < (FROM_TAPE ? 0 : ty.substeps); ++sub) {
-    float* tp = lds + sub * TAPE_N * 64 + lane;
+    float* tp = lds + sub * TN * 64 + lane;
     tp[0] = s.p.x; tp[64] = s.p.y; tp[128] = s.p.z;
     tp[192] = s.q.w; tp[256] = s.q.x; tp[320] = s.q.y; tp[384] = s.q.z;
     tp[448] = s.v.x; tp[512] = s.v.y; tp[576] = s.v.z;
@@ -347,6 +354,11 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
     }
     tp[832] = torque.x; tp[896] = torque.y; tp[960] = torque.z;
     tp[1024] = (float)cnt;
+    if (PARAMS) {
+      tp[1088] = force.x;
+      tp[1152] = force.y;
+      tp[1216] = force.z;
+    }
     potential(B, ty, s, f, force, torque);
     collision(B, s, dv, dw, cnt);
   }
@@ -354,17 +366,19 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
   // reverse substeps
   Bar G = live ? load_bar(g_out, b, e, Bm, E) : bar_zero();
   float ga[3] = {0.f, 0.f, 0.f};
+  // parameter cotangents of this lane: its body's 1/m, inertia and
+  // inverse inertia, its joint's five constants and strengths, friction
+  float invm_bar = 0.f, mu_bar = 0.f, Ib[3] = {0.f, 0.f, 0.f}, Iinvb[3] = {0.f, 0.f, 0.f};
+  float jbar[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, gbar[3] = {0.f, 0.f, 0.f};
   for (int sub = ty.substeps - 1; sub >= 0; --sub) {
     Body pre;
-    v3 ttot;
+    v3 ttot, ftot = V(0.f, 0.f, 0.f);
     int n;
     if (FROM_TAPE) {
-      const float* tp = hbm_tape + (size_t)sub * TAPE_N * Bm * E;
-      pre = tape_load_state(tp, b, e, Bm, E);
-      ttot = tape_load_torque(tp, b, e, Bm, E);
-      n = tape_load_count(tp, b, e, Bm, E);
+      wtape_load(hbm_tape + ((size_t)sub * n_work + w) * TAPE_N * 64, lane, pre, ttot, n);
     } else {
-      const float* tp = lds + sub * TAPE_N * 64 + lane;
+      const float* tp = lds + sub * TN * 64 + lane;
+      if (PARAMS) ftot = V(tp[1088], tp[1152], tp[1216]);
       pre.p = V(tp[0], tp[64], tp[128]);
       pre.q = q4{tp[192], tp[256], tp[320], tp[384]};
       pre.v = V(tp[448], tp[512], tp[576]);
@@ -380,7 +394,7 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
     // this body's frame cotangents from every item of the substep, turned
     // into its quaternion cotangent once at the end
     FrameBar fr = framebar_zero();
-    Bar tot = integrate_adj(B, ty, post, f, ttot, n, G, fb, tb, dvb, dwb, fr);
+    Bar tot = integrate_adj(B, ty, post, f, ttot, n, G, fb, tb, dvb, dwb, fr, ftot, invm_bar);
     v3 fbP = shfl3(fb, src_parent), tbP = shfl3(tb, src_parent);
     Bar bP = bar_zero(), bC = bar_zero();
     {
@@ -390,7 +404,8 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
       const v3 z3 = V(0.f, 0.f, 0.f);
       float ab[3];
       joint_eval_adj<MAXDOF>(J, P, quat_to_mat(P.q), post, f.R, a, has_joint ? fb : z3, has_joint ? tb : z3,
-                             has_joint ? fbP : z3, has_joint ? tbP : z3, bP, bC, ab, fr);
+                             has_joint ? fbP : z3, has_joint ? tbP : z3, bP, bC, ab, fr, PARAMS ? jbar : nullptr,
+                             PARAMS ? gbar : nullptr);
       for (int x = 0; x < MAXDOF; ++x) ga[x] += ab[x];
     }
     // children's cotangents for this body: reads in flight during the contact adjoints
@@ -404,13 +419,26 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
     }
     auto contact_back = [&](const ContactT& C) {
       bool applied;
-      Bar bc = contact_adj(C, ty, B, post, f, dvb, dwb, applied, fr);
+      Bar bc = contact_adj(C, ty, B, post, f, dvb, dwb, applied, fr, invm_bar, mu_bar);
       if (applied) bar_add(tot, bc);
     };
     if (n_con > 0) contact_back(Creg[0]);
     if (n_con > 1) contact_back(Creg[1]);
     for (int c = REG_CONTACTS; c < n_con; ++c) contact_back(tab->contact[t][B.c0 + c]);
     bar_add(tot, bC);
+    if (PARAMS) {
+      // Iw = R diag(I) R^T, Iwinv = R diag(1/I) R^T: d/dI_k = r_k^T S_bar r_k (r_k column k of R;
+      // an off-diagonal cotangent already holds both of its entries)
+      for (int k = 0; k < 3; ++k) {
+        const v3 r = col(f.R, k);
+        auto quad = [&](const s3& S) {
+          return S.xx * r.x * r.x + S.yy * r.y * r.y + S.zz * r.z * r.z + S.xy * r.x * r.y + S.xz * r.x * r.z +
+                 S.yz * r.y * r.z;
+        };
+        Ib[k] += quad(fr.Iwb);
+        Iinvb[k] += quad(fr.Iwinvb);
+      }
+    }
     frame_adj(B, post, f, fr, tot.q);
 #pragma unroll
     for (int i = 0; i < GATHER; ++i)
@@ -432,6 +460,26 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
     if (b == 0)
       for (int x = ty.na; x < Am; ++x) g_act[(size_t)x * E + e] = 0.f;
   }
+  if (PARAMS) {
+    // friction: summed over the environment's lanes (all lanes take part in the permutes)
+    float mu_env = 0.f;
+    for (int i = 0; i < nb; ++i) mu_env += shfl(mu_bar, base + i);
+    if (live) {
+      const int nj = ty.nj, np = 4 * nb + 5 * nj + ty.na + 1;
+      g_params[(size_t)b * E + e] = -invm_bar * B.inv_m * B.inv_m;  // m = 1 / inv_m
+      for (int k = 0; k < 3; ++k)
+        g_params[(size_t)(nb + 3 * b + k) * E + e] = Ib[k] - Iinvb[k] * B.Iinv[k] * B.Iinv[k];
+      if (has_joint) {
+        for (int q = 0; q < 5; ++q) g_params[(size_t)(4 * nb + q * nj + B.joint) * E + e] = jbar[q];
+        for (int x = 0; x < MAXDOF; ++x)
+          if (x < J.dof && J.act[x] >= 0) g_params[(size_t)(4 * nb + 5 * nj + J.act[x]) * E + e] = gbar[x];
+      }
+      if (b == 0) {
+        g_params[(size_t)(np - 1) * E + e] = mu_env;
+        for (int q = np; q < p_max; ++q) g_params[(size_t)q * E + e] = 0.f;
+      }
+    }
+  }
 }
 
 __global__ __launch_bounds__(64) void k_fused_vjp(const Tables* __restrict__ tab, const WaveWork* __restrict__ work,
@@ -446,9 +494,31 @@ __global__ __launch_bounds__(64) void k_fused_vjp(const Tables* __restrict__ tab
   float* lds = lds_tape;
   (void)smax;
   if (tab->type[wk.type].max_dof <= 1)
-    fused_vjp_run<1, false>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds, nullptr);
+    fused_vjp_run<1, false>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds, nullptr, w,
+                            n_work);
   else
-    fused_vjp_run<3, false>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds, nullptr);
+    fused_vjp_run<3, false>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds, nullptr, w,
+                            n_work);
+}
+
+// The adjoint of one step with the cotangents of the system parameters.
+__global__ __launch_bounds__(64) void k_fused_vjp_params(const Tables* __restrict__ tab,
+                                                         const WaveWork* __restrict__ work, int n_work,
+                                                         const int32_t* __restrict__ env_list,
+                                                         const int32_t* __restrict__ type_off, int E, int Bm, int Am,
+                                                         Fields in, const float* __restrict__ act, Fields g_out,
+                                                         Fields g_in, float* __restrict__ g_act,
+                                                         float* __restrict__ g_params, int p_max) {
+  extern __shared__ float lds_tape[];
+  const int w = xcd_block(blockIdx.x, gridDim.x);
+  if (w >= n_work) return;
+  const WaveWork wk = work[w];
+  if (tab->type[wk.type].max_dof <= 1)
+    fused_vjp_run<1, false, true>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds_tape,
+                                  nullptr, w, n_work, g_params, p_max);
+  else
+    fused_vjp_run<3, false, true>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds_tape,
+                                  nullptr, w, n_work, g_params, p_max);
 }
 
 // The adjoint of one step from its forward tape in HBM (no recompute, no LDS).
@@ -463,9 +533,11 @@ __global__ __launch_bounds__(64) void k_fused_vjp_tape(const Tables* __restrict_
   const WaveWork wk = work[w];
   const Fields none{nullptr, nullptr, nullptr, nullptr};
   if (tab->type[wk.type].max_dof <= 1)
-    fused_vjp_run<1, true>(tab, wk, env_list, type_off, E, Bm, Am, none, act, g_out, g_in, g_act, nullptr, tape);
+    fused_vjp_run<1, true>(tab, wk, env_list, type_off, E, Bm, Am, none, act, g_out, g_in, g_act, nullptr, tape, w,
+                           n_work);
   else
-    fused_vjp_run<3, true>(tab, wk, env_list, type_off, E, Bm, Am, none, act, g_out, g_in, g_act, nullptr, tape);
+    fused_vjp_run<3, true>(tab, wk, env_list, type_off, E, Bm, Am, none, act, g_out, g_in, g_act, nullptr, tape, w,
+                           n_work);
 }
 
 }  // namespace
@@ -495,6 +567,17 @@ void vjp_free(VjpWork& w) {
   if (w.buf) (void)hipFree(w.buf);
   w.buf = nullptr;
   w.bytes = 0;
+}
+
+hipError_t launch_vjp_params(const LaunchCtx& c, const VjpSched& sched, Fields in, const float* act, Fields g_out,
+                             Fields g_in, float* g_act, float* g_params, int p_max, hipStream_t s) {
+  if (sched.n_work == 0) return hipSuccess;
+  size_t smax = 1;
+  for (int t = 0; t < c.n_types; ++t) smax = std::max(smax, (size_t)c.host_tab->type[t].substeps);
+  const size_t lds = smax * (TAPE_N + 3) * 64 * sizeof(float);
+  hipLaunchKernelGGL(k_fused_vjp_params, dim3(sched.n_work), dim3(64), lds, s, c.tab, sched.work, sched.n_work,
+                     c.env_list, c.type_off, c.E, c.Bm, c.Am, in, act, g_out, g_in, g_act, g_params, p_max);
+  return hipGetLastError();
 }
 
 hipError_t launch_vjp_tape(const LaunchCtx& c, const VjpSched& sched, const float* tape, const float* act,

@@ -109,6 +109,68 @@ def test_rollout_gradient_tape_and_recompute_agree():
     assert err.max() < 1e-4
 
 
+@pytest.mark.parametrize("name", SYSTEMS)
+def test_step_vjp_params_matches_oracle(name):
+    """Cotangents of the system parameters (masses, inertias, joint constants,
+    actuator strengths, friction) against central differences of the FP64
+    step; the state and action cotangents equal brax_step_vjp's."""
+    E = 16
+    o, X, acts = make_states(name, E, seed=7, warm=15, vel_noise=0.3)
+    a = acts[0]
+    g = np.random.default_rng(8).normal(size=X.shape).astype(np.float32).astype(np.float64)
+    pv = o.param_vjp(X, a.astype(np.float64), g)
+    _, mg = o.step(X, a.astype(np.float64), margins=True)
+    sysg = braxmi.System(synth.system_text(synth.WORKLOADS[name].system), E)
+    P = sysg.n_params[0]
+    assert P == pv.shape[1] == sysg.p_max
+    A = acts_dev(a[None])[0].contiguous()
+    g_in, g_act, g_par = sysg.step_vjp_params(to_dev(X), A, to_dev(g))
+    gp = g_par.cpu().numpy().T
+    err = normwise(gp, pv)
+    amb = mg.min(1) < 1e-5           # a kink within reach of the differences' perturbation
+    print(f"parameter vjp {name}: P {P} max err {err.max():.2e} non-ambiguous "
+          f"{err[~amb].max() if (~amb).any() else 0:.2e} ambiguous {int(amb.sum())}/{E}", flush=True)
+    bad = err >= GRAD_TOL
+    assert not (bad & ~amb).any(), err[bad & ~amb]
+    assert bad.mean() <= 0.1
+    g_in2, g_act2 = sysg.step_vjp(to_dev(X), A, to_dev(g))
+    for x, y in zip(g_in.fields(), g_in2.fields()):
+        assert torch.allclose(x, y, rtol=1e-5, atol=1e-5)
+    assert torch.allclose(g_act, g_act2, rtol=1e-5, atol=1e-5)
+
+
+def test_step_vjp_params_mixed_batch_layout():
+    """In a mixed batch each environment's parameter cotangents follow its own
+    type's order and the rows beyond its count are zero; they equal the
+    homogeneous batch's bit for bit."""
+    per = {n: make_states(n, 5, seed=19, warm=5) for n in MIXED}
+    descs = [synth.system_text(n) for n in MIXED]
+    env = [k % 4 for k in range(20)]
+    mixed = braxmi.System(descs, 20, env_desc=env)
+    bm, am = mixed.b_max, mixed.a_max
+    Xm = np.zeros((20, bm, 13))
+    Xm[:, :, 3] = 1.0
+    Am = np.zeros((1, 20, am), np.float32)
+    Gm = np.zeros((20, bm, 13))
+    rng = np.random.default_rng(20)
+    gs = {}
+    for t, n in enumerate(MIXED):
+        o, X, acts = per[n]
+        idx = [i for i in range(20) if env[i] == t]
+        gs[n] = rng.normal(size=X.shape)
+        Xm[idx, :o.nb], Am[0, idx, :o.na], Gm[idx, :o.nb] = X, acts[0], gs[n]
+    _, _, gp = mixed.step_vjp_params(to_dev(Xm, bm), acts_dev(Am, am)[0].contiguous(), to_dev(Gm, bm))
+    gp = gp.cpu().numpy().T
+    for t, n in enumerate(MIXED):
+        o, X, acts = per[n]
+        one = braxmi.System(descs[t], 5)
+        _, _, g1 = one.step_vjp_params(to_dev(X), acts_dev(acts[:1])[0].contiguous(), to_dev(gs[n]))
+        idx = [i for i in range(20) if env[i] == t]
+        P = mixed.n_params[t]
+        assert np.array_equal(gp[idx, :P], g1.cpu().numpy().T), n
+        assert not gp[idx, P:].any(), n
+
+
 def test_vjp_plain_and_fused_tapes_agree_and_are_deterministic():
     E = 64
     o, X, acts = make_states("biped", E, seed=13, warm=10)

@@ -453,6 +453,31 @@ def test_target_angle_actuator_discrete_oscillator(target):
         assert abs(tr[t, 0, 1, 10] - w) < 1e-10 and abs(tr[t, 0, 1, 11]) < 1e-12 and abs(tr[t, 0, 1, 12]) < 1e-12
 
 
+def test_parameter_vjp_closed_form_for_an_angle_actuated_hinge():
+    """One substep of the hinge above from rest-free state (theta0, w0): the
+    kinematic update gives theta1 = theta0 + 2 atan(h w0 / 2), then
+    w1 = w0 + h gear / I_x (target - theta1); so dw1/dgear = h (target -
+    theta1) / I_x, dw1/dI_x = -h gear (target - theta1) / I_x^2 and, through
+    the (zero) angular damper c_ang (w_parent - w_child), dw1/dc_ang = -h w0 /
+    I_x, while the other parameters (masses, springs, friction) do not move
+    w1."""
+    S, dt, I, gear, target = 1, 0.004, 0.05, 3.0, 0.3
+    o = oracle.Oracle(ANGLE_HINGE.format(S=S, dt=dt, I=I, gear=gear))
+    X = o.default_qp()[None].copy()
+    th0, w0 = 0.1, 0.8
+    X[0, 1, 3:7] = [math.cos(th0 / 2), math.sin(th0 / 2), 0.0, 0.0]
+    X[0, 1, 10] = w0
+    g = np.zeros_like(X)
+    g[0, 1, 10] = 1.0
+    names = o.param_names()
+    pv = o.param_vjp(X, np.array([[target]]), g)[0]
+    th1 = th0 + 2 * math.atan(dt * w0 / 2)
+    want = {("a_gear", (0,)): dt * (target - th1) / I, ("inertia", (1, 0)): -dt * gear * (target - th1) / I ** 2,
+            ("j_c_ang", (0,)): -dt * w0 / I}
+    for (name, idx), v in zip(names, pv):
+        assert abs(v - want.get((name, idx), 0.0)) < 1e-7 * max(1.0, abs(want.get((name, idx), 0.0))), (name, idx, v)
+
+
 def test_planar_masking_keeps_motion_in_the_plane():
     """Planar runner: every body has y translation and x, z rotation frozen
     (world axes), so y, v_y, w_x, w_z stay exactly at their reset values and
