@@ -213,13 +213,14 @@ class Oracle:
 
     def param_vjp(self, X, act, g_out, rel=1e-6):
         """g_out . d(step)/d(parameter) for every parameter (param_names order),
-        by central differences of the FP64 step: [E][P]."""
+        by central differences of the FP64 step with a relative step `rel`
+        (absolute for a zero parameter): [E][P]."""
         X = np.asarray(X, dtype=np.float64)
         g = np.asarray(g_out, dtype=np.float64).reshape(len(X), -1)
         out = []
         for name, idx in self.param_names():
             v = float(self._param(name, idx))
-            eps = rel * max(abs(v), 1.0)
+            eps = rel * (abs(v) if v != 0.0 else 1.0)
             try:
                 self._param(name, idx, v + eps)
                 fp = self.step(X, act)

@@ -134,9 +134,9 @@ def test_step_vjp_params_matches_oracle(name):
     assert not (bad & ~amb).any(), err[bad & ~amb]
     assert bad.mean() <= 0.1
     g_in2, g_act2 = sysg.step_vjp(to_dev(X), A, to_dev(g))
-    for x, y in zip(g_in.fields(), g_in2.fields()):
-        assert torch.allclose(x, y, rtol=1e-5, atol=1e-5)
-    assert torch.allclose(g_act, g_act2, rtol=1e-5, atol=1e-5)
+    got = np.concatenate([from_dev(g_in, o.nb).reshape(E, -1), g_act.cpu().numpy().T], 1)
+    ref = np.concatenate([from_dev(g_in2, o.nb).reshape(E, -1), g_act2.cpu().numpy().T], 1)
+    assert normwise(got, ref).max() < 1e-5
 
 
 def test_step_vjp_params_mixed_batch_layout():
