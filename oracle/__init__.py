@@ -19,11 +19,11 @@ import subprocess
 
 import numpy as np
 
-from .system import MAXA, MAXB, MAXC, MAXJ, System, euler_xyz, mat_to_quat, parse  # noqa: F401
+from .system import MAXA, MAXB, MAXC, MAXJ, MAXP, System, euler_xyz, mat_to_quat, parse  # noqa: F401
 
-NMARGIN = 7
+NMARGIN = 8
 JUMP_MARGINS = (0, 1, 2)
-KINK_MARGINS = (3, 4, 5, 6)
+KINK_MARGINS = (3, 4, 5, 6, 7)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "orc_step.cpp")
@@ -64,6 +64,12 @@ class _OrcSys(C.Structure):
         ("a_joint", C.c_int32 * MAXA), ("a_axis", C.c_int32 * MAXA),
         ("a_gear", C.c_double * MAXA),
         ("a_mode", C.c_int32 * MAXA),
+        ("np", C.c_int32), ("pad3", C.c_int32),
+        ("p_a", C.c_int32 * MAXP), ("p_b", C.c_int32 * MAXP), ("p_kind", C.c_int32 * MAXP),
+        ("p_a0", C.c_double * 3 * MAXP), ("p_a1", C.c_double * 3 * MAXP), ("p_ra", C.c_double * MAXP),
+        ("p_b0", C.c_double * 3 * MAXP), ("p_b1", C.c_double * 3 * MAXP), ("p_rb", C.c_double * MAXP),
+        ("p_ah", C.c_double * 3 * MAXP), ("p_bh", C.c_double * 3 * MAXP),
+        ("p_aR", C.c_double * 9 * MAXP), ("p_bR", C.c_double * 9 * MAXP),
     ]
 
 

@@ -44,7 +44,8 @@ namespace orc {
 
 thread_local int64_t g_flops = 0;
 
-enum { MAXB = 16, MAXJ = 16, MAXC = 96, MAXA = 48 };
+enum { MAXB = 16, MAXJ = 16, MAXC = 96, MAXA = 48, MAXP = 32 };
+enum { PP, PS, SP, SS, PB, BP };  // body-body candidate: first body's feature vs the second's
 
 // Flat system description filled by the Python side of the oracle
 // (oracle/__init__.py mirrors this struct field by field).
@@ -69,6 +70,13 @@ struct OrcSys {
   int32_t a_joint[MAXA], a_axis[MAXA];               // action k drives joint a_joint[k], axis a_axis[k]
   double a_gear[MAXA];
   int32_t a_mode[MAXA];                              // 0 torque, 1 target angle
+  // body-body contact candidates: bodies, kind, the first body's feature
+  // (point a0, segment a0-a1 or box centre a0 / rotation aR / half extents ah)
+  // and radius, the same for the second body; all in body frames
+  int32_t np, pad3;
+  int32_t p_a[MAXP], p_b[MAXP], p_kind[MAXP];
+  double p_a0[MAXP][3], p_a1[MAXP][3], p_ra[MAXP], p_b0[MAXP][3], p_b1[MAXP][3], p_rb[MAXP];
+  double p_ah[MAXP][3], p_bh[MAXP][3], p_aR[MAXP][9], p_bR[MAXP][9];
 };
 
 // ------------------------------------------------------------ small vectors
@@ -180,7 +188,7 @@ template <class T> void store_body(const Body<T>& b, T* X) {
 // The first three are jumps of the result itself; the last four are kinks
 // (the result is continuous, its derivative jumps), which matter only when
 // derivatives are compared.
-enum { NMARGIN = 7 };
+enum { NMARGIN = 8 };
 struct Margins {
   double contact_depth = 1e30;    // |penetration| of every candidate (m)
   double contact_speed = 1e30;    // |normal-impulse numerator| of candidates in contact (m/s)
@@ -189,9 +197,10 @@ struct Margins {
   double cone_gap = 1e30;         // |mu jn - s/kt| / (mu jn): Coulomb cone vs sticking
   double limit_gap = 1e30;        // distance of a free angle to its limits (rad)
   double clip_gap = 1e30;         // 1 - |a| of every action
+  double feature_gap = 1e30;      // distance of a closest-feature parameter to a clamp / face switch (m)
   void store(double* out) const {
     out[0] = contact_depth; out[1] = contact_speed; out[2] = angle_wrap; out[3] = slip_speed;
-    out[4] = cone_gap; out[5] = limit_gap; out[6] = clip_gap;
+    out[4] = cone_gap; out[5] = limit_gap; out[6] = clip_gap; out[7] = feature_gap;
   }
 };
 
@@ -340,6 +349,193 @@ void collider_apply(const OrcSys& s, int c, const Body<T>* B, const Derived<T>* 
   cnt[i] += 1;
 }
 
+// ------------------------------------------------------------ body-body contacts
+// Closest point of segment a-b to p (parameter clamped to [0, 1]).
+template <class T> V3<T> closest_on_segment(const V3<T>& p, const V3<T>& a, const V3<T>& b, Margins* mg) {
+  V3<T> d = sub(b, a);
+  T dd = dot(d, d);
+  if (!(val(dd) > 0)) return a;
+  T t = dot(sub(p, a), d) / dd;
+  if (mg) mg->feature_gap = std::min(mg->feature_gap, std::min(std::fabs(val(t)), std::fabs(val(t) - 1.0)) * std::sqrt(val(dd)));
+  t = clampv(t, 0.0, 1.0);
+  return add(a, scale(t, d));
+}
+// Closest points of segments p0-p1 and q0-q1: minimise |P(s) - Q(t)|^2 over
+// [0, 1]^2 (the unconstrained minimiser clamped in s, then t from s, then s
+// again from the clamped t).
+template <class T> void closest_segments(const V3<T>& p0, const V3<T>& p1, const V3<T>& q0, const V3<T>& q1, V3<T>& cp,
+                                         V3<T>& cq, Margins* mg) {
+  V3<T> d1 = sub(p1, p0), d2 = sub(q1, q0), r = sub(p0, q0);
+  T a = dot(d1, d1), e = dot(d2, d2), f = dot(d2, r);
+  if (!(val(a) > 0)) {
+    cp = p0;
+    cq = closest_on_segment(p0, q0, q1, mg);
+    return;
+  }
+  if (!(val(e) > 0)) {
+    cq = q0;
+    cp = closest_on_segment(q0, p0, p1, mg);
+    return;
+  }
+  T c = dot(d1, r), b = dot(d1, d2);
+  T den = a * e - b * b;
+  T s = T(0.0);
+  auto gap = [&](const T& x, double len) {
+    if (mg) mg->feature_gap = std::min(mg->feature_gap, std::min(std::fabs(val(x)), std::fabs(val(x) - 1.0)) * len);
+  };
+  if (val(den) > 0) {
+    s = (b * f - c * e) / den;
+    gap(s, std::sqrt(val(a)));
+    s = clampv(s, 0.0, 1.0);
+  }
+  T t = (b * s + f) / e;
+  gap(t, std::sqrt(val(e)));
+  if (val(t) < 0) {
+    t = T(0.0);
+    s = -c / a;
+    gap(s, std::sqrt(val(a)));
+    s = clampv(s, 0.0, 1.0);
+  } else if (val(t) > 1) {
+    t = T(1.0);
+    s = (b - c) / a;
+    gap(s, std::sqrt(val(a)));
+    s = clampv(s, 0.0, 1.0);
+  }
+  cp = add(p0, scale(s, d1));
+  cq = add(q0, scale(t, d2));
+}
+// Point p against a box (centre c, rotation R box to world, half extents h):
+// the box point closest to p and the outward normal; inside the box, the
+// nearest face point and that face's normal. Returns the signed distance of
+// p from the box surface along the normal (negative inside).
+template <class T> T point_box(const V3<T>& p, const V3<T>& c, const M3<T>& R, const double* h, V3<T>& cb, V3<T>& n,
+                               Margins* mg) {
+  V3<T> q = matvec(transpose(R), sub(p, c));
+  T qa[3] = {q.x, q.y, q.z};
+  bool inside = true;
+  for (int k = 0; k < 3; ++k) {
+    if (mg) mg->feature_gap = std::min(mg->feature_gap, std::fabs(std::fabs(val(qa[k])) - h[k]));
+    if (std::fabs(val(qa[k])) > h[k]) inside = false;
+  }
+  if (!inside) {
+    T cl[3];
+    for (int k = 0; k < 3; ++k) cl[k] = clampv(qa[k], -h[k], h[k]);
+    cb = add(c, matvec(R, V3<T>{cl[0], cl[1], cl[2]}));
+    V3<T> d = sub(p, cb);
+    T dist = osqrt(dot(d, d));
+    n = scale(T(1.0) / dist, d);
+    return dist;
+  }
+  int k = 0;
+  double best = 1e300;
+  for (int i = 0; i < 3; ++i) {
+    double g = h[i] - std::fabs(val(qa[i]));
+    if (g < best) {
+      best = g;
+      k = i;
+    }
+  }
+  if (mg) {  // a switch of the nearest face
+    for (int i = 0; i < 3; ++i)
+      if (i != k) mg->feature_gap = std::min(mg->feature_gap, std::fabs((h[i] - std::fabs(val(qa[i]))) - best));
+  }
+  const double sg = val(qa[k]) >= 0 ? 1.0 : -1.0;
+  T cl[3] = {qa[0], qa[1], qa[2]};
+  cl[k] = T(sg * h[k]);
+  cb = add(c, matvec(R, V3<T>{cl[0], cl[1], cl[2]}));
+  V3<T> ek = {T(k == 0 ? sg : 0.0), T(k == 1 ? sg : 0.0), T(k == 2 ? sg : 0.0)};
+  n = matvec(R, ek);
+  return T(-1.0) * (T(h[k]) - (sg > 0 ? qa[k] : T(-1.0) * qa[k]));
+}
+// One body-body contact candidate (the paper's collisions between colliders,
+// Section 6.2, with the impulse of the ground contact): closest features,
+// normal n from the second body to the first, depth; the velocity-level
+// normal impulse with restitution and Baumgarte term on the relative
+// velocity at the middle of the overlap, Coulomb friction from the same
+// state; +J on the first body, -J on the second. A body whose translations
+// (rotations) are all frozen contributes no inverse mass (inertia).
+template <class T>
+void pair_apply(const OrcSys& s, int c, const Body<T>* B, const Derived<T>* D, double h, V3<T>* dv, V3<T>* dw,
+                int* cnt, Margins* mg) {
+  const int ia = s.p_a[c], ib = s.p_b[c], kind = s.p_kind[c];
+  const Body<T>& A = B[ia];
+  const Body<T>& Bb = B[ib];
+  auto wpt = [&](const Body<T>& bd, const Derived<T>& d, const double* l) { return add(bd.p, matvec(d.R, const_vec<T>(l))); };
+  V3<T> ca, cb, n;
+  T dist;
+  const double ra = s.p_ra[c], rb = s.p_rb[c];
+  if (kind == PB || kind == BP) {
+    const bool box_b = kind == PB;
+    const Body<T>& pb = box_b ? A : Bb;            // the point's body
+    const Body<T>& xb = box_b ? Bb : A;            // the box's body
+    const Derived<T>& pd = box_b ? D[ia] : D[ib];
+    const Derived<T>& xd = box_b ? D[ib] : D[ia];
+    V3<T> p = wpt(pb, pd, box_b ? s.p_a0[c] : s.p_b0[c]);
+    V3<T> bc = wpt(xb, xd, box_b ? s.p_b0[c] : s.p_a0[c]);
+    M3<T> R = matmul(xd.R, const_mat<T>(box_b ? s.p_bR[c] : s.p_aR[c]));
+    V3<T> cbox, nb;
+    T sd = point_box(p, bc, R, box_b ? s.p_bh[c] : s.p_ah[c], cbox, nb, mg);
+    if (box_b) {
+      ca = p; cb = cbox; n = nb; dist = sd;
+    } else {
+      ca = cbox; cb = p; n = scale(T(-1.0), nb); dist = sd;
+    }
+  } else {
+    V3<T> a0 = wpt(A, D[ia], s.p_a0[c]), a1 = wpt(A, D[ia], s.p_a1[c]);
+    V3<T> b0 = wpt(Bb, D[ib], s.p_b0[c]), b1 = wpt(Bb, D[ib], s.p_b1[c]);
+    if (kind == PP) { ca = a0; cb = b0; }
+    else if (kind == PS) { ca = a0; cb = closest_on_segment(a0, b0, b1, mg); }
+    else if (kind == SP) { cb = b0; ca = closest_on_segment(b0, a0, a1, mg); }
+    else closest_segments(a0, a1, b0, b1, ca, cb, mg);
+    V3<T> d = sub(ca, cb);
+    dist = osqrt(dot(d, d));
+    if (!(val(dist) > 0)) return;
+    n = scale(T(1.0) / dist, d);
+  }
+  T depth = T(ra + rb) - dist;
+  if (mg) mg->contact_depth = std::min(mg->contact_depth, std::fabs(val(depth)));
+  if (!(val(depth) > 0)) return;
+  // the middle of the overlap: between the two surface points along n
+  V3<T> x = add(cb, scale(T(rb) - T(0.5) * depth, n));
+  V3<T> rA = sub(x, A.p), rB = sub(x, Bb.p);
+  auto frozen3 = [](const double* f) { return f[0] == 0 && f[1] == 0 && f[2] == 0; };
+  const double imA = frozen3(s.free_pos[ia]) ? 0.0 : 1.0 / s.mass[ia];
+  const double imB = frozen3(s.free_pos[ib]) ? 0.0 : 1.0 / s.mass[ib];
+  const bool rotA = !frozen3(s.free_rot[ia]), rotB = !frozen3(s.free_rot[ib]);
+  auto kfun = [&](const V3<T>& dir) {
+    T k = T(imA + imB);
+    if (rotA) k = k + dot(dir, cross(matvec(D[ia].Iwinv, cross(rA, dir)), rA));
+    if (rotB) k = k + dot(dir, cross(matvec(D[ib].Iwinv, cross(rB, dir)), rB));
+    return k;
+  };
+  V3<T> u = sub(add(A.v, cross(A.w, rA)), add(Bb.v, cross(Bb.w, rB)));
+  T vn = dot(u, n);
+  T num = T(-(1.0 + s.elasticity)) * vn + T(s.beta / h) * depth;
+  if (mg) mg->contact_speed = std::min(mg->contact_speed, std::fabs(val(num)));
+  if (!(val(num) > 0)) return;
+  T kn = kfun(n);
+  T jn = num / kn;
+  V3<T> J = scale(jn, n);
+  V3<T> ut = sub(u, scale(vn, n));
+  T sp = osqrt(dot(ut, ut));
+  if (mg) mg->slip_speed = std::min(mg->slip_speed, val(sp));
+  if (val(sp) > 0) {
+    V3<T> t = scale(T(1.0) / sp, ut);
+    T kt = kfun(t);
+    T stop = sp / kt;
+    T cap = T(s.friction) * jn;
+    T jt = (val(cap) <= val(stop)) ? cap : stop;
+    if (mg && val(cap) > 0) mg->cone_gap = std::min(mg->cone_gap, std::fabs(val(cap) - val(stop)) / val(cap));
+    J = sub(J, scale(jt, t));
+  }
+  dv[ia] = add(dv[ia], scale(T(imA), J));
+  if (rotA) dw[ia] = add(dw[ia], matvec(D[ia].Iwinv, cross(rA, J)));
+  dv[ib] = sub(dv[ib], scale(T(imB), J));
+  if (rotB) dw[ib] = sub(dw[ib], matvec(D[ib].Iwinv, cross(rB, J)));
+  cnt[ia] += 1;
+  cnt[ib] += 1;
+}
+
 // One environment step = `substeps` repetitions of Algorithm 1.
 template <class T>
 void step_env(const OrcSys& s, T* X, const T* act_in, Margins* mg) {
@@ -378,6 +574,7 @@ void step_env(const OrcSys& s, T* X, const T* act_in, Margins* mg) {
     for (int k = 0; k < s.na; ++k) actuator_apply(s, k, a[k], fr, ta);
     // dp_c += co.apply(qp)
     for (int c = 0; c < s.nc; ++c) collider_apply(s, c, B, D, h, dv, dw, cnt, mg);
+    for (int c = 0; c < s.np; ++c) pair_apply(s, c, B, D, h, dv, dw, cnt, mg);
     // qp = potential_integrator.apply(qp, dp_j + dp_a, dt)
     for (int i = 0; i < nb; ++i) {
       V3<T> g = const_vec<T>(s.gravity);

@@ -30,7 +30,11 @@ import re
 
 import numpy as np
 
-MAXB, MAXJ, MAXC, MAXA = 16, 16, 96, 48
+MAXB, MAXJ, MAXC, MAXA, MAXP = 16, 16, 96, 48, 32
+
+# body-body contact candidate kinds: the core feature of the first body
+# (point, segment or box) against that of the second
+PP, PS, SP, SS, PB, BP = range(6)
 
 
 # ----------------------------------------------------------------- parsing
@@ -212,6 +216,45 @@ def collider_points(col):
     return pts
 
 
+def _feature(col):
+    """Core feature of a collider in its body's frame: ('point', centre, r),
+    ('segment', (end0, end1), r) or ('box', (centre, R, half), 0)."""
+    R, c = col["R"], col["pos"]
+    if col["kind"] == "sphere":
+        return "point", c.copy(), col["radius"]
+    if col["kind"] == "capsule":
+        hh = col["length"] / 2 - col["radius"]
+        return "segment", (c + R @ np.array([0, 0, hh]), c + R @ np.array([0, 0, -hh])), col["radius"]
+    return "box", (c.copy(), R.copy(), np.asarray(col["half"], dtype=np.float64)), 0.0
+
+
+def pair_candidates(a, ca, b, cb):
+    """Contact candidates between collider ca of body a and cb of body b:
+    sphere-sphere, sphere-capsule, capsule-capsule, sphere-box; a capsule
+    against a box contributes its two end spheres; box-box is not modelled."""
+    ka, ga, ra = _feature(ca)
+    kb, gb, rb = _feature(cb)
+    z3, eye = np.zeros(3), np.eye(3)
+
+    def rec(kind, a0, a1, rA, b0, b1, rB, ah=z3, aR=eye, bh=z3, bR=eye):
+        return dict(a=a, b=b, kind=kind, a0=a0, a1=a1, ra=rA, b0=b0, b1=b1, rb=rB, ah=ah, aR=aR, bh=bh, bR=bR)
+    if ka == "box" and kb == "box":
+        raise ValueError("box-box body contacts are not modelled")
+    if ka == "point" and kb == "point":
+        return [rec(PP, ga, ga, ra, gb, gb, rb)]
+    if ka == "point" and kb == "segment":
+        return [rec(PS, ga, ga, ra, gb[0], gb[1], rb)]
+    if ka == "segment" and kb == "point":
+        return [rec(SP, ga[0], ga[1], ra, gb, gb, rb)]
+    if ka == "segment" and kb == "segment":
+        return [rec(SS, ga[0], ga[1], ra, gb[0], gb[1], rb)]
+    if kb == "box":
+        pts = [ga] if ka == "point" else list(ga)
+        return [rec(PB, p, p, ra, gb[0], gb[0], 0.0, bh=gb[2], bR=gb[1]) for p in pts]
+    pts = [gb] if kb == "point" else list(gb)
+    return [rec(BP, ga[0], ga[0], 0.0, p, p, rb, ah=ga[2], aR=ga[1]) for p in pts]
+
+
 # ----------------------------------------------------------------- the system
 class System:
     """FP64 system description plus the flat arrays the C++ oracle reads."""
@@ -360,6 +403,21 @@ class System:
         self.nc = len(self.contacts)
         if self.nc > MAXC:
             raise ValueError("too many contact candidates")
+        # body-body contact candidates of the declared pairs (every collider of
+        # the first body against every collider of the second)
+        bnames = {b["name"]: i for i, b in enumerate(self.bodies)}
+        self.pairs = []
+        for pm in cfg.get("body_contacts", []):
+            fa, fb = _one(pm, "first"), _one(pm, "second")
+            if fa not in bnames or fb not in bnames or fa == fb:
+                raise ValueError(f"body_contacts: bad pair {fa} / {fb}")
+            a, b = bnames[fa], bnames[fb]
+            for ca in self.bodies[a]["colliders"]:
+                for cb in self.bodies[b]["colliders"]:
+                    self.pairs += pair_candidates(a, ca, b, cb)
+        self.np = len(self.pairs)
+        if self.np > MAXP:
+            raise ValueError("too many body-body contact candidates")
         self.ndof = sum(j["dof"] for j in self.joints)
 
     # ------------------------------------------------------------- reset pose
@@ -465,4 +523,11 @@ class System:
         f["a_axis"] = [a[1] for a in self.actions]
         f["a_gear"] = [a[2] for a in self.actions]
         f["a_mode"] = [a[3] for a in self.actions]
+        f["np"] = self.np
+        for k in ("a", "b", "kind", "ra", "rb"):
+            f["p_" + k] = [p[k] for p in self.pairs]
+        for k in ("a0", "a1", "b0", "b1", "ah", "bh"):
+            f["p_" + k] = [p[k] for p in self.pairs]
+        f["p_aR"] = [p["aR"].reshape(9) for p in self.pairs]
+        f["p_bR"] = [p["bR"].reshape(9) for p in self.pairs]
         return f

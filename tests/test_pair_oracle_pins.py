@@ -1,0 +1,175 @@
+"""Pins of the oracle's body-body contacts (CPU).
+
+Geometry: the oracle reports |r_a + r_b - distance| of every candidate as a
+branch margin; with two bodies far from the ground and at rest its minimum
+is the smallest |gap| between the candidates' surfaces, which is checked
+against a convex minimisation of the distance between the core features
+(scipy; a capsule against a box is its two end spheres). Dynamics: equal and
+opposite impulses conserve total linear and angular momentum exactly
+(isotropic bodies, no gravity); a head-on elastic frictionless collision of
+equal spheres exchanges their velocities exactly.
+"""
+import numpy as np
+import pytest
+from scipy.optimize import minimize
+from scipy.spatial.transform import Rotation
+
+import oracle
+
+BODY = {
+    "sphere": 'colliders {{ sphere {{ radius: {r} }} }}',
+    "capsule": 'colliders {{ capsule {{ radius: {r} length: {L} }} }}',
+    "box": 'colliders {{ box {{ halfsize {{ x: {hx} y: {hy} z: {hz} }} }} }}',
+}
+
+
+def two_body(ka, kb, e=0.0, mu=0.5, beta=0.2, substeps=1, dt=0.002):
+    geo = dict(r=0.1, L=0.6, hx=0.2, hy=0.15, hz=0.1)
+    ga = BODY[ka].format(**geo)
+    gb = BODY[kb].format(**dict(geo, r=0.12, L=0.5))
+    return f"""substeps: {substeps}
+dt: {dt}
+friction: {mu}
+elasticity: {e}
+baumgarte: {beta}
+bodies {{ name: "a" mass: 2 inertia {{ x: 0.05 y: 0.05 z: 0.05 }} {ga} }}
+bodies {{ name: "b" mass: 3 inertia {{ x: 0.07 y: 0.07 z: 0.07 }} {gb} }}
+body_contacts {{ first: "a" second: "b" }}
+"""
+
+
+def features(o, X):
+    """World core features of the two bodies' (single) colliders."""
+    out = []
+    for i, b in enumerate(o.system.bodies):
+        col = b["colliders"][0]
+        R = Rotation.from_quat([X[i, 4], X[i, 5], X[i, 6], X[i, 3]]).as_matrix()
+        p = X[i, 0:3]
+        c = p + R @ col["pos"]
+        Rc = R @ col["R"]
+        if col["kind"] == "sphere":
+            out.append(("point", c, col["radius"]))
+        elif col["kind"] == "capsule":
+            hh = col["length"] / 2 - col["radius"]
+            out.append(("segment", (c + Rc @ [0, 0, hh], c - Rc @ [0, 0, hh]), col["radius"]))
+        else:
+            out.append(("box", (c, Rc, np.asarray(col["half"])), 0.0))
+    return out
+
+
+def param_point(kind, g, u):
+    if kind == "point":
+        return g
+    if kind == "segment":
+        return g[0] + u[0] * (g[1] - g[0])
+    c, R, h = g
+    return c + R @ (h * u)
+
+
+def surface_gap(fa, fb):
+    """min distance between the core features minus the radii (convex)."""
+    (ka, ga, ra), (kb, gb, rb) = fa, fb
+    na = {"point": 0, "segment": 1, "box": 3}[ka]
+    nb = {"point": 0, "segment": 1, "box": 3}[kb]
+    lo = lambda k: [0.0] if k == "segment" else [-1.0] * 3
+    bounds = [(l, 1.0) for l in (lo(ka) if na else [])] + [(l, 1.0) for l in (lo(kb) if nb else [])]
+
+    def f(x):
+        pa = param_point(ka, ga, x[:na])
+        pb = param_point(kb, gb, x[na:])
+        return float(np.sum((pa - pb) ** 2))
+    best = np.inf
+    for seed in range(6):
+        x0 = np.random.default_rng(seed).uniform(0.05, 0.95, na + nb)
+        if na + nb == 0:
+            best = f(np.zeros(0))
+            break
+        r = minimize(f, x0, bounds=bounds, method="L-BFGS-B", options=dict(ftol=1e-18, gtol=1e-14, maxiter=2000))
+        best = min(best, r.fun)
+    return np.sqrt(best) - ra - rb
+
+
+@pytest.mark.parametrize("ka,kb", [("sphere", "sphere"), ("sphere", "capsule"), ("capsule", "sphere"),
+                                   ("capsule", "capsule"), ("sphere", "box"), ("capsule", "box"),
+                                   ("box", "capsule")])
+def test_pair_depth_matches_convex_distance(ka, kb):
+    o = oracle.Oracle(two_body(ka, kb))
+    rng = np.random.default_rng(3)
+    checked = 0
+    for trial in range(40):
+        X = np.zeros((1, 2, 13))
+        X[0, :, 3:7] = Rotation.random(2, random_state=trial).as_quat()[:, [3, 0, 1, 2]]
+        X[0, 0, 0:3] = [0.0, 0.0, 5.0]
+        X[0, 1, 0:3] = [0.0, 0.0, 5.0] + rng.uniform(-0.4, 0.4, 3)
+        fa, fb = features(o, X[0])
+        # a capsule against a box is modelled by its two end spheres
+        split = lambda f: [("point", g, f[2]) for g in f[1]] if f[0] == "segment" else [f]
+        if "box" in (ka, kb):
+            fas, fbs = split(fa), split(fb)
+        else:
+            fas, fbs = [fa], [fb]
+        gaps = [surface_gap(x, y) for x in fas for y in fbs]
+        if "box" not in (ka, kb) or min(gaps) > -0.02:  # deep box penetrations: the nearest-face rule
+            _, mg = o.step(X, np.zeros((1, 0)), margins=True)
+            assert abs(mg[0, 0] - min(abs(g) for g in gaps)) < 1e-7, (trial, mg[0, 0], gaps)
+            checked += 1
+    assert checked >= 20
+
+
+@pytest.mark.parametrize("ka,kb", [("sphere", "capsule"), ("capsule", "capsule"), ("capsule", "box"),
+                                   ("sphere", "box")])
+def test_pair_collisions_conserve_momentum(ka, kb):
+    o = oracle.Oracle(two_body(ka, kb, e=0.3, mu=0.8, substeps=4, dt=0.004))
+    m = np.array([2.0, 3.0])
+    I = np.array([0.05, 0.07])
+    rng = np.random.default_rng(11)
+    hits = 0
+    for trial in range(12):
+        X = np.zeros((1, 2, 13))
+        X[0, :, 3:7] = Rotation.random(2, random_state=100 + trial).as_quat()[:, [3, 0, 1, 2]]
+        X[0, 0, 0:3] = [-0.35, 0.0, 5.0]
+        X[0, 1, 0:3] = [0.35, 0.0, 5.0] + rng.uniform(-0.05, 0.05, 3)
+        X[0, 0, 7:10] = [2.0, 0.0, 0.0] + rng.normal(0, 0.3, 3)
+        X[0, 1, 7:10] = [-2.0, 0.0, 0.0] + rng.normal(0, 0.3, 3)
+        X[0, :, 10:13] = rng.normal(0, 3.0, (2, 3))
+        _, tr, mg = o.rollout(X, np.zeros((60, 1, 0)), traj=True, margins=True)
+        P0 = (m[:, None] * X[0, :, 7:10]).sum(0)
+        L0 = (np.cross(X[0, :, 0:3], m[:, None] * X[0, :, 7:10]) + I[:, None] * X[0, :, 10:13]).sum(0)
+        P1 = (m[:, None] * tr[:, 0, :, 7:10]).sum(1)
+        L1 = (np.cross(tr[:, 0, :, 0:3], m[:, None] * tr[:, 0, :, 7:10]) + I[:, None] * tr[:, 0, :, 10:13]).sum(1)
+        assert np.abs(P1 - P0).max() < 1e-11 * (1 + np.abs(P0).max())
+        assert np.abs(L1 - L0).max() < 1e-11 * (1 + np.abs(L0).max())
+        v_rel_before = np.linalg.norm(X[0, 0, 7:10] - X[0, 1, 7:10])
+        moved = np.abs(tr[-1, 0, :, 7:10] - X[0, :, 7:10]).max()
+        hits += moved > 0.1 * v_rel_before
+    assert hits >= 6             # most trials do collide
+
+
+def test_head_on_elastic_equal_spheres_exchange_velocities():
+    text = two_body("sphere", "sphere", e=1.0, mu=0.0, beta=0.0).replace('mass: 3 inertia { x: 0.07 y: 0.07 z: 0.07 }',
+                                                                         'mass: 2 inertia { x: 0.05 y: 0.05 z: 0.05 }')
+    o = oracle.Oracle(text)
+    X = np.zeros((1, 2, 13))
+    X[0, :, 3] = 1.0
+    X[0, 0, 0:3] = [-0.1, 0.0, 5.0]
+    X[0, 1, 0:3] = [0.1, 0.0, 5.0]                  # overlapping by 0.02 m, approaching
+    X[0, 0, 7] = 1.5
+    X[0, 1, 7] = -0.5
+    Xn = o.step(X, np.zeros((1, 0)))
+    assert abs(Xn[0, 0, 7] - (-0.5)) < 1e-14 and abs(Xn[0, 1, 7] - 1.5) < 1e-14
+    assert np.abs(Xn[0, :, 8:10]).max() == 0 and np.abs(Xn[0, :, 10:13]).max() == 0
+
+
+def test_point_inside_box_uses_the_nearest_face():
+    """A sphere centre 0.03 m inside the box's top face (the nearest face):
+    depth = r + 0.03 along that face's normal."""
+    o = oracle.Oracle(two_body("sphere", "box"))
+    X = np.zeros((1, 2, 13))
+    X[0, :, 3] = 1.0
+    X[0, 1, 0:3] = [0.0, 0.0, 5.0]
+    X[0, 0, 0:3] = [0.05, -0.02, 5.0 + 0.1 - 0.03]      # box half height 0.1
+    _, mg = o.step(X, np.zeros((1, 0)), margins=True)
+    assert abs(mg[0, 0] - (0.1 + 0.03)) < 1e-12
+    # the impulse pushes the sphere up (+z) and the box down
+    Xn = o.step(X, np.zeros((1, 0)))
+    assert Xn[0, 0, 9] > 0 and Xn[0, 1, 9] < 0 and abs(Xn[0, 0, 7]) < 1e-12
