@@ -8,7 +8,8 @@
  * updates computed from the same qp, then the potential integrator (joint and
  * actuator updates, gravity) and the collision integrator (collider updates).
  * Joints are springs (Section 6.1), contacts are velocity-level impulses with
- * Baumgarte stabilisation against the ground plane (Section 6.2), systems are
+ * Baumgarte stabilisation against the ground plane and between the colliders
+ * of declared body pairs (Section 6.2), systems are
  * described in the ProtoBuf-like text of Appendix A, and the step is
  * differentiable (Sections 2 and 5.1.4).
  *
@@ -32,8 +33,10 @@
  *   system types of the batch. Body slots b >= B of a smaller system are
  *   ignored on input and written as zeros.
  * - Actions: act[a * E + e], a in [0, Amax); rollouts take acts[t][a][e].
- *   Each action is clipped to [-1, 1] and drives one joint axis with torque
- *   gear * action. Action slots beyond a system's own count are ignored.
+ *   Each action drives one joint axis: a torque actuator clips it to
+ *   [-1, 1] and applies the torque gear * action; a target-angle actuator
+ *   clips it to the axis' angle range and applies gear * (action - angle).
+ *   Action slots beyond a system's own count are ignored.
  * - Non-finite state is not an error: NaN/Inf propagate. With
  *   BRAX_NONFINITE_FLAGS a per-environment byte (1 = some output non-finite)
  *   is written to the buffer brax_sys_query reports.
@@ -94,6 +97,7 @@ typedef struct {
   int64_t tape_step_floats;            /* floats per step of a brax_rollout_tape tape */
   int32_t n_params[BRAX_MAX_TYPES];    /* system parameters per type (brax_step_vjp_params) */
   int32_t p_max;                       /* the largest of n_params */
+  int32_t n_pairs[BRAX_MAX_TYPES];     /* body-body contact candidates per type */
 } brax_layout;
 
 /* Build a batch of n_envs environments from n_descs system descriptions.
@@ -101,8 +105,13 @@ typedef struct {
  *   (substeps, dt, gravity, bodies{name mass inertia frozen colliders position},
  *   joints{name parent child stiffness damping angular_stiffness
  *   angular_damping limit_stiffness parent_offset child_offset rotation
- *   child_rotation angle_limit{min max}...}, actuators{name joint strength},
- *   baumgarte, elasticity, friction, clearance).
+ *   child_rotation angle_limit{min max}...}, actuators{name joint strength
+ *   torque{} | angle{}}, body_contacts{first second}, baumgarte, elasticity,
+ *   friction, clearance). body_contacts declares a body pair whose colliders
+ *   collide with each other: each collider is reduced to a core feature (a
+ *   sphere's centre, a capsule's axis segment, a box) plus a radius, every
+ *   collider of the first body is paired with every one of the second, and
+ *   a capsule against a box contributes its two end spheres.
  * env_desc: host [n_envs] index of each environment's description, or NULL
  *   (all use descs[0]). Environments of one type need not be contiguous.
  * device: HIP device ordinal, or -1 to parse and validate only (no device
@@ -110,7 +119,9 @@ typedef struct {
  * Errors: BRAX_E_ARG (null/size), BRAX_E_PARSE (with line:col),
  *   BRAX_E_MODEL (unknown or repeated body, a body with two parents, a cycle,
  *   mass <= 0, inertia <= 0, capsule length < 2 radius, angle_limit min > max,
- *   DOF outside 1..3, a body without inertia or colliders, table limits),
+ *   DOF outside 1..3, a body without inertia or colliders, a body_contacts
+ *   pair naming an unknown body, the same body twice or two boxes, table
+ *   limits),
  *   BRAX_E_DEVICE, BRAX_E_NOMEM. On error *out is NULL. */
 int brax_sys_create(const char* const* descs, int32_t n_descs, const int32_t* env_desc, int32_t n_envs,
                     int32_t device, brax_sys** out);
@@ -146,7 +157,8 @@ int brax_step(const brax_sys* sys, const brax_state* in, const float* act, brax_
  * conventions are: max(0,x)' = [x > 0]; the Coulomb cap is taken when
  * cap <= stop; clamp' = 1 and clip' = 1 on the closed interval;
  * contact activation and counts have zero derivative. g_in may not alias
- * in or g_out. */
+ * in or g_out. BRAX_E_UNSUPPORTED when a system type of the batch has
+ * body-body contact candidates (the same holds for every adjoint call). */
 int brax_step_vjp(const brax_sys* sys, const brax_state* in, const float* act, const brax_state* g_out,
                   brax_state* g_in, float* g_act, int32_t flags, void* stream);
 
@@ -166,7 +178,8 @@ int brax_rollout(const brax_sys* sys, const brax_state* in, const float* acts, i
  * t * tape_step_floats; its layout inside a step is the library's own
  * (wavefront-major, for coalesced access) and is read only by
  * brax_step_vjp_tape of the same sys. Fused path only: BRAX_PLAIN gives
- * BRAX_E_UNSUPPORTED. The state results equal brax_rollout's. */
+ * BRAX_E_UNSUPPORTED, and so does a batch with body-body contact
+ * candidates. The state results equal brax_rollout's. */
 int brax_rollout_tape(const brax_sys* sys, const brax_state* in, const float* acts, int32_t T, float* tape,
                       brax_state* out, int32_t flags, void* stream);
 

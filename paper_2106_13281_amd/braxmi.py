@@ -51,7 +51,8 @@ class _Layout(C.Structure):
                 ("n_dof", C.c_int32 * MAX_TYPES), ("n_contacts", C.c_int32 * MAX_TYPES),
                 ("substeps", C.c_int32 * MAX_TYPES), ("dt", C.c_float * MAX_TYPES),
                 ("device", C.c_int32), ("nonfinite", C.c_void_p), ("tape_step_floats", C.c_int64),
-                ("n_params", C.c_int32 * MAX_TYPES), ("p_max", C.c_int32)]
+                ("n_params", C.c_int32 * MAX_TYPES), ("p_max", C.c_int32),
+                ("n_pairs", C.c_int32 * MAX_TYPES)]
 
 
 EXPORTS = ("brax_sys_create", "brax_sys_destroy", "brax_sys_query", "brax_default_angles", "brax_default_qp",
@@ -187,6 +188,7 @@ class System:
         self.tape_step_floats = lay.tape_step_floats               # floats per step of a forward tape
         self.n_params = list(lay.n_params[:nt])
         self.p_max = lay.p_max
+        self.n_pairs = list(lay.n_pairs[:nt])                      # body-body contact candidates
         self.dt = list(lay.dt[:nt])
         self.device = torch.device("cuda", device) if device >= 0 else None
 

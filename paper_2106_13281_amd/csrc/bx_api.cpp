@@ -230,6 +230,13 @@ int check_flags(int32_t flags) {
   return BRAX_OK;
 }
 
+// Whether a type of the batch has body-body contact candidates (forward only).
+bool has_pairs(const brax_sys* s) {
+  for (int t = 0; t < s->n_types; ++t)
+    if (s->host_tab.type[t].np > 0) return true;
+  return false;
+}
+
 }  // namespace
 
 extern "C" {
@@ -318,7 +325,9 @@ int brax_sys_create(const char* const* descs, int32_t n_descs, const int32_t* en
     size_t n = (size_t)s->type_cnt[t];
     if ((rc = dmalloc((void**)&s->d_jslot[t], sizeof(float) * 12 * std::max(ty.nj, 1) * std::max(n, (size_t)1))))
       return rc;
-    if ((rc = dmalloc((void**)&s->d_cslot[t], sizeof(float) * 7 * std::max(ty.nc, 1) * std::max(n, (size_t)1))))
+    // ground-contact slots (7 floats each), then body-body slots (13 floats each)
+    if ((rc = dmalloc((void**)&s->d_cslot[t],
+                      sizeof(float) * (7 * std::max(ty.nc, 1) + 13 * ty.np) * std::max(n, (size_t)1))))
       return rc;
   }
   if ((rc = upload_work(s.get()))) return rc;
@@ -353,6 +362,7 @@ int brax_sys_query(const brax_sys* s, brax_layout* out) {
   for (int t = 0; t < s->n_types; ++t) {
     const TypeT& ty = s->host_tab.type[t];
     out->n_params[t] = 4 * ty.nb + 5 * ty.nj + ty.na + 1;
+    out->n_pairs[t] = ty.np;
     out->p_max = std::max(out->p_max, out->n_params[t]);
   }
   for (int t = 0; t < s->n_types; ++t) {
@@ -488,6 +498,7 @@ int brax_rollout_tape(const brax_sys* sys, const brax_state* in, const float* ac
   if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
   if (T < 0) return fail(BRAX_E_ARG, "T must be >= 0");
   if (flags & BRAX_PLAIN) return fail(BRAX_E_UNSUPPORTED, "the tape is written by the fused path only");
+  if (has_pairs(s)) return fail(BRAX_E_UNSUPPORTED, "the tape serves the adjoint, which does not cover body-body contacts");
   if (s->E == 0) return check_flags(flags);
   if (!state_ok(in) || !state_ok(out)) return fail(BRAX_E_ARG, "state has a NULL field");
   if (T > 0 && !acts && s->Am > 0) return fail(BRAX_E_ARG, "acts is NULL");
@@ -740,6 +751,7 @@ int brax_step_vjp(const brax_sys* sys, const brax_state* in, const float* act, c
   brax_sys* s = const_cast<brax_sys*>(sys);
   if (!s) return fail(BRAX_E_ARG, "sys is NULL");
   if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
+  if (has_pairs(s)) return fail(BRAX_E_UNSUPPORTED, "the adjoint does not cover body-body contacts");
   if (s->E == 0) return check_flags(flags);
   if (!state_ok(in) || !state_ok(g_out) || !state_ok(g_in)) return fail(BRAX_E_ARG, "state has a NULL field");
   if (!act && s->Am > 0) return fail(BRAX_E_ARG, "act is NULL");
@@ -771,6 +783,7 @@ int brax_step_vjp_params(const brax_sys* sys, const brax_state* in, const float*
   brax_sys* s = const_cast<brax_sys*>(sys);
   if (!s) return fail(BRAX_E_ARG, "sys is NULL");
   if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
+  if (has_pairs(s)) return fail(BRAX_E_UNSUPPORTED, "the adjoint does not cover body-body contacts");
   if (flags & BRAX_PLAIN) return fail(BRAX_E_UNSUPPORTED, "parameter cotangents are computed on the fused path only");
   if (s->E == 0) return check_flags(flags);
   if (!state_ok(in) || !state_ok(g_out) || !state_ok(g_in)) return fail(BRAX_E_ARG, "state has a NULL field");
@@ -805,6 +818,7 @@ int brax_step_vjp_tape(const brax_sys* sys, const float* tape, const float* act,
   brax_sys* s = const_cast<brax_sys*>(sys);
   if (!s) return fail(BRAX_E_ARG, "sys is NULL");
   if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
+  if (has_pairs(s)) return fail(BRAX_E_UNSUPPORTED, "the adjoint does not cover body-body contacts");
   if (flags & BRAX_PLAIN) return fail(BRAX_E_UNSUPPORTED, "the tape adjoint runs on the fused path only");
   if (s->E == 0) return check_flags(flags);
   if (!tape) return fail(BRAX_E_ARG, "tape is NULL");

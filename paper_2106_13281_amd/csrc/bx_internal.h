@@ -54,6 +54,15 @@ struct ContactD {
   double l[3];
   double rho;
 };
+// Body-body contact candidate between two declared bodies: each side is a
+// core feature in its body's frame (point a0, segment a0-a1, or box with
+// centre a0, rotation aR and half extents ah) with a radius.
+struct PairD {
+  int a, b, kind;  // PairKind
+  int handler;     // a or b: the body whose lane evaluates it in the fused kernels
+  double a0[3], a1[3], ra, ah[3], aR[9];
+  double b0[3], b1[3], rb, bh[3], bR[9];
+};
 struct SystemDesc {
   int substeps;
   double dt, g[3], beta, elasticity, mu, clearance;
@@ -61,6 +70,7 @@ struct SystemDesc {
   std::vector<JointD> joints;
   std::vector<ActD> actions;
   std::vector<ContactD> contacts;
+  std::vector<PairD> pairs;
   int ndof;
 };
 

@@ -9,6 +9,7 @@
 
 #include "bx_access.h"
 #include "bx_internal.h"
+#include "bx_pair.h"
 #include "bx_phys.h"
 
 namespace bx {
@@ -192,6 +193,31 @@ __global__ void k_plain_contact(const Tables* __restrict__ tab, int t, const int
   for (int x = 0; x < 7; ++x) cslot[((size_t)x * NC + c) * n + k] = vals[x];
 }
 
+// Body-body phase: slot c (after the ground-contact slots) holds (dv, dw)
+// of the first body, (dv, dw) of the second and applied = 13 floats.
+__global__ void k_plain_pair(const Tables* __restrict__ tab, int t, const int32_t* __restrict__ envs, int n, int E,
+                             int Bm, Fields st, float* __restrict__ cslot) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = idx / n, k = idx - c * n;
+  const TypeT& ty = tab->type[t];
+  if (c >= ty.np) return;
+  const int e = envs[k];
+  const PairT& P = tab->pair[t][c];
+  PairSide side[2];
+  for (int i = 0; i < 2; ++i) {
+    const int b = i == 0 ? P.a : P.b;
+    const Body s = load_body(st, b, e, Bm, E);
+    const Frame f = derive(tab->body[t][b], s);
+    side[i] = PairSide{s.p, s.v, s.w, f.R, f.Iwinv};
+  }
+  v3 J, x, dvA = V(0.f, 0.f, 0.f), dwA = dvA, dvB = dvA, dwB = dvA;
+  const bool on = pair_eval(P, ty, side[0], side[1], J, x);
+  if (on) pair_shares(P, side[0], side[1], J, x, dvA, dwA, dvB, dwB);
+  float vals[13] = {dvA.x, dvA.y, dvA.z, dwA.x, dwA.y, dwA.z, dvB.x, dvB.y, dvB.z, dwB.x, dwB.y, dwB.z, on ? 1.f : 0.f};
+  float* ps = cslot + (size_t)7 * ty.nc * n;
+  for (int x2 = 0; x2 < 13; ++x2) ps[((size_t)x2 * ty.np + c) * n + k] = vals[x2];
+}
+
 // Potential integrator: gathers the body's own joint (as child) then its
 // children's joints (as parent), in that order.
 __global__ void k_plain_potential(const Tables* __restrict__ tab, int t, const int32_t* __restrict__ envs, int n,
@@ -242,6 +268,19 @@ __global__ void k_plain_collision(const Tables* __restrict__ tab, int t, const i
       ++cnt;
     }
   }
+  // then the body-body candidates it takes part in, in candidate order
+  const float* ps = cslot + (size_t)7 * NC * n;
+  const int NP = ty.np;
+  for (int i = 0; i < B.npair; ++i) {
+    const int c = B.pairs[i];
+    auto pv = [&](int x) { return ps[((size_t)x * NP + c) * n + k]; };
+    if (pv(12) != 0.f) {
+      const int o = tab->pair[t][c].a == b ? 0 : 6;
+      dv += V(pv(o), pv(o + 1), pv(o + 2));
+      dw += V(pv(o + 3), pv(o + 4), pv(o + 5));
+      ++cnt;
+    }
+  }
   Body s = load_body(st, b, e, Bm, E);
   if (tape) tape_count(tape, cnt, b, e, Bm, E);
   collision(B, s, dv, dw, cnt);
@@ -257,11 +296,67 @@ __global__ void k_plain_collision(const Tables* __restrict__ tab, int t, const i
 // fetches each child's reaction (fp, tp) in child order. State stays in
 // registers across all substeps and steps; only actions are read per step.
 
+// Body-body contacts of one substep. The lane of body b evaluates the
+// candidates it handles (evaluation slot i < nh) with the other body's state
+// and frame read from that body's lane, keeps its own share and leaves the
+// other body's; in the same slot every lane then collects the shares left for
+// it by the handler lanes listed in recv[i]. The loops run to the type's
+// maxima so that every cross-lane read executes on the whole wavefront.
+__device__ __forceinline__ void pair_phase(const Tables* __restrict__ tab, int t, int b, int base, const Body& s,
+                                           const Frame& f, v3& dv, v3& dw, int& cnt) {
+  const TypeT& ty = tab->type[t];
+  const BodyT& Bg = tab->body[t][b];
+  const int nh = Bg.nh;
+  const PairSide me{s.p, s.v, s.w, f.R, f.Iwinv};
+  for (int i = 0; i < ty.max_handled; ++i) {
+    const bool mine = i < nh;
+    const PairT& P = tab->pair[t][Bg.hp[i]];  // hp[i] = 0 past nh: a valid candidate, unused
+    const bool first = P.a == b;
+    const int src = base + (mine ? (first ? P.b : P.a) : b);
+    PairSide o;
+    o.p = V(shfl(s.p.x, src), shfl(s.p.y, src), shfl(s.p.z, src));
+    o.v = V(shfl(s.v.x, src), shfl(s.v.y, src), shfl(s.v.z, src));
+    o.w = V(shfl(s.w.x, src), shfl(s.w.y, src), shfl(s.w.z, src));
+#pragma unroll
+    for (int k = 0; k < 9; ++k) o.R.m[k] = shfl(f.R.m[k], src);
+    o.Iwinv = s3{shfl(f.Iwinv.xx, src), shfl(f.Iwinv.yy, src), shfl(f.Iwinv.zz, src),
+                 shfl(f.Iwinv.xy, src), shfl(f.Iwinv.xz, src), shfl(f.Iwinv.yz, src)};
+    v3 odv = V(0.f, 0.f, 0.f), odw = odv;
+    float on = 0.f;
+    if (mine) {
+      v3 J, x;
+      if (pair_eval(P, ty, first ? me : o, first ? o : me, J, x)) {
+        v3 dvA, dwA, dvB, dwB;
+        pair_shares(P, first ? me : o, first ? o : me, J, x, dvA, dwA, dvB, dwB);
+        dv += first ? dvA : dvB;
+        dw += first ? dwA : dwB;
+        odv = first ? dvB : dvA;
+        odw = first ? dwB : dwA;
+        on = 1.f;
+        ++cnt;
+      }
+    }
+    const int nr = Bg.nrecv[i];
+    const uint32_t rv = Bg.recv[i];
+    for (int k = 0; k < ty.recv_n[i]; ++k) {
+      const int hsrc = base + (k < nr ? (int)((rv >> (4 * k)) & 15u) : b);
+      const v3 a = V(shfl(odv.x, hsrc), shfl(odv.y, hsrc), shfl(odv.z, hsrc));
+      const v3 w = V(shfl(odw.x, hsrc), shfl(odw.y, hsrc), shfl(odw.z, hsrc));
+      const float got = shfl(on, hsrc);
+      if (k < nr && got != 0.f) {
+        dv += a;
+        dw += w;
+        ++cnt;
+      }
+    }
+  }
+}
+
 // TAPE: also write each substep's tape record (state before the kinematic
 // update, total torque, count of applied contacts) to the wavefront-major
 // tape[step][sub][work item w of n_work][TAPE_N][64], for the adjoint that
 // reads it instead of recomputing the step.
-template <int MAXDOF, bool TAPE>
+template <int MAXDOF, bool TAPE, bool PAIRS>
 __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const WaveWork& wk,
                                           const int32_t* __restrict__ env_list, const int32_t* __restrict__ type_off,
                                           int E, int Bm, const Fields& in, const Fields& out,
@@ -362,6 +457,8 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
           torque += tq;
         }
       }
+      // body-body contacts after the joint sums, where fewer values are live
+      if (PAIRS && ty.np > 0) pair_phase(tab, t, b, base, s, f, dv, dw, cnt);
       if (TAPE) wtape_rest(tp, torque, cnt, lane);
       potential(B, ty, s, f, force, torque);
       collision(B, s, dv, dw, cnt);
@@ -396,19 +493,39 @@ __global__ __launch_bounds__(256) void k_fused(const Tables* __restrict__ tab, c
   const bool one = tab->type[wk.type].max_dof <= 1;
   if (tape == nullptr) {
     if (one)
-      fused_run<1, false>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
-                          nullptr, 0, w, n_work);
+      fused_run<1, false, false>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj,
+                                 nonfinite, nullptr, 0, w, n_work);
     else
-      fused_run<3, false>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
-                          nullptr, 0, w, n_work);
+      fused_run<3, false, false>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj,
+                                 nonfinite, nullptr, 0, w, n_work);
   } else {
     if (one)
-      fused_run<1, true>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
-                         tape, smax, w, n_work);
+      fused_run<1, true, false>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj,
+                                nonfinite, tape, smax, w, n_work);
     else
-      fused_run<3, true>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
-                         tape, smax, w, n_work);
+      fused_run<3, true, false>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj,
+                                nonfinite, tape, smax, w, n_work);
   }
+}
+
+// The same for batches with body-body contacts: a kernel of its own, so that
+// the registers the body-body phase needs do not lower the occupancy of the
+// kernel above (no tape: the adjoint does not cover these contacts).
+__global__ __launch_bounds__(256) void k_fused_pairs(const Tables* __restrict__ tab,
+                                                     const WaveWork* __restrict__ work, int n_work,
+                                                     const int32_t* __restrict__ env_list,
+                                                     const int32_t* __restrict__ type_off, int E, int Bm, Fields in,
+                                                     Fields out, const float* __restrict__ acts, int Am, int T,
+                                                     int save_every, Fields traj, uint8_t* nonfinite) {
+  const int w = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (w >= n_work) return;
+  const WaveWork wk = work[w];
+  if (tab->type[wk.type].max_dof <= 1)
+    fused_run<1, false, true>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
+                              nullptr, 0, w, n_work);
+  else
+    fused_run<3, false, true>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
+                              nullptr, 0, w, n_work);
 }
 
 // ------------------------------------------------------------------ small helpers
@@ -530,6 +647,15 @@ hipError_t launch_fused(const LaunchCtx& c, const WaveWork* work, int n_work, in
                         Fields out, const float* acts, int T, int save_every, Fields traj, bool flags,
                         hipStream_t s, float* tape, int smax) {
   if (n_work == 0) return hipSuccess;
+  bool pairs = false;
+  for (int t = 0; t < c.n_types; ++t) pairs = pairs || c.host_tab->type[t].np > 0;
+  if (pairs) {
+    if (tape) return hipErrorInvalidValue;  // refused on the host before this point
+    hipLaunchKernelGGL(k_fused_pairs, dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block), 0, s, c.tab,
+                       work, n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj,
+                       flags ? c.nonfinite : nullptr);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_fused, dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block), 0, s, c.tab, work,
                      n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj,
                      flags ? c.nonfinite : nullptr, tape, smax);
@@ -575,6 +701,9 @@ hipError_t launch_plain_step(const LaunchCtx& c, Fields in, Fields out, const fl
       }
       if (ty.nc > 0)
         hipLaunchKernelGGL(k_plain_contact, dim3(cdiv((long)ty.nc * n, TB)), dim3(TB), 0, s, c.tab, t, envs, n, c.E,
+                           c.Bm, out, cslot[t]);
+      if (ty.np > 0)
+        hipLaunchKernelGGL(k_plain_pair, dim3(cdiv((long)ty.np * n, TB)), dim3(TB), 0, s, c.tab, t, envs, n, c.E,
                            c.Bm, out, cslot[t]);
       hipLaunchKernelGGL(k_plain_potential, dim3(cdiv((long)ty.nb * n, TB)), dim3(TB), 0, s, c.tab, t, envs, n, c.E,
                          c.Bm, out, jslot[t], tp);

@@ -273,7 +273,7 @@ int build_system(const char* text, SystemDesc& d, std::string& err) {
     auto root = p.message(false);
     View top{root.get()};
     top.check({"substeps", "dt", "gravity", "bodies", "joints", "actuators", "baumgarte", "elasticity", "friction",
-               "clearance"});
+               "clearance", "body_contacts"});
     d = SystemDesc();
     double sub = top.num("substeps", 1);
     d.dt = top.num("dt", 0.01);
@@ -479,6 +479,100 @@ int build_system(const char* text, SystemDesc& d, std::string& err) {
       }
     }
     if ((int)d.contacts.size() > MAXC) throw MErr{"more than 96 contact candidates"};
+
+    // body-body contacts (Section 6.2): every collider of the first body of a
+    // declared pair against every collider of the second; each collider is
+    // reduced to a core feature plus a radius: a sphere to its centre, a
+    // capsule to its axis segment, a box to itself (radius 0). A capsule
+    // against a box becomes its two end spheres; box against box is not
+    // modelled.
+    std::vector<int> involved(d.bodies.size(), 0);
+    for (const Val* pv : top.all("body_contacts")) {
+      View pm = top.sub(pv);
+      pm.check({"first", "second"});
+      const std::string fa = pm.str("first"), fb = pm.str("second");
+      if (!bidx.count(fa) || !bidx.count(fb) || fa == fb)
+        throw MErr{"body_contacts: bad pair '" + fa + "' / '" + fb + "'"};
+      const int a = bidx[fa], b = bidx[fb];
+      for (const ColliderD& ca : d.bodies[a].cols)
+        for (const ColliderD& cb : d.bodies[b].cols) {
+          if (ca.kind == 2 && cb.kind == 2)
+            throw MErr{"body_contacts '" + fa + "' / '" + fb + "': box against box is not modelled"};
+          // the segment ends (or the centre) of a sphere or capsule, in its body's frame
+          auto ends = [](const ColliderD& c, double e0[3], double e1[3]) {
+            const double hh = c.kind == 1 ? c.length / 2 - c.radius : 0.0;
+            for (int i = 0; i < 3; ++i) {
+              e0[i] = c.pos[i] + c.R[3 * i + 2] * hh;
+              e1[i] = c.pos[i] - c.R[3 * i + 2] * hh;
+            }
+          };
+          PairD P{};
+          P.a = a;
+          P.b = b;
+          for (int i = 0; i < 9; ++i) P.aR[i] = P.bR[i] = (i % 4 == 0) ? 1.0 : 0.0;
+          if (ca.kind != 2 && cb.kind != 2) {
+            ends(ca, P.a0, P.a1);
+            ends(cb, P.b0, P.b1);
+            P.ra = ca.radius;
+            P.rb = cb.radius;
+            P.kind = (ca.kind == 1 ? 2 : 0) + (cb.kind == 1 ? 1 : 0);  // PP, PS, SP, SS
+            d.pairs.push_back(P);
+            continue;
+          }
+          // one side a box: one candidate per end point of the other side
+          const bool box_b = cb.kind == 2;
+          const ColliderD& pc = box_b ? ca : cb;
+          const ColliderD& bc = box_b ? cb : ca;
+          double e[2][3];
+          ends(pc, e[0], e[1]);
+          const int n_pts = pc.kind == 1 ? 2 : 1;
+          for (int k = 0; k < n_pts; ++k) {
+            PairD Q = P;
+            Q.kind = box_b ? PK_PB : PK_BP;
+            double* pt0 = box_b ? Q.a0 : Q.b0;
+            double* pt1 = box_b ? Q.a1 : Q.b1;
+            double* bx0 = box_b ? Q.b0 : Q.a0;
+            double* bx1 = box_b ? Q.b1 : Q.a1;
+            double* bh = box_b ? Q.bh : Q.ah;
+            double* bR = box_b ? Q.bR : Q.aR;
+            for (int i = 0; i < 3; ++i) {
+              pt0[i] = pt1[i] = e[k][i];
+              bx0[i] = bx1[i] = bc.pos[i];
+              bh[i] = bc.half[i];
+            }
+            for (int i = 0; i < 9; ++i) bR[i] = bc.R[i];
+            (box_b ? Q.ra : Q.rb) = pc.radius;
+            (box_b ? Q.rb : Q.ra) = 0.0;
+            d.pairs.push_back(Q);
+          }
+        }
+    }
+    if ((int)d.pairs.size() > MAXP) throw MErr{"more than 32 body-body contact candidates"};
+    for (const PairD& P : d.pairs) {
+      ++involved[P.a];
+      ++involved[P.b];
+    }
+    for (size_t b = 0; b < d.bodies.size(); ++b)
+      if (involved[b] > MAXPI)
+        throw MErr{"body '" + d.bodies[b].name + "': more than 16 body-body contact candidates"};
+    // each candidate is evaluated on the lane of one of its bodies (the
+    // handler: the one that evaluates fewer so far, the first on a tie, or
+    // the other one where that would exceed a limit); the handler's lane
+    // keeps its own share and leaves the other body's, and a lane evaluates
+    // at most MAXH candidates and collects at most MAXR shares per slot
+    std::vector<int> handled(d.bodies.size(), 0);
+    std::vector<std::vector<int>> collects(d.bodies.size(), std::vector<int>(MAXH, 0));
+    for (PairD& P : d.pairs) {
+      auto fits = [&](int h, int o) { return handled[h] < MAXH && collects[o][handled[h]] < MAXR; };
+      int h = handled[P.a] <= handled[P.b] ? P.a : P.b;
+      int o = h == P.a ? P.b : P.a;
+      if (!fits(h, o)) std::swap(h, o);
+      if (!fits(h, o))
+        throw MErr{"body_contacts: bodies '" + d.bodies[P.a].name + "' and '" + d.bodies[P.b].name +
+                   "' take part in more candidates than a lane can evaluate or collect (limit)"};
+      P.handler = h;
+      ++collects[o][handled[h]++];
+    }
     return BRAX_OK;
   } catch (const PErr& e) {
     err = std::to_string(e.line) + ":" + std::to_string(e.col) + ": " + e.msg;
@@ -556,6 +650,51 @@ void pack_type(const SystemDesc& d, Tables& tab, int t) {
     C.body = d.contacts[c].body;
     for (int k = 0; k < 3; ++k) C.l[k] = (float)d.contacts[c].l[k];
     C.rho = (float)d.contacts[c].rho;
+  }
+  // body-body candidates and the lane that evaluates each
+  ty.np = (int)d.pairs.size();
+  for (int c = 0; c < ty.np; ++c) {
+    const PairD& S = d.pairs[c];
+    PairT& P = tab.pair[t][c];
+    P = PairT{};
+    P.a = S.a;
+    P.b = S.b;
+    P.kind = S.kind;
+    auto frozen3 = [](const double* f) { return f[0] == 0 && f[1] == 0 && f[2] == 0; };
+    P.rot_a = frozen3(d.bodies[S.a].free_r) ? 0 : 1;
+    P.rot_b = frozen3(d.bodies[S.b].free_r) ? 0 : 1;
+    P.im_a = frozen3(d.bodies[S.a].free_p) ? 0.f : (float)(1.0 / d.bodies[S.a].mass);
+    P.im_b = frozen3(d.bodies[S.b].free_p) ? 0.f : (float)(1.0 / d.bodies[S.b].mass);
+    P.ra = (float)S.ra;
+    P.rb = (float)S.rb;
+    for (int k = 0; k < 3; ++k) {
+      P.a0[k] = (float)S.a0[k];
+      P.a1[k] = (float)S.a1[k];
+      P.b0[k] = (float)S.b0[k];
+      P.b1[k] = (float)S.b1[k];
+      P.ah[k] = (float)S.ah[k];
+      P.bh[k] = (float)S.bh[k];
+    }
+    for (int k = 0; k < 9; ++k) {
+      P.aR[k] = (float)S.aR[k];
+      P.bR[k] = (float)S.bR[k];
+    }
+    BodyT& A = tab.body[t][S.a];
+    BodyT& Bb = tab.body[t][S.b];
+    A.pairs[A.npair++] = c;
+    Bb.pairs[Bb.npair++] = c;
+    const bool on_a = S.handler == S.a;
+    BodyT& H = on_a ? A : Bb;
+    BodyT& R = on_a ? Bb : A;
+    const int slot = H.nh;  // within MAXH and MAXR: checked when the description was built
+    H.hp[H.nh++] = c;
+    R.recv[slot] |= (uint32_t)(on_a ? S.a : S.b) << (4 * R.nrecv[slot]);
+    ++R.nrecv[slot];
+  }
+  for (int b = 0; b < ty.nb; ++b) {
+    const BodyT& B = tab.body[t][b];
+    ty.max_handled = std::max(ty.max_handled, B.nh);
+    for (int i = 0; i < MAXH; ++i) ty.recv_n[i] = std::max(ty.recv_n[i], B.nrecv[i]);
   }
   int dof0 = 0;
   for (int j = 0; j < ty.nj; ++j) {

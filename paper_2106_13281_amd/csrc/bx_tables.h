@@ -14,13 +14,21 @@ constexpr int MAXJ = 16;   // joints per system
 constexpr int MAXC = 96;   // ground-contact candidates per system
 constexpr int MAXA = 48;   // actions per system
 constexpr int MAXCH = 8;   // children per body
+constexpr int MAXP = 32;   // body-body contact candidates per system
+constexpr int MAXPI = 16;  // body-body candidates one body takes part in
+constexpr int MAXH = 4;    // body-body candidates one body's lane evaluates (fused kernels)
+constexpr int MAXR = 8;    // shares one body collects from other lanes per evaluation slot
+// body-body candidate kinds: the first body's core feature against the second's
+enum PairKind : int32_t { PK_PP = 0, PK_PS = 1, PK_SP = 2, PK_SS = 3, PK_PB = 4, PK_BP = 5 };
 
 struct TypeT {
   int32_t nb, nj, nc, na, ndof, substeps;
   int32_t max_dof;         // largest joint DOF (1..3; 0 without joints)
   int32_t max_children;    // largest child count of a body
   int32_t max_contacts;    // largest contact-candidate count of a body
-  int32_t pad0;
+  int32_t np;              // body-body contact candidates
+  int32_t max_handled;     // largest count of candidates one body's lane evaluates
+  int32_t recv_n[MAXH];    // per evaluation slot: largest count of shares one body collects
   float dt, h;             // step and substep length (s)
   float beta_h;            // Baumgarte factor over h (1/s)
   float one_plus_e;        // 1 + restitution
@@ -43,6 +51,15 @@ struct BodyT {
   int32_t root;            // root body of this body's tree
   int32_t has_pos;         // root with a given reset position
   float pos0[3];           // that position
+  int32_t npair;           // body-body candidates this body takes part in (as first or second)
+  int32_t pairs[MAXPI];    // their indices, ascending
+  // fused kernels: each candidate is evaluated on the lane of one of its two
+  // bodies (the handler), which keeps its own share of the impulse and
+  // leaves the other body's share for that body's lane to collect
+  int32_t nh;              // candidates this body's lane evaluates
+  int32_t hp[MAXH];        // their indices (evaluation slots 0 .. nh-1)
+  int32_t nrecv[MAXH];     // per slot: shares this body collects
+  uint32_t recv[MAXH];     // per slot: handler bodies of those shares, 4 bits each
 };
 
 struct JointT {
@@ -64,11 +81,26 @@ struct ContactT {
   float rho;               // radius (0 for box corners)
 };
 
+// One body-body contact candidate: the first body's core feature (a point
+// a0, a segment a0-a1, or a box with centre a0, rotation aR box to body and
+// half extents ah) with radius ra, the same for the second body; inverse
+// mass im (0 when all translations are frozen) and whether rotations
+// respond (0 when all are frozen) of each body.
+struct PairT {
+  int32_t a, b, kind, rot_a, rot_b, pad[3];
+  float a0[3], a1[3], ra;
+  float b0[3], b1[3], rb;
+  float ah[3], bh[3];
+  float aR[9], bR[9];
+  float im_a, im_b;
+};
+
 struct Tables {
   TypeT type[MAXT];
   BodyT body[MAXT][MAXB];
   JointT joint[MAXT][MAXJ];
   ContactT contact[MAXT][MAXC];
+  PairT pair[MAXT][MAXP];
   int32_t topo[MAXT][MAXB];  // bodies, every parent before its children
 };
 

@@ -10,6 +10,7 @@ import pytest
 
 import oracle
 from paper_2106_13281_amd import braxmi, synth
+from tests.pair_scenes import KIND_PAIRS, cluster, two_body
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "braxmi.h")
@@ -139,3 +140,29 @@ def test_last_error_is_thread_local():
     th.join()
     assert seen == [b""]
     assert L.brax_last_error() != b""
+
+
+@pytest.mark.parametrize("text", [two_body(ka, kb) for ka, kb in KIND_PAIRS] + [cluster(False), cluster(True)])
+def test_body_contact_candidates_agree_with_the_oracle(text):
+    """Both parsers expand the declared body pairs into the same number of
+    candidates (a capsule against a box gives two)."""
+    assert host(text).n_pairs == [oracle.Oracle(text).system.np]
+
+
+def test_body_contact_errors():
+    box = 'bodies {{ name: "{n}" mass: 1 colliders {{ box {{ halfsize {{ x: 0.1 y: 0.1 z: 0.1 }} }} }} }}\n'
+    ball = 'bodies {{ name: "{n}" mass: 1 colliders {{ sphere {{ radius: 0.1 }} }} }}\n'
+    expect(-3, box.format(n="a") + box.format(n="b") + 'body_contacts { first: "a" second: "b" }', match="box")
+    expect(-3, ball.format(n="a") + 'body_contacts { first: "a" second: "z" }', match="bad pair")
+    expect(-3, ball.format(n="a") + 'body_contacts { first: "a" second: "a" }', match="bad pair")
+    expect(-2, ball.format(n="a") + ball.format(n="b") + 'body_contacts { first: "a" second: "b" third: "c" }',
+           match="unknown field")
+    # spheres around one: twelve fit (eight shares collected in one slot, four
+    # evaluated on the hub's own lane), thirteen exceed what its lane can take,
+    # seventeen exceed the per-body candidate limit
+    def star(n):
+        text = ball.format(n="hub") + "".join(ball.format(n=f"s{i}") for i in range(n))
+        return text + "".join(f'body_contacts {{ first: "s{i}" second: "hub" }}\n' for i in range(n))
+    assert host(star(12)).n_pairs == [12]
+    expect(-3, star(13), match="limit")
+    expect(-3, star(17), match="more than 16")

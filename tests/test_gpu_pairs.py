@@ -1,0 +1,157 @@
+"""GPU parity of body-body contacts (fused and plain paths) against the oracle.
+
+Scenes: every ordered pair of collider shapes (two free bodies approaching
+each other without gravity) and a five-body cluster where bodies take part in
+several candidates, once with a free and once with a frozen hub. States are
+taken from the oracle's own trajectories just before each environment's
+first impact, rounded to FP32. Tolerances as for the ground contacts: 1e-4
+relative per step, 1e-3 over 20 steps, for environments that are not
+branch-ambiguous (see helpers).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2106_13281_amd import braxmi, synth
+from tests.helpers import ambiguous, rel_err
+from tests.pair_scenes import CLUSTER_BODIES, KIND_PAIRS, approach, cluster, two_body
+
+pytestmark = pytest.mark.gpu
+STEP_TOL, ROLL_TOL = 1e-4, 1e-3
+STEP_AMB, ROLL_AMB = 1e-6, 1e-5
+E = 157          # several wavefronts and a ragged tail
+
+
+def to_dev(X, b_max=None):
+    return braxmi.State(*(torch.from_numpy(a).cuda() for a in synth.to_soa(X, b_max)))
+
+
+def from_dev(st, nb):
+    torch.cuda.synchronize()
+    return synth.from_soa(*(t.cpu().numpy() for t in st.fields()), n_body=nb)
+
+
+def no_acts(T, n):
+    return torch.zeros((T, 0, n), dtype=torch.float32, device="cuda")
+
+
+def scene(text, nb, seed):
+    """Oracle, and states at the impacts: each environment of the oracle's
+    run from approach(...) is taken just before its first step with a
+    body-body impulse (no gravity: the first change of a velocity), or
+    before step 20 if it has none."""
+    o = oracle.Oracle(text)
+    X0 = approach(E, nb, seed)
+    _, tr, _ = o.rollout(X0, np.zeros((40, E, 0)), traj=True)
+    states = np.concatenate([X0[None], tr], 0)                      # states[k] = after k steps
+    dv = np.abs(np.diff(states[:, :, :, 7:10], axis=0)).max((2, 3))  # [40][E]
+    first = np.where((dv > 1e-6).any(0), (dv > 1e-6).argmax(0), 20)
+    X = states[first, np.arange(E)].astype(np.float32).astype(np.float64)
+    return o, X
+
+
+def report(tag, r, amb, hit):
+    print(f"{tag}: envs {len(r)} with a body-body impulse {int(hit.sum())}, ambiguous {int(amb.sum())}, "
+          f"max rel err (pos, rot, vel, ang) non-ambiguous {r[~amb].max(0) if (~amb).any() else 'n/a'}", flush=True)
+
+
+def check(r, amb, tol, frac=0.02):
+    bad = r.max(1) >= tol
+    assert not (bad & ~amb).any(), r[bad & ~amb].max(0)
+    assert bad.mean() <= frac, (bad.sum(), len(bad))
+
+
+def step_case(text, nb, seed, flags):
+    o, X = scene(text, nb, seed)
+    Xo, mg = o.step(X, np.zeros((E, 0)), margins=True)
+    # no gravity, no ground contact: any velocity change is a body-body impulse
+    hit = np.abs(Xo[:, :, 7:10] - X[:, :, 7:10]).max((1, 2)) > 1e-6
+    sysg = braxmi.System(text, E)
+    out = sysg.step(to_dev(X), torch.zeros((0, E), dtype=torch.float32, device="cuda"), flags=flags)
+    r = rel_err(from_dev(out, nb), Xo)
+    amb = ambiguous(mg, STEP_AMB)
+    return r, amb, hit
+
+
+@pytest.mark.parametrize("flags", [braxmi.BRAX_FUSED, braxmi.BRAX_PLAIN])
+@pytest.mark.parametrize("ka,kb", KIND_PAIRS)
+def test_pair_step_matches_oracle(ka, kb, flags):
+    r, amb, hit = step_case(two_body(ka, kb, e=0.3, mu=0.8, substeps=4, dt=0.004), 2, 5, flags)
+    report(f"pair step {ka}-{kb} flags={flags}", r, amb, hit)
+    assert hit.sum() >= E // 4
+    check(r, amb, STEP_TOL)
+
+
+@pytest.mark.parametrize("flags", [braxmi.BRAX_FUSED, braxmi.BRAX_PLAIN])
+@pytest.mark.parametrize("frozen", [False, True])
+def test_cluster_step_matches_oracle(frozen, flags):
+    r, amb, hit = step_case(cluster(frozen), len(CLUSTER_BODIES), 7, flags)
+    report(f"cluster step frozen={frozen} flags={flags}", r, amb, hit)
+    assert hit.sum() >= E // 8
+    check(r, amb, STEP_TOL)
+
+
+@pytest.mark.parametrize("text,nb,seed", [(two_body(ka, kb, e=0.3, mu=0.8, substeps=4, dt=0.004), 2, 5)
+                                          for ka, kb in KIND_PAIRS] +
+                         [(cluster(False), 5, 7), (cluster(True), 5, 7)])
+def test_pair_rollout_20_steps_matches_oracle(text, nb, seed):
+    o, X = scene(text, nb, seed)
+    Xo, _, mg = o.rollout(X, np.zeros((20, E, 0)), margins=True)
+    sysg = braxmi.System(text, E)
+    out, _ = sysg.rollout(to_dev(X), no_acts(20, E))
+    r = rel_err(from_dev(out, nb), Xo)
+    amb = ambiguous(mg, ROLL_AMB)
+    report(f"pair rollout20 nb={nb}", r, amb, np.zeros(E, bool))
+    check(r, amb, ROLL_TOL, frac=0.03)
+
+
+def test_pairs_in_a_mixed_batch():
+    """A type with body-body contacts next to types without: each environment
+    matches the oracle of its own type (fused, one launch)."""
+    E2 = 96
+    texts = [cluster(False), synth.system_text("quadruped"), two_body("capsule", "box", e=0.3, mu=0.8,
+                                                                      substeps=4, dt=0.004)]
+    nbs = [5, 9, 2]
+    env_desc = np.random.default_rng(3).permutation(np.arange(E2) % 3).astype(np.int32)
+    oracles = [oracle.Oracle(t) for t in texts]
+    b_max = max(nbs)
+    X = np.zeros((E2, b_max, 13))
+    X[:, :, 3] = 1.0
+    acts = np.zeros((E2, 8), np.float32)
+    for t in range(3):
+        idx = np.where(env_desc == t)[0]
+        if t == 1:
+            wl = synth.WORKLOADS["quadruped"]
+            s = oracles[1].system
+            ang, root = synth.reset_noise(1, len(idx), s.ndof, wl.angle_noise, wl.root_noise)
+            Xt = np.stack([oracles[1].default_qp(s.default_angles() + ang[i].astype(np.float64), root[i])
+                           for i in range(len(idx))])
+            acts[idx] = synth.actions(1, 1, len(idx), s.na, wl.act_range)[0]
+            X[idx, :9] = Xt.astype(np.float32)
+        else:
+            _, Xt = scene(texts[t], nbs[t], 11 + t)
+            X[idx, :nbs[t]] = Xt[:len(idx)]
+    sysg = braxmi.System(texts, E2, env_desc=list(env_desc))
+    a_dev = torch.from_numpy(np.ascontiguousarray(acts.T)).cuda()
+    out = sysg.step(to_dev(X, b_max), a_dev)
+    Xg = from_dev(out, b_max)
+    for t in range(3):
+        idx = np.where(env_desc == t)[0]
+        na = oracles[t].system.na
+        Xo, mg = oracles[t].step(X[idx, :nbs[t]], acts[idx, :na].astype(np.float64), margins=True)
+        r = rel_err(Xg[idx, :nbs[t]], Xo)
+        amb = ambiguous(mg, STEP_AMB)
+        print(f"mixed type {t}: max non-ambiguous {r[~amb].max(0) if (~amb).any() else 'n/a'}", flush=True)
+        check(r, amb, STEP_TOL, frac=0.05)
+        assert np.abs(Xg[idx, nbs[t]:]).max(initial=0.0) == 0.0   # padded body slots are zero
+
+
+def test_adjoint_of_pairs_is_unsupported():
+    text = cluster(False)
+    sysg = braxmi.System(text, 8)
+    X = approach(8, 5, 1)
+    st = to_dev(X)
+    with pytest.raises(braxmi.BraxError) as ei:
+        sysg.step_vjp(st, torch.zeros((0, 8), dtype=torch.float32, device="cuda"), to_dev(X))
+    assert ei.value.code == -6

@@ -16,26 +16,7 @@ from scipy.spatial.transform import Rotation
 
 import oracle
 
-BODY = {
-    "sphere": 'colliders {{ sphere {{ radius: {r} }} }}',
-    "capsule": 'colliders {{ capsule {{ radius: {r} length: {L} }} }}',
-    "box": 'colliders {{ box {{ halfsize {{ x: {hx} y: {hy} z: {hz} }} }} }}',
-}
-
-
-def two_body(ka, kb, e=0.0, mu=0.5, beta=0.2, substeps=1, dt=0.002):
-    geo = dict(r=0.1, L=0.6, hx=0.2, hy=0.15, hz=0.1)
-    ga = BODY[ka].format(**geo)
-    gb = BODY[kb].format(**dict(geo, r=0.12, L=0.5))
-    return f"""substeps: {substeps}
-dt: {dt}
-friction: {mu}
-elasticity: {e}
-baumgarte: {beta}
-bodies {{ name: "a" mass: 2 inertia {{ x: 0.05 y: 0.05 z: 0.05 }} {ga} }}
-bodies {{ name: "b" mass: 3 inertia {{ x: 0.07 y: 0.07 z: 0.07 }} {gb} }}
-body_contacts {{ first: "a" second: "b" }}
-"""
+from tests.pair_scenes import two_body
 
 
 def features(o, X):
