@@ -157,8 +157,9 @@ int brax_step(const brax_sys* sys, const brax_state* in, const float* act, brax_
  * conventions are: max(0,x)' = [x > 0]; the Coulomb cap is taken when
  * cap <= stop; clamp' = 1 and clip' = 1 on the closed interval;
  * contact activation and counts have zero derivative. g_in may not alias
- * in or g_out. BRAX_E_UNSUPPORTED when a system type of the batch has
- * body-body contact candidates (the same holds for every adjoint call). */
+ * in or g_out. Body-body contacts follow the same conventions; their closest
+ * features pass the gradient with the feature pair and face held (a
+ * clamped closest-point parameter passes on the closed interval). */
 int brax_step_vjp(const brax_sys* sys, const brax_state* in, const float* act, const brax_state* g_out,
                   brax_state* g_in, float* g_act, int32_t flags, void* stream);
 
@@ -178,8 +179,7 @@ int brax_rollout(const brax_sys* sys, const brax_state* in, const float* acts, i
  * t * tape_step_floats; its layout inside a step is the library's own
  * (wavefront-major, for coalesced access) and is read only by
  * brax_step_vjp_tape of the same sys. Fused path only: BRAX_PLAIN gives
- * BRAX_E_UNSUPPORTED, and so does a batch with body-body contact
- * candidates. The state results equal brax_rollout's. */
+ * BRAX_E_UNSUPPORTED. The state results equal brax_rollout's. */
 int brax_rollout_tape(const brax_sys* sys, const brax_state* in, const float* acts, int32_t T, float* tape,
                       brax_state* out, int32_t flags, void* stream);
 

@@ -230,13 +230,6 @@ int check_flags(int32_t flags) {
   return BRAX_OK;
 }
 
-// Whether a type of the batch has body-body contact candidates (forward only).
-bool has_pairs(const brax_sys* s) {
-  for (int t = 0; t < s->n_types; ++t)
-    if (s->host_tab.type[t].np > 0) return true;
-  return false;
-}
-
 }  // namespace
 
 extern "C" {
@@ -498,7 +491,6 @@ int brax_rollout_tape(const brax_sys* sys, const brax_state* in, const float* ac
   if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
   if (T < 0) return fail(BRAX_E_ARG, "T must be >= 0");
   if (flags & BRAX_PLAIN) return fail(BRAX_E_UNSUPPORTED, "the tape is written by the fused path only");
-  if (has_pairs(s)) return fail(BRAX_E_UNSUPPORTED, "the tape serves the adjoint, which does not cover body-body contacts");
   if (s->E == 0) return check_flags(flags);
   if (!state_ok(in) || !state_ok(out)) return fail(BRAX_E_ARG, "state has a NULL field");
   if (T > 0 && !acts && s->Am > 0) return fail(BRAX_E_ARG, "acts is NULL");
@@ -751,7 +743,6 @@ int brax_step_vjp(const brax_sys* sys, const brax_state* in, const float* act, c
   brax_sys* s = const_cast<brax_sys*>(sys);
   if (!s) return fail(BRAX_E_ARG, "sys is NULL");
   if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
-  if (has_pairs(s)) return fail(BRAX_E_UNSUPPORTED, "the adjoint does not cover body-body contacts");
   if (s->E == 0) return check_flags(flags);
   if (!state_ok(in) || !state_ok(g_out) || !state_ok(g_in)) return fail(BRAX_E_ARG, "state has a NULL field");
   if (!act && s->Am > 0) return fail(BRAX_E_ARG, "act is NULL");
@@ -783,7 +774,6 @@ int brax_step_vjp_params(const brax_sys* sys, const brax_state* in, const float*
   brax_sys* s = const_cast<brax_sys*>(sys);
   if (!s) return fail(BRAX_E_ARG, "sys is NULL");
   if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
-  if (has_pairs(s)) return fail(BRAX_E_UNSUPPORTED, "the adjoint does not cover body-body contacts");
   if (flags & BRAX_PLAIN) return fail(BRAX_E_UNSUPPORTED, "parameter cotangents are computed on the fused path only");
   if (s->E == 0) return check_flags(flags);
   if (!state_ok(in) || !state_ok(g_out) || !state_ok(g_in)) return fail(BRAX_E_ARG, "state has a NULL field");
@@ -818,7 +808,6 @@ int brax_step_vjp_tape(const brax_sys* sys, const float* tape, const float* act,
   brax_sys* s = const_cast<brax_sys*>(sys);
   if (!s) return fail(BRAX_E_ARG, "sys is NULL");
   if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
-  if (has_pairs(s)) return fail(BRAX_E_UNSUPPORTED, "the adjoint does not cover body-body contacts");
   if (flags & BRAX_PLAIN) return fail(BRAX_E_UNSUPPORTED, "the tape adjoint runs on the fused path only");
   if (s->E == 0) return check_flags(flags);
   if (!tape) return fail(BRAX_E_ARG, "tape is NULL");

@@ -9,7 +9,7 @@
 
 #include "bx_access.h"
 #include "bx_internal.h"
-#include "bx_pair.h"
+#include "bx_pair_lanes.h"
 #include "bx_phys.h"
 
 namespace bx {
@@ -210,9 +210,8 @@ __global__ void k_plain_pair(const Tables* __restrict__ tab, int t, const int32_
     const Frame f = derive(tab->body[t][b], s);
     side[i] = PairSide{s.p, s.v, s.w, f.R, f.Iwinv};
   }
-  v3 J, x, dvA = V(0.f, 0.f, 0.f), dwA = dvA, dvB = dvA, dwB = dvA;
-  const bool on = pair_eval(P, ty, side[0], side[1], J, x);
-  if (on) pair_shares(P, side[0], side[1], J, x, dvA, dwA, dvB, dwB);
+  v3 dvA = V(0.f, 0.f, 0.f), dwA = dvA, dvB = dvA, dwB = dvA;
+  const bool on = pair_eval(P, ty, side[0], side[1], dvA, dwA, dvB, dwB);
   float vals[13] = {dvA.x, dvA.y, dvA.z, dwA.x, dwA.y, dwA.z, dvB.x, dvB.y, dvB.z, dwB.x, dwB.y, dwB.z, on ? 1.f : 0.f};
   float* ps = cslot + (size_t)7 * ty.nc * n;
   for (int x2 = 0; x2 < 13; ++x2) ps[((size_t)x2 * ty.np + c) * n + k] = vals[x2];
@@ -295,62 +294,6 @@ __global__ void k_plain_collision(const Tables* __restrict__ tab, int t, const i
 // (ds_bpermute): the child lane fetches its parent's state; the parent lane
 // fetches each child's reaction (fp, tp) in child order. State stays in
 // registers across all substeps and steps; only actions are read per step.
-
-// Body-body contacts of one substep. The lane of body b evaluates the
-// candidates it handles (evaluation slot i < nh) with the other body's state
-// and frame read from that body's lane, keeps its own share and leaves the
-// other body's; in the same slot every lane then collects the shares left for
-// it by the handler lanes listed in recv[i]. The loops run to the type's
-// maxima so that every cross-lane read executes on the whole wavefront.
-__device__ __forceinline__ void pair_phase(const Tables* __restrict__ tab, int t, int b, int base, const Body& s,
-                                           const Frame& f, v3& dv, v3& dw, int& cnt) {
-  const TypeT& ty = tab->type[t];
-  const BodyT& Bg = tab->body[t][b];
-  const int nh = Bg.nh;
-  const PairSide me{s.p, s.v, s.w, f.R, f.Iwinv};
-  for (int i = 0; i < ty.max_handled; ++i) {
-    const bool mine = i < nh;
-    const PairT& P = tab->pair[t][Bg.hp[i]];  // hp[i] = 0 past nh: a valid candidate, unused
-    const bool first = P.a == b;
-    const int src = base + (mine ? (first ? P.b : P.a) : b);
-    PairSide o;
-    o.p = V(shfl(s.p.x, src), shfl(s.p.y, src), shfl(s.p.z, src));
-    o.v = V(shfl(s.v.x, src), shfl(s.v.y, src), shfl(s.v.z, src));
-    o.w = V(shfl(s.w.x, src), shfl(s.w.y, src), shfl(s.w.z, src));
-#pragma unroll
-    for (int k = 0; k < 9; ++k) o.R.m[k] = shfl(f.R.m[k], src);
-    o.Iwinv = s3{shfl(f.Iwinv.xx, src), shfl(f.Iwinv.yy, src), shfl(f.Iwinv.zz, src),
-                 shfl(f.Iwinv.xy, src), shfl(f.Iwinv.xz, src), shfl(f.Iwinv.yz, src)};
-    v3 odv = V(0.f, 0.f, 0.f), odw = odv;
-    float on = 0.f;
-    if (mine) {
-      v3 J, x;
-      if (pair_eval(P, ty, first ? me : o, first ? o : me, J, x)) {
-        v3 dvA, dwA, dvB, dwB;
-        pair_shares(P, first ? me : o, first ? o : me, J, x, dvA, dwA, dvB, dwB);
-        dv += first ? dvA : dvB;
-        dw += first ? dwA : dwB;
-        odv = first ? dvB : dvA;
-        odw = first ? dwB : dwA;
-        on = 1.f;
-        ++cnt;
-      }
-    }
-    const int nr = Bg.nrecv[i];
-    const uint32_t rv = Bg.recv[i];
-    for (int k = 0; k < ty.recv_n[i]; ++k) {
-      const int hsrc = base + (k < nr ? (int)((rv >> (4 * k)) & 15u) : b);
-      const v3 a = V(shfl(odv.x, hsrc), shfl(odv.y, hsrc), shfl(odv.z, hsrc));
-      const v3 w = V(shfl(odw.x, hsrc), shfl(odw.y, hsrc), shfl(odw.z, hsrc));
-      const float got = shfl(on, hsrc);
-      if (k < nr && got != 0.f) {
-        dv += a;
-        dw += w;
-        ++cnt;
-      }
-    }
-  }
-}
 
 // TAPE: also write each substep's tape record (state before the kinematic
 // update, total torque, count of applied contacts) to the wavefront-major
@@ -508,24 +451,26 @@ __global__ __launch_bounds__(256) void k_fused(const Tables* __restrict__ tab, c
   }
 }
 
-// The same for batches with body-body contacts: a kernel of its own, so that
-// the registers the body-body phase needs do not lower the occupancy of the
-// kernel above (no tape: the adjoint does not cover these contacts).
+// The same for batches with body-body contacts: kernels of their own (with
+// and without the tape), so that the registers the body-body phase needs do
+// not lower the occupancy of the kernel above.
+template <bool TAPE>
 __global__ __launch_bounds__(256) void k_fused_pairs(const Tables* __restrict__ tab,
                                                      const WaveWork* __restrict__ work, int n_work,
                                                      const int32_t* __restrict__ env_list,
                                                      const int32_t* __restrict__ type_off, int E, int Bm, Fields in,
                                                      Fields out, const float* __restrict__ acts, int Am, int T,
-                                                     int save_every, Fields traj, uint8_t* nonfinite) {
+                                                     int save_every, Fields traj, uint8_t* nonfinite, float* tape,
+                                                     int smax) {
   const int w = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (w >= n_work) return;
   const WaveWork wk = work[w];
   if (tab->type[wk.type].max_dof <= 1)
-    fused_run<1, false, true>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
-                              nullptr, 0, w, n_work);
+    fused_run<1, TAPE, true>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
+                             tape, smax, w, n_work);
   else
-    fused_run<3, false, true>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
-                              nullptr, 0, w, n_work);
+    fused_run<3, TAPE, true>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
+                             tape, smax, w, n_work);
 }
 
 // ------------------------------------------------------------------ small helpers
@@ -650,10 +595,14 @@ hipError_t launch_fused(const LaunchCtx& c, const WaveWork* work, int n_work, in
   bool pairs = false;
   for (int t = 0; t < c.n_types; ++t) pairs = pairs || c.host_tab->type[t].np > 0;
   if (pairs) {
-    if (tape) return hipErrorInvalidValue;  // refused on the host before this point
-    hipLaunchKernelGGL(k_fused_pairs, dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block), 0, s, c.tab,
-                       work, n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj,
-                       flags ? c.nonfinite : nullptr);
+    if (tape)
+      hipLaunchKernelGGL(k_fused_pairs<true>, dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block), 0, s,
+                         c.tab, work, n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every,
+                         traj, flags ? c.nonfinite : nullptr, tape, smax);
+    else
+      hipLaunchKernelGGL(k_fused_pairs<false>, dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block), 0, s,
+                         c.tab, work, n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every,
+                         traj, flags ? c.nonfinite : nullptr, nullptr, 0);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_fused, dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block), 0, s, c.tab, work,

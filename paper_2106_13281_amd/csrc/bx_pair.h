@@ -22,40 +22,90 @@ struct PairSide {
   s3 Iwinv;
 };
 
+// Lane-varying choices between two values are made field by field on
+// copies, never by choosing between the addresses of two locals (which would
+// move them to scratch memory).
+BXF v3 sel(bool c, v3 a, v3 b) { return V(c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z); }
+BXF m3 sel(bool c, const m3& a, const m3& b) {
+  m3 r;
+  for (int i = 0; i < 9; ++i) r.m[i] = c ? a.m[i] : b.m[i];
+  return r;
+}
+BXF s3 sel(bool c, const s3& a, const s3& b) {
+  return s3{c ? a.xx : b.xx, c ? a.yy : b.yy, c ? a.zz : b.zz, c ? a.xy : b.xy, c ? a.xz : b.xz, c ? a.yz : b.yz};
+}
+BXF PairSide sel(bool c, const PairSide& a, const PairSide& b) {
+  return PairSide{sel(c, a.p, b.p), sel(c, a.v, b.v), sel(c, a.w, b.w), sel(c, a.R, b.R), sel(c, a.Iwinv, b.Iwinv)};
+}
+
+// Closest features of a candidate and what their adjoint needs.
+struct PairGeo {
+  v3 ca, cb, n;        // closest point on the first body, on the second, unit normal (second -> first)
+  float dist;          // their distance along n (signed for a point against a box)
+  // point / segment kinds: the first side a0 + s da, the second b0 + t db (world)
+  v3 a0, da, b0, db;
+  float s, t;          // closest-point parameters
+  float sraw, traw;    // before clamping
+  float a, b, c, e, f, den;  // segment-segment quadratic
+  int kase;            // segment-segment case (see seg_seg)
+  // point-box kinds
+  v3 p, bc, q, cl, nbx;  // point, box centre, box coordinates of p, closest box point in them, box normal
+  m3 Rb;                 // box rotation (box to world)
+  int face;              // -1: p outside the box, else the nearest face's axis
+  float sg;              // that face's side (+1 / -1)
+};
+
 // Parameter in [0, 1] of the point of segment a + u d closest to p; 0 for a
-// zero-length segment.
-BXF float seg_param(v3 p, v3 a, v3 d) {
+// zero-length segment. raw: the value before clamping.
+BXF float seg_param(v3 p, v3 a, v3 d, float& raw) {
   const float dd = dot(d, d);
-  return dd > 0.f ? clampf(dot(p - a, d) / dd, 0.f, 1.f) : 0.f;
+  raw = dd > 0.f ? dot(p - a, d) / dd : 0.f;
+  return dd > 0.f ? clampf(raw, 0.f, 1.f) : 0.f;
 }
 
 // Parameters (s, t) of the closest points of segments p0 + s d1 and q0 + t d2
 // on [0, 1]^2: the unconstrained minimiser's s clamped, t from that s, and
-// where t had to be clamped, s again from the clamped t.
-BXF void seg_seg(v3 p0, v3 d1, v3 q0, v3 d2, float& s, float& t) {
+// where t had to be clamped, s again from the clamped t. Cases: 0 first
+// segment of zero length, 1 second of zero length, 2 t inside [0, 1], 3 t
+// clamped to 0, 4 t clamped to 1.
+BXF void seg_seg(v3 p0, v3 d1, v3 q0, v3 d2, PairGeo& g) {
   const v3 r = p0 - q0;
-  const float a = dot(d1, d1), e = dot(d2, d2), f = dot(d2, r);
-  if (!(a > 0.f)) {
-    s = 0.f;
-    t = e > 0.f ? clampf(f / e, 0.f, 1.f) : 0.f;
+  g.a = dot(d1, d1);
+  g.e = dot(d2, d2);
+  g.f = dot(d2, r);
+  g.c = dot(d1, r);
+  g.b = dot(d1, d2);
+  g.den = 0.f;
+  if (!(g.a > 0.f)) {
+    g.kase = 0;
+    g.s = g.sraw = 0.f;
+    g.traw = g.e > 0.f ? g.f / g.e : 0.f;
+    g.t = g.e > 0.f ? clampf(g.traw, 0.f, 1.f) : 0.f;
     return;
   }
-  const float c = dot(d1, r);
-  if (!(e > 0.f)) {
-    t = 0.f;
-    s = clampf(-c / a, 0.f, 1.f);
+  if (!(g.e > 0.f)) {
+    g.kase = 1;
+    g.t = g.traw = 0.f;
+    g.sraw = -g.c / g.a;
+    g.s = clampf(g.sraw, 0.f, 1.f);
     return;
   }
-  const float b = dot(d1, d2);
-  const float den = a * e - b * b;
-  s = den > 0.f ? clampf((b * f - c * e) / den, 0.f, 1.f) : 0.f;
-  t = (b * s + f) / e;
-  if (t < 0.f) {
-    t = 0.f;
-    s = clampf(-c / a, 0.f, 1.f);
-  } else if (t > 1.f) {
-    t = 1.f;
-    s = clampf((b - c) / a, 0.f, 1.f);
+  g.den = g.a * g.e - g.b * g.b;
+  g.sraw = g.den > 0.f ? (g.b * g.f - g.c * g.e) / g.den : 0.f;
+  g.s = clampf(g.sraw, 0.f, 1.f);
+  g.traw = (g.b * g.s + g.f) / g.e;
+  g.kase = 2;
+  g.t = g.traw;
+  if (g.traw < 0.f) {
+    g.kase = 3;
+    g.t = 0.f;
+    g.sraw = -g.c / g.a;
+    g.s = clampf(g.sraw, 0.f, 1.f);
+  } else if (g.traw > 1.f) {
+    g.kase = 4;
+    g.t = 1.f;
+    g.sraw = (g.b - g.c) / g.a;
+    g.s = clampf(g.sraw, 0.f, 1.f);
   }
 }
 
@@ -63,69 +113,74 @@ BXF void seg_seg(v3 p0, v3 d1, v3 q0, v3 d2, float& s, float& t) {
 // extents h: the box point cb closest to p and the unit normal n from the box
 // towards p; for p inside, the nearest face's point and outward normal.
 // Returns the signed distance of p from the surface along n (negative inside).
-// `face` returns -1 outside, else the nearest face's axis.
-BXF float point_box(v3 p, v3 c, const m3& Rb, const float* h, v3& cb, v3& n, int& face) {
+BXF float point_box(v3 p, v3 c, const m3& Rb, const float* h, PairGeo& g) {
   const v3 q = mul_t(Rb, p - c);
+  g.q = q;
   const bool inside = fabsf(q.x) <= h[0] && fabsf(q.y) <= h[1] && fabsf(q.z) <= h[2];
   if (!inside) {
-    face = -1;
-    cb = c + mul(Rb, V(clampf(q.x, -h[0], h[0]), clampf(q.y, -h[1], h[1]), clampf(q.z, -h[2], h[2])));
+    g.face = -1;
+    g.cl = V(clampf(q.x, -h[0], h[0]), clampf(q.y, -h[1], h[1]), clampf(q.z, -h[2], h[2]));
+    const v3 cb = c + mul(Rb, g.cl);
     const v3 d = p - cb;
     const float dist = sqrtf(dot(d, d));
-    n = (1.f / dist) * d;
+    g.nbx = (1.f / dist) * d;
+    g.cb = cb;
     return dist;
   }
   const float g0 = h[0] - fabsf(q.x), g1 = h[1] - fabsf(q.y), g2 = h[2] - fabsf(q.z);
   int k = 0;
-  float g = g0;
-  if (g1 < g) { k = 1; g = g1; }
-  if (g2 < g) { k = 2; g = g2; }
-  face = k;
+  float gk = g0;
+  if (g1 < gk) { k = 1; gk = g1; }
+  if (g2 < gk) { k = 2; gk = g2; }
+  g.face = k;
   const float qk = k == 0 ? q.x : (k == 1 ? q.y : q.z);
-  const float sg = qk >= 0.f ? 1.f : -1.f;
+  g.sg = qk >= 0.f ? 1.f : -1.f;
   v3 cl = q;
-  if (k == 0) cl.x = sg * h[0];
-  else if (k == 1) cl.y = sg * h[1];
-  else cl.z = sg * h[2];
-  cb = c + mul(Rb, cl);
-  n = sg * col(Rb, k);
-  return -g;
+  if (k == 0) cl.x = g.sg * h[0];
+  else if (k == 1) cl.y = g.sg * h[1];
+  else cl.z = g.sg * h[2];
+  g.cl = cl;
+  g.cb = c + mul(Rb, cl);
+  // column k of Rb, chosen by value (k varies across lanes)
+  const v3 ck = sel(k == 0, col(Rb, 0), sel(k == 1, col(Rb, 1), col(Rb, 2)));
+  g.nbx = g.sg * ck;
+  return -gk;
 }
 
 // Closest points of a candidate's features: ca on the first body, cb on the
 // second, unit normal n from cb towards ca, and their distance along n
 // (signed for a point against a box). Returns false where the normal is
 // undefined (coincident core points).
-BXF bool pair_geometry(const PairT& c, const PairSide& A, const PairSide& B, v3& ca, v3& cb, v3& n, float& dist) {
+BXF bool pair_geometry(const PairT& c, const PairSide& A, const PairSide& B, PairGeo& g) {
   if (c.kind >= PK_PB) {
     const bool box_b = c.kind == PK_PB;
-    const PairSide& P = box_b ? A : B;  // the point's body
-    const PairSide& X = box_b ? B : A;  // the box's body
-    const v3 p = P.p + mul(P.R, ld3(box_b ? c.a0 : c.b0));
-    const v3 bc = X.p + mul(X.R, ld3(box_b ? c.b0 : c.a0));
-    const m3 Rb = mul(X.R, box_b ? c.bR : c.aR);
-    v3 cbox, nb;
-    int face;
-    dist = point_box(p, bc, Rb, box_b ? c.bh : c.ah, cbox, nb, face);
-    ca = box_b ? p : cbox;
-    cb = box_b ? cbox : p;
-    n = box_b ? nb : -nb;
+    // the point's body (first for PB) and the box's body
+    g.p = sel(box_b, A.p, B.p) + mul(sel(box_b, A.R, B.R), ld3(box_b ? c.a0 : c.b0));
+    const m3 XR = sel(box_b, B.R, A.R);
+    g.bc = sel(box_b, B.p, A.p) + mul(XR, ld3(box_b ? c.b0 : c.a0));
+    g.Rb = mul(XR, box_b ? c.bR : c.aR);
+    g.dist = point_box(g.p, g.bc, g.Rb, box_b ? c.bh : c.ah, g);
+    const v3 cbox = g.cb;
+    g.ca = sel(box_b, g.p, cbox);
+    g.cb = sel(box_b, cbox, g.p);
+    g.n = sel(box_b, g.nbx, -g.nbx);
     return true;
   }
-  const v3 a0 = A.p + mul(A.R, ld3(c.a0)), b0 = B.p + mul(B.R, ld3(c.b0));
-  float s = 0.f, t = 0.f;
-  v3 da = V(0.f, 0.f, 0.f), db = V(0.f, 0.f, 0.f);
-  if (c.kind == PK_SP || c.kind == PK_SS) da = mul(A.R, ld3(c.a1) - ld3(c.a0));
-  if (c.kind == PK_PS || c.kind == PK_SS) db = mul(B.R, ld3(c.b1) - ld3(c.b0));
-  if (c.kind == PK_PS) t = seg_param(a0, b0, db);
-  else if (c.kind == PK_SP) s = seg_param(b0, a0, da);
-  else if (c.kind == PK_SS) seg_seg(a0, da, b0, db, s, t);
-  ca = a0 + s * da;
-  cb = b0 + t * db;
-  const v3 d = ca - cb;
-  dist = sqrtf(dot(d, d));
-  if (!(dist > 0.f)) return false;
-  n = (1.f / dist) * d;
+  g.a0 = A.p + mul(A.R, ld3(c.a0));
+  g.b0 = B.p + mul(B.R, ld3(c.b0));
+  g.s = g.t = g.sraw = g.traw = 0.f;
+  g.da = g.db = V(0.f, 0.f, 0.f);
+  if (c.kind == PK_SP || c.kind == PK_SS) g.da = mul(A.R, ld3(c.a1) - ld3(c.a0));
+  if (c.kind == PK_PS || c.kind == PK_SS) g.db = mul(B.R, ld3(c.b1) - ld3(c.b0));
+  if (c.kind == PK_PS) g.t = seg_param(g.a0, g.b0, g.db, g.traw);
+  else if (c.kind == PK_SP) g.s = seg_param(g.b0, g.a0, g.da, g.sraw);
+  else if (c.kind == PK_SS) seg_seg(g.a0, g.da, g.b0, g.db, g);
+  g.ca = g.a0 + g.s * g.da;
+  g.cb = g.b0 + g.t * g.db;
+  const v3 d = g.ca - g.cb;
+  g.dist = sqrtf(dot(d, d));
+  if (!(g.dist > 0.f)) return false;
+  g.n = (1.f / g.dist) * d;
   return true;
 }
 
@@ -139,43 +194,65 @@ BXF float pair_k(const PairT& c, const PairSide& A, const PairSide& B, v3 rA, v3
   return k;
 }
 
-// One candidate. Returns whether an impulse applies; J is the impulse on the
-// first body at the contact point x (the second body takes -J).
-BXF bool pair_eval(const PairT& c, const TypeT& ty, const PairSide& A, const PairSide& B, v3& J, v3& x) {
-  v3 ca, cb, n;
-  float dist;
-  if (!pair_geometry(c, A, B, ca, cb, n, dist)) return false;
-  const float depth = (c.ra + c.rb) - dist;
-  if (!(depth > 0.f)) return false;
-  x = cb + (c.rb - 0.5f * depth) * n;  // the middle of the overlap
-  const v3 rA = x - A.p, rB = x - B.p;
-  const v3 u = (A.v + cross(A.w, rA)) - (B.v + cross(B.w, rB));
-  const float vn = dot(u, n);
-  const float num = ty.beta_h * depth - ty.one_plus_e * vn;
-  if (!(num > 0.f)) return false;
-  const float jn = num / pair_k(c, A, B, rA, rB, n);
-  J = jn * n;
-  const v3 ut = u - vn * n;
-  const float sp = sqrtf(dot(ut, ut));
-  if (sp > 0.f) {
-    const v3 tt = (1.f / sp) * ut;
-    const float stop = sp / pair_k(c, A, B, rA, rB, tt);
-    const float cap = ty.mu * jn;
-    const float jt = cap <= stop ? cap : stop;
-    J = J - jt * tt;
+// The impulse of a candidate and what its adjoint needs.
+struct PairImp {
+  float depth, vn, num, kn, jn, sp, kt, stop, jt;
+  v3 x, rA, rB, u, t, J;  // contact point, lever arms, relative velocity, slip direction, impulse on the first body
+  bool use_cap;           // the Coulomb cap is the applied friction impulse
+};
+
+// Returns whether an impulse applies: depth > 0 and a positive normal
+// impulse. Needs pair_geometry's result.
+BXF bool pair_impulse(const PairT& c, const TypeT& ty, const PairSide& A, const PairSide& B, const PairGeo& g,
+                      PairImp& m) {
+  m.depth = (c.ra + c.rb) - g.dist;
+  if (!(m.depth > 0.f)) return false;
+  m.x = g.cb + (c.rb - 0.5f * m.depth) * g.n;  // the middle of the overlap
+  m.rA = m.x - A.p;
+  m.rB = m.x - B.p;
+  m.u = (A.v + cross(A.w, m.rA)) - (B.v + cross(B.w, m.rB));
+  m.vn = dot(m.u, g.n);
+  m.num = ty.beta_h * m.depth - ty.one_plus_e * m.vn;
+  if (!(m.num > 0.f)) return false;
+  m.kn = pair_k(c, A, B, m.rA, m.rB, g.n);
+  m.jn = m.num / m.kn;
+  m.J = m.jn * g.n;
+  const v3 ut = m.u - m.vn * g.n;
+  m.sp = sqrtf(dot(ut, ut));
+  m.t = V(0.f, 0.f, 0.f);
+  m.kt = m.stop = m.jt = 0.f;
+  m.use_cap = false;
+  if (m.sp > 0.f) {
+    m.t = (1.f / m.sp) * ut;
+    m.kt = pair_k(c, A, B, m.rA, m.rB, m.t);
+    m.stop = m.sp / m.kt;
+    const float cap = ty.mu * m.jn;
+    m.use_cap = cap <= m.stop;
+    m.jt = m.use_cap ? cap : m.stop;
+    m.J = m.J - m.jt * m.t;
   }
   return true;
 }
 
 // The velocity changes of an applied candidate: the first body's (dvA, dwA)
 // and the second's (dvB, dwB).
-BXF void pair_shares(const PairT& c, const PairSide& A, const PairSide& B, v3 J, v3 x, v3& dvA, v3& dwA, v3& dvB,
-                     v3& dwB) {
+BXF void pair_shares(const PairT& c, const PairSide& A, const PairSide& B, const PairImp& m, v3& dvA, v3& dwA,
+                     v3& dvB, v3& dwB) {
   const v3 z3 = V(0.f, 0.f, 0.f);
-  dvA = c.im_a * J;
-  dvB = -(c.im_b * J);
-  dwA = c.rot_a ? mul(A.Iwinv, cross(x - A.p, J)) : z3;
-  dwB = c.rot_b ? -mul(B.Iwinv, cross(x - B.p, J)) : z3;
+  dvA = c.im_a * m.J;
+  dvB = -(c.im_b * m.J);
+  dwA = c.rot_a ? mul(A.Iwinv, cross(m.rA, m.J)) : z3;
+  dwB = c.rot_b ? -mul(B.Iwinv, cross(m.rB, m.J)) : z3;
+}
+
+// One candidate: whether an impulse applies and, if so, the shares.
+BXF bool pair_eval(const PairT& c, const TypeT& ty, const PairSide& A, const PairSide& B, v3& dvA, v3& dwA, v3& dvB,
+                   v3& dwB) {
+  PairGeo g;
+  PairImp m;
+  if (!pair_geometry(c, A, B, g) || !pair_impulse(c, ty, A, B, g, m)) return false;
+  pair_shares(c, A, B, m, dvA, dwA, dvB, dwB);
+  return true;
 }
 
 }  // namespace bx

@@ -34,6 +34,7 @@ BXF v3 operator-(v3 a, v3 b) { return v3{a.x - b.x, a.y - b.y, a.z - b.z}; }
 BXF v3 operator-(v3 a) { return v3{-a.x, -a.y, -a.z}; }
 BXF v3 operator*(float s, v3 a) { return v3{s * a.x, s * a.y, s * a.z}; }
 BXF v3& operator+=(v3& a, v3 b) { a = a + b; return a; }
+BXF v3& operator-=(v3& a, v3 b) { a = a - b; return a; }
 BXF float dot(v3 a, v3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 BXF v3 cross(v3 a, v3 b) { return v3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
 BXF v3 ld3(const float* p) { return v3{p[0], p[1], p[2]}; }

@@ -21,6 +21,7 @@
 
 #include "bx_access.h"
 #include "bx_adj.h"
+#include "bx_pair_lanes.h"
 #include "bx_vjp.h"
 
 namespace bx {
@@ -198,11 +199,48 @@ __global__ void k_adj_contact(const Tables* __restrict__ tab, int t, const int32
   slot_store_bar(cbar, 0, ty.nc, c, n, k, r);
 }
 
+// Body-body phase adjoint: slot c holds the first body's bar, then the
+// second's (zero when no impulse).
+__global__ void k_adj_pair(const Tables* __restrict__ tab, int t, const int32_t* __restrict__ envs, int n, int E,
+                           int Bm, const float* __restrict__ tape_s, const float* __restrict__ dvw,
+                           float* __restrict__ pbar) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = idx / n, k = idx - c * n;
+  const TypeT& ty = tab->type[t];
+  if (c >= ty.np) return;
+  const int e = envs[k];
+  const PairT& P = tab->pair[t][c];
+  const int ids[2] = {P.a, P.b};
+  Body post[2];
+  Frame f[2];
+  PairSide side[2];
+  v3 dvb[2], dwb[2];
+  for (int i = 0; i < 2; ++i) {
+    post[i] = post_kin(tab, t, tape_s, ids[i], e, Bm, E);
+    f[i] = derive(tab->body[t][ids[i]], post[i]);
+    side[i] = PairSide{post[i].p, post[i].v, post[i].w, f[i].R, f[i].Iwinv};
+    load2(dvw, dvb[i], dwb[i], ids[i], e, Bm, E);
+  }
+  PairSideBar sb[2] = {pairbar_zero(), pairbar_zero()};
+  float mu_b = 0.f;
+  const bool on = pair_adj(P, ty, side[0], side[1], dvb[0], dwb[0], dvb[1], dwb[1], sb[0], sb[1], mu_b);
+  for (int i = 0; i < 2; ++i) {
+    Bar r = bar_zero();
+    if (on) {
+      r.p = sb[i].p;
+      r.v = sb[i].v;
+      r.w = sb[i].w;
+      frame_adj(tab->body[t][ids[i]], post[i], f[i], FrameBar{sb[i].R, s3_zero(), sb[i].Iwinv}, r.q);
+    }
+    slot_store_bar(pbar, 13 * i, ty.np, c, n, k, r);
+  }
+}
+
 // Gather and kinematic adjoint: G <- cotangent of the substep's input state.
 __global__ void k_adj_kinematic(const Tables* __restrict__ tab, int t, const int32_t* __restrict__ envs, int n,
                                 int E, int Bm, const float* __restrict__ tape_s, const float* __restrict__ bpart,
                                 const float* __restrict__ jbar, const float* __restrict__ abar,
-                                const float* __restrict__ cbar, Fields G) {
+                                const float* __restrict__ cbar, const float* __restrict__ pbar, Fields G) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int b = idx / n, k = idx - b * n;
   const TypeT& ty = tab->type[t];
@@ -222,6 +260,10 @@ __global__ void k_adj_kinematic(const Tables* __restrict__ tab, int t, const int
     slot_add_bar(abar, 0, ty.nj, j, n, k, tot);
   }
   for (int c = B.c0; c < B.c1; ++c) slot_add_bar(cbar, 0, ty.nc, c, n, k, tot);
+  for (int i = 0; i < B.npair; ++i) {
+    const int c = B.pairs[i];
+    slot_add_bar(pbar, tab->pair[t][c].a == b ? 0 : 13, ty.np, c, n, k, tot);
+  }
   Body pre = tape_load_state(tape_s, b, e, Bm, E);
   store_bar(G, kinematic_adj(B, pre, ty.h, tot), b, e, Bm, E);
 }
@@ -260,7 +302,7 @@ __device__ __forceinline__ v3 shfl3(v3 a, int src) { return V(shfl(a.x, src), sh
 // into g_params[P_max][E] (order: mass per body, inertia per body x, y, z,
 // per joint k_lin, c_lin, k_ang, c_ang, k_lim, strength per action,
 // friction); the LDS tape then also keeps each body's total force.
-template <int MAXDOF, bool FROM_TAPE, bool PARAMS = false>
+template <int MAXDOF, bool FROM_TAPE, bool PARAMS, bool PAIRS>
 __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, const WaveWork& wk,
                                               const int32_t* __restrict__ env_list,
                                               const int32_t* __restrict__ type_off, int E, int Bm, int Am,
@@ -352,6 +394,7 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
         torque += tq;
       }
     }
+    if (PAIRS && ty.np > 0) pair_phase(tab, t, b, base, s, f, dv, dw, cnt);
     tp[832] = torque.x; tp[896] = torque.y; tp[960] = torque.z;
     tp[1024] = (float)cnt;
     if (PARAMS) {
@@ -425,6 +468,7 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
     if (n_con > 0) contact_back(Creg[0]);
     if (n_con > 1) contact_back(Creg[1]);
     for (int c = REG_CONTACTS; c < n_con; ++c) contact_back(tab->contact[t][B.c0 + c]);
+    if (PAIRS && ty.np > 0) pair_phase_adj(tab, t, b, base, post, f, dvb, dwb, tot, fr, invm_bar, mu_bar);
     bar_add(tot, bC);
     if (PARAMS) {
       // Iw = R diag(I) R^T, Iwinv = R diag(1/I) R^T: d/dI_k = r_k^T S_bar r_k (r_k column k of R;
@@ -482,6 +526,7 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
   }
 }
 
+template <bool PAIRS>
 __global__ __launch_bounds__(64) void k_fused_vjp(const Tables* __restrict__ tab, const WaveWork* __restrict__ work,
                                                   int n_work, const int32_t* __restrict__ env_list,
                                                   const int32_t* __restrict__ type_off, int E, int Bm, int Am,
@@ -494,14 +539,15 @@ __global__ __launch_bounds__(64) void k_fused_vjp(const Tables* __restrict__ tab
   float* lds = lds_tape;
   (void)smax;
   if (tab->type[wk.type].max_dof <= 1)
-    fused_vjp_run<1, false>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds, nullptr, w,
-                            n_work);
+    fused_vjp_run<1, false, false, PAIRS>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds,
+        nullptr, w, n_work);
   else
-    fused_vjp_run<3, false>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds, nullptr, w,
-                            n_work);
+    fused_vjp_run<3, false, false, PAIRS>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds,
+        nullptr, w, n_work);
 }
 
 // The adjoint of one step with the cotangents of the system parameters.
+template <bool PAIRS>
 __global__ __launch_bounds__(64) void k_fused_vjp_params(const Tables* __restrict__ tab,
                                                          const WaveWork* __restrict__ work, int n_work,
                                                          const int32_t* __restrict__ env_list,
@@ -514,14 +560,15 @@ __global__ __launch_bounds__(64) void k_fused_vjp_params(const Tables* __restric
   if (w >= n_work) return;
   const WaveWork wk = work[w];
   if (tab->type[wk.type].max_dof <= 1)
-    fused_vjp_run<1, false, true>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds_tape,
+    fused_vjp_run<1, false, true, PAIRS>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds_tape,
                                   nullptr, w, n_work, g_params, p_max);
   else
-    fused_vjp_run<3, false, true>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds_tape,
+    fused_vjp_run<3, false, true, PAIRS>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds_tape,
                                   nullptr, w, n_work, g_params, p_max);
 }
 
 // The adjoint of one step from its forward tape in HBM (no recompute, no LDS).
+template <bool PAIRS>
 __global__ __launch_bounds__(64) void k_fused_vjp_tape(const Tables* __restrict__ tab,
                                                        const WaveWork* __restrict__ work, int n_work,
                                                        const int32_t* __restrict__ env_list,
@@ -533,11 +580,19 @@ __global__ __launch_bounds__(64) void k_fused_vjp_tape(const Tables* __restrict_
   const WaveWork wk = work[w];
   const Fields none{nullptr, nullptr, nullptr, nullptr};
   if (tab->type[wk.type].max_dof <= 1)
-    fused_vjp_run<1, true>(tab, wk, env_list, type_off, E, Bm, Am, none, act, g_out, g_in, g_act, nullptr, tape, w,
-                           n_work);
+    fused_vjp_run<1, true, false, PAIRS>(tab, wk, env_list, type_off, E, Bm, Am, none, act, g_out, g_in, g_act,
+        nullptr, tape, w, n_work);
   else
-    fused_vjp_run<3, true>(tab, wk, env_list, type_off, E, Bm, Am, none, act, g_out, g_in, g_act, nullptr, tape, w,
-                           n_work);
+    fused_vjp_run<3, true, false, PAIRS>(tab, wk, env_list, type_off, E, Bm, Am, none, act, g_out, g_in, g_act,
+        nullptr, tape, w, n_work);
+}
+
+// Whether a type of the batch has body-body contact candidates: the kernels
+// with the body-body phases are launched for such batches only.
+bool any_pairs(const LaunchCtx& c) {
+  for (int t = 0; t < c.n_types; ++t)
+    if (c.host_tab->type[t].np > 0) return true;
+  return false;
 }
 
 }  // namespace
@@ -548,7 +603,8 @@ int vjp_reserve(VjpWork& w, const Tables& tab, int n_types, const int* type_cnt,
   for (int t = 0; t < n_types; ++t) {
     smax = std::max(smax, (size_t)tab.type[t].substeps);
     size_t nt = std::max(type_cnt[t], 1);
-    per_type += nt * (26 * (size_t)std::max(tab.type[t].nj, 1) * 2 + 13 * (size_t)std::max(tab.type[t].nc, 1));
+    per_type += nt * (26 * (size_t)std::max(tab.type[t].nj, 1) * 2 + 13 * (size_t)std::max(tab.type[t].nc, 1) +
+                      26 * (size_t)tab.type[t].np);
   }
   const size_t nbe = (size_t)Bm * std::max(E, 1);
   const size_t need = (smax * TAPE_N + 13 + 13 + 6 + 6) * nbe + per_type + 64;
@@ -575,16 +631,26 @@ hipError_t launch_vjp_params(const LaunchCtx& c, const VjpSched& sched, Fields i
   size_t smax = 1;
   for (int t = 0; t < c.n_types; ++t) smax = std::max(smax, (size_t)c.host_tab->type[t].substeps);
   const size_t lds = smax * (TAPE_N + 3) * 64 * sizeof(float);
-  hipLaunchKernelGGL(k_fused_vjp_params, dim3(sched.n_work), dim3(64), lds, s, c.tab, sched.work, sched.n_work,
-                     c.env_list, c.type_off, c.E, c.Bm, c.Am, in, act, g_out, g_in, g_act, g_params, p_max);
+  if (any_pairs(c))
+    hipLaunchKernelGGL(k_fused_vjp_params<true>, dim3(sched.n_work), dim3(64), lds, s, c.tab, sched.work,
+                       sched.n_work, c.env_list, c.type_off, c.E, c.Bm, c.Am, in, act, g_out, g_in, g_act, g_params,
+                       p_max);
+  else
+    hipLaunchKernelGGL(k_fused_vjp_params<false>, dim3(sched.n_work), dim3(64), lds, s, c.tab, sched.work,
+                       sched.n_work, c.env_list, c.type_off, c.E, c.Bm, c.Am, in, act, g_out, g_in, g_act, g_params,
+                       p_max);
   return hipGetLastError();
 }
 
 hipError_t launch_vjp_tape(const LaunchCtx& c, const VjpSched& sched, const float* tape, const float* act,
                            Fields g_out, Fields g_in, float* g_act, hipStream_t s) {
   if (sched.n_work == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fused_vjp_tape, dim3(sched.n_work), dim3(64), 0, s, c.tab, sched.work, sched.n_work,
-                     c.env_list, c.type_off, c.E, c.Bm, c.Am, tape, act, g_out, g_in, g_act);
+  if (any_pairs(c))
+    hipLaunchKernelGGL(k_fused_vjp_tape<true>, dim3(sched.n_work), dim3(64), 0, s, c.tab, sched.work, sched.n_work,
+                       c.env_list, c.type_off, c.E, c.Bm, c.Am, tape, act, g_out, g_in, g_act);
+  else
+    hipLaunchKernelGGL(k_fused_vjp_tape<false>, dim3(sched.n_work), dim3(64), 0, s, c.tab, sched.work, sched.n_work,
+                       c.env_list, c.type_off, c.E, c.Bm, c.Am, tape, act, g_out, g_in, g_act);
   return hipGetLastError();
 }
 
@@ -608,8 +674,12 @@ hipError_t launch_vjp(const LaunchCtx& c, VjpWork& w, const VjpSched& sched, Fie
     // one wavefront per block; its tape lives in LDS
     const size_t lds = smax * TAPE_N * 64 * sizeof(float);
     if (sched.n_work == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fused_vjp, dim3(sched.n_work), dim3(64), lds, s, c.tab, sched.work, sched.n_work, c.env_list,
-                       c.type_off, E, Bm, c.Am, (int)smax, in, act, g_out, g_in, g_act);
+    if (any_pairs(c))
+      hipLaunchKernelGGL(k_fused_vjp<true>, dim3(sched.n_work), dim3(64), lds, s, c.tab, sched.work, sched.n_work,
+                         c.env_list, c.type_off, E, Bm, c.Am, (int)smax, in, act, g_out, g_in, g_act);
+    else
+      hipLaunchKernelGGL(k_fused_vjp<false>, dim3(sched.n_work), dim3(64), lds, s, c.tab, sched.work, sched.n_work,
+                         c.env_list, c.type_off, E, Bm, c.Am, (int)smax, in, act, g_out, g_in, g_act);
     return hipGetLastError();
   }
   if (c.Am > 0) {
@@ -629,7 +699,8 @@ hipError_t launch_vjp(const LaunchCtx& c, VjpWork& w, const VjpSched& sched, Fie
     float* jbar = p;
     float* abar = jbar + 26 * nj * n;
     float* cbar = abar + 26 * nj * n;
-    p = cbar + 13 * nc * n;
+    float* pbar = cbar + 13 * nc * n;
+    p = pbar + 26 * (size_t)ty.np * n;
     hipLaunchKernelGGL(k_adj_init, dim3(cdiv((long)Bm * n, TB)), dim3(TB), 0, s, c.tab, t, envs, n, E, Bm, g_out,
                        g_in);
     for (int sub = ty.substeps - 1; sub >= 0; --sub) {
@@ -652,8 +723,11 @@ hipError_t launch_vjp(const LaunchCtx& c, VjpWork& w, const VjpSched& sched, Fie
       if (ty.nc > 0)
         hipLaunchKernelGGL(k_adj_contact, dim3(cdiv((long)ty.nc * n, TB)), dim3(TB), 0, s, c.tab, t, envs, n, E, Bm,
                            tape_s, dvw, cbar);
+      if (ty.np > 0)
+        hipLaunchKernelGGL(k_adj_pair, dim3(cdiv((long)ty.np * n, TB)), dim3(TB), 0, s, c.tab, t, envs, n, E, Bm,
+                           tape_s, dvw, pbar);
       hipLaunchKernelGGL(k_adj_kinematic, dim3(cdiv((long)ty.nb * n, TB)), dim3(TB), 0, s, c.tab, t, envs, n, E, Bm,
-                         tape_s, bpart, jbar, abar, cbar, g_in);
+                         tape_s, bpart, jbar, abar, cbar, pbar, g_in);
       if ((err = hipGetLastError()) != hipSuccess) return err;
     }
   }

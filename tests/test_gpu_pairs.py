@@ -147,11 +147,74 @@ def test_pairs_in_a_mixed_batch():
         assert np.abs(Xg[idx, nbs[t]:]).max(initial=0.0) == 0.0   # padded body slots are zero
 
 
-def test_adjoint_of_pairs_is_unsupported():
-    text = cluster(False)
-    sysg = braxmi.System(text, 8)
-    X = approach(8, 5, 1)
-    st = to_dev(X)
-    with pytest.raises(braxmi.BraxError) as ei:
-        sysg.step_vjp(st, torch.zeros((0, 8), dtype=torch.float32, device="cuda"), to_dev(X))
-    assert ei.value.code == -6
+PAIR_CASES = [(two_body(ka, kb, e=0.3, mu=0.8, substeps=4, dt=0.004), 2, 5) for ka, kb in KIND_PAIRS] + \
+    [(cluster(False), 5, 7), (cluster(True), 5, 7)]
+PAIR_IDS = [f"{ka}-{kb}" for ka, kb in KIND_PAIRS] + ["cluster", "cluster-frozen-hub"]
+GRAD_TOL = 1e-3
+
+
+def normwise(got, ref):
+    got = got.reshape(len(got), -1)
+    ref = ref.reshape(len(ref), -1)
+    return np.linalg.norm(got - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), 1e-30)
+
+
+def check_grad(err, amb, frac=0.05):
+    bad = err >= GRAD_TOL
+    assert not (bad & ~amb).any(), err[bad & ~amb]
+    assert bad.mean() <= frac
+
+
+@pytest.mark.parametrize("flags", [braxmi.BRAX_FUSED, braxmi.BRAX_PLAIN])
+@pytest.mark.parametrize("case", PAIR_CASES, ids=PAIR_IDS)
+def test_pair_step_vjp_matches_oracle(case, flags):
+    """Adjoint of a step with body-body impulses against the oracle's
+    (J^T g with J from dual numbers through the FP64 step)."""
+    text, nb, seed = case
+    o, X = scene(text, nb, seed)
+    n = 64
+    X = X[:n]
+    g = np.random.default_rng(12).normal(size=X.shape).astype(np.float32).astype(np.float64)
+    gi_o, _ = o.step_vjp(X, np.zeros((n, 0)), g)
+    _, mg = o.step(X, np.zeros((n, 0)), margins=True)
+    sysg = braxmi.System(text, n)
+    g_in, _ = sysg.step_vjp(to_dev(X), torch.zeros((0, n), dtype=torch.float32, device="cuda"), to_dev(g),
+                            flags=flags)
+    err = normwise(from_dev(g_in, nb), gi_o)
+    amb = mg.min(1) < 1e-6
+    print(f"pair vjp nb={nb} flags={flags}: max err {err.max():.2e} non-ambiguous "
+          f"{err[~amb].max() if (~amb).any() else 0:.2e} ambiguous {int(amb.sum())}/{n}", flush=True)
+    check_grad(err, amb)
+
+
+@pytest.mark.parametrize("case", [PAIR_CASES[6], PAIR_CASES[3], PAIR_CASES[8], PAIR_CASES[9]],
+                         ids=[PAIR_IDS[6], PAIR_IDS[3], PAIR_IDS[8], PAIR_IDS[9]])
+def test_pair_vjp_from_tape_and_parameters(case):
+    """The tape adjoint equals the recomputing one; the parameter cotangents
+    (masses, inertias, friction) match central differences of the FP64 step."""
+    text, nb, seed = case
+    o, X = scene(text, nb, seed)
+    n = 48
+    X = X[:n]
+    g = np.random.default_rng(13).normal(size=X.shape).astype(np.float32).astype(np.float64)
+    sysg = braxmi.System(text, n)
+    A = torch.zeros((1, 0, n), dtype=torch.float32, device="cuda")
+    a0 = torch.zeros((0, n), dtype=torch.float32, device="cuda")
+    out_t, tape = sysg.rollout_tape(to_dev(X), A)
+    out_r, _ = sysg.rollout(to_dev(X), A)
+    for x, y in zip(out_t.fields(), out_r.fields()):
+        assert torch.allclose(x, y, rtol=1e-6, atol=1e-6)
+    gt, _ = sysg.step_vjp_tape(tape[0], a0, to_dev(g))
+    gr, _ = sysg.step_vjp(to_dev(X), a0, to_dev(g))
+    _, mg = o.step(X, np.zeros((n, 0)), margins=True)
+    amb = mg.min(1) < 1e-6
+    e_t = normwise(from_dev(gt, nb), from_dev(gr, nb))
+    assert (e_t[~amb] < 1e-4).all(), e_t.max()
+    pv = o.param_vjp(X, np.zeros((n, 0)), g)
+    g_in, _, g_par = sysg.step_vjp_params(to_dev(X), a0, to_dev(g))
+    err = normwise(g_par.cpu().numpy().T, pv)
+    amb = mg.min(1) < 1e-5
+    print(f"pair parameter vjp nb={nb}: P {pv.shape[1]} max err {err.max():.2e} ambiguous {int(amb.sum())}/{n}",
+          flush=True)
+    check_grad(err, amb, frac=0.1)
+    assert normwise(from_dev(g_in, nb), from_dev(gr, nb)).max() < 1e-5
