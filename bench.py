@@ -39,6 +39,11 @@ def algorithmic_flops(name):
         return json.load(f)["workloads"][name]["mean"]
 
 
+# the sources k_fused is compiled from (its translation unit and the headers it includes)
+KERNEL_SOURCES = ("bx_kernels.hip", "bx_phys.h", "bx_access.h", "bx_tables.h", "bx_internal.h", "bx_pair.h",
+                  "bx_pair_lanes.h", "bx_pair_adj.h", "bx_adj.h")
+
+
 def measured_traffic():
     """HBM bytes per k_fused launch from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE, scaled by a 256 MiB copy), or None
@@ -52,7 +57,7 @@ def measured_traffic():
     except (OSError, AttributeError):
         return None
     h = hashlib.sha256()
-    for name in ("bx_kernels.hip", "bx_phys.h", "bx_access.h", "bx_tables.h", "bx_internal.h"):
+    for name in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2106_13281_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return nbytes if h.hexdigest() == want else None
@@ -230,6 +235,20 @@ def main():
     extra["cheetah_fwd_env_steps_per_s"] = wc.envs * wc.steps / (ms_c / 1e3)
     extra["cheetah_fwd_frac"] = algorithmic_flops("cheetah") * wc.envs * wc.steps / (ms_c / 1e3) / 1e12 / PEAK_FP32_TFLOPS
     log(f"cheetah forward: {ms_c:.2f} ms per {wc.envs}x{wc.steps} rollout")
+    # manipulator with finger-box contacts (body-body candidates), 4096 environments
+    wm = synth.WORKLOADS["manipulator"]
+    Eg = 4096
+    gsys = braxmi.System(synth.system_text("manipulator"), Eg, device=0)
+    gsys.autotune()
+    g0, gacts = make_inputs(gsys, wm)
+    gout = gsys.new_state()
+    ms_g = time_calls(lambda: gsys.rollout(g0, gacts, out=gout), args.steps, args.warmup)
+    extra["manipulator_fwd_env_steps_per_s"] = Eg * wm.steps / (ms_g / 1e3)
+    extra["manipulator_fwd_frac"] = (algorithmic_flops("manipulator") * Eg * wm.steps / (ms_g / 1e3) / 1e12 /
+                                     PEAK_FP32_TFLOPS)
+    extra["manipulator_workload"] = (f"manipulator with four finger-box body-body candidates, {Eg} environments x "
+                                     f"{wm.steps} steps, actions U(-1,1)")
+    log(f"manipulator forward: {ms_g:.2f} ms per {Eg}x{wm.steps} rollout")
 
     types = synth.mixed_assignment(0)
     msys = braxmi.System([synth.system_text(n) for n in synth.MIXED_TYPES], len(types), env_desc=types, device=0)
@@ -261,7 +280,8 @@ def main():
     ms_mv = time_calls(mixed_fwd_bwd, 1, 1)
     extra["mixed_fwd_vjp_env_steps_per_s"] = len(types) * Tv / (ms_mv / 1e3)
     extra["mixed_workload"] = ("8192 environments: 2048 chains, 3277 quadrupeds, 2048 bipeds, 819 manipulators "
-                               "(seeded permutation), reset pose, actions U(-1,1); forward 1000 steps, "
+                               "(with finger-box contacts; seeded permutation), reset pose, actions U(-1,1); "
+                               "forward 1000 steps, "
                                "forward+VJP 100 steps with checkpoints every 10")
     log(f"mixed forward: {ms_m:.2f} ms ({ms_mg:.2f} ms graph); step {ms_ms * 1e3:.1f} us "
         f"({ms_msg * 1e3:.1f} us graph); forward+VJP {ms_mv:.2f} ms")

@@ -455,7 +455,7 @@ __global__ __launch_bounds__(256) void k_fused(const Tables* __restrict__ tab, c
 // and without the tape), so that the registers the body-body phase needs do
 // not lower the occupancy of the kernel above.
 template <bool TAPE>
-__global__ __launch_bounds__(256) void k_fused_pairs(const Tables* __restrict__ tab,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_pairs(const Tables* __restrict__ tab,
                                                      const WaveWork* __restrict__ work, int n_work,
                                                      const int32_t* __restrict__ env_list,
                                                      const int32_t* __restrict__ type_off, int E, int Bm, Fields in,
