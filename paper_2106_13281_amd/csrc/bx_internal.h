@@ -59,7 +59,7 @@ struct ContactD {
 // centre a0, rotation aR and half extents ah) with a radius.
 struct PairD {
   int a, b, kind;  // PairKind
-  int handler;     // a or b: the body whose lane evaluates it in the fused kernels
+  int handler;     // the body whose lane evaluates it in the fused kernels (any body of the system)
   double a0[3], a1[3], ra, ah[3], aR[9];
   double b0[3], b1[3], rb, bh[3], bR[9];
 };

@@ -1,10 +1,14 @@
 // Body-body contacts in the one-lane-per-body kernels (device code).
 //
-// Each candidate is evaluated on the lane of one of its two bodies (its
-// handler, chosen when the tables are packed); the other body's state and
-// frame come by cross-lane reads. The handler keeps its own body's share and
-// leaves the other's, which that body's lane collects in the same evaluation
-// slot from the handler lanes listed in its table row. The loops run to the
+// Each candidate is evaluated on the lane of one body of the environment
+// (its handler, chosen when the tables are packed so that the candidates
+// spread over all of the environment's lanes); the two bodies' states and
+// frames come by cross-lane reads. The handler leaves both shares in
+// registers; in the same evaluation slot each body's lane collects its
+// shares from the handler lanes listed in its table row, first-body shares
+// and second-body shares in two passes. An evaluation slot in which no lane
+// of the wavefront has a candidate whose body origins are within reach is
+// skipped as a whole (no contact is possible there). The loops run to the
 // type's maxima so that every cross-lane read executes on the whole
 // wavefront; a lane without work in a slot reads its own values and
 // discards them.
@@ -29,6 +33,13 @@ __device__ __forceinline__ PairSide shfl_side(const PairSide& s, int src) {
   return o;
 }
 
+// Whether any lane of the wavefront has a candidate within reach in this
+// slot; the two body origins come by cross-lane reads.
+__device__ __forceinline__ bool pair_near(const PairT& P, bool mine, v3 pA, v3 pB) {
+  const v3 d = pA - pB;
+  return mine && dot(d, d) <= P.reach * P.reach;
+}
+
 // Forward: adds this body's body-body velocity changes to dv, dw and the
 // applied candidates to cnt (post-kinematic state s, frame f).
 __device__ __forceinline__ void pair_phase(const Tables* __restrict__ tab, int t, int b, int base, const Body& s,
@@ -40,32 +51,28 @@ __device__ __forceinline__ void pair_phase(const Tables* __restrict__ tab, int t
   for (int i = 0; i < ty.max_handled; ++i) {
     const bool mine = i < nh;
     const PairT& P = tab->pair[t][Bg.hp[i]];  // hp[i] = 0 past nh: a valid candidate, unused
-    const bool first = P.a == b;
-    const PairSide o = shfl_side(me, base + (mine ? (first ? P.b : P.a) : b));
-    v3 odv = V(0.f, 0.f, 0.f), odw = odv;
+    const int sa = base + (mine ? P.a : b), sb = base + (mine ? P.b : b);
+    const bool near = pair_near(P, mine, shfl_v3(s.p, sa), shfl_v3(s.p, sb));
+    if (__ballot(near) == 0ull) continue;  // wave-uniform
+    const PairSide A = shfl_side(me, sa), B = shfl_side(me, sb);
+    v3 dvA = V(0.f, 0.f, 0.f), dwA = dvA, dvB = dvA, dwB = dvA;
     float on = 0.f;
-    if (mine) {
-      const PairSide A = sel(first, me, o), B = sel(first, o, me);
-      v3 dvA, dwA, dvB, dwB;
-      if (pair_eval(P, ty, A, B, dvA, dwA, dvB, dwB)) {
-        dv += sel(first, dvA, dvB);
-        dw += sel(first, dwA, dwB);
-        odv = sel(first, dvB, dvA);
-        odw = sel(first, dwB, dwA);
-        on = 1.f;
-        ++cnt;
-      }
-    }
-    const int nr = Bg.nrecv[i];
-    const uint32_t rv = Bg.recv[i];
-    for (int k = 0; k < ty.recv_n[i]; ++k) {
-      const int hsrc = base + (k < nr ? (int)((rv >> (4 * k)) & 15u) : b);
-      const v3 a = shfl_v3(odv, hsrc), w = shfl_v3(odw, hsrc);
-      const float got = shfl(on, hsrc);
-      if (k < nr && got != 0.f) {
-        dv += a;
-        dw += w;
-        ++cnt;
+    if (near && pair_eval(P, ty, A, B, dvA, dwA, dvB, dwB)) on = 1.f;
+    // collect: first-body shares, then second-body shares
+    for (int side = 0; side < 2; ++side) {
+      const int nr = side == 0 ? Bg.nra[i] : Bg.nrb[i];
+      const uint32_t rv = side == 0 ? Bg.recva[i] : Bg.recvb[i];
+      const int kmax = side == 0 ? ty.recv_na[i] : ty.recv_nb[i];
+      const v3 xv = sel(side == 0, dvA, dvB), xw = sel(side == 0, dwA, dwB);
+      for (int k = 0; k < kmax; ++k) {
+        const int hsrc = base + (k < nr ? (int)((rv >> (4 * k)) & 15u) : b);
+        const v3 a = shfl_v3(xv, hsrc), w = shfl_v3(xw, hsrc);
+        const float got = shfl(on, hsrc);
+        if (k < nr && got != 0.f) {
+          dv += a;
+          dw += w;
+          ++cnt;
+        }
       }
     }
   }
@@ -82,54 +89,51 @@ __device__ __forceinline__ void pair_phase_adj(const Tables* __restrict__ tab, i
   const BodyT& Bg = tab->body[t][b];
   const int nh = Bg.nh;
   const PairSide me{post.p, post.v, post.w, f.R, f.Iwinv};
-  auto add = [&](const PairSideBar& x) {
-    tot.p += x.p;
-    tot.v += x.v;
-    tot.w += x.w;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) fr.Rb.m[k] += x.R.m[k];
-    fr.Iwinvb.xx += x.Iwinv.xx;
-    fr.Iwinvb.yy += x.Iwinv.yy;
-    fr.Iwinvb.zz += x.Iwinv.zz;
-    fr.Iwinvb.xy += x.Iwinv.xy;
-    fr.Iwinvb.xz += x.Iwinv.xz;
-    fr.Iwinvb.yz += x.Iwinv.yz;
-    invm_bar += x.im;
-  };
   for (int i = 0; i < ty.max_handled; ++i) {
     const bool mine = i < nh;
     const PairT& P = tab->pair[t][Bg.hp[i]];
-    const bool first = P.a == b;
-    const int src = base + (mine ? (first ? P.b : P.a) : b);
-    const PairSide o = shfl_side(me, src);
-    const v3 odvb = shfl_v3(dvb, src), odwb = shfl_v3(dwb, src);
-    PairSideBar ob = pairbar_zero();  // the other body's cotangents, left for its lane
-    if (mine) {
-      const PairSide A = sel(first, me, o), B = sel(first, o, me);
-      PairSideBar Ab = pairbar_zero(), Bb = pairbar_zero();
-      if (pair_adj(P, ty, A, B, sel(first, dvb, odvb), sel(first, dwb, odwb), sel(first, odvb, dvb),
-                   sel(first, odwb, dwb), Ab, Bb, mu_bar)) {
-        // a body without inverse mass here (all translations frozen) has no mass cotangent from it
-        if (P.im_a == 0.f) Ab.im = 0.f;
-        if (P.im_b == 0.f) Bb.im = 0.f;
-        add(sel(first, Ab, Bb));
-        ob = sel(first, Bb, Ab);
-      }
+    const int sa = base + (mine ? P.a : b), sb = base + (mine ? P.b : b);
+    const bool near = pair_near(P, mine, shfl_v3(post.p, sa), shfl_v3(post.p, sb));
+    if (__ballot(near) == 0ull) continue;  // wave-uniform
+    const PairSide A = shfl_side(me, sa), B = shfl_side(me, sb);
+    const v3 dvbA = shfl_v3(dvb, sa), dwbA = shfl_v3(dwb, sa), dvbB = shfl_v3(dvb, sb), dwbB = shfl_v3(dwb, sb);
+    PairSideBar Ab = pairbar_zero(), Bb = pairbar_zero();
+    if (near && pair_adj(P, ty, A, B, dvbA, dwbA, dvbB, dwbB, Ab, Bb, mu_bar)) {
+      // a body without inverse mass here (all translations frozen) has no mass cotangent from it
+      if (P.im_a == 0.f) Ab.im = 0.f;
+      if (P.im_b == 0.f) Bb.im = 0.f;
     }
-    const int nr = Bg.nrecv[i];
-    const uint32_t rv = Bg.recv[i];
-    for (int k = 0; k < ty.recv_n[i]; ++k) {
-      const int hsrc = base + (k < nr ? (int)((rv >> (4 * k)) & 15u) : b);
-      PairSideBar x;
-      x.p = shfl_v3(ob.p, hsrc);
-      x.v = shfl_v3(ob.v, hsrc);
-      x.w = shfl_v3(ob.w, hsrc);
+    for (int side = 0; side < 2; ++side) {
+      const int nr = side == 0 ? Bg.nra[i] : Bg.nrb[i];
+      const uint32_t rv = side == 0 ? Bg.recva[i] : Bg.recvb[i];
+      const int kmax = side == 0 ? ty.recv_na[i] : ty.recv_nb[i];
+      const PairSideBar ob = sel(side == 0, Ab, Bb);
+      for (int k = 0; k < kmax; ++k) {
+        const int hsrc = base + (k < nr ? (int)((rv >> (4 * k)) & 15u) : b);
+        PairSideBar x;
+        x.p = shfl_v3(ob.p, hsrc);
+        x.v = shfl_v3(ob.v, hsrc);
+        x.w = shfl_v3(ob.w, hsrc);
 #pragma unroll
-      for (int q = 0; q < 9; ++q) x.R.m[q] = shfl(ob.R.m[q], hsrc);
-      x.Iwinv = s3{shfl(ob.Iwinv.xx, hsrc), shfl(ob.Iwinv.yy, hsrc), shfl(ob.Iwinv.zz, hsrc),
-                   shfl(ob.Iwinv.xy, hsrc), shfl(ob.Iwinv.xz, hsrc), shfl(ob.Iwinv.yz, hsrc)};
-      x.im = shfl(ob.im, hsrc);
-      if (k < nr) add(x);
+        for (int q = 0; q < 9; ++q) x.R.m[q] = shfl(ob.R.m[q], hsrc);
+        x.Iwinv = s3{shfl(ob.Iwinv.xx, hsrc), shfl(ob.Iwinv.yy, hsrc), shfl(ob.Iwinv.zz, hsrc),
+                     shfl(ob.Iwinv.xy, hsrc), shfl(ob.Iwinv.xz, hsrc), shfl(ob.Iwinv.yz, hsrc)};
+        x.im = shfl(ob.im, hsrc);
+        if (k < nr) {
+          tot.p += x.p;
+          tot.v += x.v;
+          tot.w += x.w;
+#pragma unroll
+          for (int q = 0; q < 9; ++q) fr.Rb.m[q] += x.R.m[q];
+          fr.Iwinvb.xx += x.Iwinv.xx;
+          fr.Iwinvb.yy += x.Iwinv.yy;
+          fr.Iwinvb.zz += x.Iwinv.zz;
+          fr.Iwinvb.xy += x.Iwinv.xy;
+          fr.Iwinvb.xz += x.Iwinv.xz;
+          fr.Iwinvb.yz += x.Iwinv.yz;
+          invm_bar += x.im;
+        }
+      }
     }
   }
 }

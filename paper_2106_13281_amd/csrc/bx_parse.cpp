@@ -555,23 +555,27 @@ int build_system(const char* text, SystemDesc& d, std::string& err) {
     for (size_t b = 0; b < d.bodies.size(); ++b)
       if (involved[b] > MAXPI)
         throw MErr{"body '" + d.bodies[b].name + "': more than 16 body-body contact candidates"};
-    // each candidate is evaluated on the lane of one of its bodies (the
-    // handler: the one that evaluates fewer so far, the first on a tie, or
-    // the other one where that would exceed a limit); the handler's lane
-    // keeps its own share and leaves the other body's, and a lane evaluates
-    // at most MAXH candidates and collects at most MAXR shares per slot
-    std::vector<int> handled(d.bodies.size(), 0);
-    std::vector<std::vector<int>> collects(d.bodies.size(), std::vector<int>(MAXH, 0));
+    // each candidate is evaluated on the lane of some body of the system
+    // (its handler): the body that evaluates the fewest so far (the lowest
+    // index on a tie) among those where the candidate fits, so that the
+    // candidates spread over all lanes of an environment. A lane evaluates at
+    // most MAXH candidates; in one evaluation slot a body collects at most
+    // MAXR shares as a first body and MAXR as a second body.
+    const int nb = (int)d.bodies.size();
+    std::vector<int> handled(nb, 0);
+    std::vector<std::vector<int>> col_a(nb, std::vector<int>(MAXH, 0)), col_b(nb, std::vector<int>(MAXH, 0));
     for (PairD& P : d.pairs) {
-      auto fits = [&](int h, int o) { return handled[h] < MAXH && collects[o][handled[h]] < MAXR; };
-      int h = handled[P.a] <= handled[P.b] ? P.a : P.b;
-      int o = h == P.a ? P.b : P.a;
-      if (!fits(h, o)) std::swap(h, o);
-      if (!fits(h, o))
+      int h = -1;
+      for (int want = 0; want < MAXH && h < 0; ++want)
+        for (int x = 0; x < nb && h < 0; ++x)
+          if (handled[x] == want && col_a[P.a][want] < MAXR && col_b[P.b][want] < MAXR) h = x;
+      if (h < 0)
         throw MErr{"body_contacts: bodies '" + d.bodies[P.a].name + "' and '" + d.bodies[P.b].name +
-                   "' take part in more candidates than a lane can evaluate or collect (limit)"};
+                   "' take part in more candidates than the lanes can evaluate or collect (limit)"};
       P.handler = h;
-      ++collects[o][handled[h]++];
+      const int slot = handled[h]++;
+      ++col_a[P.a][slot];
+      ++col_b[P.b][slot];
     }
     return BRAX_OK;
   } catch (const PErr& e) {
@@ -679,22 +683,34 @@ void pack_type(const SystemDesc& d, Tables& tab, int t) {
       P.aR[k] = (float)S.aR[k];
       P.bR[k] = (float)S.bR[k];
     }
+    // origins farther apart than the two features' extents from their
+    // origins plus the radii cannot be in contact
+    auto norm = [](const double* v) { return std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); };
+    auto extent = [&](bool box, const double* p0, const double* p1, const double* half, double r) {
+      return box ? norm(p0) + norm(half) : std::max(norm(p0), norm(p1)) + r;
+    };
+    const double reach = extent(S.kind == PK_BP, S.a0, S.a1, S.ah, S.ra) + extent(S.kind == PK_PB, S.b0, S.b1, S.bh, S.rb);
+    // with a margin (0.01% and 0.1 mm) far above the FP32 rounding of positions and of the test
+    P.reach = (float)(reach * (1.0 + 1e-4) + 1e-4);
     BodyT& A = tab.body[t][S.a];
     BodyT& Bb = tab.body[t][S.b];
     A.pairs[A.npair++] = c;
     Bb.pairs[Bb.npair++] = c;
-    const bool on_a = S.handler == S.a;
-    BodyT& H = on_a ? A : Bb;
-    BodyT& R = on_a ? Bb : A;
+    BodyT& H = tab.body[t][S.handler];
     const int slot = H.nh;  // within MAXH and MAXR: checked when the description was built
     H.hp[H.nh++] = c;
-    R.recv[slot] |= (uint32_t)(on_a ? S.a : S.b) << (4 * R.nrecv[slot]);
-    ++R.nrecv[slot];
+    A.recva[slot] |= (uint32_t)S.handler << (4 * A.nra[slot]);
+    ++A.nra[slot];
+    Bb.recvb[slot] |= (uint32_t)S.handler << (4 * Bb.nrb[slot]);
+    ++Bb.nrb[slot];
   }
   for (int b = 0; b < ty.nb; ++b) {
     const BodyT& B = tab.body[t][b];
     ty.max_handled = std::max(ty.max_handled, B.nh);
-    for (int i = 0; i < MAXH; ++i) ty.recv_n[i] = std::max(ty.recv_n[i], B.nrecv[i]);
+    for (int i = 0; i < MAXH; ++i) {
+      ty.recv_na[i] = std::max(ty.recv_na[i], B.nra[i]);
+      ty.recv_nb[i] = std::max(ty.recv_nb[i], B.nrb[i]);
+    }
   }
   int dof0 = 0;
   for (int j = 0; j < ty.nj; ++j) {

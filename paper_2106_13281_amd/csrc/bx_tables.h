@@ -16,8 +16,8 @@ constexpr int MAXA = 48;   // actions per system
 constexpr int MAXCH = 8;   // children per body
 constexpr int MAXP = 32;   // body-body contact candidates per system
 constexpr int MAXPI = 16;  // body-body candidates one body takes part in
-constexpr int MAXH = 4;    // body-body candidates one body's lane evaluates (fused kernels)
-constexpr int MAXR = 8;    // shares one body collects from other lanes per evaluation slot
+constexpr int MAXH = 8;    // body-body candidates one lane evaluates (fused kernels)
+constexpr int MAXR = 8;    // shares of one side one body collects per evaluation slot
 // body-body candidate kinds: the first body's core feature against the second's
 enum PairKind : int32_t { PK_PP = 0, PK_PS = 1, PK_SP = 2, PK_SS = 3, PK_PB = 4, PK_BP = 5 };
 
@@ -27,8 +27,9 @@ struct TypeT {
   int32_t max_children;    // largest child count of a body
   int32_t max_contacts;    // largest contact-candidate count of a body
   int32_t np;              // body-body contact candidates
-  int32_t max_handled;     // largest count of candidates one body's lane evaluates
-  int32_t recv_n[MAXH];    // per evaluation slot: largest count of shares one body collects
+  int32_t max_handled;     // largest count of candidates one lane evaluates
+  int32_t recv_na[MAXH];   // per evaluation slot: largest count of first-body shares one body collects
+  int32_t recv_nb[MAXH];   // the same for second-body shares
   float dt, h;             // step and substep length (s)
   float beta_h;            // Baumgarte factor over h (1/s)
   float one_plus_e;        // 1 + restitution
@@ -53,13 +54,15 @@ struct BodyT {
   float pos0[3];           // that position
   int32_t npair;           // body-body candidates this body takes part in (as first or second)
   int32_t pairs[MAXPI];    // their indices, ascending
-  // fused kernels: each candidate is evaluated on the lane of one of its two
-  // bodies (the handler), which keeps its own share of the impulse and
-  // leaves the other body's share for that body's lane to collect
+  // fused kernels: each candidate is evaluated on the lane of some body of
+  // the system (its handler), which leaves both bodies' shares in registers
+  // for their lanes to collect in the same evaluation slot
   int32_t nh;              // candidates this body's lane evaluates
   int32_t hp[MAXH];        // their indices (evaluation slots 0 .. nh-1)
-  int32_t nrecv[MAXH];     // per slot: shares this body collects
-  uint32_t recv[MAXH];     // per slot: handler bodies of those shares, 4 bits each
+  int32_t nra[MAXH];       // per slot: shares this body collects as a candidate's first body
+  uint32_t recva[MAXH];    // per slot: the handler bodies of those shares, 4 bits each
+  int32_t nrb[MAXH];       // the same as a candidate's second body
+  uint32_t recvb[MAXH];
 };
 
 struct JointT {
@@ -87,7 +90,8 @@ struct ContactT {
 // mass im (0 when all translations are frozen) and whether rotations
 // respond (0 when all are frozen) of each body.
 struct PairT {
-  int32_t a, b, kind, rot_a, rot_b, pad[3];
+  int32_t a, b, kind, rot_a, rot_b, pad[2];
+  float reach;             // no contact while the two body origins are farther apart than this
   float a0[3], a1[3], ra;
   float b0[3], b1[3], rb;
   float ah[3], bh[3];

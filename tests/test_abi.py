@@ -157,12 +157,12 @@ def test_body_contact_errors():
     expect(-3, ball.format(n="a") + 'body_contacts { first: "a" second: "a" }', match="bad pair")
     expect(-2, ball.format(n="a") + ball.format(n="b") + 'body_contacts { first: "a" second: "b" third: "c" }',
            match="unknown field")
-    # spheres around one: twelve fit (eight shares collected in one slot, four
-    # evaluated on the hub's own lane), thirteen exceed what its lane can take,
-    # seventeen exceed the per-body candidate limit
-    def star(n):
-        text = ball.format(n="hub") + "".join(ball.format(n=f"s{i}") for i in range(n))
+    # spheres around one: fifteen fit (the hub collects eight shares in one
+    # evaluation slot and seven in the next); with two spheres on the hub,
+    # nine satellites give it eighteen candidates, beyond the per-body limit
+    def star(n, hub=ball):
+        text = hub.format(n="hub") + "".join(ball.format(n=f"s{i}") for i in range(n))
         return text + "".join(f'body_contacts {{ first: "s{i}" second: "hub" }}\n' for i in range(n))
-    assert host(star(12)).n_pairs == [12]
-    expect(-3, star(13), match="limit")
-    expect(-3, star(17), match="more than 16")
+    assert host(star(15)).n_pairs == [15]
+    two = 'bodies {{ name: "{n}" mass: 1 colliders {{ sphere {{ radius: 0.1 }} }} colliders {{ sphere {{ radius: 0.1 }} }} }}\n'
+    expect(-3, star(9, two), match="more than 16 body-body")
