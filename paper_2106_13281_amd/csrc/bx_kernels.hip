@@ -305,7 +305,7 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
                                           int E, int Bm, const Fields& in, const Fields& out,
                                           const float* __restrict__ acts, int Am, int T, int save_every,
                                           const Fields& traj, uint8_t* nonfinite, float* __restrict__ tape,
-                                          int smax, int w, int n_work) {
+                                          int smax, int w, int n_work, PairLanes* pl = nullptr) {
   const int t = wk.type;
   const TypeT ty = tab->type[t];
   const int nb = ty.nb;
@@ -326,6 +326,7 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
   pin_consts<MAXDOF>(B, J, has_joint, Creg, REG_CONTACTS);
   const float h = ty.h;
 
+  if (PAIRS && ty.np > 0) pair_lanes_load(tab, t, pl, lane);
   Body s = load_body(in, b, e, Bm, E);
   // frozen velocity components zeroed once; every update below keeps them zero
   s.v = keep(s.v, B.free_p);
@@ -401,7 +402,7 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
         }
       }
       // body-body contacts after the joint sums, where fewer values are live
-      if (PAIRS && ty.np > 0) pair_phase(tab, t, b, base, s, f, dv, dw, cnt);
+      if (PAIRS && ty.np > 0) pair_phase(tab, t, *pl, b, base, s, f, dv, dw, cnt);
       if (TAPE) wtape_rest(tp, torque, cnt, lane);
       potential(B, ty, s, f, force, torque);
       collision(B, s, dv, dw, cnt);
@@ -462,15 +463,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                                                      Fields out, const float* __restrict__ acts, int Am, int T,
                                                      int save_every, Fields traj, uint8_t* nonfinite, float* tape,
                                                      int smax) {
+  extern __shared__ PairLanes pair_lds[];  // one per wavefront of the block
   const int w = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (w >= n_work) return;
   const WaveWork wk = work[w];
+  PairLanes* pl = pair_lds + (threadIdx.x >> 6);
   if (tab->type[wk.type].max_dof <= 1)
     fused_run<1, TAPE, true>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
-                             tape, smax, w, n_work);
+                             tape, smax, w, n_work, pl);
   else
     fused_run<3, TAPE, true>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
-                             tape, smax, w, n_work);
+                             tape, smax, w, n_work, pl);
 }
 
 // ------------------------------------------------------------------ small helpers
@@ -595,13 +598,14 @@ hipError_t launch_fused(const LaunchCtx& c, const WaveWork* work, int n_work, in
   bool pairs = false;
   for (int t = 0; t < c.n_types; ++t) pairs = pairs || c.host_tab->type[t].np > 0;
   if (pairs) {
+    const size_t lds = sizeof(PairLanes) * waves_per_block;
     if (tape)
-      hipLaunchKernelGGL(k_fused_pairs<true>, dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block), 0, s,
-                         c.tab, work, n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every,
+      hipLaunchKernelGGL(k_fused_pairs<true>, dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block), lds,
+                         s, c.tab, work, n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every,
                          traj, flags ? c.nonfinite : nullptr, tape, smax);
     else
-      hipLaunchKernelGGL(k_fused_pairs<false>, dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block), 0, s,
-                         c.tab, work, n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every,
+      hipLaunchKernelGGL(k_fused_pairs<false>, dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block), lds,
+                         s, c.tab, work, n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every,
                          traj, flags ? c.nonfinite : nullptr, nullptr, 0);
     return hipGetLastError();
   }

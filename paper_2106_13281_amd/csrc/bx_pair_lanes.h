@@ -20,6 +20,41 @@ namespace bx {
 
 __device__ __forceinline__ v3 shfl_v3(v3 a, int src) { return V(shfl(a.x, src), shfl(a.y, src), shfl(a.z, src)); }
 
+// One wavefront's copy, in LDS, of its system type's body-body tables: the
+// lanes read them at lane-varying indices every substep, which from LDS
+// costs a fraction of the latency of the device-memory tables.
+struct PairLanes {
+  PairT pair[MAXP];
+  int32_t nh[MAXB];
+  int32_t hp[MAXB][MAXH];
+  int32_t nra[MAXB][MAXH];
+  uint32_t recva[MAXB][MAXH];
+  int32_t nrb[MAXB][MAXH];
+  uint32_t recvb[MAXB][MAXH];
+};
+
+// All lanes of the wavefront copy type t's tables into L; the wavefront's
+// own later LDS reads see the writes (LDS operations of a wavefront are
+// performed in order).
+__device__ __forceinline__ void pair_lanes_load(const Tables* __restrict__ tab, int t, PairLanes* L, int lane) {
+  const TypeT& ty = tab->type[t];
+  const int n_words = ty.np * (int)(sizeof(PairT) / 4);
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(&tab->pair[t][0]);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&L->pair[0]);
+  for (int x = lane; x < n_words; x += 64) dst[x] = src[x];
+  for (int x = lane; x < ty.nb * MAXH; x += 64) {
+    const int b = x / MAXH, i = x - b * MAXH;
+    const BodyT& B = tab->body[t][b];
+    if (i == 0) L->nh[b] = B.nh;
+    L->hp[b][i] = B.hp[i];
+    L->nra[b][i] = B.nra[i];
+    L->recva[b][i] = B.recva[i];
+    L->nrb[b][i] = B.nrb[i];
+    L->recvb[b][i] = B.recvb[i];
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
 // The state and frame of the body on lane src.
 __device__ __forceinline__ PairSide shfl_side(const PairSide& s, int src) {
   PairSide o;
@@ -42,15 +77,14 @@ __device__ __forceinline__ bool pair_near(const PairT& P, bool mine, v3 pA, v3 p
 
 // Forward: adds this body's body-body velocity changes to dv, dw and the
 // applied candidates to cnt (post-kinematic state s, frame f).
-__device__ __forceinline__ void pair_phase(const Tables* __restrict__ tab, int t, int b, int base, const Body& s,
-                                           const Frame& f, v3& dv, v3& dw, int& cnt) {
+__device__ __forceinline__ void pair_phase(const Tables* __restrict__ tab, int t, const PairLanes& L, int b,
+                                           int base, const Body& s, const Frame& f, v3& dv, v3& dw, int& cnt) {
   const TypeT& ty = tab->type[t];
-  const BodyT& Bg = tab->body[t][b];
-  const int nh = Bg.nh;
+  const int nh = L.nh[b];
   const PairSide me{s.p, s.v, s.w, f.R, f.Iwinv};
   for (int i = 0; i < ty.max_handled; ++i) {
     const bool mine = i < nh;
-    const PairT& P = tab->pair[t][Bg.hp[i]];  // hp[i] = 0 past nh: a valid candidate, unused
+    const PairT& P = L.pair[L.hp[b][i]];  // hp = 0 past nh: a valid candidate, unused
     const int sa = base + (mine ? P.a : b), sb = base + (mine ? P.b : b);
     const bool near = pair_near(P, mine, shfl_v3(s.p, sa), shfl_v3(s.p, sb));
     if (__ballot(near) == 0ull) continue;  // wave-uniform
@@ -60,8 +94,8 @@ __device__ __forceinline__ void pair_phase(const Tables* __restrict__ tab, int t
     if (near && pair_eval(P, ty, A, B, dvA, dwA, dvB, dwB)) on = 1.f;
     // collect: first-body shares, then second-body shares
     for (int side = 0; side < 2; ++side) {
-      const int nr = side == 0 ? Bg.nra[i] : Bg.nrb[i];
-      const uint32_t rv = side == 0 ? Bg.recva[i] : Bg.recvb[i];
+      const int nr = side == 0 ? L.nra[b][i] : L.nrb[b][i];
+      const uint32_t rv = side == 0 ? L.recva[b][i] : L.recvb[b][i];
       const int kmax = side == 0 ? ty.recv_na[i] : ty.recv_nb[i];
       const v3 xv = sel(side == 0, dvA, dvB), xw = sel(side == 0, dwA, dwB);
       for (int k = 0; k < kmax; ++k) {
@@ -82,16 +116,15 @@ __device__ __forceinline__ void pair_phase(const Tables* __restrict__ tab, int t
 // dwb), adds the cotangents of its post-kinematic state to tot, of its frame
 // to fr, of its inverse mass to invm_bar (unless it has none here) and of the
 // friction coefficient (on handler lanes) to mu_bar.
-__device__ __forceinline__ void pair_phase_adj(const Tables* __restrict__ tab, int t, int b, int base,
-                                               const Body& post, const Frame& f, v3 dvb, v3 dwb, Bar& tot,
+__device__ __forceinline__ void pair_phase_adj(const Tables* __restrict__ tab, int t, const PairLanes& L, int b,
+                                               int base, const Body& post, const Frame& f, v3 dvb, v3 dwb, Bar& tot,
                                                FrameBar& fr, float& invm_bar, float& mu_bar) {
   const TypeT& ty = tab->type[t];
-  const BodyT& Bg = tab->body[t][b];
-  const int nh = Bg.nh;
+  const int nh = L.nh[b];
   const PairSide me{post.p, post.v, post.w, f.R, f.Iwinv};
   for (int i = 0; i < ty.max_handled; ++i) {
     const bool mine = i < nh;
-    const PairT& P = tab->pair[t][Bg.hp[i]];
+    const PairT& P = L.pair[L.hp[b][i]];
     const int sa = base + (mine ? P.a : b), sb = base + (mine ? P.b : b);
     const bool near = pair_near(P, mine, shfl_v3(post.p, sa), shfl_v3(post.p, sb));
     if (__ballot(near) == 0ull) continue;  // wave-uniform
@@ -104,8 +137,8 @@ __device__ __forceinline__ void pair_phase_adj(const Tables* __restrict__ tab, i
       if (P.im_b == 0.f) Bb.im = 0.f;
     }
     for (int side = 0; side < 2; ++side) {
-      const int nr = side == 0 ? Bg.nra[i] : Bg.nrb[i];
-      const uint32_t rv = side == 0 ? Bg.recva[i] : Bg.recvb[i];
+      const int nr = side == 0 ? L.nra[b][i] : L.nrb[b][i];
+      const uint32_t rv = side == 0 ? L.recva[b][i] : L.recvb[b][i];
       const int kmax = side == 0 ? ty.recv_na[i] : ty.recv_nb[i];
       const PairSideBar ob = sel(side == 0, Ab, Bb);
       for (int k = 0; k < kmax; ++k) {

@@ -309,7 +309,8 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
                                               const Fields& in, const float* __restrict__ act, const Fields& g_out,
                                               const Fields& g_in, float* __restrict__ g_act, float* lds,
                                               const float* __restrict__ hbm_tape, int w, int n_work,
-                                              float* __restrict__ g_params = nullptr, int p_max = 0) {
+                                              float* __restrict__ g_params = nullptr, int p_max = 0,
+                                              PairLanes* pl = nullptr) {
   constexpr int TN = PARAMS ? TAPE_N + 3 : TAPE_N;  // LDS tape rows per substep
   const int t = wk.type;
   const TypeT ty = tab->type[t];
@@ -330,6 +331,7 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
   Creg[1] = tab->contact[t][B.c0 + (n_con > 1 ? 1 : 0)];
   pin_consts<MAXDOF>(B, J, has_joint, Creg, REG_CONTACTS);
   const float h = ty.h;
+  if (PAIRS && ty.np > 0) pair_lanes_load(tab, t, pl, lane);
   float a[3] = {0.f, 0.f, 0.f}, raw[3] = {0.f, 0.f, 0.f};
   if (has_joint)
     for (int x = 0; x < MAXDOF; ++x) {
@@ -394,7 +396,7 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
         torque += tq;
       }
     }
-    if (PAIRS && ty.np > 0) pair_phase(tab, t, b, base, s, f, dv, dw, cnt);
+    if (PAIRS && ty.np > 0) pair_phase(tab, t, *pl, b, base, s, f, dv, dw, cnt);
     tp[832] = torque.x; tp[896] = torque.y; tp[960] = torque.z;
     tp[1024] = (float)cnt;
     if (PARAMS) {
@@ -468,7 +470,7 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
     if (n_con > 0) contact_back(Creg[0]);
     if (n_con > 1) contact_back(Creg[1]);
     for (int c = REG_CONTACTS; c < n_con; ++c) contact_back(tab->contact[t][B.c0 + c]);
-    if (PAIRS && ty.np > 0) pair_phase_adj(tab, t, b, base, post, f, dvb, dwb, tot, fr, invm_bar, mu_bar);
+    if (PAIRS && ty.np > 0) pair_phase_adj(tab, t, *pl, b, base, post, f, dvb, dwb, tot, fr, invm_bar, mu_bar);
     bar_add(tot, bC);
     if (PARAMS) {
       // Iw = R diag(I) R^T, Iwinv = R diag(1/I) R^T: d/dI_k = r_k^T S_bar r_k (r_k column k of R;
@@ -532,18 +534,19 @@ __global__ __launch_bounds__(64) void k_fused_vjp(const Tables* __restrict__ tab
                                                   const int32_t* __restrict__ type_off, int E, int Bm, int Am,
                                                   int smax, Fields in, const float* __restrict__ act, Fields g_out,
                                                   Fields g_in, float* __restrict__ g_act) {
-  extern __shared__ float lds_tape[];
+  extern __shared__ float lds_tape[];  // [body-body tables (PAIRS)] [substep tape]
   const int w = xcd_block(blockIdx.x, gridDim.x);
   if (w >= n_work) return;
   const WaveWork wk = work[w];
-  float* lds = lds_tape;
+  PairLanes* pl = PAIRS ? reinterpret_cast<PairLanes*>(lds_tape) : nullptr;
+  float* lds = lds_tape + (PAIRS ? sizeof(PairLanes) / 4 : 0);
   (void)smax;
   if (tab->type[wk.type].max_dof <= 1)
     fused_vjp_run<1, false, false, PAIRS>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds,
-        nullptr, w, n_work);
+        nullptr, w, n_work, nullptr, 0, pl);
   else
     fused_vjp_run<3, false, false, PAIRS>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds,
-        nullptr, w, n_work);
+        nullptr, w, n_work, nullptr, 0, pl);
 }
 
 // The adjoint of one step with the cotangents of the system parameters.
@@ -555,16 +558,18 @@ __global__ __launch_bounds__(64) void k_fused_vjp_params(const Tables* __restric
                                                          Fields in, const float* __restrict__ act, Fields g_out,
                                                          Fields g_in, float* __restrict__ g_act,
                                                          float* __restrict__ g_params, int p_max) {
-  extern __shared__ float lds_tape[];
+  extern __shared__ float lds_tape[];  // [body-body tables (PAIRS)] [substep tape]
   const int w = xcd_block(blockIdx.x, gridDim.x);
   if (w >= n_work) return;
   const WaveWork wk = work[w];
+  PairLanes* pl = PAIRS ? reinterpret_cast<PairLanes*>(lds_tape) : nullptr;
+  float* lds = lds_tape + (PAIRS ? sizeof(PairLanes) / 4 : 0);
   if (tab->type[wk.type].max_dof <= 1)
-    fused_vjp_run<1, false, true, PAIRS>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds_tape,
-                                  nullptr, w, n_work, g_params, p_max);
+    fused_vjp_run<1, false, true, PAIRS>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds,
+                                         nullptr, w, n_work, g_params, p_max, pl);
   else
-    fused_vjp_run<3, false, true, PAIRS>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds_tape,
-                                  nullptr, w, n_work, g_params, p_max);
+    fused_vjp_run<3, false, true, PAIRS>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds,
+                                         nullptr, w, n_work, g_params, p_max, pl);
 }
 
 // The adjoint of one step from its forward tape in HBM (no recompute, no LDS).
@@ -575,16 +580,18 @@ __global__ __launch_bounds__(64) void k_fused_vjp_tape(const Tables* __restrict_
                                                        const int32_t* __restrict__ type_off, int E, int Bm, int Am,
                                                        const float* __restrict__ tape, const float* __restrict__ act,
                                                        Fields g_out, Fields g_in, float* __restrict__ g_act) {
+  extern __shared__ float lds_pairs[];  // body-body tables (PAIRS)
   const int w = xcd_block(blockIdx.x, gridDim.x);
   if (w >= n_work) return;
   const WaveWork wk = work[w];
   const Fields none{nullptr, nullptr, nullptr, nullptr};
+  PairLanes* pl = PAIRS ? reinterpret_cast<PairLanes*>(lds_pairs) : nullptr;
   if (tab->type[wk.type].max_dof <= 1)
     fused_vjp_run<1, true, false, PAIRS>(tab, wk, env_list, type_off, E, Bm, Am, none, act, g_out, g_in, g_act,
-        nullptr, tape, w, n_work);
+        nullptr, tape, w, n_work, nullptr, 0, pl);
   else
     fused_vjp_run<3, true, false, PAIRS>(tab, wk, env_list, type_off, E, Bm, Am, none, act, g_out, g_in, g_act,
-        nullptr, tape, w, n_work);
+        nullptr, tape, w, n_work, nullptr, 0, pl);
 }
 
 // Whether a type of the batch has body-body contact candidates: the kernels
@@ -632,9 +639,9 @@ hipError_t launch_vjp_params(const LaunchCtx& c, const VjpSched& sched, Fields i
   for (int t = 0; t < c.n_types; ++t) smax = std::max(smax, (size_t)c.host_tab->type[t].substeps);
   const size_t lds = smax * (TAPE_N + 3) * 64 * sizeof(float);
   if (any_pairs(c))
-    hipLaunchKernelGGL(k_fused_vjp_params<true>, dim3(sched.n_work), dim3(64), lds, s, c.tab, sched.work,
-                       sched.n_work, c.env_list, c.type_off, c.E, c.Bm, c.Am, in, act, g_out, g_in, g_act, g_params,
-                       p_max);
+    hipLaunchKernelGGL(k_fused_vjp_params<true>, dim3(sched.n_work), dim3(64), lds + sizeof(PairLanes), s, c.tab,
+                       sched.work, sched.n_work, c.env_list, c.type_off, c.E, c.Bm, c.Am, in, act, g_out, g_in, g_act,
+                       g_params, p_max);
   else
     hipLaunchKernelGGL(k_fused_vjp_params<false>, dim3(sched.n_work), dim3(64), lds, s, c.tab, sched.work,
                        sched.n_work, c.env_list, c.type_off, c.E, c.Bm, c.Am, in, act, g_out, g_in, g_act, g_params,
@@ -646,8 +653,8 @@ hipError_t launch_vjp_tape(const LaunchCtx& c, const VjpSched& sched, const floa
                            Fields g_out, Fields g_in, float* g_act, hipStream_t s) {
   if (sched.n_work == 0) return hipSuccess;
   if (any_pairs(c))
-    hipLaunchKernelGGL(k_fused_vjp_tape<true>, dim3(sched.n_work), dim3(64), 0, s, c.tab, sched.work, sched.n_work,
-                       c.env_list, c.type_off, c.E, c.Bm, c.Am, tape, act, g_out, g_in, g_act);
+    hipLaunchKernelGGL(k_fused_vjp_tape<true>, dim3(sched.n_work), dim3(64), sizeof(PairLanes), s, c.tab, sched.work,
+                       sched.n_work, c.env_list, c.type_off, c.E, c.Bm, c.Am, tape, act, g_out, g_in, g_act);
   else
     hipLaunchKernelGGL(k_fused_vjp_tape<false>, dim3(sched.n_work), dim3(64), 0, s, c.tab, sched.work, sched.n_work,
                        c.env_list, c.type_off, c.E, c.Bm, c.Am, tape, act, g_out, g_in, g_act);
@@ -675,8 +682,9 @@ hipError_t launch_vjp(const LaunchCtx& c, VjpWork& w, const VjpSched& sched, Fie
     const size_t lds = smax * TAPE_N * 64 * sizeof(float);
     if (sched.n_work == 0) return hipSuccess;
     if (any_pairs(c))
-      hipLaunchKernelGGL(k_fused_vjp<true>, dim3(sched.n_work), dim3(64), lds, s, c.tab, sched.work, sched.n_work,
-                         c.env_list, c.type_off, E, Bm, c.Am, (int)smax, in, act, g_out, g_in, g_act);
+      hipLaunchKernelGGL(k_fused_vjp<true>, dim3(sched.n_work), dim3(64), lds + sizeof(PairLanes), s, c.tab,
+                         sched.work, sched.n_work, c.env_list, c.type_off, E, Bm, c.Am, (int)smax, in, act, g_out, g_in,
+                         g_act);
     else
       hipLaunchKernelGGL(k_fused_vjp<false>, dim3(sched.n_work), dim3(64), lds, s, c.tab, sched.work, sched.n_work,
                          c.env_list, c.type_off, E, Bm, c.Am, (int)smax, in, act, g_out, g_in, g_act);
