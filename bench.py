@@ -235,20 +235,18 @@ def main():
     extra["cheetah_fwd_env_steps_per_s"] = wc.envs * wc.steps / (ms_c / 1e3)
     extra["cheetah_fwd_frac"] = algorithmic_flops("cheetah") * wc.envs * wc.steps / (ms_c / 1e3) / 1e12 / PEAK_FP32_TFLOPS
     log(f"cheetah forward: {ms_c:.2f} ms per {wc.envs}x{wc.steps} rollout")
-    # manipulator with finger-box contacts (body-body candidates), 4096 environments
-    wm = synth.WORKLOADS["manipulator"]
-    Eg = 4096
-    gsys = braxmi.System(synth.system_text("manipulator"), Eg, device=0)
+    # grasp: the manipulator with finger-box body-body contacts
+    wg = synth.WORKLOADS["grasp"]
+    gsys = braxmi.System(synth.system_text("grasp"), wg.envs, device=0)
     gsys.autotune()
-    g0, gacts = make_inputs(gsys, wm)
+    g0, gacts = make_inputs(gsys, wg)
     gout = gsys.new_state()
     ms_g = time_calls(lambda: gsys.rollout(g0, gacts, out=gout), args.steps, args.warmup)
-    extra["manipulator_fwd_env_steps_per_s"] = Eg * wm.steps / (ms_g / 1e3)
-    extra["manipulator_fwd_frac"] = (algorithmic_flops("manipulator") * Eg * wm.steps / (ms_g / 1e3) / 1e12 /
-                                     PEAK_FP32_TFLOPS)
-    extra["manipulator_workload"] = (f"manipulator with four finger-box body-body candidates, {Eg} environments x "
-                                     f"{wm.steps} steps, actions U(-1,1)")
-    log(f"manipulator forward: {ms_g:.2f} ms per {Eg}x{wm.steps} rollout")
+    extra["grasp_fwd_env_steps_per_s"] = wg.envs * wg.steps / (ms_g / 1e3)
+    extra["grasp_fwd_frac"] = algorithmic_flops("grasp") * wg.envs * wg.steps / (ms_g / 1e3) / 1e12 / PEAK_FP32_TFLOPS
+    extra["grasp_workload"] = (f"manipulator with four finger-box body-body candidates, box within reach, "
+                               f"{wg.envs} environments x {wg.steps} steps, actions U(-1,1)")
+    log(f"grasp forward: {ms_g:.2f} ms per {wg.envs}x{wg.steps} rollout")
 
     types = synth.mixed_assignment(0)
     msys = braxmi.System([synth.system_text(n) for n in synth.MIXED_TYPES], len(types), env_desc=types, device=0)
@@ -280,8 +278,7 @@ def main():
     ms_mv = time_calls(mixed_fwd_bwd, 1, 1)
     extra["mixed_fwd_vjp_env_steps_per_s"] = len(types) * Tv / (ms_mv / 1e3)
     extra["mixed_workload"] = ("8192 environments: 2048 chains, 3277 quadrupeds, 2048 bipeds, 819 manipulators "
-                               "(with finger-box contacts; seeded permutation), reset pose, actions U(-1,1); "
-                               "forward 1000 steps, "
+                               "(seeded permutation), reset pose, actions U(-1,1); forward 1000 steps, "
                                "forward+VJP 100 steps with checkpoints every 10")
     log(f"mixed forward: {ms_m:.2f} ms ({ms_mg:.2f} ms graph); step {ms_ms * 1e3:.1f} us "
         f"({ms_msg * 1e3:.1f} us graph); forward+VJP {ms_mv:.2f} ms")

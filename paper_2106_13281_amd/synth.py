@@ -40,8 +40,8 @@ class Workload:
 
 
 # The workload shapes (small chain, quadruped, biped, differentiation,
-# manipulator, planar runner; the mixed batch below). Sizes: environments x
-# steps.
+# manipulator, planar runner, grasp; the mixed batch below). Sizes:
+# environments x steps.
 WORKLOADS = {
     "chain": Workload("chain", 64, 200, 1.0, 0.2, 0.0),
     "quadruped": Workload("quadruped", 4096, 1000, 1.0, 0.1, 0.1),
@@ -50,6 +50,8 @@ WORKLOADS = {
     "manipulator": Workload("manipulator", 819, 1000, 1.0, 0.1, 0.0),
     # planar runner with target-angle actuators: actions are joint angles (rad)
     "cheetah": Workload("cheetah", 2048, 1000, 0.6, 0.1, 0.1),
+    # the manipulator with finger-box body-body contacts
+    "grasp": Workload("grasp", 4096, 1000, 1.0, 0.1, 0.0),
 }
 
 # Mixed batch: 8192 environments, 25% chains, 40% quadrupeds, 25% bipeds,

@@ -35,7 +35,7 @@ def count(name, E=32, warm=20, steps=100, every=5):
 
 def main():
     out = {"unit": "FLOP per environment step (all substeps)", "workloads": {}}
-    for name in ("chain", "quadruped", "biped", "manipulator", "cheetah"):
+    for name in ("chain", "quadruped", "biped", "manipulator", "cheetah", "grasp"):
         mean, lo, hi = count(name)
         out["workloads"][name] = {"mean": mean, "min": lo, "max": hi}
         print(name, mean, lo, hi)

@@ -14,7 +14,7 @@ from tests.pair_scenes import KIND_PAIRS, cluster, two_body
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "braxmi.h")
-SYSTEMS = ("chain", "quadruped", "biped", "manipulator", "cheetah")
+SYSTEMS = ("chain", "quadruped", "biped", "manipulator", "cheetah", "grasp")
 MIXED = synth.MIXED_TYPES      # the four types of the mixed batch
 
 

@@ -14,7 +14,7 @@ from paper_2106_13281_amd import braxmi, synth
 from tests.helpers import ambiguous, make_states, rel_err
 
 pytestmark = pytest.mark.gpu
-SYSTEMS = ("chain", "quadruped", "biped", "manipulator", "cheetah")
+SYSTEMS = ("chain", "quadruped", "biped", "manipulator", "cheetah", "grasp")
 MIXED = synth.MIXED_TYPES      # the four types of the mixed batch
 STEP_TOL, ROLL_TOL = 1e-4, 1e-3
 STEP_AMB, ROLL_AMB = 1e-6, 1e-5

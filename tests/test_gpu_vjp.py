@@ -13,7 +13,7 @@ from paper_2106_13281_amd import braxmi, synth
 from tests.helpers import make_states
 
 pytestmark = pytest.mark.gpu
-SYSTEMS = ("chain", "quadruped", "biped", "manipulator", "cheetah")
+SYSTEMS = ("chain", "quadruped", "biped", "manipulator", "cheetah", "grasp")
 MIXED = synth.MIXED_TYPES      # the four types of the mixed batch
 GRAD_TOL = 1e-3
 

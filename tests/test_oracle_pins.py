@@ -662,7 +662,7 @@ def test_default_pose_realises_joint_angles():
 
 
 # ------------------------------------------------------------ P13 adjoint
-@pytest.mark.parametrize("name", ["chain", "quadruped", "biped", "manipulator", "cheetah"])
+@pytest.mark.parametrize("name", ["chain", "quadruped", "biped", "manipulator", "cheetah", "grasp"])
 def test_dual_jacobian_matches_central_differences(name):
     wl = synth.WORKLOADS[name]
     o = oracle.Oracle(synth.system_text(name))
@@ -698,7 +698,7 @@ def test_dual_jacobian_matches_central_differences(name):
 
 
 # ------------------------------------------------------------ stability + work
-@pytest.mark.parametrize("name", ["chain", "quadruped", "biped", "manipulator", "cheetah"])
+@pytest.mark.parametrize("name", ["chain", "quadruped", "biped", "manipulator", "cheetah", "grasp"])
 def test_workloads_stay_finite_and_joints_hold(name):
     wl = synth.WORKLOADS[name]
     o = oracle.Oracle(synth.system_text(name))
