@@ -225,6 +225,18 @@ def main():
     extra["biped_fwd_env_steps_per_s"] = wb.envs * wb.steps / (ms_b / 1e3)
     extra["biped_fwd_frac"] = algorithmic_flops("biped") * wb.envs * wb.steps / (ms_b / 1e3) / 1e12 / PEAK_FP32_TFLOPS
     log(f"biped forward: {ms_b:.2f} ms per {wb.envs}x{wb.steps} rollout")
+    # the quadruped at twice the environments: 8192 fill every SIMD with
+    # wavefronts (4096 leave the GPU one wavefront per SIMD at most)
+    E2 = 2 * E
+    qsys = braxmi.System(synth.system_text("quadruped"), E2, device=0)
+    qsys.autotune()
+    q0, qacts = make_inputs(qsys, wl)
+    qout = qsys.new_state()
+    ms_q = time_calls(lambda: qsys.rollout(q0, qacts, out=qout), args.steps, args.warmup)
+    extra["quadruped_8192_fwd_env_steps_per_s"] = E2 * T / (ms_q / 1e3)
+    extra["quadruped_8192_fwd_frac"] = algorithmic_flops("quadruped") * E2 * T / (ms_q / 1e3) / 1e12 / PEAK_FP32_TFLOPS
+    log(f"quadruped {E2} forward: {ms_q:.2f} ms per {E2}x{T} rollout")
+    del qsys, q0, qacts, qout
     # planar runner with target-angle actuators
     wc = synth.WORKLOADS["cheetah"]
     csys = braxmi.System(synth.system_text("cheetah"), wc.envs, device=0)
