@@ -36,7 +36,7 @@ def check(r, amb, tol, frac=0.05):
     assert bad.mean() <= frac, (bad.sum(), len(bad))
 
 
-@pytest.mark.parametrize("name", ["quadruped", "biped"])
+@pytest.mark.parametrize("name", ["quadruped", "biped", "grasp"])
 def test_full_size_workload_sampled_parity(name):
     wl = synth.WORKLOADS[name]
     o = oracle.Oracle(synth.system_text(wl.system))
