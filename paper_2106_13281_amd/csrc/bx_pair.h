@@ -158,7 +158,10 @@ BXF bool pair_geometry(const PairT& c, const PairSide& A, const PairSide& B, Pai
     g.p = sel(box_b, A.p, B.p) + mul(sel(box_b, A.R, B.R), ld3(box_b ? c.a0 : c.b0));
     const m3 XR = sel(box_b, B.R, A.R);
     g.bc = sel(box_b, B.p, A.p) + mul(XR, ld3(box_b ? c.b0 : c.a0));
-    g.Rb = mul(XR, box_b ? c.bR : c.aR);
+    if (c.box_rot)
+      g.Rb = mul(XR, box_b ? c.bR : c.aR);
+    else
+      g.Rb = XR;
     g.dist = point_box(g.p, g.bc, g.Rb, box_b ? c.bh : c.ah, g);
     const v3 cbox = g.cb;
     g.ca = sel(box_b, g.p, cbox);

@@ -154,10 +154,15 @@ BXF void pair_geometry_adj(const PairT& c, const PairGeo& g, v3 cbb, v3 nb, floa
     m3 PRb = m3_zero(), XRb = m3_zero();
     outer_add(PRb, pb, ld3(box_b ? c.a0 : c.b0));
     outer_add(XRb, ccb, ld3(box_b ? c.b0 : c.a0));
-    const float* bR = box_b ? c.bR : c.aR;
-    for (int i = 0; i < 3; ++i)
-      for (int k = 0; k < 3; ++k)
-        XRb.m[3 * i + k] += Rbb.m[3 * i] * bR[3 * k] + Rbb.m[3 * i + 1] * bR[3 * k + 1] + Rbb.m[3 * i + 2] * bR[3 * k + 2];
+    if (c.box_rot) {
+      const float* bR = box_b ? c.bR : c.aR;
+      for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k)
+          XRb.m[3 * i + k] +=
+              Rbb.m[3 * i] * bR[3 * k] + Rbb.m[3 * i + 1] * bR[3 * k + 1] + Rbb.m[3 * i + 2] * bR[3 * k + 2];
+    } else {
+      add_to(XRb, Rbb);
+    }
     Ab.p += sel(box_b, pb, ccb);
     Bb.p += sel(box_b, ccb, pb);
     add_to(Ab.R, sel(box_b, PRb, XRb));

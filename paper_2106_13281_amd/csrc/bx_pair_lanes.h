@@ -55,10 +55,10 @@ __device__ __forceinline__ void pair_lanes_load(const Tables* __restrict__ tab, 
   __builtin_amdgcn_wave_barrier();
 }
 
-// The state and frame of the body on lane src.
-__device__ __forceinline__ PairSide shfl_side(const PairSide& s, int src) {
+// The state and frame of the body on lane src, whose position p was read already.
+__device__ __forceinline__ PairSide shfl_side(const PairSide& s, int src, v3 p) {
   PairSide o;
-  o.p = shfl_v3(s.p, src);
+  o.p = p;
   o.v = shfl_v3(s.v, src);
   o.w = shfl_v3(s.w, src);
 #pragma unroll
@@ -86,9 +86,10 @@ __device__ __forceinline__ void pair_phase(const Tables* __restrict__ tab, int t
     const bool mine = i < nh;
     const PairT& P = L.pair[L.hp[b][i]];  // hp = 0 past nh: a valid candidate, unused
     const int sa = base + (mine ? P.a : b), sb = base + (mine ? P.b : b);
-    const bool near = pair_near(P, mine, shfl_v3(s.p, sa), shfl_v3(s.p, sb));
+    const v3 pA = shfl_v3(s.p, sa), pB = shfl_v3(s.p, sb);
+    const bool near = pair_near(P, mine, pA, pB);
     if (__ballot(near) == 0ull) continue;  // wave-uniform
-    const PairSide A = shfl_side(me, sa), B = shfl_side(me, sb);
+    const PairSide A = shfl_side(me, sa, pA), B = shfl_side(me, sb, pB);
     v3 dvA = V(0.f, 0.f, 0.f), dwA = dvA, dvB = dvA, dwB = dvA;
     float on = 0.f;
     if (near && pair_eval(P, ty, A, B, dvA, dwA, dvB, dwB)) on = 1.f;
@@ -126,9 +127,10 @@ __device__ __forceinline__ void pair_phase_adj(const Tables* __restrict__ tab, i
     const bool mine = i < nh;
     const PairT& P = L.pair[L.hp[b][i]];
     const int sa = base + (mine ? P.a : b), sb = base + (mine ? P.b : b);
-    const bool near = pair_near(P, mine, shfl_v3(post.p, sa), shfl_v3(post.p, sb));
+    const v3 pA = shfl_v3(post.p, sa), pB = shfl_v3(post.p, sb);
+    const bool near = pair_near(P, mine, pA, pB);
     if (__ballot(near) == 0ull) continue;  // wave-uniform
-    const PairSide A = shfl_side(me, sa), B = shfl_side(me, sb);
+    const PairSide A = shfl_side(me, sa, pA), B = shfl_side(me, sb, pB);
     const v3 dvbA = shfl_v3(dvb, sa), dwbA = shfl_v3(dwb, sa), dvbB = shfl_v3(dvb, sb), dwbB = shfl_v3(dwb, sb);
     PairSideBar Ab = pairbar_zero(), Bb = pairbar_zero();
     if (near && pair_adj(P, ty, A, B, dvbA, dwbA, dvbB, dwbB, Ab, Bb, mu_bar)) {

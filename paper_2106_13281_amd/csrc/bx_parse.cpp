@@ -682,6 +682,7 @@ void pack_type(const SystemDesc& d, Tables& tab, int t) {
     for (int k = 0; k < 9; ++k) {
       P.aR[k] = (float)S.aR[k];
       P.bR[k] = (float)S.bR[k];
+      if (S.aR[k] != (k % 4 == 0 ? 1.0 : 0.0) || S.bR[k] != (k % 4 == 0 ? 1.0 : 0.0)) P.box_rot = 1;
     }
     // origins farther apart than the two features' extents from their
     // origins plus the radii cannot be in contact

@@ -90,7 +90,9 @@ struct ContactT {
 // mass im (0 when all translations are frozen) and whether rotations
 // respond (0 when all are frozen) of each body.
 struct PairT {
-  int32_t a, b, kind, rot_a, rot_b, pad[2];
+  int32_t a, b, kind, rot_a, rot_b;
+  int32_t box_rot;         // the box collider is rotated in its body (aR / bR not the identity)
+  int32_t pad;
   float reach;             // no contact while the two body origins are farther apart than this
   float a0[3], a1[3], ra;
   float b0[3], b1[3], rb;

@@ -18,9 +18,13 @@ BODY = {
     "sphere": 'colliders {{ sphere {{ radius: {r} }} }}',
     "capsule": 'colliders {{ capsule {{ radius: {r} length: {L} }} }}',
     "box": 'colliders {{ box {{ halfsize {{ x: {hx} y: {hy} z: {hz} }} }} }}',
+    # a box collider off its body's centre and rotated in it
+    "boxr": ('colliders {{ position {{ x: 0.04 y: -0.03 }} rotation {{ x: 30 y: 20 z: 10 }} '
+             'box {{ halfsize {{ x: {hx} y: {hy} z: {hz} }} }} }}'),
 }
 KIND_PAIRS = [("sphere", "sphere"), ("sphere", "capsule"), ("capsule", "sphere"), ("capsule", "capsule"),
-              ("sphere", "box"), ("box", "sphere"), ("capsule", "box"), ("box", "capsule")]
+              ("sphere", "box"), ("box", "sphere"), ("capsule", "box"), ("box", "capsule"),
+              ("sphere", "boxr"), ("boxr", "capsule")]
 
 
 def two_body(ka, kb, e=0.0, mu=0.5, beta=0.2, substeps=1, dt=0.002):
