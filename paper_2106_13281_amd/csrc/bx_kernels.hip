@@ -424,6 +424,9 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
   }
 }
 
+// ONE_AXIS: every type of the batch has joints of at most one axis, so only
+// that path is compiled in (fewer registers).
+template <bool ONE_AXIS>
 __global__ __launch_bounds__(256) void k_fused(const Tables* __restrict__ tab, const WaveWork* __restrict__ work,
                                                int n_work, const int32_t* __restrict__ env_list,
                                                const int32_t* __restrict__ type_off, int E, int Bm, Fields in,
@@ -434,22 +437,32 @@ __global__ __launch_bounds__(256) void k_fused(const Tables* __restrict__ tab, c
   if (w >= n_work) return;
   const WaveWork wk = work[w];
   // wave-uniform: joints of at most one axis take the shorter path
-  const bool one = tab->type[wk.type].max_dof <= 1;
-  if (tape == nullptr) {
-    if (one)
-      fused_run<1, false, false>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj,
-                                 nonfinite, nullptr, 0, w, n_work);
-    else
-      fused_run<3, false, false>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj,
-                                 nonfinite, nullptr, 0, w, n_work);
-  } else {
-    if (one)
-      fused_run<1, true, false>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj,
-                                nonfinite, tape, smax, w, n_work);
-    else
-      fused_run<3, true, false>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj,
-                                nonfinite, tape, smax, w, n_work);
-  }
+  if (ONE_AXIS || tab->type[wk.type].max_dof <= 1)
+    fused_run<1, false, false>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
+                               nullptr, 0, w, n_work);
+  else
+    fused_run<3, false, false>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
+                               nullptr, 0, w, n_work);
+}
+
+// The same with the forward tape: a kernel of its own, so that the tape
+// code does not add to the registers of the kernel above.
+__global__ __launch_bounds__(256) void k_fused_tape(const Tables* __restrict__ tab,
+                                                    const WaveWork* __restrict__ work, int n_work,
+                                                    const int32_t* __restrict__ env_list,
+                                                    const int32_t* __restrict__ type_off, int E, int Bm, Fields in,
+                                                    Fields out, const float* __restrict__ acts, int Am, int T,
+                                                    int save_every, Fields traj, uint8_t* nonfinite, float* tape,
+                                                    int smax) {
+  const int w = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (w >= n_work) return;
+  const WaveWork wk = work[w];
+  if (tab->type[wk.type].max_dof <= 1)
+    fused_run<1, true, false>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
+                              tape, smax, w, n_work);
+  else
+    fused_run<3, true, false>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
+                              tape, smax, w, n_work);
 }
 
 // The same for batches with body-body contacts: kernels of their own (with
@@ -595,8 +608,11 @@ hipError_t launch_fused(const LaunchCtx& c, const WaveWork* work, int n_work, in
                         Fields out, const float* acts, int T, int save_every, Fields traj, bool flags,
                         hipStream_t s, float* tape, int smax) {
   if (n_work == 0) return hipSuccess;
-  bool pairs = false;
-  for (int t = 0; t < c.n_types; ++t) pairs = pairs || c.host_tab->type[t].np > 0;
+  bool pairs = false, one_axis = true;
+  for (int t = 0; t < c.n_types; ++t) {
+    pairs = pairs || c.host_tab->type[t].np > 0;
+    one_axis = one_axis && c.host_tab->type[t].max_dof <= 1;
+  }
   if (pairs) {
     const size_t lds = sizeof(PairLanes) * waves_per_block;
     if (tape)
@@ -609,9 +625,18 @@ hipError_t launch_fused(const LaunchCtx& c, const WaveWork* work, int n_work, in
                          traj, flags ? c.nonfinite : nullptr, nullptr, 0);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_fused, dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block), 0, s, c.tab, work,
-                     n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj,
-                     flags ? c.nonfinite : nullptr, tape, smax);
+  if (tape)
+    hipLaunchKernelGGL(k_fused_tape, dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block), 0, s, c.tab,
+                       work, n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj,
+                       flags ? c.nonfinite : nullptr, tape, smax);
+  else if (one_axis)
+    hipLaunchKernelGGL(k_fused<true>, dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block), 0, s, c.tab,
+                       work, n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj,
+                       flags ? c.nonfinite : nullptr, nullptr, 0);
+  else
+    hipLaunchKernelGGL(k_fused<false>, dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block), 0, s, c.tab,
+                       work, n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj,
+                       flags ? c.nonfinite : nullptr, nullptr, 0);
   return hipGetLastError();
 }
 
