@@ -468,7 +468,7 @@ __global__ __launch_bounds__(256) void k_fused_tape(const Tables* __restrict__ t
 // The same for batches with body-body contacts: kernels of their own (with
 // and without the tape), so that the registers the body-body phase needs do
 // not lower the occupancy of the kernel above.
-template <bool TAPE>
+template <bool TAPE, bool ONE_AXIS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_pairs(const Tables* __restrict__ tab,
                                                      const WaveWork* __restrict__ work, int n_work,
                                                      const int32_t* __restrict__ env_list,
@@ -481,7 +481,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   if (w >= n_work) return;
   const WaveWork wk = work[w];
   PairLanes* pl = pair_lds + (threadIdx.x >> 6);
-  if (tab->type[wk.type].max_dof <= 1)
+  if (ONE_AXIS || tab->type[wk.type].max_dof <= 1)
     fused_run<1, TAPE, true>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
                              tape, smax, w, n_work, pl);
   else
@@ -615,14 +615,17 @@ hipError_t launch_fused(const LaunchCtx& c, const WaveWork* work, int n_work, in
   }
   if (pairs) {
     const size_t lds = sizeof(PairLanes) * waves_per_block;
+    const dim3 grid(cdiv(n_work, waves_per_block)), block(64 * waves_per_block);
+    uint8_t* nf = flags ? c.nonfinite : nullptr;
     if (tape)
-      hipLaunchKernelGGL(k_fused_pairs<true>, dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block), lds,
-                         s, c.tab, work, n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every,
-                         traj, flags ? c.nonfinite : nullptr, tape, smax);
+      hipLaunchKernelGGL((k_fused_pairs<true, false>), grid, block, lds, s, c.tab, work, n_work, c.env_list, c.type_off,
+                         c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, tape, smax);
+    else if (one_axis)
+      hipLaunchKernelGGL((k_fused_pairs<false, true>), grid, block, lds, s, c.tab, work, n_work, c.env_list, c.type_off,
+                         c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0);
     else
-      hipLaunchKernelGGL(k_fused_pairs<false>, dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block), lds,
-                         s, c.tab, work, n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every,
-                         traj, flags ? c.nonfinite : nullptr, nullptr, 0);
+      hipLaunchKernelGGL((k_fused_pairs<false, false>), grid, block, lds, s, c.tab, work, n_work, c.env_list,
+                         c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0);
     return hipGetLastError();
   }
   if (tape)

@@ -528,7 +528,7 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
   }
 }
 
-template <bool PAIRS>
+template <bool PAIRS, bool ONE_AXIS>
 __global__ __launch_bounds__(64) void k_fused_vjp(const Tables* __restrict__ tab, const WaveWork* __restrict__ work,
                                                   int n_work, const int32_t* __restrict__ env_list,
                                                   const int32_t* __restrict__ type_off, int E, int Bm, int Am,
@@ -541,7 +541,7 @@ __global__ __launch_bounds__(64) void k_fused_vjp(const Tables* __restrict__ tab
   PairLanes* pl = PAIRS ? reinterpret_cast<PairLanes*>(lds_tape) : nullptr;
   float* lds = lds_tape + (PAIRS ? sizeof(PairLanes) / 4 : 0);
   (void)smax;
-  if (tab->type[wk.type].max_dof <= 1)
+  if (ONE_AXIS || tab->type[wk.type].max_dof <= 1)
     fused_vjp_run<1, false, false, PAIRS>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds,
         nullptr, w, n_work, nullptr, 0, pl);
   else
@@ -550,7 +550,7 @@ __global__ __launch_bounds__(64) void k_fused_vjp(const Tables* __restrict__ tab
 }
 
 // The adjoint of one step with the cotangents of the system parameters.
-template <bool PAIRS>
+template <bool PAIRS, bool ONE_AXIS>
 __global__ __launch_bounds__(64) void k_fused_vjp_params(const Tables* __restrict__ tab,
                                                          const WaveWork* __restrict__ work, int n_work,
                                                          const int32_t* __restrict__ env_list,
@@ -564,7 +564,7 @@ __global__ __launch_bounds__(64) void k_fused_vjp_params(const Tables* __restric
   const WaveWork wk = work[w];
   PairLanes* pl = PAIRS ? reinterpret_cast<PairLanes*>(lds_tape) : nullptr;
   float* lds = lds_tape + (PAIRS ? sizeof(PairLanes) / 4 : 0);
-  if (tab->type[wk.type].max_dof <= 1)
+  if (ONE_AXIS || tab->type[wk.type].max_dof <= 1)
     fused_vjp_run<1, false, true, PAIRS>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds,
                                          nullptr, w, n_work, g_params, p_max, pl);
   else
@@ -573,7 +573,7 @@ __global__ __launch_bounds__(64) void k_fused_vjp_params(const Tables* __restric
 }
 
 // The adjoint of one step from its forward tape in HBM (no recompute, no LDS).
-template <bool PAIRS>
+template <bool PAIRS, bool ONE_AXIS>
 __global__ __launch_bounds__(64) void k_fused_vjp_tape(const Tables* __restrict__ tab,
                                                        const WaveWork* __restrict__ work, int n_work,
                                                        const int32_t* __restrict__ env_list,
@@ -586,7 +586,7 @@ __global__ __launch_bounds__(64) void k_fused_vjp_tape(const Tables* __restrict_
   const WaveWork wk = work[w];
   const Fields none{nullptr, nullptr, nullptr, nullptr};
   PairLanes* pl = PAIRS ? reinterpret_cast<PairLanes*>(lds_pairs) : nullptr;
-  if (tab->type[wk.type].max_dof <= 1)
+  if (ONE_AXIS || tab->type[wk.type].max_dof <= 1)
     fused_vjp_run<1, true, false, PAIRS>(tab, wk, env_list, type_off, E, Bm, Am, none, act, g_out, g_in, g_act,
         nullptr, tape, w, n_work, nullptr, 0, pl);
   else
@@ -602,7 +602,25 @@ bool any_pairs(const LaunchCtx& c) {
   return false;
 }
 
+// Whether every type of the batch has joints of at most one axis: such
+// batches take the kernels compiled for that path alone (fewer registers).
+bool all_one_axis(const LaunchCtx& c) {
+  for (int t = 0; t < c.n_types; ++t)
+    if (c.host_tab->type[t].max_dof > 1) return false;
+  return true;
+}
+
 }  // namespace
+
+// Launches kernel template K<PAIRS, ONE_AXIS> with ONE_AXIS from the batch
+// (`c` in scope); the remaining arguments are hipLaunchKernelGGL's.
+#define LAUNCH_AXES(K, PAIRS, ...)                                   \
+  do {                                                               \
+    if (all_one_axis(c))                                             \
+      hipLaunchKernelGGL((K<PAIRS, true>), __VA_ARGS__);             \
+    else                                                             \
+      hipLaunchKernelGGL((K<PAIRS, false>), __VA_ARGS__);            \
+  } while (0)
 
 int vjp_reserve(VjpWork& w, const Tables& tab, int n_types, const int* type_cnt, int E, int Bm) {
   size_t smax = 1;
@@ -639,13 +657,11 @@ hipError_t launch_vjp_params(const LaunchCtx& c, const VjpSched& sched, Fields i
   for (int t = 0; t < c.n_types; ++t) smax = std::max(smax, (size_t)c.host_tab->type[t].substeps);
   const size_t lds = smax * (TAPE_N + 3) * 64 * sizeof(float);
   if (any_pairs(c))
-    hipLaunchKernelGGL(k_fused_vjp_params<true>, dim3(sched.n_work), dim3(64), lds + sizeof(PairLanes), s, c.tab,
-                       sched.work, sched.n_work, c.env_list, c.type_off, c.E, c.Bm, c.Am, in, act, g_out, g_in, g_act,
-                       g_params, p_max);
+    LAUNCH_AXES(k_fused_vjp_params, true, dim3(sched.n_work), dim3(64), lds + sizeof(PairLanes), s, c.tab, sched.work,
+                sched.n_work, c.env_list, c.type_off, c.E, c.Bm, c.Am, in, act, g_out, g_in, g_act, g_params, p_max);
   else
-    hipLaunchKernelGGL(k_fused_vjp_params<false>, dim3(sched.n_work), dim3(64), lds, s, c.tab, sched.work,
-                       sched.n_work, c.env_list, c.type_off, c.E, c.Bm, c.Am, in, act, g_out, g_in, g_act, g_params,
-                       p_max);
+    LAUNCH_AXES(k_fused_vjp_params, false, dim3(sched.n_work), dim3(64), lds, s, c.tab, sched.work, sched.n_work,
+                c.env_list, c.type_off, c.E, c.Bm, c.Am, in, act, g_out, g_in, g_act, g_params, p_max);
   return hipGetLastError();
 }
 
@@ -653,11 +669,11 @@ hipError_t launch_vjp_tape(const LaunchCtx& c, const VjpSched& sched, const floa
                            Fields g_out, Fields g_in, float* g_act, hipStream_t s) {
   if (sched.n_work == 0) return hipSuccess;
   if (any_pairs(c))
-    hipLaunchKernelGGL(k_fused_vjp_tape<true>, dim3(sched.n_work), dim3(64), sizeof(PairLanes), s, c.tab, sched.work,
-                       sched.n_work, c.env_list, c.type_off, c.E, c.Bm, c.Am, tape, act, g_out, g_in, g_act);
+    LAUNCH_AXES(k_fused_vjp_tape, true, dim3(sched.n_work), dim3(64), sizeof(PairLanes), s, c.tab, sched.work,
+                sched.n_work, c.env_list, c.type_off, c.E, c.Bm, c.Am, tape, act, g_out, g_in, g_act);
   else
-    hipLaunchKernelGGL(k_fused_vjp_tape<false>, dim3(sched.n_work), dim3(64), 0, s, c.tab, sched.work, sched.n_work,
-                       c.env_list, c.type_off, c.E, c.Bm, c.Am, tape, act, g_out, g_in, g_act);
+    LAUNCH_AXES(k_fused_vjp_tape, false, dim3(sched.n_work), dim3(64), 0, s, c.tab, sched.work, sched.n_work,
+                c.env_list, c.type_off, c.E, c.Bm, c.Am, tape, act, g_out, g_in, g_act);
   return hipGetLastError();
 }
 
@@ -682,12 +698,11 @@ hipError_t launch_vjp(const LaunchCtx& c, VjpWork& w, const VjpSched& sched, Fie
     const size_t lds = smax * TAPE_N * 64 * sizeof(float);
     if (sched.n_work == 0) return hipSuccess;
     if (any_pairs(c))
-      hipLaunchKernelGGL(k_fused_vjp<true>, dim3(sched.n_work), dim3(64), lds + sizeof(PairLanes), s, c.tab,
-                         sched.work, sched.n_work, c.env_list, c.type_off, E, Bm, c.Am, (int)smax, in, act, g_out, g_in,
-                         g_act);
+      LAUNCH_AXES(k_fused_vjp, true, dim3(sched.n_work), dim3(64), lds + sizeof(PairLanes), s, c.tab, sched.work,
+                  sched.n_work, c.env_list, c.type_off, E, Bm, c.Am, (int)smax, in, act, g_out, g_in, g_act);
     else
-      hipLaunchKernelGGL(k_fused_vjp<false>, dim3(sched.n_work), dim3(64), lds, s, c.tab, sched.work, sched.n_work,
-                         c.env_list, c.type_off, E, Bm, c.Am, (int)smax, in, act, g_out, g_in, g_act);
+      LAUNCH_AXES(k_fused_vjp, false, dim3(sched.n_work), dim3(64), lds, s, c.tab, sched.work, sched.n_work,
+                  c.env_list, c.type_off, E, Bm, c.Am, (int)smax, in, act, g_out, g_in, g_act);
     return hipGetLastError();
   }
   if (c.Am > 0) {
