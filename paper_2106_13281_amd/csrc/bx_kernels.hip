@@ -299,7 +299,9 @@ __global__ void k_plain_collision(const Tables* __restrict__ tab, int t, const i
 // update, total torque, count of applied contacts) to the wavefront-major
 // tape[step][sub][work item w of n_work][TAPE_N][64], for the adjoint that
 // reads it instead of recomputing the step.
-template <int MAXDOF, bool TAPE, bool PAIRS>
+// REGC: contact candidates of a body kept in registers (the rest are read
+// from the table inside the loop).
+template <int MAXDOF, bool TAPE, bool PAIRS, int REGC = REG_CONTACTS>
 __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const WaveWork& wk,
                                           const int32_t* __restrict__ env_list, const int32_t* __restrict__ type_off,
                                           int E, int Bm, const Fields& in, const Fields& out,
@@ -320,10 +322,10 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
   JointT J = tab->joint[t][has_joint ? B.joint : 0];
   const int src_parent = base + (has_joint ? J.parent : b);
   const int n_con = B.c1 - B.c0;
-  ContactT Creg[REG_CONTACTS];
-  Creg[0] = tab->contact[t][B.c0];
-  Creg[1] = tab->contact[t][B.c0 + (n_con > 1 ? 1 : 0)];
-  pin_consts<MAXDOF>(B, J, has_joint, Creg, REG_CONTACTS);
+  ContactT Creg[REGC];
+#pragma unroll
+  for (int k = 0; k < REGC; ++k) Creg[k] = tab->contact[t][B.c0 + (n_con > k ? k : 0)];
+  pin_consts<MAXDOF>(B, J, has_joint, Creg, REGC);
   const float h = ty.h;
 
   if (PAIRS && ty.np > 0) pair_lanes_load(tab, t, pl, lane);
@@ -378,11 +380,14 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
       }
       v3 dv = V(0.f, 0.f, 0.f), dw = V(0.f, 0.f, 0.f);
       int cnt = 0;
-      // the first REG_CONTACTS candidates from registers (no dynamic indexing), the rest from the table;
-      // a candidate is skipped by the whole wave when it touches the ground on no lane
-      if (n_con > 0) cnt += contact_eval(Creg[0], ty, B, s, f, dv, dw) ? 1 : 0;
-      if (n_con > 1) cnt += contact_eval(Creg[1], ty, B, s, f, dv, dw) ? 1 : 0;
-      for (int c = REG_CONTACTS; c < n_con; ++c) cnt += contact_eval(tab->contact[t][B.c0 + c], ty, B, s, f, dv, dw) ? 1 : 0;
+      // the first REGC candidates from registers (no dynamic indexing; a slot
+      // no body of the type has is skipped by the whole wave), the rest from
+      // the table; a candidate is skipped by the whole wave when it touches
+      // the ground on no lane
+#pragma unroll
+      for (int k = 0; k < REGC; ++k)
+        if (k < ty.max_contacts && n_con > k) cnt += contact_eval(Creg[k], ty, B, s, f, dv, dw) ? 1 : 0;
+      for (int c = REGC; c < n_con; ++c) cnt += contact_eval(tab->contact[t][B.c0 + c], ty, B, s, f, dv, dw) ? 1 : 0;
       const v3 z3 = V(0.f, 0.f, 0.f);
       v3 force = has_joint ? jo.fc : z3, torque = has_joint ? jo.tc : z3;
 #pragma unroll
@@ -425,8 +430,10 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
 }
 
 // ONE_AXIS: every type of the batch has joints of at most one axis, so only
-// that path is compiled in (fewer registers).
-template <bool ONE_AXIS>
+// that path is compiled in (fewer registers). REGC: contact candidates per
+// body held in registers (8 for batches with a body of more than two, such
+// as a box's eight corners; 2 otherwise, where more registers only cost).
+template <bool ONE_AXIS, int REGC>
 __global__ __launch_bounds__(256) void k_fused(const Tables* __restrict__ tab, const WaveWork* __restrict__ work,
                                                int n_work, const int32_t* __restrict__ env_list,
                                                const int32_t* __restrict__ type_off, int E, int Bm, Fields in,
@@ -438,11 +445,11 @@ __global__ __launch_bounds__(256) void k_fused(const Tables* __restrict__ tab, c
   const WaveWork wk = work[w];
   // wave-uniform: joints of at most one axis take the shorter path
   if (ONE_AXIS || tab->type[wk.type].max_dof <= 1)
-    fused_run<1, false, false>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
-                               nullptr, 0, w, n_work);
+    fused_run<1, false, false, REGC>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj,
+                                     nonfinite, nullptr, 0, w, n_work);
   else
-    fused_run<3, false, false>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
-                               nullptr, 0, w, n_work);
+    fused_run<3, false, false, REGC>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj,
+                                     nonfinite, nullptr, 0, w, n_work);
 }
 
 // The same with the forward tape: a kernel of its own, so that the tape
@@ -608,10 +615,11 @@ hipError_t launch_fused(const LaunchCtx& c, const WaveWork* work, int n_work, in
                         Fields out, const float* acts, int T, int save_every, Fields traj, bool flags,
                         hipStream_t s, float* tape, int smax) {
   if (n_work == 0) return hipSuccess;
-  bool pairs = false, one_axis = true;
+  bool pairs = false, one_axis = true, many_contacts = false;
   for (int t = 0; t < c.n_types; ++t) {
     pairs = pairs || c.host_tab->type[t].np > 0;
     one_axis = one_axis && c.host_tab->type[t].max_dof <= 1;
+    many_contacts = many_contacts || c.host_tab->type[t].max_contacts > REG_CONTACTS;
   }
   if (pairs) {
     const size_t lds = sizeof(PairLanes) * waves_per_block;
@@ -632,14 +640,22 @@ hipError_t launch_fused(const LaunchCtx& c, const WaveWork* work, int n_work, in
     hipLaunchKernelGGL(k_fused_tape, dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block), 0, s, c.tab,
                        work, n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj,
                        flags ? c.nonfinite : nullptr, tape, smax);
-  else if (one_axis)
-    hipLaunchKernelGGL(k_fused<true>, dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block), 0, s, c.tab,
-                       work, n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj,
-                       flags ? c.nonfinite : nullptr, nullptr, 0);
-  else
-    hipLaunchKernelGGL(k_fused<false>, dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block), 0, s, c.tab,
-                       work, n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj,
-                       flags ? c.nonfinite : nullptr, nullptr, 0);
+  else {
+    const dim3 grid(cdiv(n_work, waves_per_block)), block(64 * waves_per_block);
+    uint8_t* nf = flags ? c.nonfinite : nullptr;
+    if (one_axis && many_contacts)
+      hipLaunchKernelGGL((k_fused<true, 8>), grid, block, 0, s, c.tab, work, n_work, c.env_list, c.type_off, c.E,
+                         c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0);
+    else if (one_axis)
+      hipLaunchKernelGGL((k_fused<true, REG_CONTACTS>), grid, block, 0, s, c.tab, work, n_work, c.env_list,
+                         c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0);
+    else if (many_contacts)
+      hipLaunchKernelGGL((k_fused<false, 8>), grid, block, 0, s, c.tab, work, n_work, c.env_list, c.type_off, c.E,
+                         c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0);
+    else
+      hipLaunchKernelGGL((k_fused<false, REG_CONTACTS>), grid, block, 0, s, c.tab, work, n_work, c.env_list,
+                         c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0);
+  }
   return hipGetLastError();
 }
 
