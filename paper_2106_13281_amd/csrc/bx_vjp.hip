@@ -302,7 +302,7 @@ __device__ __forceinline__ v3 shfl3(v3 a, int src) { return V(shfl(a.x, src), sh
 // into g_params[P_max][E] (order: mass per body, inertia per body x, y, z,
 // per joint k_lin, c_lin, k_ang, c_ang, k_lim, strength per action,
 // friction); the LDS tape then also keeps each body's total force.
-template <int MAXDOF, bool FROM_TAPE, bool PARAMS, bool PAIRS>
+template <int MAXDOF, bool FROM_TAPE, bool PARAMS, bool PAIRS, int REGC>
 __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, const WaveWork& wk,
                                               const int32_t* __restrict__ env_list,
                                               const int32_t* __restrict__ type_off, int E, int Bm, int Am,
@@ -326,10 +326,10 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
   JointT J = tab->joint[t][has_joint ? B.joint : 0];
   const int src_parent = base + (has_joint ? J.parent : b);
   const int n_con = B.c1 - B.c0;
-  ContactT Creg[REG_CONTACTS];
-  Creg[0] = tab->contact[t][B.c0];
-  Creg[1] = tab->contact[t][B.c0 + (n_con > 1 ? 1 : 0)];
-  pin_consts<MAXDOF>(B, J, has_joint, Creg, REG_CONTACTS);
+  ContactT Creg[REGC];  // the first REGC contact candidates in registers
+#pragma unroll
+  for (int k = 0; k < REGC; ++k) Creg[k] = tab->contact[t][B.c0 + (n_con > k ? k : 0)];
+  pin_consts<MAXDOF>(B, J, has_joint, Creg, REGC);
   const float h = ty.h;
   if (PAIRS && ty.np > 0) pair_lanes_load(tab, t, pl, lane);
   float a[3] = {0.f, 0.f, 0.f}, raw[3] = {0.f, 0.f, 0.f};
@@ -375,11 +375,12 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
     }
     v3 dv = z3, dw = z3;
     int cnt = 0;
-    // the first REG_CONTACTS candidates from registers (no dynamic indexing), the rest from the table;
+    // the first REGC candidates from registers (no dynamic indexing), the rest from the table;
     // a candidate is skipped by the whole wave when it touches the ground on no lane
-    if (n_con > 0) cnt += contact_eval(Creg[0], ty, B, s, f, dv, dw) ? 1 : 0;
-    if (n_con > 1) cnt += contact_eval(Creg[1], ty, B, s, f, dv, dw) ? 1 : 0;
-    for (int c = REG_CONTACTS; c < n_con; ++c) cnt += contact_eval(tab->contact[t][B.c0 + c], ty, B, s, f, dv, dw) ? 1 : 0;
+#pragma unroll
+    for (int k = 0; k < REGC; ++k)
+      if (k < ty.max_contacts && n_con > k) cnt += contact_eval(Creg[k], ty, B, s, f, dv, dw) ? 1 : 0;
+    for (int c = REGC; c < n_con; ++c) cnt += contact_eval(tab->contact[t][B.c0 + c], ty, B, s, f, dv, dw) ? 1 : 0;
     v3 force = jo.fc, torque = jo.tc;
 #pragma unroll
     for (int i = 0; i < GATHER; ++i) {
@@ -467,9 +468,10 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
       Bar bc = contact_adj(C, ty, B, post, f, dvb, dwb, applied, fr, invm_bar, mu_bar);
       if (applied) bar_add(tot, bc);
     };
-    if (n_con > 0) contact_back(Creg[0]);
-    if (n_con > 1) contact_back(Creg[1]);
-    for (int c = REG_CONTACTS; c < n_con; ++c) contact_back(tab->contact[t][B.c0 + c]);
+#pragma unroll
+    for (int k = 0; k < REGC; ++k)
+      if (k < ty.max_contacts && n_con > k) contact_back(Creg[k]);
+    for (int c = REGC; c < n_con; ++c) contact_back(tab->contact[t][B.c0 + c]);
     if (PAIRS && ty.np > 0) pair_phase_adj(tab, t, *pl, b, base, post, f, dvb, dwb, tot, fr, invm_bar, mu_bar);
     bar_add(tot, bC);
     if (PARAMS) {
@@ -528,7 +530,7 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
   }
 }
 
-template <bool PAIRS, bool ONE_AXIS>
+template <bool PAIRS, bool ONE_AXIS, int REGC>
 __global__ __launch_bounds__(64) void k_fused_vjp(const Tables* __restrict__ tab, const WaveWork* __restrict__ work,
                                                   int n_work, const int32_t* __restrict__ env_list,
                                                   const int32_t* __restrict__ type_off, int E, int Bm, int Am,
@@ -542,15 +544,15 @@ __global__ __launch_bounds__(64) void k_fused_vjp(const Tables* __restrict__ tab
   float* lds = lds_tape + (PAIRS ? sizeof(PairLanes) / 4 : 0);
   (void)smax;
   if (ONE_AXIS || tab->type[wk.type].max_dof <= 1)
-    fused_vjp_run<1, false, false, PAIRS>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds,
+    fused_vjp_run<1, false, false, PAIRS, REGC>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds,
         nullptr, w, n_work, nullptr, 0, pl);
   else
-    fused_vjp_run<3, false, false, PAIRS>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds,
+    fused_vjp_run<3, false, false, PAIRS, REGC>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds,
         nullptr, w, n_work, nullptr, 0, pl);
 }
 
 // The adjoint of one step with the cotangents of the system parameters.
-template <bool PAIRS, bool ONE_AXIS>
+template <bool PAIRS, bool ONE_AXIS, int REGC>
 __global__ __launch_bounds__(64) void k_fused_vjp_params(const Tables* __restrict__ tab,
                                                          const WaveWork* __restrict__ work, int n_work,
                                                          const int32_t* __restrict__ env_list,
@@ -565,15 +567,15 @@ __global__ __launch_bounds__(64) void k_fused_vjp_params(const Tables* __restric
   PairLanes* pl = PAIRS ? reinterpret_cast<PairLanes*>(lds_tape) : nullptr;
   float* lds = lds_tape + (PAIRS ? sizeof(PairLanes) / 4 : 0);
   if (ONE_AXIS || tab->type[wk.type].max_dof <= 1)
-    fused_vjp_run<1, false, true, PAIRS>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds,
+    fused_vjp_run<1, false, true, PAIRS, REGC>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds,
                                          nullptr, w, n_work, g_params, p_max, pl);
   else
-    fused_vjp_run<3, false, true, PAIRS>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds,
+    fused_vjp_run<3, false, true, PAIRS, REGC>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds,
                                          nullptr, w, n_work, g_params, p_max, pl);
 }
 
 // The adjoint of one step from its forward tape in HBM (no recompute, no LDS).
-template <bool PAIRS, bool ONE_AXIS>
+template <bool PAIRS, bool ONE_AXIS, int REGC>
 __global__ __launch_bounds__(64) void k_fused_vjp_tape(const Tables* __restrict__ tab,
                                                        const WaveWork* __restrict__ work, int n_work,
                                                        const int32_t* __restrict__ env_list,
@@ -587,10 +589,10 @@ __global__ __launch_bounds__(64) void k_fused_vjp_tape(const Tables* __restrict_
   const Fields none{nullptr, nullptr, nullptr, nullptr};
   PairLanes* pl = PAIRS ? reinterpret_cast<PairLanes*>(lds_pairs) : nullptr;
   if (ONE_AXIS || tab->type[wk.type].max_dof <= 1)
-    fused_vjp_run<1, true, false, PAIRS>(tab, wk, env_list, type_off, E, Bm, Am, none, act, g_out, g_in, g_act,
+    fused_vjp_run<1, true, false, PAIRS, REGC>(tab, wk, env_list, type_off, E, Bm, Am, none, act, g_out, g_in, g_act,
         nullptr, tape, w, n_work, nullptr, 0, pl);
   else
-    fused_vjp_run<3, true, false, PAIRS>(tab, wk, env_list, type_off, E, Bm, Am, none, act, g_out, g_in, g_act,
+    fused_vjp_run<3, true, false, PAIRS, REGC>(tab, wk, env_list, type_off, E, Bm, Am, none, act, g_out, g_in, g_act,
         nullptr, tape, w, n_work, nullptr, 0, pl);
 }
 
@@ -610,16 +612,29 @@ bool all_one_axis(const LaunchCtx& c) {
   return true;
 }
 
+// Whether a type of the batch has a body with more contact candidates than
+// the default held in registers: such batches take the kernels holding 8.
+bool many_contacts(const LaunchCtx& c) {
+  for (int t = 0; t < c.n_types; ++t)
+    if (c.host_tab->type[t].max_contacts > REG_CONTACTS) return true;
+  return false;
+}
+
 }  // namespace
 
-// Launches kernel template K<PAIRS, ONE_AXIS> with ONE_AXIS from the batch
-// (`c` in scope); the remaining arguments are hipLaunchKernelGGL's.
+// Launches kernel template K<PAIRS, ONE_AXIS, REGC> with ONE_AXIS and REGC from
+// the batch (`c` in scope); the remaining arguments are hipLaunchKernelGGL's.
 #define LAUNCH_AXES(K, PAIRS, ...)                                   \
   do {                                                               \
-    if (all_one_axis(c))                                             \
-      hipLaunchKernelGGL((K<PAIRS, true>), __VA_ARGS__);             \
+    const bool one_ = all_one_axis(c), many_ = many_contacts(c);     \
+    if (one_ && many_)                                               \
+      hipLaunchKernelGGL((K<PAIRS, true, 8>), __VA_ARGS__);          \
+    else if (one_)                                                   \
+      hipLaunchKernelGGL((K<PAIRS, true, REG_CONTACTS>), __VA_ARGS__); \
+    else if (many_)                                                  \
+      hipLaunchKernelGGL((K<PAIRS, false, 8>), __VA_ARGS__);         \
     else                                                             \
-      hipLaunchKernelGGL((K<PAIRS, false>), __VA_ARGS__);            \
+      hipLaunchKernelGGL((K<PAIRS, false, REG_CONTACTS>), __VA_ARGS__); \
   } while (0)
 
 int vjp_reserve(VjpWork& w, const Tables& tab, int n_types, const int* type_cnt, int E, int Bm) {

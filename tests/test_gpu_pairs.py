@@ -204,8 +204,7 @@ def test_pair_vjp_from_tape_and_parameters(case):
     a0 = torch.zeros((0, n), dtype=torch.float32, device="cuda")
     out_t, tape = sysg.rollout_tape(to_dev(X), A)
     out_r, _ = sysg.rollout(to_dev(X), A)
-    for x, y in zip(out_t.fields(), out_r.fields()):
-        assert torch.allclose(x, y, rtol=1e-6, atol=1e-6)
+    assert rel_err(from_dev(out_t, nb), from_dev(out_r, nb)).max() < 1e-5   # two kernels, as with plain vs fused
     gt, _ = sysg.step_vjp_tape(tape[0], a0, to_dev(g))
     gr, _ = sysg.step_vjp(to_dev(X), a0, to_dev(g))
     _, mg = o.step(X, np.zeros((n, 0)), margins=True)

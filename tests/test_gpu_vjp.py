@@ -10,7 +10,7 @@ import torch
 
 import oracle
 from paper_2106_13281_amd import braxmi, synth
-from tests.helpers import make_states
+from tests.helpers import make_states, rel_err
 
 pytestmark = pytest.mark.gpu
 SYSTEMS = ("chain", "quadruped", "biped", "manipulator", "cheetah", "grasp")
@@ -74,8 +74,10 @@ def test_step_vjp_from_tape_matches_oracle_and_recompute(name):
     A = acts_dev(a[None])
     out_t, tape = sysg.rollout_tape(to_dev(X), A)
     out_r, _ = sysg.rollout(to_dev(X), A)
-    for x, y in zip(out_t.fields(), out_r.fields()):
-        assert torch.allclose(x, y, rtol=1e-6, atol=1e-6)
+    # two kernels (with and without the tape) compiled separately: the same
+    # arithmetic up to the compiler's fused multiply-add choices, so the same
+    # bar as the plain and fused kernels' agreement
+    assert rel_err(from_dev(out_t, o.nb), from_dev(out_r, o.nb)).max() < 1e-5
     g_in, g_act = sysg.step_vjp_tape(tape[0], A[0].contiguous(), to_dev(g))
     gi = from_dev(g_in, o.nb)
     ga = g_act.cpu().numpy().T[:, :o.na]
