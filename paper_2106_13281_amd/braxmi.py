@@ -353,12 +353,15 @@ class System:
 class RolloutFn(torch.autograd.Function):
     """Differentiable T-step rollout (final state) with checkpoints every k steps.
 
-    Forward keeps the state every k steps. Backward recomputes each segment
-    from its checkpoint and runs the step adjoint backwards through it: with
-    tape=True the recompute writes every substep's tape (brax_rollout_tape,
-    one segment at a time) and the adjoint reads it (brax_step_vjp_tape);
-    with tape=False the recompute keeps the step states (brax_rollout) and
-    brax_step_vjp recomputes each step's substeps itself. Inputs: the four
+    Forward keeps the state every k steps, computed segment by segment with
+    brax_rollout_tape into a scratch segment tape (the taped kernel, so that
+    the checkpoints and the backward's recomputed segments come from the same
+    compiled code and the gradient does not depend on k). Backward recomputes
+    each segment from its checkpoint and runs the step adjoint backwards
+    through it: with tape=True the recompute writes every substep's tape
+    (brax_rollout_tape, one segment at a time) and the adjoint reads it
+    (brax_step_vjp_tape); with tape=False the recompute keeps the step states
+    (brax_rollout) and brax_step_vjp recomputes each step's substeps itself. Inputs: the four
     initial-state tensors and the action sequence [T][Amax][E]; outputs: the
     four final-state tensors.
     """
@@ -373,9 +376,11 @@ class RolloutFn(torch.autograd.Function):
         ckpts = [s0]
         cur = s0
         t = 0
+        scratch = torch.empty((min(k, max(T, 1)), system.tape_step_floats), dtype=torch.float32,
+                              device=acts_d.device) if T else None
         while t < T:
             n = min(k, T - t)
-            nxt, _ = system.rollout(cur, acts_d[t:t + n])
+            nxt, _ = system.rollout_tape(cur, acts_d[t:t + n], tape=scratch[:n])
             ckpts.append(nxt)
             cur = nxt
             t += n

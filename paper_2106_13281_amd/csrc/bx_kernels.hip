@@ -453,7 +453,11 @@ __global__ __launch_bounds__(256) void k_fused(const Tables* __restrict__ tab, c
 }
 
 // The same with the forward tape: a kernel of its own, so that the tape
-// code does not add to the registers of the kernel above.
+// code does not add to the registers of the kernel above. Its states may
+// differ from k_fused's at the rounding level (the compiler may fuse
+// multiply-adds differently in the two), so a checkpointed gradient takes
+// both its checkpoints and its recomputed segments from this kernel.
+template <int REGC>
 __global__ __launch_bounds__(256) void k_fused_tape(const Tables* __restrict__ tab,
                                                     const WaveWork* __restrict__ work, int n_work,
                                                     const int32_t* __restrict__ env_list,
@@ -465,11 +469,11 @@ __global__ __launch_bounds__(256) void k_fused_tape(const Tables* __restrict__ t
   if (w >= n_work) return;
   const WaveWork wk = work[w];
   if (tab->type[wk.type].max_dof <= 1)
-    fused_run<1, true, false>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
-                              tape, smax, w, n_work);
+    fused_run<1, true, false, REGC>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj,
+                                    nonfinite, tape, smax, w, n_work);
   else
-    fused_run<3, true, false>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
-                              tape, smax, w, n_work);
+    fused_run<3, true, false, REGC>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj,
+                                    nonfinite, tape, smax, w, n_work);
 }
 
 // The same for batches with body-body contacts: kernels of their own (with
@@ -636,10 +640,14 @@ hipError_t launch_fused(const LaunchCtx& c, const WaveWork* work, int n_work, in
                          c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0);
     return hipGetLastError();
   }
-  if (tape)
-    hipLaunchKernelGGL(k_fused_tape, dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block), 0, s, c.tab,
-                       work, n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj,
-                       flags ? c.nonfinite : nullptr, tape, smax);
+  if (tape && many_contacts)
+    hipLaunchKernelGGL((k_fused_tape<8>), dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block), 0, s,
+                       c.tab, work, n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every,
+                       traj, flags ? c.nonfinite : nullptr, tape, smax);
+  else if (tape)
+    hipLaunchKernelGGL((k_fused_tape<REG_CONTACTS>), dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block),
+                       0, s, c.tab, work, n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T,
+                       save_every, traj, flags ? c.nonfinite : nullptr, tape, smax);
   else {
     const dim3 grid(cdiv(n_work, waves_per_block)), block(64 * waves_per_block);
     uint8_t* nf = flags ? c.nonfinite : nullptr;

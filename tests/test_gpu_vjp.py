@@ -291,9 +291,15 @@ def test_rollout_gradient_differentiation_workload():
     ga20 = _gpu_loss_grad(sysg, s0, acts[:T0], k).cpu().numpy().transpose(0, 2, 1)[:, :, :s.na]
     err20 = normwise(ga20.transpose(1, 0, 2), ga_o20.transpose(1, 0, 2))
 
-    # the GPU's own forward trajectory (FP32), then the oracle adjoint along it
-    _, traj = sysg.rollout(s0, acts_dev(acts[:T - 1]), save_every=1)
-    states = [X0] + [from_dev(traj[i], s.nb) for i in range(T - 1)]
+    # the GPU's own forward trajectory (FP32) from the kernel the gradient's
+    # checkpoints and segments come from (the taped one), then the oracle
+    # adjoint along it
+    A = acts_dev(acts)
+    scratch = torch.empty((1, sysg.tape_step_floats), dtype=torch.float32, device="cuda")
+    cur, states = s0, [X0]
+    for t in range(T - 1):
+        cur, _ = sysg.rollout_tape(cur, A[t:t + 1], tape=scratch)
+        states.append(from_dev(cur, s.nb))
     ga_along = _loss_grad_oracle(o, X0, acts, states=states)
     err_along = normwise(ga.transpose(1, 0, 2), ga_along.transpose(1, 0, 2))
     p = lambda x: np.array2string(x, precision=2)
