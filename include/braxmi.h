@@ -204,6 +204,20 @@ int brax_step_vjp_params(const brax_sys* sys, const brax_state* in, const float*
 int brax_step_vjp_tape(const brax_sys* sys, const float* tape, const float* act, const brax_state* g_out,
                        brax_state* g_in, float* g_act, int32_t flags, void* stream);
 
+/* Adjoint of T consecutive steps from their tape (Section 3: the backward
+ * pass through a trajectory of steps), in one launch: the same results as T
+ * calls of brax_step_vjp_tape from the last step to the first, each call's
+ * g_in the next one's g_out, with the state cotangent held on chip between
+ * steps. tape: T * tape_step_floats floats as written by brax_rollout_tape
+ * of the same sys over the same acts [T][Amax][E]; g_out: cotangent of the
+ * state after step T; g_in (overwritten): cotangent of the state before step
+ * 0, may not alias g_out; g_acts [T][Amax][E] (device, caller-owned,
+ * overwritten): the action cotangents of every step, zero where an action
+ * was clamped and in rows beyond a type's actions. T == 0 copies g_out to
+ * g_in. Fused path only: BRAX_PLAIN gives BRAX_E_UNSUPPORTED. */
+int brax_rollout_vjp_tape(const brax_sys* sys, const float* tape, const float* acts, int32_t T,
+                          const brax_state* g_out, brax_state* g_in, float* g_acts, int32_t flags, void* stream);
+
 /* Environment layer (Section 4.2: gym-like environments; App. E: rewards
  * close to the MuJoCo gym ones without a contact cost, termination on the
  * torso height leaving a range). Per system type: */

@@ -57,7 +57,7 @@ class _Layout(C.Structure):
 
 EXPORTS = ("brax_sys_create", "brax_sys_destroy", "brax_sys_query", "brax_default_angles", "brax_default_qp",
            "brax_step", "brax_step_vjp", "brax_step_vjp_params", "brax_rollout", "brax_rollout_tape",
-           "brax_step_vjp_tape",
+           "brax_step_vjp_tape", "brax_rollout_vjp_tape",
            "brax_env_configure", "brax_env_step", "brax_autotune", "brax_schedule", "brax_set_schedule",
            "brax_nonfinite", "brax_last_error")
 
@@ -90,6 +90,8 @@ def lib():
                                         C.c_int32, C.c_void_p]
         L.brax_step_vjp_tape.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, P(_State), P(_State), C.c_void_p,
                                          C.c_int32, C.c_void_p]
+        L.brax_rollout_vjp_tape.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, P(_State), P(_State),
+                                            C.c_void_p, C.c_int32, C.c_void_p]
         L.brax_env_configure.argtypes = [C.c_void_p, P(_EnvParams)]
         L.brax_env_step.argtypes = [C.c_void_p, P(_State), C.c_void_p, P(_State), P(_State), C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_int32, C.c_void_p]
@@ -301,6 +303,25 @@ class System:
                                         flags, _stream(stream)))
         return g_in, g_act
 
+    def rollout_vjp_tape(self, tape, acts, g_out, g_in=None, g_acts=None, flags=0, stream=None):
+        """Adjoint of T steps from their tape [T][tape_step_floats] (rollout_tape over
+        the same acts [T][Amax][E]) in one launch: (g_in, g_acts [T][Amax][E])."""
+        T = int(acts.shape[0])
+        shape = (T, self.tape_step_floats)
+        if tuple(tape.shape) != shape or tape.dtype != torch.float32 or not tape.is_contiguous():
+            raise ValueError(f"tape must be a contiguous float32 tensor of shape {shape}")
+        acts = self._act(acts, (T, self.a_max, self.n_envs))
+        g_in = self.new_state() if g_in is None else g_in
+        if g_acts is None:
+            g_acts = torch.empty(T, self.a_max, self.n_envs, dtype=torch.float32, device=self.device)
+        elif tuple(g_acts.shape) != (T, self.a_max, self.n_envs) or g_acts.dtype != torch.float32 \
+                or not g_acts.is_contiguous():
+            raise ValueError(f"g_acts must be a contiguous float32 tensor of shape {(T, self.a_max, self.n_envs)}")
+        sg, sgi = g_out.struct(), g_in.struct()
+        _check(lib().brax_rollout_vjp_tape(self._h, _ptr(tape), _ptr(acts), T, C.byref(sg), C.byref(sgi),
+                                           _ptr(g_acts), flags, _stream(stream)))
+        return g_in, g_acts
+
     def env_configure(self, params):
         """Environment-layer parameters, one dict per system type with keys root,
         forward_weight, healthy_reward, ctrl_cost, z_min, z_max."""
@@ -360,7 +381,7 @@ class RolloutFn(torch.autograd.Function):
     each segment from its checkpoint and runs the step adjoint backwards
     through it: with tape=True the recompute writes every substep's tape
     (brax_rollout_tape, one segment at a time) and the adjoint reads it
-    (brax_step_vjp_tape); with tape=False the recompute keeps the step states
+    (brax_rollout_vjp_tape, one launch per segment); with tape=False the recompute keeps the step states
     (brax_rollout) and brax_step_vjp recomputes each step's substeps itself. Inputs: the four
     initial-state tensors and the action sequence [T][Amax][E]; outputs: the
     four final-state tensors.
@@ -409,10 +430,7 @@ class RolloutFn(torch.autograd.Function):
                 if tape is None or tape.shape[0] < n:
                     tape = torch.empty((n, system.tape_step_floats), dtype=torch.float32, device=acts.device)
                 system.rollout_tape(ck[si], acts[t0:t0 + n], tape=tape[:n])
-                for i in reversed(range(n)):
-                    g_in, g_a = system.step_vjp_tape(tape[i], acts[t0 + i], g)
-                    g_acts[t0 + i] = g_a
-                    g = g_in
+                g, _ = system.rollout_vjp_tape(tape[:n], acts[t0:t0 + n], g, g_acts=g_acts[t0:t0 + n])
                 continue
             # states s_{t0}, ..., s_{t0+n-1}
             states = [ck[si]]

@@ -69,10 +69,13 @@ __device__ __forceinline__ void wtape_rest(float* tp, v3 torque, int cnt, int la
   tp[15 * 64 + lane] = torque.z;
   tp[16 * 64 + lane] = (float)cnt;
 }
-__device__ __forceinline__ void wtape_load(const float* tp, int lane, Body& s, v3& torque, int& cnt) {
-  float v[17];
+// one record's rows into registers (issued ahead of use by the adjoint, so
+// that the load's latency overlaps the substep before it)
+__device__ __forceinline__ void wtape_fetch(const float* tp, int lane, float (&v)[17]) {
 #pragma unroll
   for (int k = 0; k < 17; ++k) v[k] = tp[k * 64 + lane];
+}
+__device__ __forceinline__ void wtape_unpack(const float (&v)[17], Body& s, v3& torque, int& cnt) {
   s.p = V(v[0], v[1], v[2]);
   s.q = q4{v[3], v[4], v[5], v[6]};
   s.v = V(v[7], v[8], v[9]);

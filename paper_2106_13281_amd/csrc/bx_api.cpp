@@ -55,7 +55,8 @@ struct DeviceGuard {
 }  // namespace
 
 struct GraphKey {
-  int kind;  // 0 step, 1 rollout, 2 adjoint, 3 rollout with tape, 4 adjoint from a tape
+  int kind;  // 0 step, 1 rollout, 2 adjoint, 3 rollout with tape, 4 adjoint from a tape, 5 environment
+             // step, 6 adjoint with parameters, 7 adjoint of T steps from a tape
   int flags, T, save_every;
   const void* p[12];
   bool operator<(const GraphKey& o) const {
@@ -828,7 +829,44 @@ int brax_step_vjp_tape(const brax_sys* sys, const float* tape, const float* act,
   return run_maybe_graph(s, flags & BRAX_GRAPH, key, st, [&](hipStream_t cs) -> int {
     LaunchCtx c = s->ctx();
     VjpSched sched{s->d_vjp_work, (int)s->vjp_work.size(), 1, s->d_jslot, s->d_cslot};
-    HIP_TRY(launch_vjp_tape(c, sched, tape, act, F(g_out), F(g_in), g_act, cs));
+    HIP_TRY(launch_vjp_tape(c, sched, tape, 0, 1, act, F(g_out), F(g_in), g_act, cs));
+    return BRAX_OK;
+  });
+}
+
+int brax_rollout_vjp_tape(const brax_sys* sys, const float* tape, const float* acts, int32_t T,
+                          const brax_state* g_out, brax_state* g_in, float* g_acts, int32_t flags, void* stream) {
+  brax_sys* s = const_cast<brax_sys*>(sys);
+  if (!s) return fail(BRAX_E_ARG, "sys is NULL");
+  if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
+  if (flags & BRAX_PLAIN) return fail(BRAX_E_UNSUPPORTED, "the tape adjoint runs on the fused path only");
+  if (T < 0) return fail(BRAX_E_ARG, "T < 0");
+  if (!state_ok(g_out) || !state_ok(g_in)) return fail(BRAX_E_ARG, "state has a NULL field");
+  if (g_in->pos == g_out->pos) return fail(BRAX_E_ARG, "g_in may not alias g_out");
+  int rc = check_flags(flags);
+  if (rc) return rc;
+  if (s->E == 0) return BRAX_OK;
+  if (!tape && T > 0) return fail(BRAX_E_ARG, "tape is NULL");
+  if (!acts && s->Am > 0 && T > 0) return fail(BRAX_E_ARG, "acts is NULL");
+  if (!g_acts && s->Am > 0 && T > 0) return fail(BRAX_E_ARG, "g_acts is NULL");
+  DeviceGuard g(s->device);
+  hipStream_t st = (hipStream_t)stream;
+  const size_t tstride = (size_t)s->smax * s->vjp_work.size() * TAPE_N * 64;
+  GraphKey key{};
+  key.kind = 7;
+  key.flags = flags;
+  key.T = T;
+  const void* ptrs[] = {tape, acts, g_out->pos, g_out->rot, g_out->vel, g_out->ang, g_in->pos, g_in->rot, g_acts};
+  std::memcpy(key.p, ptrs, sizeof ptrs);
+  return run_maybe_graph(s, flags & BRAX_GRAPH, key, st, [&](hipStream_t cs) -> int {
+    LaunchCtx c = s->ctx();
+    if (T == 0) {
+      // no step: the cotangent passes through unchanged
+      HIP_TRY(launch_copy_state(c, F(g_out), F(g_in), cs));
+      return BRAX_OK;
+    }
+    VjpSched sched{s->d_vjp_work, (int)s->vjp_work.size(), 1, s->d_jslot, s->d_cslot};
+    HIP_TRY(launch_vjp_tape(c, sched, tape, tstride, T, acts, F(g_out), F(g_in), g_acts, cs));
     return BRAX_OK;
   });
 }

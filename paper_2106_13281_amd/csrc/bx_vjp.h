@@ -31,10 +31,11 @@ hipError_t launch_vjp(const LaunchCtx& c, VjpWork& w, const VjpSched& sched, Fie
 // g_params[p_max][E] (see brax_step_vjp_params for the order).
 hipError_t launch_vjp_params(const LaunchCtx& c, const VjpSched& sched, Fields in, const float* act, Fields g_out,
                              Fields g_in, float* g_act, float* g_params, int p_max, hipStream_t s);
-// The same adjoint from the step's wavefront-major forward tape
-// [Smax][n_work][TAPE_N][64] (written by the fused forward with the same
-// work list), without recomputing the step.
-hipError_t launch_vjp_tape(const LaunchCtx& c, const VjpSched& sched, const float* tape, const float* act,
-                           Fields g_out, Fields g_in, float* g_act, hipStream_t s);
+// The same adjoint, over T consecutive steps (the last first), from their
+// wavefront-major forward tape [T][Smax][n_work][TAPE_N][64] (tstride floats
+// per step; written by the fused forward with the same work list), without
+// recomputing the steps: act and g_act [T][Am][E].
+hipError_t launch_vjp_tape(const LaunchCtx& c, const VjpSched& sched, const float* tape, size_t tstride, int T,
+                           const float* act, Fields g_out, Fields g_in, float* g_act, hipStream_t s);
 
 }  // namespace bx

@@ -295,9 +295,11 @@ __device__ __forceinline__ Bar shfl_bar(const Bar& s, int src) {
 __device__ __forceinline__ v3 shfl3(v3 a, int src) { return V(shfl(a.x, src), shfl(a.y, src), shfl(a.z, src)); }
 
 // FROM_TAPE: the forward substeps are not recomputed; their tape records are
-// read from the wavefront-major hbm_tape[sub][work item w of n_work][TAPE_N][64]
-// (written by the fused forward with a tape, same work list) instead of the
-// LDS tape.
+// read from the wavefront-major hbm_tape[step][sub][work item w of n_work][TAPE_N][64]
+// (written by the fused forward with a tape, same work list; tstride floats
+// per step) instead of the LDS tape, and T consecutive steps are
+// differentiated in reverse in one pass (act and g_act [T][Am][E]), the
+// state cotangent staying in registers between them. Without a tape T is 1.
 // PARAMS: also the cotangents of the system parameters, per environment,
 // into g_params[P_max][E] (order: mass per body, inertia per body x, y, z,
 // per joint k_lin, c_lin, k_ang, c_ang, k_lim, strength per action,
@@ -310,7 +312,7 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
                                               const Fields& g_in, float* __restrict__ g_act, float* lds,
                                               const float* __restrict__ hbm_tape, int w, int n_work,
                                               float* __restrict__ g_params = nullptr, int p_max = 0,
-                                              PairLanes* pl = nullptr) {
+                                              PairLanes* pl = nullptr, int T = 1, size_t tstride = 0) {
   constexpr int TN = PARAMS ? TAPE_N + 3 : TAPE_N;  // LDS tape rows per substep
   const int t = wk.type;
   const TypeT ty = tab->type[t];
@@ -332,10 +334,12 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
   pin_consts<MAXDOF>(B, J, has_joint, Creg, REGC);
   const float h = ty.h;
   if (PAIRS && ty.np > 0) pair_lanes_load(tab, t, pl, lane);
+  const size_t AE = (size_t)Am * E;
+  // actions of the step being differentiated, the last one first
   float a[3] = {0.f, 0.f, 0.f}, raw[3] = {0.f, 0.f, 0.f};
   if (has_joint)
     for (int x = 0; x < MAXDOF; ++x) {
-      raw[x] = J.act[x] >= 0 ? act[(size_t)J.act[x] * E + e] : 0.f;
+      raw[x] = J.act[x] >= 0 ? act[(T - 1) * AE + (size_t)J.act[x] * E + e] : 0.f;
       a[x] = clampf(raw[x], J.act_lo[x], J.act_hi[x]);
     }
 
@@ -416,97 +420,124 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
   // inverse inertia, its joint's five constants and strengths, friction
   float invm_bar = 0.f, mu_bar = 0.f, Ib[3] = {0.f, 0.f, 0.f}, Iinvb[3] = {0.f, 0.f, 0.f};
   float jbar[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, gbar[3] = {0.f, 0.f, 0.f};
-  for (int sub = ty.substeps - 1; sub >= 0; --sub) {
-    Body pre;
-    v3 ttot, ftot = V(0.f, 0.f, 0.f);
-    int n;
-    if (FROM_TAPE) {
-      wtape_load(hbm_tape + ((size_t)sub * n_work + w) * TAPE_N * 64, lane, pre, ttot, n);
-    } else {
-      const float* tp = lds + sub * TN * 64 + lane;
-      if (PARAMS) ftot = V(tp[1088], tp[1152], tp[1216]);
-      pre.p = V(tp[0], tp[64], tp[128]);
-      pre.q = q4{tp[192], tp[256], tp[320], tp[384]};
-      pre.v = V(tp[448], tp[512], tp[576]);
-      pre.w = V(tp[640], tp[704], tp[768]);
-      ttot = V(tp[832], tp[896], tp[960]);
-      n = (int)tp[1024];
-    }
-    Body post = pre;
-    kinematic(B, post, h);
-    Body P = shfl_body(post, src_parent);
-    Frame f = derive(B, post);
-    v3 fb, tb, dvb, dwb;
-    // this body's frame cotangents from every item of the substep, turned
-    // into its quaternion cotangent once at the end
-    FrameBar fr = framebar_zero();
-    Bar tot = integrate_adj(B, ty, post, f, ttot, n, G, fb, tb, dvb, dwb, fr, ftot, invm_bar);
-    v3 fbP = shfl3(fb, src_parent), tbP = shfl3(tb, src_parent);
-    Bar bP = bar_zero(), bC = bar_zero();
-    {
-      // evaluated on every lane so that it interleaves with the contacts; a
-      // root's joint gets zero cotangents, and the adjoint being linear in
-      // them, every output is then exactly zero
-      const v3 z3 = V(0.f, 0.f, 0.f);
-      float ab[3];
-      joint_eval_adj<MAXDOF>(J, P, quat_to_mat(P.q), post, f.R, a, has_joint ? fb : z3, has_joint ? tb : z3,
-                             has_joint ? fbP : z3, has_joint ? tbP : z3, bP, bC, ab, fr, PARAMS ? jbar : nullptr,
-                             PARAMS ? gbar : nullptr);
-      for (int x = 0; x < MAXDOF; ++x) ga[x] += ab[x];
-    }
-    // children's cotangents for this body: reads in flight during the contact adjoints
-    Bar cb[GATHER];
-#pragma unroll
-    for (int i = 0; i < GATHER; ++i) {
-      if (i < ty.max_children) {
+  // tape records from HBM one substep ahead of their use
+  auto rec_at = [&](int step, int sub) {
+    return hbm_tape + step * tstride + ((size_t)sub * n_work + w) * TAPE_N * 64;
+  };
+  float rec[17];
+  if (FROM_TAPE) wtape_fetch(rec_at(T - 1, ty.substeps - 1), lane, rec);
+  for (int step = T - 1; step >= 0; --step) {
+    // the previous step's actions, loaded while this one is differentiated
+    float raw_prev[3] = {0.f, 0.f, 0.f};
+    if (has_joint && step > 0)
+      for (int x = 0; x < MAXDOF; ++x)
+        raw_prev[x] = J.act[x] >= 0 ? act[(step - 1) * AE + (size_t)J.act[x] * E + e] : 0.f;
+    for (int sub = ty.substeps - 1; sub >= 0; --sub) {
+      Body pre;
+      v3 ttot, ftot = V(0.f, 0.f, 0.f);
+      int n;
+      if (FROM_TAPE) {
+        wtape_unpack(rec, pre, ttot, n);
+        if (sub > 0)
+          wtape_fetch(rec_at(step, sub - 1), lane, rec);
+        else if (step > 0)
+          wtape_fetch(rec_at(step - 1, ty.substeps - 1), lane, rec);
+      } else {
+        const float* tp = lds + sub * TN * 64 + lane;
+        if (PARAMS) ftot = V(tp[1088], tp[1152], tp[1216]);
+        pre.p = V(tp[0], tp[64], tp[128]);
+        pre.q = q4{tp[192], tp[256], tp[320], tp[384]};
+        pre.v = V(tp[448], tp[512], tp[576]);
+        pre.w = V(tp[640], tp[704], tp[768]);
+        ttot = V(tp[832], tp[896], tp[960]);
+        n = (int)tp[1024];
+      }
+      Body post = pre;
+      kinematic(B, post, h);
+      Body P = shfl_body(post, src_parent);
+      Frame f = derive(B, post);
+      v3 fb, tb, dvb, dwb;
+      // this body's frame cotangents from every item of the substep, turned
+      // into its quaternion cotangent once at the end
+      FrameBar fr = framebar_zero();
+      Bar tot = integrate_adj(B, ty, post, f, ttot, n, G, fb, tb, dvb, dwb, fr, ftot, invm_bar);
+      v3 fbP = shfl3(fb, src_parent), tbP = shfl3(tb, src_parent);
+      Bar bP = bar_zero(), bC = bar_zero();
+      {
+        // evaluated on every lane so that it interleaves with the contacts; a
+        // root's joint gets zero cotangents, and the adjoint being linear in
+        // them, every output is then exactly zero
+        const v3 z3 = V(0.f, 0.f, 0.f);
+        float ab[3];
+        joint_eval_adj<MAXDOF>(J, P, quat_to_mat(P.q), post, f.R, a, has_joint ? fb : z3, has_joint ? tb : z3,
+                               has_joint ? fbP : z3, has_joint ? tbP : z3, bP, bC, ab, fr, PARAMS ? jbar : nullptr,
+                               PARAMS ? gbar : nullptr);
+        for (int x = 0; x < MAXDOF; ++x) ga[x] += ab[x];
+      }
+      // children's cotangents for this body: reads in flight during the contact adjoints
+      Bar cb[GATHER];
+  #pragma unroll
+      for (int i = 0; i < GATHER; ++i) {
+        if (i < ty.max_children) {
+          const int src = base + (i < B.nch ? (int)((B.ch_packed >> (4 * i)) & 15u) : b);
+          cb[i] = shfl_bar(bP, src);
+        }
+      }
+      auto contact_back = [&](const ContactT& C) {
+        bool applied;
+        Bar bc = contact_adj(C, ty, B, post, f, dvb, dwb, applied, fr, invm_bar, mu_bar);
+        if (applied) bar_add(tot, bc);
+      };
+  #pragma unroll
+      for (int k = 0; k < REGC; ++k)
+        if (k < ty.max_contacts && n_con > k) contact_back(Creg[k]);
+      for (int c = REGC; c < n_con; ++c) contact_back(tab->contact[t][B.c0 + c]);
+      if (PAIRS && ty.np > 0) pair_phase_adj(tab, t, *pl, b, base, post, f, dvb, dwb, tot, fr, invm_bar, mu_bar);
+      bar_add(tot, bC);
+      if (PARAMS) {
+        // Iw = R diag(I) R^T, Iwinv = R diag(1/I) R^T: d/dI_k = r_k^T S_bar r_k (r_k column k of R;
+        // an off-diagonal cotangent already holds both of its entries)
+        for (int k = 0; k < 3; ++k) {
+          const v3 r = col(f.R, k);
+          auto quad = [&](const s3& S) {
+            return S.xx * r.x * r.x + S.yy * r.y * r.y + S.zz * r.z * r.z + S.xy * r.x * r.y + S.xz * r.x * r.z +
+                   S.yz * r.y * r.z;
+          };
+          Ib[k] += quad(fr.Iwb);
+          Iinvb[k] += quad(fr.Iwinvb);
+        }
+      }
+      frame_adj(B, post, f, fr, tot.q);
+  #pragma unroll
+      for (int i = 0; i < GATHER; ++i)
+        if (i < B.nch) bar_add(tot, cb[i]);
+      for (int i = GATHER; i < ty.max_children; ++i) {
         const int src = base + (i < B.nch ? (int)((B.ch_packed >> (4 * i)) & 15u) : b);
-        cb[i] = shfl_bar(bP, src);
+        Bar x = shfl_bar(bP, src);
+        if (i < B.nch) bar_add(tot, x);
       }
+      G = kinematic_adj(B, pre, h, tot);
     }
-    auto contact_back = [&](const ContactT& C) {
-      bool applied;
-      Bar bc = contact_adj(C, ty, B, post, f, dvb, dwb, applied, fr, invm_bar, mu_bar);
-      if (applied) bar_add(tot, bc);
-    };
-#pragma unroll
-    for (int k = 0; k < REGC; ++k)
-      if (k < ty.max_contacts && n_con > k) contact_back(Creg[k]);
-    for (int c = REGC; c < n_con; ++c) contact_back(tab->contact[t][B.c0 + c]);
-    if (PAIRS && ty.np > 0) pair_phase_adj(tab, t, *pl, b, base, post, f, dvb, dwb, tot, fr, invm_bar, mu_bar);
-    bar_add(tot, bC);
-    if (PARAMS) {
-      // Iw = R diag(I) R^T, Iwinv = R diag(1/I) R^T: d/dI_k = r_k^T S_bar r_k (r_k column k of R;
-      // an off-diagonal cotangent already holds both of its entries)
-      for (int k = 0; k < 3; ++k) {
-        const v3 r = col(f.R, k);
-        auto quad = [&](const s3& S) {
-          return S.xx * r.x * r.x + S.yy * r.y * r.y + S.zz * r.z * r.z + S.xy * r.x * r.y + S.xz * r.x * r.z +
-                 S.yz * r.y * r.z;
-        };
-        Ib[k] += quad(fr.Iwb);
-        Iinvb[k] += quad(fr.Iwinvb);
+    // this step's action cotangents (zero where the action was clamped)
+    if (live) {
+      float* ga_t = g_act + step * AE;
+      if (has_joint)
+        for (int x = 0; x < MAXDOF; ++x)
+          if (x < J.dof && J.act[x] >= 0)
+            ga_t[(size_t)J.act[x] * E + e] = (raw[x] >= J.act_lo[x] && raw[x] <= J.act_hi[x]) ? ga[x] : 0.f;
+      if (b == 0)
+        for (int x = ty.na; x < Am; ++x) ga_t[(size_t)x * E + e] = 0.f;
+    }
+    if (has_joint)
+      for (int x = 0; x < MAXDOF; ++x) {
+        raw[x] = raw_prev[x];
+        a[x] = clampf(raw[x], J.act_lo[x], J.act_hi[x]);
+        ga[x] = 0.f;
       }
-    }
-    frame_adj(B, post, f, fr, tot.q);
-#pragma unroll
-    for (int i = 0; i < GATHER; ++i)
-      if (i < B.nch) bar_add(tot, cb[i]);
-    for (int i = GATHER; i < ty.max_children; ++i) {
-      const int src = base + (i < B.nch ? (int)((B.ch_packed >> (4 * i)) & 15u) : b);
-      Bar x = shfl_bar(bP, src);
-      if (i < B.nch) bar_add(tot, x);
-    }
-    G = kinematic_adj(B, pre, h, tot);
   }
   if (live) {
     store_bar(g_in, G, b, e, Bm, E);
     for (int pb = nb + b; pb < Bm; pb += nb) zero_body(g_in, pb, e, Bm, E);
-    if (has_joint)
-      for (int x = 0; x < MAXDOF; ++x)
-        if (x < J.dof && J.act[x] >= 0)
-          g_act[(size_t)J.act[x] * E + e] = (raw[x] >= J.act_lo[x] && raw[x] <= J.act_hi[x]) ? ga[x] : 0.f;
-    if (b == 0)
-      for (int x = ty.na; x < Am; ++x) g_act[(size_t)x * E + e] = 0.f;
   }
   if (PARAMS) {
     // friction: summed over the environment's lanes (all lanes take part in the permutes)
@@ -574,14 +605,16 @@ __global__ __launch_bounds__(64) void k_fused_vjp_params(const Tables* __restric
                                          nullptr, w, n_work, g_params, p_max, pl);
 }
 
-// The adjoint of one step from its forward tape in HBM (no recompute, no LDS).
+// The adjoint of T consecutive steps from their forward tape in HBM (no
+// recompute, no LDS), the last step first.
 template <bool PAIRS, bool ONE_AXIS, int REGC>
 __global__ __launch_bounds__(64) void k_fused_vjp_tape(const Tables* __restrict__ tab,
                                                        const WaveWork* __restrict__ work, int n_work,
                                                        const int32_t* __restrict__ env_list,
                                                        const int32_t* __restrict__ type_off, int E, int Bm, int Am,
-                                                       const float* __restrict__ tape, const float* __restrict__ act,
-                                                       Fields g_out, Fields g_in, float* __restrict__ g_act) {
+                                                       const float* __restrict__ tape, size_t tstride, int T,
+                                                       const float* __restrict__ act, Fields g_out, Fields g_in,
+                                                       float* __restrict__ g_act) {
   extern __shared__ float lds_pairs[];  // body-body tables (PAIRS)
   const int w = xcd_block(blockIdx.x, gridDim.x);
   if (w >= n_work) return;
@@ -590,10 +623,10 @@ __global__ __launch_bounds__(64) void k_fused_vjp_tape(const Tables* __restrict_
   PairLanes* pl = PAIRS ? reinterpret_cast<PairLanes*>(lds_pairs) : nullptr;
   if (ONE_AXIS || tab->type[wk.type].max_dof <= 1)
     fused_vjp_run<1, true, false, PAIRS, REGC>(tab, wk, env_list, type_off, E, Bm, Am, none, act, g_out, g_in, g_act,
-        nullptr, tape, w, n_work, nullptr, 0, pl);
+        nullptr, tape, w, n_work, nullptr, 0, pl, T, tstride);
   else
     fused_vjp_run<3, true, false, PAIRS, REGC>(tab, wk, env_list, type_off, E, Bm, Am, none, act, g_out, g_in, g_act,
-        nullptr, tape, w, n_work, nullptr, 0, pl);
+        nullptr, tape, w, n_work, nullptr, 0, pl, T, tstride);
 }
 
 // Whether a type of the batch has body-body contact candidates: the kernels
@@ -680,15 +713,15 @@ hipError_t launch_vjp_params(const LaunchCtx& c, const VjpSched& sched, Fields i
   return hipGetLastError();
 }
 
-hipError_t launch_vjp_tape(const LaunchCtx& c, const VjpSched& sched, const float* tape, const float* act,
-                           Fields g_out, Fields g_in, float* g_act, hipStream_t s) {
-  if (sched.n_work == 0) return hipSuccess;
+hipError_t launch_vjp_tape(const LaunchCtx& c, const VjpSched& sched, const float* tape, size_t tstride, int T,
+                           const float* act, Fields g_out, Fields g_in, float* g_act, hipStream_t s) {
+  if (sched.n_work == 0 || T <= 0) return hipSuccess;
   if (any_pairs(c))
     LAUNCH_AXES(k_fused_vjp_tape, true, dim3(sched.n_work), dim3(64), sizeof(PairLanes), s, c.tab, sched.work,
-                sched.n_work, c.env_list, c.type_off, c.E, c.Bm, c.Am, tape, act, g_out, g_in, g_act);
+                sched.n_work, c.env_list, c.type_off, c.E, c.Bm, c.Am, tape, tstride, T, act, g_out, g_in, g_act);
   else
     LAUNCH_AXES(k_fused_vjp_tape, false, dim3(sched.n_work), dim3(64), 0, s, c.tab, sched.work, sched.n_work,
-                c.env_list, c.type_off, c.E, c.Bm, c.Am, tape, act, g_out, g_in, g_act);
+                c.env_list, c.type_off, c.E, c.Bm, c.Am, tape, tstride, T, act, g_out, g_in, g_act);
   return hipGetLastError();
 }
 

@@ -122,6 +122,8 @@ def test_argument_errors():
     st = braxmi._State()
     assert L.brax_step(s._h, C.byref(st), None, C.byref(st), 0, None) == -1
     assert L.brax_rollout(s._h, C.byref(st), None, -1, 0, None, C.byref(st), 0, None) == -1
+    assert L.brax_rollout_vjp_tape(s._h, None, None, 1, C.byref(st), C.byref(st), None, 0, None) == -1
+    assert b"host-only" in L.brax_last_error()
     assert L.brax_sys_query(None, None) == -1
     L.brax_sys_destroy(None)  # no-op
 

@@ -112,6 +112,37 @@ def test_rollout_gradient_tape_and_recompute_agree():
 
 
 @pytest.mark.parametrize("name", SYSTEMS)
+def test_rollout_vjp_tape_equals_step_by_step(name):
+    """brax_rollout_vjp_tape over T steps of a tape (one launch) gives what T
+    calls of brax_step_vjp_tape give, last step first, each call's g_in the
+    next one's g_out (the same kernel code; the state cotangent stays in
+    registers between steps); T = 0 passes the cotangent through."""
+    E, T = 45, 7
+    o, X, _ = make_states(name, E, seed=31, warm=5)
+    acts = synth.actions(31, T, E, o.na, synth.WORKLOADS[name].act_range)
+    sysg = braxmi.System(synth.system_text(synth.WORKLOADS[name].system), E)
+    A = acts_dev(acts, sysg.a_max)
+    _, tape = sysg.rollout_tape(to_dev(X), A)
+    g = to_dev(np.random.default_rng(32).normal(size=X.shape).astype(np.float32).astype(np.float64))
+    gi, ga = sysg.rollout_vjp_tape(tape, A, g)
+    cur, ga_steps = g, []
+    for t in reversed(range(T)):
+        cur, a_t = sysg.step_vjp_tape(tape[t], A[t].contiguous(), cur)
+        ga_steps.append(a_t)
+    ga_ref = torch.stack(ga_steps[::-1])
+    torch.cuda.synchronize()
+    e_s = normwise(from_dev(gi, o.nb), from_dev(cur, o.nb))
+    e_a = normwise(ga.cpu().numpy().transpose(2, 0, 1), ga_ref.cpu().numpy().transpose(2, 0, 1))
+    print(f"rollout_vjp_tape {name}: state {e_s.max():.1e} actions {e_a.max():.1e}", flush=True)
+    assert e_s.max() < 1e-6 and e_a.max() < 1e-6
+    assert torch.isfinite(ga).all() and torch.isfinite(gi.pos).all()
+    g0, ga0 = sysg.rollout_vjp_tape(tape[:0], A[:0], g)
+    for a_, b_ in zip(g0.fields(), g.fields()):
+        assert torch.equal(a_, b_)
+    assert ga0.shape[0] == 0
+
+
+@pytest.mark.parametrize("name", SYSTEMS)
 def test_step_vjp_params_matches_oracle(name):
     """Cotangents of the system parameters (masses, inertias, joint constants,
     actuator strengths, friction) against central differences of the FP64
