@@ -377,8 +377,9 @@ class RolloutFn(torch.autograd.Function):
     Forward keeps the state every k steps, computed segment by segment with
     brax_rollout_tape into a scratch segment tape (the taped kernel, so that
     the checkpoints and the backward's recomputed segments come from the same
-    compiled code and the gradient does not depend on k). Backward recomputes
-    each segment from its checkpoint and runs the step adjoint backwards
+    compiled code and the gradient does not depend on k); the last segment's
+    tape is kept for the backward. Backward recomputes each other segment
+    from its checkpoint and runs the step adjoint backwards
     through it: with tape=True the recompute writes every substep's tape
     (brax_rollout_tape, one segment at a time) and the adjoint reads it
     (brax_rollout_vjp_tape, one launch per segment); with tape=False the recompute keeps the step states
@@ -406,6 +407,9 @@ class RolloutFn(torch.autograd.Function):
             cur = nxt
             t += n
         ctx.system, ctx.k, ctx.T, ctx.tape = system, k, T, bool(tape)
+        # the last segment's tape is the one the backward starts with: kept
+        # (with the tape adjoint), so that segment is not recomputed
+        ctx.last_tape = scratch if tape else None
         ctx.save_for_backward(acts_d, *[x for c in ckpts[:-1] for x in c.fields()])
         return cur.pos, cur.rot, cur.vel, cur.ang
 
@@ -422,14 +426,15 @@ class RolloutFn(torch.autograd.Function):
         g = State(z(gp, ck[0].pos), z(gr, ck[0].rot), z(gv, ck[0].vel), z(gw, ck[0].ang))
         g_acts = torch.zeros_like(acts)
         seg_starts = list(range(0, T, k))
-        tape = None
+        tape, ctx.last_tape = ctx.last_tape, None
         for si in reversed(range(len(seg_starts))):
             t0 = seg_starts[si]
             n = min(k, T - t0)
             if use_tape:
-                if tape is None or tape.shape[0] < n:
-                    tape = torch.empty((n, system.tape_step_floats), dtype=torch.float32, device=acts.device)
-                system.rollout_tape(ck[si], acts[t0:t0 + n], tape=tape[:n])
+                if si < len(seg_starts) - 1 or tape is None:
+                    if tape is None or tape.shape[0] < n:
+                        tape = torch.empty((n, system.tape_step_floats), dtype=torch.float32, device=acts.device)
+                    system.rollout_tape(ck[si], acts[t0:t0 + n], tape=tape[:n])
                 g, _ = system.rollout_vjp_tape(tape[:n], acts[t0:t0 + n], g, g_acts=g_acts[t0:t0 + n])
                 continue
             # states s_{t0}, ..., s_{t0+n-1}

@@ -476,7 +476,7 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
       }
       // children's cotangents for this body: reads in flight during the contact adjoints
       Bar cb[GATHER];
-  #pragma unroll
+#pragma unroll
       for (int i = 0; i < GATHER; ++i) {
         if (i < ty.max_children) {
           const int src = base + (i < B.nch ? (int)((B.ch_packed >> (4 * i)) & 15u) : b);
@@ -488,7 +488,7 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
         Bar bc = contact_adj(C, ty, B, post, f, dvb, dwb, applied, fr, invm_bar, mu_bar);
         if (applied) bar_add(tot, bc);
       };
-  #pragma unroll
+#pragma unroll
       for (int k = 0; k < REGC; ++k)
         if (k < ty.max_contacts && n_con > k) contact_back(Creg[k]);
       for (int c = REGC; c < n_con; ++c) contact_back(tab->contact[t][B.c0 + c]);
@@ -508,7 +508,7 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
         }
       }
       frame_adj(B, post, f, fr, tot.q);
-  #pragma unroll
+#pragma unroll
       for (int i = 0; i < GATHER; ++i)
         if (i < B.nch) bar_add(tot, cb[i]);
       for (int i = GATHER; i < ty.max_children; ++i) {
