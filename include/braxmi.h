@@ -24,7 +24,12 @@
  *   and cached HIP graphs and frees them in brax_sys_destroy.
  * - Streams: `stream` is a hipStream_t (NULL = the legacy default stream).
  *   Step/rollout/VJP calls are asynchronous on it. A brax_sys is used by one
- *   stream at a time: its workspace is shared by its calls.
+ *   stream at a time: its workspace is shared by its calls. Exception:
+ *   brax_rollout_tape and brax_rollout_vjp_tape with neither BRAX_GRAPH nor
+ *   BRAX_NONFINITE_FLAGS use none of the handle's workspace and may run on
+ *   several streams at once, on disjoint output buffers (a checkpointed
+ *   backward recomputes one segment's tape while the previous one's adjoint
+ *   runs).
  * - State layout (structure of arrays, environment index fastest):
  *     element (c, b, e) of a field = ptr[(c * Bmax + b) * E + e]
  *   pos, vel, ang: c in [0,3) (x, y, z; world frame, m, m/s, rad/s)

@@ -193,6 +193,7 @@ class System:
         self.n_pairs = list(lay.n_pairs[:nt])                      # body-body contact candidates
         self.dt = list(lay.dt[:nt])
         self.device = torch.device("cuda", device) if device >= 0 else None
+        self._side = None  # second stream of the checkpointed backward (created on first use)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -382,7 +383,8 @@ class RolloutFn(torch.autograd.Function):
     from its checkpoint and runs the step adjoint backwards
     through it: with tape=True the recompute writes every substep's tape
     (brax_rollout_tape, one segment at a time) and the adjoint reads it
-    (brax_rollout_vjp_tape, one launch per segment); with tape=False the recompute keeps the step states
+    (brax_rollout_vjp_tape, one launch per segment; each recompute runs on a
+    second stream during the adjoint of the segment after it); with tape=False the recompute keeps the step states
     (brax_rollout) and brax_step_vjp recomputes each step's substeps itself. Inputs: the four
     initial-state tensors and the action sequence [T][Amax][E]; outputs: the
     four final-state tensors.
@@ -426,17 +428,13 @@ class RolloutFn(torch.autograd.Function):
         g = State(z(gp, ck[0].pos), z(gr, ck[0].rot), z(gv, ck[0].vel), z(gw, ck[0].ang))
         g_acts = torch.zeros_like(acts)
         seg_starts = list(range(0, T, k))
-        tape, ctx.last_tape = ctx.last_tape, None
+        last, ctx.last_tape = ctx.last_tape, None
+        if use_tape:
+            g = _segments_backward(system, ck, acts, seg_starts, k, T, g, g_acts, last)
+            return None, None, None, g.pos, g.rot, g.vel, g.ang, g_acts
         for si in reversed(range(len(seg_starts))):
             t0 = seg_starts[si]
             n = min(k, T - t0)
-            if use_tape:
-                if si < len(seg_starts) - 1 or tape is None:
-                    if tape is None or tape.shape[0] < n:
-                        tape = torch.empty((n, system.tape_step_floats), dtype=torch.float32, device=acts.device)
-                    system.rollout_tape(ck[si], acts[t0:t0 + n], tape=tape[:n])
-                g, _ = system.rollout_vjp_tape(tape[:n], acts[t0:t0 + n], g, g_acts=g_acts[t0:t0 + n])
-                continue
             # states s_{t0}, ..., s_{t0+n-1}
             states = [ck[si]]
             if n > 1:
@@ -447,6 +445,66 @@ class RolloutFn(torch.autograd.Function):
                 g_acts[t0 + i] = g_a
                 g = g_in
         return None, None, None, g.pos, g.rot, g.vel, g.ang, g_acts
+
+
+def _segments_backward(system, ck, acts, seg_starts, k, T, g, g_acts, last):
+    """Tape adjoint of the segments, last first. Segment si's tape is
+    recomputed from its checkpoint (brax_rollout_tape) on a second stream
+    while segment si+1's adjoint (brax_rollout_vjp_tape) runs on the current
+    one: both are small launches on disjoint SIMDs, so the recompute hides
+    behind the adjoint. Two tape buffers alternate; a buffer is rewritten only
+    after the adjoint that read it has finished (events), and every adjoint
+    waits for its tape. `last`: the forward's tape of the last segment, or
+    None (then it is recomputed too)."""
+    nseg = len(seg_starts)
+    if nseg == 0:
+        return g
+    main = torch.cuda.current_stream(acts.device)
+    if system._side is None:
+        system._side = torch.cuda.Stream(device=acts.device)  # default priority
+    side = system._side
+    rows = min(k, T)
+    use_last = last is not None and tuple(last.shape) == (rows, system.tape_step_floats)
+    bufs = [torch.empty((rows, system.tape_step_floats), dtype=torch.float32, device=acts.device),
+            last if use_last else None]
+    if bufs[1] is None:
+        bufs[1] = torch.empty_like(bufs[0])
+    for b in bufs:
+        b.record_stream(side)
+    freed = [None, None]     # event after the adjoint that last read each buffer
+    tapes = {}
+    side.wait_stream(main)   # checkpoints, actions and buffers are ready
+    nxt = [0]
+
+    def recompute(si):
+        j = nxt[0]
+        nxt[0] ^= 1
+        t0 = seg_starts[si]
+        n = min(k, T - t0)
+        with torch.cuda.stream(side):
+            if freed[j] is not None:
+                side.wait_event(freed[j])
+            system.rollout_tape(ck[si], acts[t0:t0 + n], tape=bufs[j][:n], stream=side)
+            ev = torch.cuda.Event()
+            ev.record(side)
+        tapes[si] = (j, ev)
+
+    if use_last:
+        tapes[nseg - 1] = (1, None)   # the forward's tape is in buffer 1
+    else:
+        recompute(nseg - 1)
+    for si in reversed(range(nseg)):
+        if si > 0:
+            recompute(si - 1)         # overlaps the adjoint below
+        j, ev = tapes.pop(si)
+        if ev is not None:
+            main.wait_event(ev)
+        t0 = seg_starts[si]
+        n = min(k, T - t0)
+        g, _ = system.rollout_vjp_tape(bufs[j][:n], acts[t0:t0 + n], g, g_acts=g_acts[t0:t0 + n], stream=main)
+        freed[j] = torch.cuda.Event()
+        freed[j].record(main)
+    return g
 
 
 def _contig(s):

@@ -142,6 +142,43 @@ def test_rollout_vjp_tape_equals_step_by_step(name):
     assert ga0.shape[0] == 0
 
 
+def test_overlapped_segment_backward_equals_serial_chain():
+    """RolloutFn's backward (recompute of a segment on a second stream during
+    the adjoint of the next, alternating tape buffers, the forward's last
+    tape kept) equals a serial chain of brax_rollout_tape and
+    brax_rollout_vjp_tape calls on one stream, bit for bit, with a ragged
+    last segment; a second backward of the same graph (no kept tape) too."""
+    name, E, T, k = "biped", 16, 23, 5
+    o, X, _ = make_states(name, E, seed=41, warm=5)
+    acts = synth.actions(41, T, E, o.na, synth.WORKLOADS[name].act_range)
+    sysg = braxmi.System(synth.system_text(name), E)
+    A = acts_dev(acts).requires_grad_(True)
+    out = braxmi.rollout_grad(sysg, to_dev(X), A, k=k)
+    loss = out.pos[0].sum() + 0.1 * out.vel.sum()
+    loss.backward(retain_graph=True)
+    g1 = A.grad.clone()
+    A.grad = None
+    loss.backward()
+    g2 = A.grad.clone()
+    # serial reference: checkpoints from the taped kernel, segments last first
+    Ad = A.detach()
+    ck, cur = [], to_dev(X)
+    for t0 in range(0, T, k):
+        ck.append(cur)
+        cur, _ = sysg.rollout_tape(cur, Ad[t0:t0 + k])
+    g = braxmi.State(torch.zeros_like(cur.pos), torch.zeros_like(cur.rot), torch.zeros_like(cur.vel),
+                     torch.zeros_like(cur.ang))
+    g.pos[0].fill_(1.0)
+    g.vel.fill_(0.1)
+    ref = torch.empty_like(Ad)
+    for si in reversed(range(len(ck))):
+        t0 = si * k
+        _, tape = sysg.rollout_tape(ck[si], Ad[t0:t0 + k])
+        g, _ = sysg.rollout_vjp_tape(tape, Ad[t0:t0 + k], g, g_acts=ref[t0:t0 + k])
+    torch.cuda.synchronize()
+    assert torch.equal(g1, ref) and torch.equal(g2, ref)
+
+
 @pytest.mark.parametrize("name", SYSTEMS)
 def test_step_vjp_params_matches_oracle(name):
     """Cotangents of the system parameters (masses, inertias, joint constants,
