@@ -109,8 +109,9 @@ hipError_t launch_plain_step(const LaunchCtx& c, Fields in, Fields out, const fl
                              float* const* cslot, bool flags, hipStream_t s, float* tape = nullptr);
 hipError_t launch_copy_state(const LaunchCtx& c, Fields in, Fields out, hipStream_t s);
 // Environment layer: k_env_pre keeps each environment's root x before the
-// step (x0 [E]); k_env, after the step, writes reward, done and (after the
-// reset of finished environments) the observations [Omax][E].
+// step (x0 [E]); after the step, k_env writes reward, done and the
+// observations [Omax][E] (of the reset state for finished environments),
+// then k_env_reset copies the reset state into finished environments.
 hipError_t launch_env_pre(const LaunchCtx& c, const EnvT* env, Fields in, float* x0, hipStream_t s);
 hipError_t launch_env(const LaunchCtx& c, const EnvT* env, int Omax, const float* x0, Fields out,
                       const float* act, Fields reset, float* obs, float* reward, uint8_t* done, hipStream_t s);

@@ -529,52 +529,39 @@ __global__ void k_env_pre(const Tables* __restrict__ tab, const EnvT* __restrict
 //   done = not healthy; a finished environment takes its reset state; the
 //   observation of the (reset) state is [z_root, q_root, v_root, w_root,
 //   joint angles (D), (w_child - w_parent) . Euler axis (D)], zero-padded.
+// Grid: x over environments (coalesced SoA access), y over rows: row j <
+// n_rows - 1 writes the observation entries of joint j, the last row the
+// reward, termination, root entries and padding. Each thread decides
+// `healthy` itself from the stepped state and reads bodies from the reset
+// state when the environment finished; `out` is not written here (the reset
+// copy follows in k_env_reset), so every thread sees the same stepped state.
 __global__ void k_env(const Tables* __restrict__ tab, const EnvT* __restrict__ env,
-                      const int32_t* __restrict__ env_type, int E, int Bm, int Am, int Omax,
+                      const int32_t* __restrict__ env_type, int E, int Bm, int Am, int Omax, int n_rows,
                       const float* __restrict__ x0, Fields out, const float* __restrict__ act, Fields reset,
                       float* __restrict__ obs, float* __restrict__ reward, uint8_t* __restrict__ done) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= E) return;
+  const int row = blockIdx.y;
   const int t = env_type[e];
   const TypeT& ty = tab->type[t];
   const EnvT P = env[t];
   const size_t BE = (size_t)Bm * E;
-  const float x1 = out.pos[(size_t)P.root * E + e];
   const float z1 = out.pos[2 * BE + (size_t)P.root * E + e];
   const bool healthy = z1 >= P.z_min && z1 <= P.z_max;
-  float ctrl = 0.f;
-  for (int k = 0; k < ty.na; ++k) {
-    const float a = act[(size_t)k * E + e];
-    ctrl += a * a;
-  }
-  reward[e] = P.forward_weight * (x1 - x0[e]) / ty.dt + (healthy ? P.healthy_reward : 0.f) - P.ctrl_cost * ctrl;
-  done[e] = healthy ? 0 : 1;
-  if (!healthy) {
-    for (int b = 0; b < Bm; ++b) {
-      const size_t i = (size_t)b * E + e;
-      for (int c = 0; c < 3; ++c) {
-        out.pos[c * BE + i] = reset.pos[c * BE + i];
-        out.vel[c * BE + i] = reset.vel[c * BE + i];
-        out.ang[c * BE + i] = reset.ang[c * BE + i];
-      }
-      for (int c = 0; c < 4; ++c) out.rot[c * BE + i] = reset.rot[c * BE + i];
-    }
-  }
+  const Fields src = healthy ? out : reset;  // the state the observation is of
   auto load = [&](int b) {
     const size_t i = (size_t)b * E + e;
     Body s;
-    s.p = V(out.pos[i], out.pos[BE + i], out.pos[2 * BE + i]);
-    s.q = q4{out.rot[i], out.rot[BE + i], out.rot[2 * BE + i], out.rot[3 * BE + i]};
-    s.v = V(out.vel[i], out.vel[BE + i], out.vel[2 * BE + i]);
-    s.w = V(out.ang[i], out.ang[BE + i], out.ang[2 * BE + i]);
+    s.p = V(src.pos[i], src.pos[BE + i], src.pos[2 * BE + i]);
+    s.q = q4{src.rot[i], src.rot[BE + i], src.rot[2 * BE + i], src.rot[3 * BE + i]};
+    s.v = V(src.vel[i], src.vel[BE + i], src.vel[2 * BE + i]);
+    s.w = V(src.ang[i], src.ang[BE + i], src.ang[2 * BE + i]);
     return s;
   };
-  const Body r = load(P.root);
-  const float head[11] = {r.p.z, r.q.w, r.q.x, r.q.y, r.q.z, r.v.x, r.v.y, r.v.z, r.w.x, r.w.y, r.w.z};
-  for (int k = 0; k < 11; ++k) obs[(size_t)k * E + e] = head[k];
   const int D = ty.ndof;
-  for (int j = 0; j < ty.nj; ++j) {
-    const JointT& J = tab->joint[t][j];
+  if (row < n_rows - 1) {
+    if (row >= ty.nj) return;
+    const JointT& J = tab->joint[t][row];
     const Body Pb = load(J.parent), Cb = load(J.child);
     const JointGeo g = joint_geo<3>(J, quat_to_mat(Pb.q), quat_to_mat(Cb.q));
     const v3 wrel = Cb.w - Pb.w;
@@ -582,8 +569,36 @@ __global__ void k_env(const Tables* __restrict__ tab, const EnvT* __restrict__ e
       obs[(size_t)(11 + J.dof0 + k) * E + e] = g.th[k];
       obs[(size_t)(11 + D + J.dof0 + k) * E + e] = dot(wrel, g.ax[k]);
     }
+    return;
   }
+  const float x1 = out.pos[(size_t)P.root * E + e];
+  float ctrl = 0.f;
+  for (int k = 0; k < ty.na; ++k) {
+    const float a = act[(size_t)k * E + e];
+    ctrl += a * a;
+  }
+  reward[e] = P.forward_weight * (x1 - x0[e]) / ty.dt + (healthy ? P.healthy_reward : 0.f) - P.ctrl_cost * ctrl;
+  done[e] = healthy ? 0 : 1;
+  const Body r = load(P.root);
+  const float head[11] = {r.p.z, r.q.w, r.q.x, r.q.y, r.q.z, r.v.x, r.v.y, r.v.z, r.w.x, r.w.y, r.w.z};
+  for (int k = 0; k < 11; ++k) obs[(size_t)k * E + e] = head[k];
   for (int k = 11 + 2 * D; k < Omax; ++k) obs[(size_t)k * E + e] = 0.f;
+}
+
+// A finished environment takes its reset state: one thread per (body slot,
+// environment) element, after k_env.
+__global__ void k_env_reset(int E, int Bm, const uint8_t* __restrict__ done, Fields out, Fields reset) {
+  const size_t BE = (size_t)Bm * E;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= BE) return;
+  const int e = (int)(i % E);
+  if (!done[e]) return;
+  for (int c = 0; c < 3; ++c) {
+    out.pos[c * BE + i] = reset.pos[c * BE + i];
+    out.vel[c * BE + i] = reset.vel[c * BE + i];
+    out.ang[c * BE + i] = reset.ang[c * BE + i];
+  }
+  for (int c = 0; c < 4; ++c) out.rot[c * BE + i] = reset.rot[c * BE + i];
 }
 
 hipError_t launch_env_pre(const LaunchCtx& c, const EnvT* env, Fields in, float* x0, hipStream_t s) {
@@ -595,8 +610,14 @@ hipError_t launch_env_pre(const LaunchCtx& c, const EnvT* env, Fields in, float*
 hipError_t launch_env(const LaunchCtx& c, const EnvT* env, int Omax, const float* x0, Fields out, const float* act,
                       Fields reset, float* obs, float* reward, uint8_t* done, hipStream_t s) {
   if (c.E == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_env, dim3(cdiv(c.E, 256)), dim3(256), 0, s, c.tab, env, c.env_type, c.E, c.Bm, c.Am, Omax,
-                     x0, out, act, reset, obs, reward, done);
+  int max_nj = 0;
+  for (int t = 0; t < c.n_types; ++t) max_nj = std::max(max_nj, (int)c.host_tab->type[t].nj);
+  const int n_rows = max_nj + 1;
+  hipLaunchKernelGGL(k_env, dim3(cdiv(c.E, 64), n_rows), dim3(64), 0, s, c.tab, env, c.env_type, c.E, c.Bm, c.Am,
+                     Omax, n_rows, x0, out, act, reset, obs, reward, done);
+  const hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_env_reset, dim3(cdiv((long)c.Bm * c.E, 256)), dim3(256), 0, s, c.E, c.Bm, done, out, reset);
   return hipGetLastError();
 }
 

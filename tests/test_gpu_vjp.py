@@ -275,6 +275,18 @@ def test_vjp_graph_replay_matches_eager():
             assert torch.equal(x, y), rep
         assert torch.equal(ref_a, ga)
         _ = torch.randn(1000, device="cuda").sum()
+    # the segment adjoint from a tape, replayed from its graph
+    A = acts_dev(acts[:6])
+    _, tape = sysg.rollout_tape(st, A)
+    ref_g, ref_a = sysg.rollout_vjp_tape(tape, A, go)
+    ga = torch.empty_like(ref_a)
+    for rep in range(3):
+        sysg.rollout_vjp_tape(tape, A, go, g_in=gi, g_acts=ga, flags=braxmi.BRAX_GRAPH)
+        torch.cuda.synchronize()
+        for x, y in zip(ref_g.fields(), gi.fields()):
+            assert torch.equal(x, y), rep
+        assert torch.equal(ref_a, ga)
+        _ = torch.randn(1000, device="cuda").sum()
 
 
 def _loss_grad_oracle(o, X0, acts, states=None):
