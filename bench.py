@@ -208,7 +208,7 @@ def main():
         loss = -(out_d.pos[0, 0] - d0.pos[0, 0]).sum() + 1e-3 * (A ** 2).sum()
         loss.backward()
         return A.grad
-    ms_vjp = time_calls(fwd_bwd, 1, 1)
+    ms_vjp = time_calls(fwd_bwd, 5, 2)
     fwd_vjp = wd.envs * wd.steps / (ms_vjp / 1e3)
     log(f"forward+VJP: {ms_vjp:.2f} ms per {wd.envs}x{wd.steps} rollout gradient, {fwd_vjp:.3e} env-steps/s")
 
@@ -287,7 +287,7 @@ def main():
         o2 = braxmi.rollout_grad(msys, m0, A, k=10)
         (o2.pos.sum() + 1e-3 * (A ** 2).sum()).backward()
         return A.grad
-    ms_mv = time_calls(mixed_fwd_bwd, 1, 1)
+    ms_mv = time_calls(mixed_fwd_bwd, 3, 1)
     extra["mixed_fwd_vjp_env_steps_per_s"] = len(types) * Tv / (ms_mv / 1e3)
     extra["mixed_workload"] = ("8192 environments: 2048 chains, 3277 quadrupeds, 2048 bipeds, 819 manipulators "
                                "(seeded permutation), reset pose, actions U(-1,1); forward 1000 steps, "
