@@ -646,7 +646,8 @@ bool all_one_axis(const LaunchCtx& c) {
 }
 
 // Whether a type of the batch has a body with more contact candidates than
-// the default held in registers: such batches take the kernels holding 8.
+// the default held in registers: one-axis such batches take the kernels
+// holding 8.
 bool many_contacts(const LaunchCtx& c) {
   for (int t = 0; t < c.n_types; ++t)
     if (c.host_tab->type[t].max_contacts > REG_CONTACTS) return true;
@@ -657,16 +658,18 @@ bool many_contacts(const LaunchCtx& c) {
 
 // Launches kernel template K<PAIRS, ONE_AXIS, REGC> with ONE_AXIS and REGC from
 // the batch (`c` in scope); the remaining arguments are hipLaunchKernelGGL's.
-#define LAUNCH_AXES(K, PAIRS, ...)                                   \
-  do {                                                               \
-    const bool one_ = all_one_axis(c), many_ = many_contacts(c);     \
-    if (one_ && many_)                                               \
-      hipLaunchKernelGGL((K<PAIRS, true, 8>), __VA_ARGS__);          \
-    else if (one_)                                                   \
+// Eight contact candidates are held in registers only for one-axis batches:
+// with three-axis joints the adjoint already fills the registers and the six
+// more candidates spill (a mixed batch's segment adjoint measured 774 us with
+// eight, 626 us with two), while a one-axis manipulator gains (388 -> 346 us).
+#define LAUNCH_AXES(K, PAIRS, ...)                                     \
+  do {                                                                 \
+    const bool one_ = all_one_axis(c);                                 \
+    if (one_ && many_contacts(c))                                      \
+      hipLaunchKernelGGL((K<PAIRS, true, 8>), __VA_ARGS__);            \
+    else if (one_)                                                     \
       hipLaunchKernelGGL((K<PAIRS, true, REG_CONTACTS>), __VA_ARGS__); \
-    else if (many_)                                                  \
-      hipLaunchKernelGGL((K<PAIRS, false, 8>), __VA_ARGS__);         \
-    else                                                             \
+    else                                                               \
       hipLaunchKernelGGL((K<PAIRS, false, REG_CONTACTS>), __VA_ARGS__); \
   } while (0)
 
