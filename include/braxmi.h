@@ -71,7 +71,7 @@ enum {
   BRAX_E_MODEL = -3,       /* parses but is not a valid system (see brax_sys_create) */
   BRAX_E_DEVICE = -4,      /* a HIP call failed */
   BRAX_E_NOMEM = -5,       /* device or host allocation failed */
-  BRAX_E_UNSUPPORTED = -6  /* valid request this build does not handle */
+  BRAX_E_UNSUPPORTED = -6  /* valid request the library does not handle */
 };
 
 enum {
