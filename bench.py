@@ -118,6 +118,25 @@ def cpu_baseline(s0, acts, system, budget_s=12.0, budget_1core_s=4.0):
     return full, one
 
 
+def segment_adjoint(n):
+    """The adjoint of one 10-step checkpoint segment of the differentiation
+    workload (1024 quadrupeds) from its tape (brax_rollout_vjp_tape), n times."""
+    wd = synth.WORKLOADS["quadruped_diff"]
+    dsys = braxmi.System(synth.system_text("quadruped"), wd.envs, device=0)
+    d0, dall = make_inputs(dsys, wd)
+    K = 10
+    acts = dall[:K].contiguous()
+    tape = torch.empty((K, dsys.tape_step_floats), dtype=torch.float32, device="cuda")
+    dsys.rollout_tape(d0, acts, tape=tape)
+    g = dsys.new_state()
+    for f in g.fields():
+        f.normal_()
+    gi = dsys.new_state()
+    gA = torch.empty((K, dsys.a_max, dsys.n_envs), dtype=torch.float32, device="cuda")
+    ms = time_calls(lambda: dsys.rollout_vjp_tape(tape, acts, g, g_in=gi, g_acts=gA), max(n, 1), 0)
+    log(f"segment adjoint: {ms * 1e3:.1f} us per {wd.envs}x{K} segment ({max(n, 1)} calls)")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,14 +146,21 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=100, help="env steps timed for the plain path")
     ap.add_argument("--schedule", default="auto",
                     help="fused launch shape 'ENVS_PER_WAVE,WAVES_PER_BLOCK' for the quadruped batch, or 'auto'")
-    ap.add_argument("--only", choices=["all", "fused"], default="all",
+    ap.add_argument("--only", choices=["all", "fused", "segment_adjoint"], default="all",
                     help="fused: time only the fused forward rollout (for profiler runs), after a 256 MiB "
-                         "device copy that calibrates the HBM byte counters")
+                         "device copy that calibrates the HBM byte counters; segment_adjoint: only the "
+                         "adjoint of one 10-step checkpoint segment of the differentiation workload from "
+                         "its tape, --steps times without warm-up (for profiler runs; the kernel trace gives "
+                         "its duration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the environments are independent and need no exchange); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
+
+    if args.only == "segment_adjoint":
+        segment_adjoint(args.steps)
+        return
 
     wl = synth.WORKLOADS["quadruped"]
     E, T = wl.envs, wl.steps
