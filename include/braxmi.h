@@ -183,7 +183,8 @@ int brax_rollout(const brax_sys* sys, const brax_state* in, const float* acts, i
  * T * brax_layout.tape_step_floats floats, step t at offset
  * t * tape_step_floats; its layout inside a step is the library's own
  * (wavefront-major, for coalesced access) and is read only by
- * brax_step_vjp_tape of the same sys. Fused path only: BRAX_PLAIN gives
+ * brax_step_vjp_tape and brax_rollout_vjp_tape of the same sys. Fused path
+ * only: BRAX_PLAIN gives
  * BRAX_E_UNSUPPORTED. The state results equal brax_rollout's. */
 int brax_rollout_tape(const brax_sys* sys, const brax_state* in, const float* acts, int32_t T, float* tape,
                       brax_state* out, int32_t flags, void* stream);
