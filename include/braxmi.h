@@ -184,8 +184,9 @@ int brax_rollout(const brax_sys* sys, const brax_state* in, const float* acts, i
  * t * tape_step_floats; its layout inside a step is the library's own
  * (wavefront-major, for coalesced access) and is read only by
  * brax_step_vjp_tape and brax_rollout_vjp_tape of the same sys. Fused path
- * only: BRAX_PLAIN gives
- * BRAX_E_UNSUPPORTED. The state results equal brax_rollout's. */
+ * only: BRAX_PLAIN gives BRAX_E_UNSUPPORTED. The states agree with
+ * brax_rollout's up to rounding (a separately compiled kernel, whose
+ * multiply-add fusions may differ); repeated calls give the same bits. */
 int brax_rollout_tape(const brax_sys* sys, const brax_state* in, const float* acts, int32_t T, float* tape,
                       brax_state* out, int32_t flags, void* stream);
 
