@@ -206,8 +206,9 @@ int brax_step_vjp_params(const brax_sys* sys, const brax_state* in, const float*
 
 /* Adjoint of one step from its tape (the tape_step_floats written by
  * brax_rollout_tape of the same sys for that step, with the same actions)
- * instead of recomputing the forward substeps: same outputs and kink
- * conventions as brax_step_vjp. g_in may not alias g_out. Fused path only. */
+ * instead of recomputing the forward substeps: the outputs and kink
+ * conventions of brax_step_vjp (equal up to rounding, the forward values
+ * coming from the taped kernel). g_in may not alias g_out. Fused path only. */
 int brax_step_vjp_tape(const brax_sys* sys, const float* tape, const float* act, const brax_state* g_out,
                        brax_state* g_in, float* g_act, int32_t flags, void* stream);
 
