@@ -7,9 +7,9 @@
  * Algorithm 1 — kinematic integration, then joint, actuator and collider
  * updates computed from the same qp, then the potential integrator (joint and
  * actuator updates, gravity) and the collision integrator (collider updates).
- * Joints are springs (Section 6.1), contacts are velocity-level impulses with
+ * Joints are springs (Section 7.1), contacts are velocity-level impulses with
  * Baumgarte stabilisation against the ground plane and between the colliders
- * of declared body pairs (Section 6.2), systems are
+ * of declared body pairs (Section 7.2), systems are
  * described in the ProtoBuf-like text of Appendix A, and the step is
  * differentiable (Sections 2 and 5.1.4).
  *
@@ -74,9 +74,12 @@ enum {
   BRAX_E_UNSUPPORTED = -6  /* valid request the library does not handle */
 };
 
+/* Kernel choice: BRAX_FUSED (or neither bit: the default) runs one
+ * persistent fused kernel, BRAX_PLAIN one launch per phase per substep;
+ * both bits together are BRAX_E_ARG. */
 enum {
-  BRAX_FUSED = 0,          /* default: one persistent fused kernel */
   BRAX_PLAIN = 1,          /* one launch per phase per substep (baseline) */
+  BRAX_FUSED = 2,          /* one persistent fused kernel (the default) */
   BRAX_GRAPH = 4,          /* capture the launch(es) in a HIP graph and replay it */
   BRAX_NONFINITE_FLAGS = 8 /* also write per-environment non-finite flags */
 };
@@ -103,6 +106,9 @@ typedef struct {
   int32_t n_params[BRAX_MAX_TYPES];    /* system parameters per type (brax_step_vjp_params) */
   int32_t p_max;                       /* the largest of n_params */
   int32_t n_pairs[BRAX_MAX_TYPES];     /* body-body contact candidates per type */
+  int64_t vjp_lds_bytes;               /* on-chip memory per wavefront of the fused brax_step_vjp */
+  int64_t vjp_params_lds_bytes;        /* the same for brax_step_vjp_params */
+  int64_t lds_limit;                   /* the device's per-workgroup limit (160 KiB for a host-only handle) */
 } brax_layout;
 
 /* Build a batch of n_envs environments from n_descs system descriptions.
@@ -158,7 +164,10 @@ int brax_step(const brax_sys* sys, const brax_state* in, const float* act, brax_
 /* Adjoint of brax_step (Sections 2 and 5.1.4: gradients through the step):
  * given g_out = dL/d(out), writes g_in = dL/d(in) and g_act = dL/d(act)
  * (overwritten, not accumulated) for the same function brax_step computes.
- * The forward substeps are recomputed inside. At kinks the one-sided
+ * The forward substeps are recomputed inside. The fused adjoint keeps their
+ * tape on chip (brax_layout.vjp_lds_bytes per wavefront); a batch whose
+ * tape exceeds lds_limit (many substeps) runs the per-phase adjoint of
+ * BRAX_PLAIN instead, whose tape lives in the handle's device workspace. At kinks the one-sided
  * conventions are: max(0,x)' = [x > 0]; the Coulomb cap is taken when
  * cap <= stop; clamp' = 1 and clip' = 1 on the closed interval;
  * contact activation and counts have zero derivative. g_in may not alias
@@ -200,7 +209,8 @@ int brax_rollout_tape(const brax_sys* sys, const brax_state* in, const float* ac
  * strength of every action (na), then the friction coefficient (1): n_params
  * = 4 nb + 5 nj + na + 1 entries; rows beyond them are zero. The gradient of
  * a loss summed over environments sharing the parameters is the sum over
- * E. Fused path only. */
+ * E. Fused path only; BRAX_E_UNSUPPORTED when brax_layout.vjp_params_lds_bytes
+ * exceeds lds_limit. */
 int brax_step_vjp_params(const brax_sys* sys, const brax_state* in, const float* act, const brax_state* g_out,
                          brax_state* g_in, float* g_act, float* g_params, int32_t flags, void* stream);
 

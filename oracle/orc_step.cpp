@@ -13,8 +13,8 @@
 //   * Section 3 — maximal coordinates: the only dynamic data per body are
 //     position, orientation, velocity and angular velocity (the QP); the
 //     update is symplectic (semi-implicit) Euler.
-//   * Section 6.1 "Spring Joints" — joints are stiff springs (with damping).
-//   * Section 6.2 "Collisions" — velocity-level contact impulses with
+//   * Section 7.1 "Spring Joints" — joints are stiff springs (with damping).
+//   * Section 7.2 "Collisions" — velocity-level contact impulses with
 //     Baumgarte stabilisation against the ground.
 //   * Appendix A — the system fields (mass, inertia, frozen axes, joint
 //     stiffness, offsets, angle limits, dt, substeps, gravity).
@@ -252,7 +252,7 @@ template <class T> JointFrame<T> joint_frame(const OrcSys& s, int j, const Deriv
   return f;
 }
 
-// Joint update (Algorithm 1, joint loop; Section 6.1 spring joints).
+// Joint update (Algorithm 1, joint loop; Section 7.1 spring joints).
 template <class T>
 void joint_apply(const OrcSys& s, int j, const Body<T>* B, const Derived<T>* D, const JointFrame<T>& fr, V3<T>* f,
                  V3<T>* t, Margins* mg) {
@@ -310,7 +310,7 @@ void actuator_apply(const OrcSys& s, int k, const T& a, const JointFrame<T>* fra
   t[P] = sub(t[P], tau);
 }
 
-// Collider update (Algorithm 1, collider loop; Section 6.2): one contact
+// Collider update (Algorithm 1, collider loop; Section 7.2): one contact
 // candidate against the ground plane z = 0 with normal +z.
 template <class T>
 void collider_apply(const OrcSys& s, int c, const Body<T>* B, const Derived<T>* D, double h, V3<T>* dv,
@@ -448,7 +448,7 @@ template <class T> T point_box(const V3<T>& p, const V3<T>& c, const M3<T>& R, c
   return T(-1.0) * (T(h[k]) - (sg > 0 ? qa[k] : T(-1.0) * qa[k]));
 }
 // One body-body contact candidate (the paper's collisions between colliders,
-// Section 6.2, with the impulse of the ground contact): closest features,
+// Section 7.2, with the impulse of the ground contact): closest features,
 // normal n from the second body to the first, depth; the velocity-level
 // normal impulse with restitution and Baumgarte term on the relative
 // velocity at the middle of the overlap, Coulomb friction from the same

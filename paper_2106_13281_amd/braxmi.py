@@ -21,7 +21,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbraxmi.so")
 
-BRAX_FUSED, BRAX_PLAIN, BRAX_GRAPH, BRAX_NONFINITE_FLAGS = 0, 1, 4, 8
+BRAX_PLAIN, BRAX_FUSED, BRAX_GRAPH, BRAX_NONFINITE_FLAGS = 1, 2, 4, 8
 MAX_TYPES = 8
 
 ERRORS = {-1: "BRAX_E_ARG", -2: "BRAX_E_PARSE", -3: "BRAX_E_MODEL", -4: "BRAX_E_DEVICE", -5: "BRAX_E_NOMEM",
@@ -52,7 +52,8 @@ class _Layout(C.Structure):
                 ("substeps", C.c_int32 * MAX_TYPES), ("dt", C.c_float * MAX_TYPES),
                 ("device", C.c_int32), ("nonfinite", C.c_void_p), ("tape_step_floats", C.c_int64),
                 ("n_params", C.c_int32 * MAX_TYPES), ("p_max", C.c_int32),
-                ("n_pairs", C.c_int32 * MAX_TYPES)]
+                ("n_pairs", C.c_int32 * MAX_TYPES),
+                ("vjp_lds_bytes", C.c_int64), ("vjp_params_lds_bytes", C.c_int64), ("lds_limit", C.c_int64)]
 
 
 EXPORTS = ("brax_sys_create", "brax_sys_destroy", "brax_sys_query", "brax_default_angles", "brax_default_qp",
@@ -191,6 +192,9 @@ class System:
         self.n_params = list(lay.n_params[:nt])
         self.p_max = lay.p_max
         self.n_pairs = list(lay.n_pairs[:nt])                      # body-body contact candidates
+        self.vjp_lds_bytes = lay.vjp_lds_bytes                     # on-chip tape of the fused adjoint
+        self.vjp_params_lds_bytes = lay.vjp_params_lds_bytes
+        self.lds_limit = lay.lds_limit
         self.dt = list(lay.dt[:nt])
         self.device = torch.device("cuda", device) if device >= 0 else None
         self._side = None  # second stream of the checkpointed backward (created on first use)

@@ -54,17 +54,29 @@ struct DeviceGuard {
 
 }  // namespace
 
+// A captured graph holds the addresses of every buffer its launches use, so
+// the key lists every device pointer of the call (all four fields of each
+// state, the actions, tapes and outputs, the workspace); a call that differs
+// in any of them captures a graph of its own.
 struct GraphKey {
-  int kind;  // 0 step, 1 rollout, 2 adjoint, 3 rollout with tape, 4 adjoint from a tape, 5 environment
-             // step, 6 adjoint with parameters, 7 adjoint of T steps from a tape
-  int flags, T, save_every;
-  const void* p[12];
+  int kind = 0;  // 0 step, 1 rollout, 2 adjoint, 3 rollout with tape, 4 adjoint from a tape, 5 environment
+                 // step, 6 adjoint with parameters, 7 adjoint of T steps from a tape
+  int flags = 0, T = 0, save_every = 0;
+  std::vector<const void*> p;
+  GraphKey(int kind_, int flags_, int T_, int save_every_ = 0)
+      : kind(kind_), flags(flags_), T(T_), save_every(save_every_) {}
+  GraphKey& add(const void* x) {
+    p.push_back(x);
+    return *this;
+  }
+  GraphKey& add(const brax_state* st) {
+    for (const void* x : {(const void*)(st ? st->pos : nullptr), (const void*)(st ? st->rot : nullptr),
+                          (const void*)(st ? st->vel : nullptr), (const void*)(st ? st->ang : nullptr)})
+      p.push_back(x);
+    return *this;
+  }
   bool operator<(const GraphKey& o) const {
-    if (kind != o.kind) return kind < o.kind;
-    if (flags != o.flags) return flags < o.flags;
-    if (T != o.T) return T < o.T;
-    if (save_every != o.save_every) return save_every < o.save_every;
-    return std::memcmp(p, o.p, sizeof p) < 0;
+    return std::tie(kind, flags, T, save_every, p) < std::tie(o.kind, o.flags, o.T, o.save_every, o.p);
   }
 };
 
@@ -79,6 +91,7 @@ struct brax_sys {
   int32_t* d_env_type = nullptr;
   int32_t* d_env_list = nullptr;
   int32_t* d_type_off = nullptr;
+  size_t lds_limit = LDS_LIMIT_GFX950;  // per-workgroup LDS of the device
   // fused schedule
   int envs_per_wave[MAXT] = {0};
   int waves_per_block = 1;
@@ -227,7 +240,9 @@ int run_maybe_graph(brax_sys* s, bool use_graph, const GraphKey& key, hipStream_
 }
 
 int check_flags(int32_t flags) {
-  if (flags & ~(BRAX_PLAIN | BRAX_GRAPH | BRAX_NONFINITE_FLAGS)) return fail(BRAX_E_ARG, "unknown flag bits 0x%x", flags);
+  if (flags & ~(BRAX_PLAIN | BRAX_FUSED | BRAX_GRAPH | BRAX_NONFINITE_FLAGS))
+    return fail(BRAX_E_ARG, "unknown flag bits 0x%x", flags);
+  if ((flags & BRAX_PLAIN) && (flags & BRAX_FUSED)) return fail(BRAX_E_ARG, "BRAX_PLAIN and BRAX_FUSED both set");
   return BRAX_OK;
 }
 
@@ -294,6 +309,11 @@ int brax_sys_create(const char* const* descs, int32_t n_descs, const int32_t* en
   s->device = device;
   DeviceGuard g(device);
   if (!g.ok) return fail(BRAX_E_DEVICE, "cannot select device %d", device);
+  {
+    int lds = 0;
+    HIP_TRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+    if (lds > 0) s->lds_limit = (size_t)lds;
+  }
   auto dmalloc = [&](void** p, size_t n) -> int {
     if (n == 0) n = 4;
     hipError_t e = hipMalloc(p, n);
@@ -372,6 +392,9 @@ int brax_sys_query(const brax_sys* s, brax_layout* out) {
   }
   out->device = s->device;
   out->nonfinite = s->d_nonfinite;
+  out->vjp_lds_bytes = (int64_t)vjp_lds_bytes(s->host_tab, s->n_types, false);
+  out->vjp_params_lds_bytes = (int64_t)vjp_lds_bytes(s->host_tab, s->n_types, true);
+  out->lds_limit = (int64_t)s->lds_limit;
   return BRAX_OK;
 }
 
@@ -402,6 +425,7 @@ int brax_step(const brax_sys* sys, const brax_state* in, const float* act, brax_
               void* stream) {
   brax_sys* s = const_cast<brax_sys*>(sys);
   if (!s) return fail(BRAX_E_ARG, "sys is NULL");
+  if (const int frc = check_flags(flags)) return frc;
   if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
   int rc = check_flags(flags);
   if (rc) return rc;
@@ -411,12 +435,8 @@ int brax_step(const brax_sys* sys, const brax_state* in, const float* act, brax_
   DeviceGuard g(s->device);
   hipStream_t st = (hipStream_t)stream;
   const bool nf = flags & BRAX_NONFINITE_FLAGS;
-  GraphKey key{};
-  key.kind = 0;
-  key.flags = flags;
-  key.T = 1;
-  const void* ptrs[] = {in->pos, in->rot, in->vel, in->ang, out->pos, out->rot, out->vel, out->ang, act};
-  std::memcpy(key.p, ptrs, sizeof ptrs);
+  GraphKey key(0, flags, 1);
+  key.add(in).add(out).add(act);
   return run_maybe_graph(s, flags & BRAX_GRAPH, key, st, [&](hipStream_t cs) -> int {
     LaunchCtx c = s->ctx();
     if (flags & BRAX_PLAIN) {
@@ -434,6 +454,7 @@ int brax_rollout(const brax_sys* sys, const brax_state* in, const float* acts, i
                  brax_state* traj, brax_state* out, int32_t flags, void* stream) {
   brax_sys* s = const_cast<brax_sys*>(sys);
   if (!s) return fail(BRAX_E_ARG, "sys is NULL");
+  if (const int frc = check_flags(flags)) return frc;
   if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
   if (T < 0) return fail(BRAX_E_ARG, "T must be >= 0");
   if (save_every < 0) return fail(BRAX_E_ARG, "save_every must be >= 0");
@@ -447,14 +468,8 @@ int brax_rollout(const brax_sys* sys, const brax_state* in, const float* acts, i
   hipStream_t st = (hipStream_t)stream;
   const bool nf = flags & BRAX_NONFINITE_FLAGS;
   Fields tr = (save_every > 0 && traj) ? F(traj) : Fields{nullptr, nullptr, nullptr, nullptr};
-  GraphKey key{};
-  key.kind = 1;
-  key.flags = flags;
-  key.T = T;
-  key.save_every = save_every;
-  const void* ptrs[] = {in->pos, in->rot, in->vel, in->ang, out->pos, out->rot, out->vel, out->ang, acts,
-                        tr.pos, tr.rot, tr.vel};
-  std::memcpy(key.p, ptrs, sizeof ptrs);
+  GraphKey key(1, flags, T, save_every);
+  key.add(in).add(out).add(acts).add(tr.pos).add(tr.rot).add(tr.vel).add(tr.ang);
   return run_maybe_graph(s, flags & BRAX_GRAPH, key, st, [&](hipStream_t cs) -> int {
     LaunchCtx c = s->ctx();
     if (T == 0) {
@@ -489,6 +504,7 @@ int brax_rollout_tape(const brax_sys* sys, const brax_state* in, const float* ac
                       brax_state* out, int32_t flags, void* stream) {
   brax_sys* s = const_cast<brax_sys*>(sys);
   if (!s) return fail(BRAX_E_ARG, "sys is NULL");
+  if (const int frc = check_flags(flags)) return frc;
   if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
   if (T < 0) return fail(BRAX_E_ARG, "T must be >= 0");
   if (flags & BRAX_PLAIN) return fail(BRAX_E_UNSUPPORTED, "the tape is written by the fused path only");
@@ -501,12 +517,8 @@ int brax_rollout_tape(const brax_sys* sys, const brax_state* in, const float* ac
   DeviceGuard g(s->device);
   hipStream_t st = (hipStream_t)stream;
   const bool nf = flags & BRAX_NONFINITE_FLAGS;
-  GraphKey key{};
-  key.kind = 3;
-  key.flags = flags;
-  key.T = T;
-  const void* ptrs[] = {in->pos, in->rot, in->vel, in->ang, out->pos, out->rot, out->vel, out->ang, acts, tape};
-  std::memcpy(key.p, ptrs, sizeof ptrs);
+  GraphKey key(3, flags, T);
+  key.add(in).add(out).add(acts).add(tape);
   return run_maybe_graph(s, flags & BRAX_GRAPH, key, st, [&](hipStream_t cs) -> int {
     LaunchCtx c = s->ctx();
     if (T == 0) {
@@ -548,6 +560,7 @@ int brax_env_step(const brax_sys* sys, const brax_state* in, const float* act, c
                   brax_state* out, float* obs, float* reward, uint8_t* done, int32_t flags, void* stream) {
   brax_sys* s = const_cast<brax_sys*>(sys);
   if (!s) return fail(BRAX_E_ARG, "sys is NULL");
+  if (const int frc = check_flags(flags)) return frc;
   if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
   if (!s->env_ready) return fail(BRAX_E_ARG, "brax_env_configure has not been called");
   if (flags & BRAX_PLAIN) return fail(BRAX_E_UNSUPPORTED, "the environment step runs on the fused path only");
@@ -561,12 +574,8 @@ int brax_env_step(const brax_sys* sys, const brax_state* in, const float* act, c
   DeviceGuard g(s->device);
   hipStream_t st = (hipStream_t)stream;
   const int omax = 11 + 2 * s->Dm;
-  GraphKey key{};
-  key.kind = 5;
-  key.flags = flags;
-  key.T = 1;
-  const void* ptrs[] = {in->pos, in->rot, act, reset->pos, reset->rot, out->pos, out->rot, obs, reward, done};
-  std::memcpy(key.p, ptrs, sizeof ptrs);
+  GraphKey key(5, flags, 1);
+  key.add(in).add(act).add(reset).add(out).add(obs).add(reward).add(done).add(s->d_env).add(s->d_env_x0);
   return run_maybe_graph(s, flags & BRAX_GRAPH, key, st, [&](hipStream_t cs) -> int {
     LaunchCtx c = s->ctx();
     HIP_TRY(launch_env_pre(c, s->d_env, F(in), s->d_env_x0, cs));
@@ -743,6 +752,7 @@ int brax_step_vjp(const brax_sys* sys, const brax_state* in, const float* act, c
                   brax_state* g_in, float* g_act, int32_t flags, void* stream) {
   brax_sys* s = const_cast<brax_sys*>(sys);
   if (!s) return fail(BRAX_E_ARG, "sys is NULL");
+  if (const int frc = check_flags(flags)) return frc;
   if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
   if (s->E == 0) return check_flags(flags);
   if (!state_ok(in) || !state_ok(g_out) || !state_ok(g_in)) return fail(BRAX_E_ARG, "state has a NULL field");
@@ -755,17 +765,14 @@ int brax_step_vjp(const brax_sys* sys, const brax_state* in, const float* act, c
   hipStream_t st = (hipStream_t)stream;
   if ((rc = vjp_reserve(s->vjp, s->host_tab, s->n_types, s->type_cnt, s->E, s->Bm)))
     return fail(BRAX_E_NOMEM, "adjoint workspace allocation failed");
-  GraphKey key{};
-  key.kind = 2;
-  key.flags = flags;
-  key.T = 1;
-  const void* ptrs[] = {in->pos, in->rot, in->vel, in->ang, act, g_out->pos, g_out->rot, g_out->vel, g_out->ang,
-                        g_in->pos, g_in->rot, g_act};
-  std::memcpy(key.p, ptrs, sizeof ptrs);
+  GraphKey key(2, flags, 1);
+  key.add(in).add(act).add(g_out).add(g_in).add(g_act).add(s->vjp.buf);
   return run_maybe_graph(s, flags & BRAX_GRAPH, key, st, [&](hipStream_t cs) -> int {
     LaunchCtx c = s->ctx();
     VjpSched sched{s->d_vjp_work, (int)s->vjp_work.size(), 1, s->d_jslot, s->d_cslot};
-    HIP_TRY(launch_vjp(c, s->vjp, sched, F(in), act, F(g_out), F(g_in), g_act, (flags & BRAX_PLAIN) != 0, cs));
+    // a tape that does not fit on chip: the per-phase adjoint, tape in the workspace
+    const bool plain = (flags & BRAX_PLAIN) || vjp_lds_bytes(s->host_tab, s->n_types, false) > s->lds_limit;
+    HIP_TRY(launch_vjp(c, s->vjp, sched, F(in), act, F(g_out), F(g_in), g_act, plain, cs));
     return BRAX_OK;
   });
 }
@@ -774,6 +781,7 @@ int brax_step_vjp_params(const brax_sys* sys, const brax_state* in, const float*
                          brax_state* g_in, float* g_act, float* g_params, int32_t flags, void* stream) {
   brax_sys* s = const_cast<brax_sys*>(sys);
   if (!s) return fail(BRAX_E_ARG, "sys is NULL");
+  if (const int frc = check_flags(flags)) return frc;
   if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
   if (flags & BRAX_PLAIN) return fail(BRAX_E_UNSUPPORTED, "parameter cotangents are computed on the fused path only");
   if (s->E == 0) return check_flags(flags);
@@ -781,6 +789,9 @@ int brax_step_vjp_params(const brax_sys* sys, const brax_state* in, const float*
   if (!act && s->Am > 0) return fail(BRAX_E_ARG, "act is NULL");
   if (!g_act && s->Am > 0) return fail(BRAX_E_ARG, "g_act is NULL");
   if (!g_params) return fail(BRAX_E_ARG, "g_params is NULL");
+  if (vjp_lds_bytes(s->host_tab, s->n_types, true) > s->lds_limit)
+    return fail(BRAX_E_UNSUPPORTED, "the parameter adjoint's on-chip tape (%zu bytes for %d substeps) exceeds the %zu-byte "
+                "workgroup limit", vjp_lds_bytes(s->host_tab, s->n_types, true), s->smax, s->lds_limit);
   if (g_in->pos == in->pos || g_in->pos == g_out->pos) return fail(BRAX_E_ARG, "g_in may not alias in or g_out");
   int rc = check_flags(flags);
   if (rc) return rc;
@@ -789,13 +800,8 @@ int brax_step_vjp_params(const brax_sys* sys, const brax_state* in, const float*
     p_max = std::max(p_max, 4 * s->host_tab.type[t].nb + 5 * s->host_tab.type[t].nj + s->host_tab.type[t].na + 1);
   DeviceGuard g(s->device);
   hipStream_t st = (hipStream_t)stream;
-  GraphKey key{};
-  key.kind = 6;
-  key.flags = flags;
-  key.T = 1;
-  const void* ptrs[] = {in->pos, in->rot, act, g_out->pos, g_out->rot, g_out->vel, g_out->ang, g_in->pos, g_in->rot,
-                        g_act, g_params};
-  std::memcpy(key.p, ptrs, sizeof ptrs);
+  GraphKey key(6, flags, 1);
+  key.add(in).add(act).add(g_out).add(g_in).add(g_act).add(g_params);
   return run_maybe_graph(s, flags & BRAX_GRAPH, key, st, [&](hipStream_t cs) -> int {
     LaunchCtx c = s->ctx();
     VjpSched sched{s->d_vjp_work, (int)s->vjp_work.size(), 1, s->d_jslot, s->d_cslot};
@@ -808,6 +814,7 @@ int brax_step_vjp_tape(const brax_sys* sys, const float* tape, const float* act,
                        brax_state* g_in, float* g_act, int32_t flags, void* stream) {
   brax_sys* s = const_cast<brax_sys*>(sys);
   if (!s) return fail(BRAX_E_ARG, "sys is NULL");
+  if (const int frc = check_flags(flags)) return frc;
   if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
   if (flags & BRAX_PLAIN) return fail(BRAX_E_UNSUPPORTED, "the tape adjoint runs on the fused path only");
   if (s->E == 0) return check_flags(flags);
@@ -820,12 +827,8 @@ int brax_step_vjp_tape(const brax_sys* sys, const float* tape, const float* act,
   if (rc) return rc;
   DeviceGuard g(s->device);
   hipStream_t st = (hipStream_t)stream;
-  GraphKey key{};
-  key.kind = 4;
-  key.flags = flags;
-  key.T = 1;
-  const void* ptrs[] = {tape, act, g_out->pos, g_out->rot, g_out->vel, g_out->ang, g_in->pos, g_in->rot, g_act};
-  std::memcpy(key.p, ptrs, sizeof ptrs);
+  GraphKey key(4, flags, 1);
+  key.add(tape).add(act).add(g_out).add(g_in).add(g_act);
   return run_maybe_graph(s, flags & BRAX_GRAPH, key, st, [&](hipStream_t cs) -> int {
     LaunchCtx c = s->ctx();
     VjpSched sched{s->d_vjp_work, (int)s->vjp_work.size(), 1, s->d_jslot, s->d_cslot};
@@ -838,6 +841,7 @@ int brax_rollout_vjp_tape(const brax_sys* sys, const float* tape, const float* a
                           const brax_state* g_out, brax_state* g_in, float* g_acts, int32_t flags, void* stream) {
   brax_sys* s = const_cast<brax_sys*>(sys);
   if (!s) return fail(BRAX_E_ARG, "sys is NULL");
+  if (const int frc = check_flags(flags)) return frc;
   if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
   if (flags & BRAX_PLAIN) return fail(BRAX_E_UNSUPPORTED, "the tape adjoint runs on the fused path only");
   if (T < 0) return fail(BRAX_E_ARG, "T < 0");
@@ -852,12 +856,8 @@ int brax_rollout_vjp_tape(const brax_sys* sys, const float* tape, const float* a
   DeviceGuard g(s->device);
   hipStream_t st = (hipStream_t)stream;
   const size_t tstride = (size_t)s->smax * s->vjp_work.size() * TAPE_N * 64;
-  GraphKey key{};
-  key.kind = 7;
-  key.flags = flags;
-  key.T = T;
-  const void* ptrs[] = {tape, acts, g_out->pos, g_out->rot, g_out->vel, g_out->ang, g_in->pos, g_in->rot, g_acts};
-  std::memcpy(key.p, ptrs, sizeof ptrs);
+  GraphKey key(7, flags, T);
+  key.add(tape).add(acts).add(g_out).add(g_in).add(g_acts);
   return run_maybe_graph(s, flags & BRAX_GRAPH, key, st, [&](hipStream_t cs) -> int {
     LaunchCtx c = s->ctx();
     if (T == 0) {

@@ -1,6 +1,6 @@
 // Body-body contacts in FP32 (device code; also compiles for the host).
 //
-// The paper's collisions between colliders (Section 6.2) with the impulse of
+// The paper's collisions between colliders (Section 7.2) with the impulse of
 // its ground contact: each candidate pairs a core feature of the first body
 // (a point, a segment, or a box; plus a radius) with one of the second body.
 // The closest points of the two features give the normal n (from the second

@@ -480,7 +480,7 @@ int build_system(const char* text, SystemDesc& d, std::string& err) {
     }
     if ((int)d.contacts.size() > MAXC) throw MErr{"more than 96 contact candidates"};
 
-    // body-body contacts (Section 6.2): every collider of the first body of a
+    // body-body contacts (Section 7.2): every collider of the first body of a
     // declared pair against every collider of the second; each collider is
     // reduced to a core feature plus a radius: a sphere to its centre, a
     // capsule to its axis segment, a box to itself (radius 0). A capsule

@@ -249,7 +249,7 @@ BXF JointGeo joint_geo(const JointT& J, const m3& RP, const m3& RC) {
   return joint_geo<MAXDOF>(J, RP, joint_child<MAXDOF>(J, none, RC));
 }
 
-// Spring joint (Section 6.1) from the parent's and the child's
+// Spring joint (Section 7.1) from the parent's and the child's
 // post-kinematic state. Force/torque on the child (fc, tc) and on the parent
 // (fp, tp):
 //   anchor spring-damper  F = k_lin (xP - xC) + c_lin (uP - uC), at each anchor;
@@ -313,7 +313,7 @@ BXF JointOut joint_eval(const JointT& J, const Body& P, const m3& RP, const Body
   return joint_eval<MAXDOF>(J, P, RP, C, joint_child<MAXDOF>(J, C, RC), a);
 }
 
-// One ground-contact candidate (Section 6.2): velocity-level normal impulse
+// One ground-contact candidate (Section 7.2): velocity-level normal impulse
 // with restitution and Baumgarte term, jn = max(0, -(1+e) vn + beta depth / h)
 // / kn, and a Coulomb friction impulse from the same pre-impulse state,
 // jt = min(mu jn, s / kt). Adds the velocity changes to dv, dw and returns

@@ -21,6 +21,15 @@ struct VjpSched {
   float* const* cslot;
 };
 
+// On-chip memory (LDS) per wavefront of the recomputing fused adjoint: its
+// forward tape of every substep (TAPE_N floats per lane, 3 more with the
+// parameter cotangents) plus the body-body candidate lists of batches that
+// have them.
+size_t vjp_lds_bytes(const Tables& tab, int n_types, bool params);
+// The largest LDS allocation of one workgroup on gfx950 (160 KiB), the limit
+// a host-only handle reports.
+constexpr size_t LDS_LIMIT_GFX950 = 160 * 1024;
+
 // 0 or BRAX_E_NOMEM.
 int vjp_reserve(VjpWork& w, const Tables& tab, int n_types, const int* type_cnt, int E, int Bm);
 void vjp_free(VjpWork& w);

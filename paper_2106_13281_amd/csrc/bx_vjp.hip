@@ -701,6 +701,16 @@ void vjp_free(VjpWork& w) {
   w.bytes = 0;
 }
 
+size_t vjp_lds_bytes(const Tables& tab, int n_types, bool params) {
+  size_t smax = 1;
+  bool pairs = false;
+  for (int t = 0; t < n_types; ++t) {
+    smax = std::max(smax, (size_t)tab.type[t].substeps);
+    pairs = pairs || tab.type[t].np > 0;
+  }
+  return smax * (TAPE_N + (params ? 3 : 0)) * 64 * sizeof(float) + (pairs ? sizeof(PairLanes) : 0);
+}
+
 hipError_t launch_vjp_params(const LaunchCtx& c, const VjpSched& sched, Fields in, const float* act, Fields g_out,
                              Fields g_in, float* g_act, float* g_params, int p_max, hipStream_t s) {
   if (sched.n_work == 0) return hipSuccess;

@@ -168,3 +168,42 @@ def test_body_contact_errors():
     assert host(star(15)).n_pairs == [15]
     two = 'bodies {{ name: "{n}" mass: 1 colliders {{ sphere {{ radius: 0.1 }} }} colliders {{ sphere {{ radius: 0.1 }} }} }}\n'
     expect(-3, star(9, two), match="more than 16 body-body")
+
+
+def test_flag_values_and_combinations():
+    """BRAX_PLAIN = 1, BRAX_FUSED = 2 (the default when neither is set),
+    BRAX_GRAPH = 4, BRAX_NONFINITE_FLAGS = 8; PLAIN with FUSED and unknown
+    bits are BRAX_E_ARG, checked before anything else of the call (here on a
+    batch of zero environments, which launches nothing)."""
+    text = open(HEADER).read()
+    for name, value in (("BRAX_PLAIN", 1), ("BRAX_FUSED", 2), ("BRAX_GRAPH", 4), ("BRAX_NONFINITE_FLAGS", 8)):
+        assert re.search(rf"\b{name}\s*=\s*{value}\b", text), name
+        assert getattr(braxmi, name) == value
+    L = braxmi.lib()
+    s = host(BODY.format(n="a"), 3)
+    st = braxmi._State()
+    for flags, msg in ((3, b"both set"), (16, b"unknown flag"), (2, b"host-only"), (0, b"host-only")):
+        assert L.brax_rollout(s._h, C.byref(st), None, 0, 0, None, C.byref(st), flags, None) == -1
+        assert msg in L.brax_last_error(), (flags, L.brax_last_error())
+        assert L.brax_step_vjp(s._h, C.byref(st), None, C.byref(st), C.byref(st), None, flags, None) == -1
+        assert msg in L.brax_last_error(), (flags, L.brax_last_error())
+
+
+def test_adjoint_tape_size_is_reported_against_the_lds_limit():
+    """The fused adjoint keeps each substep's tape on chip: 17 floats per lane
+    (20 with parameter cotangents) x 64 lanes per substep; the query reports
+    it beside the per-workgroup limit (160 KiB for a host-only handle), so a
+    system with many substeps is seen to exceed it (such batches take the
+    per-phase adjoint; the parameter adjoint refuses them)."""
+    few = "substeps: 10\n" + BODY.format(n="a")
+    many = "substeps: 200\n" + BODY.format(n="a")
+    s10, s200 = host(few), host(many)
+    assert s10.vjp_lds_bytes == 10 * 17 * 64 * 4
+    assert s10.vjp_params_lds_bytes == 10 * 20 * 64 * 4
+    assert s10.lds_limit == 160 * 1024
+    assert s10.vjp_lds_bytes <= s10.lds_limit
+    assert s200.vjp_lds_bytes == 200 * 17 * 64 * 4 > s200.lds_limit
+    # the bench and test systems all fit
+    for name in SYSTEMS:
+        s = host(synth.system_text(name))
+        assert s.vjp_params_lds_bytes <= s.lds_limit, name

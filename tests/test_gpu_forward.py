@@ -244,3 +244,52 @@ def test_autotune_keeps_results():
     after, _ = sysg.rollout(to_dev(X), a)
     for x, y in zip(before.fields(), after.fields()):
         assert torch.equal(x, y)
+
+
+def test_graph_cache_tells_apart_every_buffer():
+    """A replayed graph holds the addresses it was captured with: a call whose
+    pos/rot buffers match a cached graph but whose vel/ang (or actions, or
+    trajectory) buffers differ must capture its own graph. The new buffers
+    are written, the old ones keep what they hold."""
+    E = 40
+    o, X, acts = make_states("quadruped", E, seed=31, warm=5)
+    sysg = braxmi.System(synth.system_text("quadruped"), E)
+    a = acts_dev(acts[:2])
+    ref, _ = sysg.rollout(to_dev(X), a)
+    inp = to_dev(X)
+    out1 = sysg.new_state()
+    sysg.rollout(inp, a, out=out1, flags=braxmi.BRAX_GRAPH)
+    torch.cuda.synchronize()
+    # same pos/rot output buffers, fresh vel/ang
+    out2 = braxmi.State(out1.pos, out1.rot, torch.full_like(out1.vel, 7.0), torch.full_like(out1.ang, 7.0))
+    old_vel, old_ang = out1.vel.clone(), out1.ang.clone()
+    out1.vel.fill_(-3.0)
+    out1.ang.fill_(-3.0)
+    sysg.rollout(inp, a, out=out2, flags=braxmi.BRAX_GRAPH)
+    torch.cuda.synchronize()
+    for f1, f2 in zip(ref.fields(), out2.fields()):
+        assert torch.equal(f1, f2)
+    assert torch.equal(old_vel, ref.vel) and torch.equal(old_ang, ref.ang)
+    assert torch.all(out1.vel == -3.0) and torch.all(out1.ang == -3.0)
+    # same state buffers, a different action buffer with other values
+    a2 = acts_dev(acts[2:4])
+    ref2, _ = sysg.rollout(to_dev(X), a2)
+    sysg.rollout(inp, a2, out=out2, flags=braxmi.BRAX_GRAPH)
+    torch.cuda.synchronize()
+    for f1, f2 in zip(ref2.fields(), out2.fields()):
+        assert torch.equal(f1, f2)
+    # the adjoint: same g_in pos/rot, fresh g_in vel/ang
+    g = np.random.default_rng(32).normal(size=X.shape).astype(np.float32).astype(np.float64)
+    gi_ref, ga_ref = sysg.step_vjp(to_dev(X), a[0].contiguous(), to_dev(g))
+    gi1, ga1 = sysg.step_vjp(to_dev(X), a[0].contiguous(), to_dev(g), flags=braxmi.BRAX_GRAPH)
+    gi2 = braxmi.State(gi1.pos, gi1.rot, torch.zeros_like(gi1.vel), torch.zeros_like(gi1.ang))
+    gi1.vel.fill_(5.0)
+    gi1.ang.fill_(5.0)
+    inX, gout = to_dev(X), to_dev(g)
+    ga2 = torch.empty_like(ga1)
+    sysg.step_vjp(inX, a[0].contiguous(), gout, g_in=gi2, g_act=ga2, flags=braxmi.BRAX_GRAPH)
+    torch.cuda.synchronize()
+    for f1, f2 in zip(gi_ref.fields(), gi2.fields()):
+        assert torch.equal(f1, f2)
+    assert torch.equal(ga_ref, ga2)
+    assert torch.all(gi1.vel == 5.0) and torch.all(gi1.ang == 5.0)

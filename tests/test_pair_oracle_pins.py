@@ -155,3 +155,138 @@ def test_point_inside_box_uses_the_nearest_face():
     # the impulse pushes the sphere up (+z) and the box down
     Xn = o.step(X, np.zeros((1, 0)))
     assert Xn[0, 0, 9] > 0 and Xn[0, 1, 9] < 0 and abs(Xn[0, 0, 7]) < 1e-12
+
+
+def _two_spheres(mu, seed):
+    """Two free spheres (r 0.1 and 0.12, masses 2 and 3, isotropic inertia),
+    no gravity, overlapping by about 1 cm, approaching along the line of
+    centres and slipping across it, both spinning."""
+    o = oracle.Oracle(two_body("sphere", "sphere", e=0.0, mu=mu, beta=0.2, substeps=1, dt=0.002))
+    rng = np.random.default_rng(seed)
+    X = np.zeros((1, 2, 13))
+    X[0, :, 3:7] = Rotation.random(2, random_state=seed).as_quat()[:, [3, 0, 1, 2]]
+    n = rng.normal(size=3)
+    n /= np.linalg.norm(n)
+    X[0, 0, 0:3] = [0.0, 0.0, 5.0]
+    X[0, 1, 0:3] = X[0, 0, 0:3] - 0.21 * n              # n points from b to a
+    t = np.cross(n, rng.normal(size=3))
+    t /= np.linalg.norm(t)
+    X[0, 0, 7:10] = -0.8 * n + 1.5 * t
+    X[0, 1, 7:10] = 0.4 * n - 0.5 * t
+    X[0, :, 10:13] = rng.normal(0, 4.0, (2, 3))
+    return o, X
+
+
+def _contact_frame(Xn):
+    """Normal (from b to a), depth and the middle of the overlap, from the
+    post-kinematic positions (a step moves positions only in its kinematic
+    update, so the stepped state holds them)."""
+    pa, pb = Xn[0, 0, 0:3], Xn[0, 1, 0:3]
+    d = pa - pb
+    dist = np.linalg.norm(d)
+    n = d / dist
+    depth = 0.1 + 0.12 - dist
+    x = pb + (0.12 - depth / 2) * n
+    return n, depth, x
+
+
+def test_pair_sticking_friction_stops_the_slip_at_the_contact_point():
+    """Coulomb cone wide enough (mu = 10) that the tangential impulse is the
+    one that stops the slip: after the step the two spheres' velocities at
+    the contact point agree in the tangent plane. This holds only with the
+    tangential effective mass of both bodies, translations and rotations
+    (1/m_a + 1/m_b + (r_a x t).Ia^-1(r_a x t) + (r_b x t).Ib^-1(r_b x t)),
+    taken at the point where the impulse is applied (Sec. 7.2; the impulse
+    law of the ground contact, between two bodies)."""
+    for seed in range(6):
+        o, X = _two_spheres(10.0, seed)
+        Xn = o.step(X, np.zeros((1, 0)))
+        n, depth, x = _contact_frame(Xn)
+        assert depth > 0
+        ua = Xn[0, 0, 7:10] + np.cross(Xn[0, 0, 10:13], x - Xn[0, 0, 0:3])
+        ub = Xn[0, 1, 7:10] + np.cross(Xn[0, 1, 10:13], x - Xn[0, 1, 0:3])
+        u = ua - ub
+        ut = u - np.dot(u, n) * n
+        u0 = (X[0, 0, 7:10] + np.cross(X[0, 0, 10:13], x - Xn[0, 0, 0:3])
+              - X[0, 1, 7:10] - np.cross(X[0, 1, 10:13], x - Xn[0, 1, 0:3]))
+        assert np.linalg.norm(u0 - np.dot(u0, n) * n) > 0.5      # it was slipping
+        assert np.linalg.norm(ut) < 1e-13, (seed, ut)
+        assert np.dot(u, n) > -1e-12                             # no longer approaching
+
+
+def test_pair_sliding_friction_is_mu_times_the_normal_impulse_at_the_overlap_middle():
+    """Narrow cone (mu = 0.05): the impulse J on the first sphere has
+    tangential part exactly mu times its normal part, opposite to the slip;
+    both spheres' angular momenta change by r x (+-J) with the lever arms
+    ending at the middle of the overlap, |r_a| = r_a - depth/2 and
+    |r_b| = r_b - depth/2 (a contact point anywhere else along the normal
+    gives other angular changes)."""
+    m = np.array([2.0, 3.0])
+    I = np.array([0.05, 0.07])
+    for seed in range(6):
+        o, X = _two_spheres(0.05, seed)
+        Xn = o.step(X, np.zeros((1, 0)))
+        n, depth, x = _contact_frame(Xn)
+        J = m[0] * (Xn[0, 0, 7:10] - X[0, 0, 7:10])
+        assert np.abs(J + m[1] * (Xn[0, 1, 7:10] - X[0, 1, 7:10])).max() < 1e-13
+        jn = np.dot(J, n)
+        jt = J - jn * n
+        assert jn > 0
+        assert abs(np.linalg.norm(jt) - 0.05 * jn) < 1e-13 * jn, (seed, np.linalg.norm(jt) / jn)
+        u0 = (X[0, 0, 7:10] + np.cross(X[0, 0, 10:13], x - Xn[0, 0, 0:3])
+              - X[0, 1, 7:10] - np.cross(X[0, 1, 10:13], x - Xn[0, 1, 0:3]))
+        slip = u0 - np.dot(u0, n) * n
+        assert np.dot(jt, slip) < -0.999 * np.linalg.norm(jt) * np.linalg.norm(slip)
+        ra = -(0.1 - depth / 2) * n
+        rb = (0.12 - depth / 2) * n
+        assert np.abs(I[0] * (Xn[0, 0, 10:13] - X[0, 0, 10:13]) - np.cross(ra, J)).max() < 1e-13
+        assert np.abs(I[1] * (Xn[0, 1, 10:13] - X[0, 1, 10:13]) - np.cross(rb, -J)).max() < 1e-13
+
+
+SPHERE_ON_BOX = """substeps: 10
+dt: 0.05
+gravity {{ z: -9.81 }}
+friction: {mu}
+elasticity: 0
+baumgarte: 0.2
+bodies {{ name: "ball" mass: 1 inertia {{ x: 0.004 y: 0.004 z: 0.004 }}
+  colliders {{ sphere {{ radius: 0.1 }} }} }}
+bodies {{ name: "table" mass: 50 inertia {{ x: 1 y: 1 z: 1 }}
+  frozen {{ position {{ x: 1 y: 1 z: 1 }} rotation {{ x: 1 y: 1 z: 1 }} }}
+  colliders {{ box {{ halfsize {{ x: 1 y: 1 z: 0.1 }} }} }} }}
+body_contacts {{ first: "ball" second: "table" }}
+"""
+
+
+def test_sphere_sliding_on_a_frozen_box_rolls_at_the_lever_arm_speed():
+    """A solid ball (m 1 kg, r 0.1 m, I = 2/5 m r^2) resting on a frozen box
+    at the contact fixed point depth* = g h^2 / beta (h = 5 ms: the Baumgarte
+    impulse then cancels the substep's gravity exactly, as on the ground),
+    launched at v0 = 1 m/s without spin. While it slips its speed drops by
+    exactly mu g h per substep; then it rolls, and since the friction
+    impulse's angular momentum about the contact level is conserved, at
+    v = v0 m l^2 / (m l^2 + I) with the lever arm l = r - depth*/2 from the
+    centre to the middle of the overlap (l = r would give 5/7 v0: 0.714286;
+    here 0.711766), with w = v / l."""
+    g, h, beta, r, m, I, mu, v0 = 9.81, 0.005, 0.2, 0.1, 1.0, 0.004, 0.5, 1.0
+    o = oracle.Oracle(SPHERE_ON_BOX.format(mu=mu))
+    depth = g * h * h / beta
+    X = np.zeros((1, 2, 13))
+    X[0, :, 3] = 1.0
+    X[0, 1, 0:3] = [0.0, 0.0, 1.0]                      # top face at z = 1.1
+    X[0, 0, 0:3] = [-0.3, 0.0, 1.1 + r - depth]
+    X[0, 0, 7] = v0
+    Xs, tr, _ = o.rollout(X, np.zeros((6, 1, 0)), traj=True)
+    # first step (10 substeps): still slipping, exact Coulomb deceleration
+    assert abs(tr[0, 0, 0, 7] - (v0 - 10 * mu * g * h)) < 1e-12
+    ell = r - depth / 2
+    assert abs(tr[0, 0, 0, 11] - 10 * mu * m * g * h * ell / I) < 1e-10
+    # then rolling at the conserved angular momentum's speed
+    v_roll = v0 * m * ell ** 2 / (m * ell ** 2 + I)
+    for t in (3, 5):
+        assert abs(tr[t, 0, 0, 7] - v_roll) < 1e-12, (tr[t, 0, 0, 7], v_roll)
+        assert abs(tr[t, 0, 0, 11] - v_roll / ell) < 1e-10
+    assert abs(v_roll - 5.0 / 7.0) > 1e-3                 # the pin tells the contact points apart
+    # the normal direction stays at the fixed point; the table never moves
+    assert abs(Xs[0, 0, 2] - X[0, 0, 2]) < 1e-12 and abs(Xs[0, 0, 9]) < 1e-12
+    assert np.array_equal(Xs[0, 1], X[0, 1])
