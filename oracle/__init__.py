@@ -90,6 +90,8 @@ def lib():
         L.orc_step_jacobian.restype = C.c_int
         L.orc_count_flops.argtypes = [C.c_void_p, dp, dp]
         L.orc_count_flops.restype = C.c_int64
+        L.orc_count_vjp_flops.argtypes = [C.c_void_p, dp, dp]
+        L.orc_count_vjp_flops.restype = C.c_int64
         L.orc_quat_to_mat.argtypes = [dp, dp]
         L.orc_joint_angles.argtypes = [C.c_void_p, dp, dp, dp]
         L.orc_joint_forces.argtypes = [C.c_void_p, dp, dp, dp, dp]
@@ -244,6 +246,15 @@ class Oracle:
         if a.size == 0:
             a = np.zeros(1)
         return int(lib().orc_count_flops(C.byref(self._s), _ptr(X), _ptr(a)))
+
+    def count_vjp_flops(self, X, act):
+        """Floating-point operations of one reverse (adjoint) sweep through one
+        step of one environment (the forward pass not included)."""
+        X = np.ascontiguousarray(X, dtype=np.float64).reshape(self.nb, 13)
+        a = np.ascontiguousarray(act, dtype=np.float64).reshape(-1)
+        if a.size == 0:
+            a = np.zeros(1)
+        return int(lib().orc_count_vjp_flops(C.byref(self._s), _ptr(X), _ptr(a)))
 
     # ---------------------------------------------------------------- pieces
     def joint_angles(self, X):

@@ -12,9 +12,14 @@
 //   Counted   — a double that counts its floating-point operations
 //               (add/sub/mul/div/sqrt/atan2/asin each count one), used to
 //               measure the algorithmic work per environment step.
+//   Traced    — a double that records every operation on a state- or
+//               action-dependent value (a linear trace of the computation),
+//               used to count the operations of one reverse (adjoint) sweep
+//               through the step.
 #pragma once
 #include <cmath>
 #include <cstdint>
+#include <vector>
 
 namespace orc {
 
@@ -107,5 +112,52 @@ inline Counted oasin(Counted x) { ++g_flops; return Counted(std::asin(x.v)); }
 inline Counted ocos(Counted x) { ++g_flops; return Counted(std::cos(x.v)); }
 inline Counted osin(Counted x) { ++g_flops; return Counted(std::sin(x.v)); }
 inline Counted oatan2(Counted y, Counted x) { ++g_flops; return Counted(std::atan2(y.v, x.v)); }
+
+// ---------------------------------------------------------------- Traced
+// Each value computed from the inputs is a node of a thread-local trace:
+// (kind, up to two operand nodes; -1 marks a constant operand). Values built
+// from constants only are constants and are not recorded. Comparisons and
+// branches read the value and record nothing (a selected value passes
+// through), so the trace holds exactly the arithmetic the outputs depend on
+// along the branches taken.
+enum TraceOp : int8_t { T_LEAF, T_ADD, T_SUB, T_NEG, T_MUL, T_DIV, T_SQRT, T_ASIN, T_SIN, T_COS, T_ATAN2 };
+struct TraceNode {
+  int8_t op;
+  int32_t a, b;
+};
+extern thread_local std::vector<TraceNode>* g_trace;
+struct Traced {
+  double v;
+  int32_t id;
+  Traced() : v(0), id(-1) {}
+  Traced(double x) : v(x), id(-1) {}  // NOLINT
+};
+inline Traced trace_leaf(double x) {
+  Traced r(x);
+  r.id = (int32_t)g_trace->size();
+  g_trace->push_back(TraceNode{T_LEAF, -1, -1});
+  return r;
+}
+inline Traced trace_op(double v, TraceOp op, int32_t a, int32_t b) {
+  Traced r(v);
+  if (a >= 0 || b >= 0) {
+    r.id = (int32_t)g_trace->size();
+    g_trace->push_back(TraceNode{op, a, b});
+  }
+  return r;
+}
+inline double val(const Traced& a) { return a.v; }
+inline Traced operator+(Traced a, Traced b) { return trace_op(a.v + b.v, T_ADD, a.id, b.id); }
+inline Traced operator-(Traced a, Traced b) { return trace_op(a.v - b.v, T_SUB, a.id, b.id); }
+inline Traced operator-(Traced a) { return trace_op(-a.v, T_NEG, a.id, -1); }
+inline Traced operator*(Traced a, Traced b) { return trace_op(a.v * b.v, T_MUL, a.id, b.id); }
+inline Traced operator/(Traced a, Traced b) { return trace_op(a.v / b.v, T_DIV, a.id, b.id); }
+inline Traced& operator+=(Traced& a, Traced b) { a = a + b; return a; }
+inline Traced& operator-=(Traced& a, Traced b) { a = a - b; return a; }
+inline Traced osqrt(Traced x) { return trace_op(std::sqrt(x.v), T_SQRT, x.id, -1); }
+inline Traced oasin(Traced x) { return trace_op(std::asin(x.v), T_ASIN, x.id, -1); }
+inline Traced ocos(Traced x) { return trace_op(std::cos(x.v), T_COS, x.id, -1); }
+inline Traced osin(Traced x) { return trace_op(std::sin(x.v), T_SIN, x.id, -1); }
+inline Traced oatan2(Traced y, Traced x) { return trace_op(std::atan2(y.v, x.v), T_ATAN2, y.id, x.id); }
 
 }  // namespace orc

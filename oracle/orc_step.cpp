@@ -43,6 +43,7 @@
 namespace orc {
 
 thread_local int64_t g_flops = 0;
+thread_local std::vector<TraceNode>* g_trace = nullptr;
 
 enum { MAXB = 16, MAXJ = 16, MAXC = 96, MAXA = 48, MAXP = 32 };
 enum { PP, PS, SP, SS, PB, BP };  // body-body candidate: first body's feature vs the second's
@@ -667,6 +668,53 @@ int64_t orc_count_flops(const OrcSys* s, const double* X, const double* act) {
   g_flops = 0;
   step_env<Counted>(*s, Xc.data(), Ac.data(), nullptr);
   return g_flops;
+}
+
+// Floating-point operations of one reverse (adjoint) sweep through one
+// environment step from the given state: the step is traced on the Traced
+// scalar, the operations the outputs depend on are found by walking the
+// trace backwards from the output state, and each contributes the cost of
+// its adjoint rule (a fused multiply-add counts two):
+//   z = x +- y   1 per operand that depends on the inputs (accumulate z')
+//   z = x * y    2 per such operand (x' += z' y)
+//   z = x / y    1 for t = z'/y, then 1 if x depends on the inputs (x' += t),
+//                2 if y does (y' -= t z)
+//   sqrt 3 (x' += z' * 0.5/z), asin 6 (1/sqrt(1 - x^2), then x' += z' *
+//   that), sin and cos 3, atan2 4 (den = x^2 + y^2, t = z'/den) + 2 per
+//   operand that depends on the inputs; a sign flip is free.
+// This is the arithmetic of a reverse sweep over a stored forward pass; the
+// forward pass itself is counted by orc_count_flops.
+int64_t orc_count_vjp_flops(const OrcSys* s, const double* X, const double* act) {
+  std::vector<TraceNode> trace;
+  trace.reserve(1 << 16);
+  g_trace = &trace;
+  const int ns = s->nb * 13;
+  std::vector<Traced> Xt(ns), At(s->na > 0 ? s->na : 1);
+  for (int i = 0; i < ns; ++i) Xt[i] = trace_leaf(X[i]);
+  for (int i = 0; i < s->na; ++i) At[i] = trace_leaf(act[i]);
+  step_env<Traced>(*s, Xt.data(), At.data(), nullptr);
+  g_trace = nullptr;
+  std::vector<char> need(trace.size(), 0);
+  for (int i = 0; i < ns; ++i)
+    if (Xt[i].id >= 0) need[Xt[i].id] = 1;
+  int64_t n = 0;
+  for (int64_t k = (int64_t)trace.size() - 1; k >= 0; --k) {
+    if (!need[k]) continue;
+    const TraceNode& t = trace[k];
+    const int na = t.a >= 0, nb = t.b >= 0;
+    if (na) need[t.a] = 1;
+    if (nb) need[t.b] = 1;
+    switch (t.op) {
+      case T_ADD: case T_SUB: n += na + nb; break;
+      case T_MUL: n += 2 * (na + nb); break;
+      case T_DIV: n += 1 + na + 2 * nb; break;
+      case T_SQRT: case T_SIN: case T_COS: n += 3; break;
+      case T_ASIN: n += 6; break;
+      case T_ATAN2: n += 4 + 2 * (na + nb); break;
+      default: break;
+    }
+  }
+  return n;
 }
 
 // ---- single-phase entry points used by the pin tests ---------------------

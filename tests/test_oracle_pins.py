@@ -736,6 +736,34 @@ def test_flop_count_of_a_free_body_substep():
     assert o.count_flops(X, np.zeros(0)) == 54 + 39 + 144 + 63
 
 
+def test_reverse_sweep_count_of_a_free_body_substep():
+    """Reverse-sweep count of the same substep, by hand from the adjoint rules
+    (x +- y: 1 per input-dependent operand; x * y: 2 per such operand;
+    x / y: 1 + 1 (x) + 2 (y); sqrt 3; a constant operand costs nothing):
+
+    K: p += h v: 3 x (2 + 2) = 12; (0, w) (x) q: per component one product
+       with the constant 0 (2), three products of two inputs (4 each) and
+       three subtractions/additions (2 each) = 20, x 4 = 80; q + h/2 dq:
+       4 x (2 + 2) = 16; norm: 4 squares (4 each) + 3 adds (2) + sqrt 3 = 25;
+       4 divides (4 each) = 16                                        -> 149
+    D: R(q): diagonal 2 squares (8) + add (2) + 2* (2) + 1 - (1) = 13,
+       off-diagonal 2 products (8) + add/sub (2) + 2* (2) = 12      -> 111
+       R diag R^T: per entry 3 x (R d: 2, times R: 4) + 2 adds (4) = 22,
+       9 entries, two matrices                                        -> 396
+    P: v += h acc with a constant acc: 3 adds with one input operand (3);
+       Iw w 9 products (36) + 6 adds (12); cross 6 products (24) + 3 subs (6);
+       torque - gyro with a constant torque (3); Iwinv (.) 48; w += h alpha
+       3 x (2 + 2) = 12                                               -> 144
+    Three substeps cost three times one.
+    """
+    X = np.zeros((1, 13))
+    X[0, 3] = 1
+    o1 = oracle.Oracle("substeps: 1\ndt: 0.01\n" + FREE_BODY)
+    assert o1.count_vjp_flops(X, np.zeros(0)) == 149 + 111 + 396 + 144
+    o3 = oracle.Oracle("substeps: 3\ndt: 0.01\n" + FREE_BODY)
+    assert o3.count_vjp_flops(X, np.zeros(0)) == 3 * (149 + 111 + 396 + 144)
+
+
 def test_rollout_loss_gradient_matches_central_differences():
     """Differentiation workload (quadruped): the chained oracle adjoint of
     L = -(x_torso(T) - x_torso(0)) + 1e-3 sum |a|^2 against FP64 central
