@@ -25,8 +25,8 @@ import torch  # noqa: E402
 
 from paper_2106_13281_amd import braxmi, synth  # noqa: E402
 
-PEAK_FP32_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, no packed FP32
-PEAK_FP32_PACKED = 157.3    # with packed FP32 (not generated: disabled at build)
+PEAK_FP32_TFLOPS = 157.3    # published FP32 vector peak: 256 CU x 2.4 GHz x 256 FLOP/clock (packed FP32 FMA)
+ISSUE_FP32_TFLOPS = 78.6     # the same without packed FP32 (not generated: disabled at build)
 PEAK_HBM_GBS = 8000.0
 
 
@@ -34,9 +34,11 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def algorithmic_flops(name):
+def algorithmic_flops(name, key="mean"):
+    """Oracle-counted FLOP per environment step: the forward ("mean") or one
+    reverse sweep ("vjp_mean")."""
     with open(os.path.join(ROOT, "tests", "golden", "algorithmic_flops.json")) as f:
-        return json.load(f)["workloads"][name]["mean"]
+        return json.load(f)["workloads"][name][key]
 
 
 # the sources k_fused is compiled from (its translation unit and the headers it includes)
@@ -61,6 +63,17 @@ def measured_traffic():
         with open(os.path.join(ROOT, "paper_2106_13281_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return nbytes if h.hexdigest() == want else None
+
+
+def plain_bytes_per_env_substep(system, t=0):
+    """Bytes the plain per-phase kernels read and write per environment and
+    substep (FP32; 13 floats of state per body): kinematic 2x13 per body; joint
+    2x13 state + one action per axis + a 12-float slot per joint; contact 13
+    state + a 7-float slot per candidate; potential 2x13 state per body + the
+    6-float child or parent half of every joint's slot; collision 2x13 state
+    per body + every candidate's slot. = 312 nb + 200 nj + 4 D + 108 nc."""
+    nb, nj, nd, nc = system.n_bodies[t], system.n_joints[t], system.n_dof[t], system.n_contacts[t]
+    return 312 * nb + 200 * nj + 4 * nd + 108 * nc
 
 
 def make_inputs(system, wl, seed=0):
@@ -88,11 +101,13 @@ def time_calls(fn, reps, warmup):
     return e0.elapsed_time(e1) / reps
 
 
-def cpu_baseline(s0, acts, system, budget_s=12.0, budget_1core_s=4.0):
+def cpu_baseline(s0, acts, system, budget_s=4.0, budget_1core_s=1.5, reps=3):
     """The FP64 oracle on the host cores, on a bounded sample of the same
     workload (all environments, as many leading steps as fit the budget), and
-    on one core on a smaller sample."""
+    on one core on a smaller sample; built -O3 -march=native on this host,
+    each figure the median of `reps` timed runs."""
     import oracle
+    build_cmd = oracle.use_native()
     o = oracle.Oracle(synth.system_text("quadruped"))
     E = system.n_envs
     X = synth.from_soa(*(t.cpu().numpy() for t in s0.fields()), n_body=o.nb)
@@ -102,19 +117,28 @@ def cpu_baseline(s0, acts, system, budget_s=12.0, budget_1core_s=4.0):
     o.rollout(X, A[:2], threads=threads)
     per = (time.perf_counter() - t0) / (2 * E)          # seconds per env-step on all threads
     T = int(max(2, min(A.shape[0], budget_s / max(per * E, 1e-9))))
-    t0 = time.perf_counter()
-    o.rollout(X, A[:T], threads=threads)
-    dt = time.perf_counter() - t0
+
+    def median_time(fn):
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), ts
+
+    dt, ts = median_time(lambda: o.rollout(X, A[:T], threads=threads))
+    model = oracle.cpu_model()
     full = {"value": E * T / dt, "unit": "env-steps/s", "cores": threads, "kind": "oracle",
+            "cpu": model, "build": build_cmd,
             "sample": f"all {E} quadruped environments x first {T} of the {A.shape[0]} steps, FP64, "
-                      f"OpenMP over environments ({dt:.1f} s)"}
+                      f"OpenMP over environments on {threads} threads of {model}; median of {reps} runs "
+                      f"({', '.join(f'{x:.2f}' for x in ts)} s)"}
     n1 = min(E, 256)
     T1 = int(max(2, min(A.shape[0], budget_1core_s / max(per * threads * n1, 1e-9))))
-    t0 = time.perf_counter()
-    o.rollout(X[:n1], A[:T1, :n1], threads=1)
-    dt1 = time.perf_counter() - t0
-    one = {"value": n1 * T1 / dt1, "unit": "env-steps/s", "cores": 1, "kind": "oracle",
-           "sample": f"{n1} of the {E} quadruped environments x first {T1} steps, FP64, one thread ({dt1:.1f} s)"}
+    dt1, ts1 = median_time(lambda: o.rollout(X[:n1], A[:T1, :n1], threads=1))
+    one = {"value": n1 * T1 / dt1, "unit": "env-steps/s", "cores": 1, "kind": "oracle", "cpu": model,
+           "sample": f"{n1} of the {E} quadruped environments x first {T1} steps, FP64, one thread; median of "
+                     f"{reps} runs ({', '.join(f'{x:.2f}' for x in ts1)} s)"}
     return full, one
 
 
@@ -200,8 +224,11 @@ def main():
     ms_plain_g = time_calls(lambda: system.rollout(s0, acts[:Tp], out=out, flags=braxmi.BRAX_PLAIN | braxmi.BRAX_GRAPH),
                             1, 1)
     plain_g = E * Tp / (ms_plain_g / 1e3)
+    S = system.substeps[0]
+    plain_launches = 5 * S * Tp            # kinematic, joint, contact, potential, collision per substep
+    plain_bytes = plain_bytes_per_env_substep(system) * E * S * Tp
     log(f"plain forward: {ms_plain:.2f} ms per {Tp}-step rollout, {plain:.3e} env-steps/s; "
-        f"graph-replayed {ms_plain_g:.2f} ms")
+        f"graph-replayed {ms_plain_g:.2f} ms; {plain_bytes / (ms_plain / 1e3) / 1e9:.0f} GB/s")
 
     # environment layer after the step (reward, termination, auto-reset,
     # observation), single steps graph-replayed, ant-like parameters
@@ -322,6 +349,7 @@ def main():
         f"({ms_msg * 1e3:.1f} us graph); forward+VJP {ms_mv:.2f} ms")
 
     fpe = algorithmic_flops("quadruped")
+    vpe = algorithmic_flops("quadruped", "vjp_mean")
     achieved = fpe * E * T / (ms_fused / 1e3) / 1e12
     result = {
         "metric": "quadruped env-steps/s, fwd and fwd+VJP, fused vs plain kernels, 1 MI355X",
@@ -347,14 +375,22 @@ def main():
         "env_step_workload": f"quadruped {E} environments, single environment steps (step, reward, termination, "
                              f"auto-reset, observation) graph-replayed, {n_env_steps} steps",
         "fwd_vjp_env_steps_per_s": fwd_vjp,
-        "fwd_vjp_workload": f"quadruped {wd.envs} environments x {wd.steps} steps, checkpoints every 10 steps",
+        "fwd_vjp_frac": fwd_vjp * (fpe + vpe) / 1e12 / PEAK_FP32_TFLOPS,
+        "fwd_vjp_flop_per_env_step": fpe + vpe,
+        "fwd_vjp_workload": f"quadruped {wd.envs} environments x {wd.steps} steps, checkpoints every 10 steps; "
+                            f"algorithmic work per env-step = forward {fpe:.0f} + one reverse sweep {vpe:.0f} "
+                            f"FLOP (the checkpointed recompute is not counted)",
+        "plain_fwd_gbs": plain_bytes / (ms_plain / 1e3) / 1e9,
+        "plain_bytes_per_env_substep": plain_bytes_per_env_substep(system),
+        "plain_us_per_launch": ms_plain * 1e3 / plain_launches,
+        "plain_graph_us_per_launch": ms_plain_g * 1e3 / plain_launches,
         **extra,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
                      "kernel": "k_fused", "flop_per_env_step": fpe,
-                     "peak_note": "FP32 FMA issue rate without packed FP32 (disabled at build); "
-                                  f"frac vs the packed {PEAK_FP32_PACKED} TFLOP/s = "
-                                  f"{achieved / PEAK_FP32_PACKED:.4f}"},
+                     "peak_note": "published FP32 vector peak (packed FP32 FMA); packed FP32 is disabled at "
+                                  f"build, so the reachable issue rate is {ISSUE_FP32_TFLOPS} TFLOP/s: frac vs it = "
+                                  f"{achieved / ISSUE_FP32_TFLOPS:.4f}"},
     }
     if not args.no_cpu:
         result["cpu_baseline"], result["cpu_baseline_1core"] = cpu_baseline(s0, acts, system)

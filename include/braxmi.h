@@ -80,7 +80,10 @@ enum {
 enum {
   BRAX_PLAIN = 1,          /* one launch per phase per substep (baseline) */
   BRAX_FUSED = 2,          /* one persistent fused kernel (the default) */
-  BRAX_GRAPH = 4,          /* capture the launch(es) in a HIP graph and replay it */
+  BRAX_GRAPH = 4,          /* capture the launch(es) in a HIP graph and replay it; the graph is
+                              cached per call kind and set of buffer addresses. A call that is a
+                              single kernel launch (the fused paths) is launched directly, since
+                              replaying a one-node graph costs more than the launch itself */
   BRAX_NONFINITE_FLAGS = 8 /* also write per-environment non-finite flags */
 };
 

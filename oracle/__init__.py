@@ -30,8 +30,12 @@ _SRC = os.path.join(_HERE, "orc_step.cpp")
 _LIB = os.path.join(_HERE, "liborc.so")
 
 
+_LIB_NATIVE = os.path.join(_HERE, "liborc_native.so")
+
+
 def build(force=True):
-    """Compile the C++ stepper (plain -O2, OpenMP over environments)."""
+    """Compile the C++ stepper (plain -O2 for the build machine's baseline
+    instruction set, OpenMP over environments): the library the tests load."""
     if not force and os.path.exists(_LIB):
         return _LIB
     tmp = _LIB + f".tmp{os.getpid()}"
@@ -39,6 +43,33 @@ def build(force=True):
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB)
     return _LIB
+
+
+def use_native():
+    """Compile the stepper with -O3 -march=native for the machine this runs on
+    and load it in place of the portable build (for timing the oracle on the
+    host cores; the source is the same, only the compiler's choices differ,
+    e.g. fused multiply-adds). Returns the compile command."""
+    global _lib
+    tmp = _LIB_NATIVE + f".tmp{os.getpid()}"
+    cmd = ["g++", "-O3", "-march=native", "-std=c++17", "-fopenmp", "-shared", "-fPIC", _SRC, "-o", tmp]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_NATIVE)
+    _lib = None
+    lib(_LIB_NATIVE)
+    return " ".join(cmd[:5])
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or 'unknown'."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 class _OrcSys(C.Structure):
@@ -76,12 +107,13 @@ class _OrcSys(C.Structure):
 _lib = None
 
 
-def lib():
+def lib(path=None):
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        path = path or _LIB
+        if path == _LIB and not os.path.exists(_LIB):
             build()
-        L = C.CDLL(_LIB)
+        L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
         L.orc_sizeof_sys.restype = C.c_int
         L.orc_rollout.argtypes = [C.c_void_p, dp, dp, C.c_int, C.c_int, dp, dp, C.c_int]

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <set>
 #include <memory>
 #include <string>
 #include <tuple>
@@ -105,7 +106,6 @@ struct brax_sys {
   // environment layer (brax_env_configure)
   bool env_ready = false;
   EnvT* d_env = nullptr;
-  float* d_env_x0 = nullptr;
   // plain scratch per type
   float* d_jslot[MAXT] = {nullptr};
   float* d_cslot[MAXT] = {nullptr};
@@ -113,6 +113,7 @@ struct brax_sys {
   VjpWork vjp{};
   uint8_t* d_nonfinite = nullptr;
   std::map<GraphKey, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+  std::set<GraphKey> direct_keys;  // BRAX_GRAPH calls whose capture held one node: launched directly
 
   LaunchCtx ctx() const {
     LaunchCtx c{};
@@ -151,7 +152,6 @@ void free_all(brax_sys* s) {
     (void)hipFree(s->d_work);
     (void)hipFree(s->d_vjp_work);
     (void)hipFree(s->d_env);
-    (void)hipFree(s->d_env_x0);
     (void)hipFree(s->d_nonfinite);
     for (int t = 0; t < MAXT; ++t) {
       (void)hipFree(s->d_jslot[t]);
@@ -199,10 +199,13 @@ Fields F(const brax_state* st) { return Fields{st->pos, st->rot, st->vel, st->an
 bool state_ok(const brax_state* st) { return st && st->pos && st->rot && st->vel && st->ang; }
 
 // Run `body(stream)` directly, or capture it once per key into a HIP graph
-// and replay that graph.
+// and replay that graph. A capture that holds a single node (one fused
+// kernel) is not kept as a graph: replaying a one-node graph costs more than
+// launching its kernel, so such keys are remembered and run directly.
 template <class Fn>
 int run_maybe_graph(brax_sys* s, bool use_graph, const GraphKey& key, hipStream_t stream, Fn body) {
   if (!use_graph) return body(stream);
+  if (s->direct_keys.count(key)) return body(stream);
   auto it = s->graphs.find(key);
   if (it == s->graphs.end()) {
     hipStream_t cap = stream;
@@ -221,6 +224,14 @@ int run_maybe_graph(brax_sys* s, bool use_graph, const GraphKey& key, hipStream_
       return rc;
     }
     if (e != hipSuccess) return fail(BRAX_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    size_t n_nodes = 0;
+    e = hipGraphGetNodes(g, nullptr, &n_nodes);
+    if (e == hipSuccess && n_nodes <= 1) {
+      (void)hipGraphDestroy(g);
+      if (s->direct_keys.size() >= 64) s->direct_keys.clear();  // bounded
+      s->direct_keys.insert(key);
+      return body(stream);
+    }
     hipGraphExec_t x = nullptr;
     e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
@@ -547,9 +558,8 @@ int brax_env_configure(brax_sys* s, const brax_env_params* params) {
   DeviceGuard g(s->device);
   HIP_TRY(hipDeviceSynchronize());  // a running call may read the old parameters
   if (!s->d_env) {
-    hipError_t e1 = hipMalloc(&s->d_env, sizeof(EnvT) * MAXT);
-    hipError_t e2 = hipMalloc(&s->d_env_x0, sizeof(float) * std::max(s->E, 1));
-    if (e1 != hipSuccess || e2 != hipSuccess) return fail(BRAX_E_NOMEM, "environment-layer allocation failed");
+    if (hipMalloc(&s->d_env, sizeof(EnvT) * MAXT) != hipSuccess)
+      return fail(BRAX_E_NOMEM, "environment-layer allocation failed");
   }
   HIP_TRY(hipMemcpy(s->d_env, h, sizeof(EnvT) * MAXT, hipMemcpyHostToDevice));
   s->env_ready = true;
@@ -575,13 +585,11 @@ int brax_env_step(const brax_sys* sys, const brax_state* in, const float* act, c
   hipStream_t st = (hipStream_t)stream;
   const int omax = 11 + 2 * s->Dm;
   GraphKey key(5, flags, 1);
-  key.add(in).add(act).add(reset).add(out).add(obs).add(reward).add(done).add(s->d_env).add(s->d_env_x0);
+  key.add(in).add(act).add(reset).add(out).add(obs).add(reward).add(done).add(s->d_env);
   return run_maybe_graph(s, flags & BRAX_GRAPH, key, st, [&](hipStream_t cs) -> int {
     LaunchCtx c = s->ctx();
-    HIP_TRY(launch_env_pre(c, s->d_env, F(in), s->d_env_x0, cs));
-    HIP_TRY(launch_fused(c, s->d_work, (int)s->work.size(), s->waves_per_block, F(in), F(out), act, 1, 0,
-                         Fields{nullptr, nullptr, nullptr, nullptr}, (flags & BRAX_NONFINITE_FLAGS) != 0, cs));
-    HIP_TRY(launch_env(c, s->d_env, omax, s->d_env_x0, F(out), act, F(reset), obs, reward, done, cs));
+    HIP_TRY(launch_env_step(c, s->d_work, (int)s->work.size(), s->waves_per_block, s->d_env, omax, F(in), F(out), act,
+                            F(reset), obs, reward, done, (flags & BRAX_NONFINITE_FLAGS) != 0, cs));
     return BRAX_OK;
   });
 }

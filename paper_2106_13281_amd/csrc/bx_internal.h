@@ -108,13 +108,12 @@ hipError_t launch_fused(const LaunchCtx& c, const WaveWork* work, int n_work, in
 hipError_t launch_plain_step(const LaunchCtx& c, Fields in, Fields out, const float* act, float* const* jslot,
                              float* const* cslot, bool flags, hipStream_t s, float* tape = nullptr);
 hipError_t launch_copy_state(const LaunchCtx& c, Fields in, Fields out, hipStream_t s);
-// Environment layer: k_env_pre keeps each environment's root x before the
-// step (x0 [E]); after the step, k_env writes reward, done and the
-// observations [Omax][E] (of the reset state for finished environments),
-// then k_env_reset copies the reset state into finished environments.
-hipError_t launch_env_pre(const LaunchCtx& c, const EnvT* env, Fields in, float* x0, hipStream_t s);
-hipError_t launch_env(const LaunchCtx& c, const EnvT* env, int Omax, const float* x0, Fields out,
-                      const float* act, Fields reset, float* obs, float* reward, uint8_t* done, hipStream_t s);
+// One environment step with the environment layer fused after it, in one
+// launch: the fused step, then reward, done, the reset of finished
+// environments and the observations [Omax][E] of the final state.
+hipError_t launch_env_step(const LaunchCtx& c, const WaveWork* work, int n_work, int waves_per_block,
+                           const EnvT* env, int Omax, Fields in, Fields out, const float* act, Fields reset, float* obs,
+                           float* reward, uint8_t* done, bool flags, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, int n, uint8_t v, hipStream_t s);
 
 }  // namespace bx

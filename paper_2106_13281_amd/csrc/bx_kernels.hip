@@ -295,19 +295,33 @@ __global__ void k_plain_collision(const Tables* __restrict__ tab, int t, const i
 // fetches each child's reaction (fp, tp) in child order. State stays in
 // registers across all substeps and steps; only actions are read per step.
 
+// What the environment epilogue reads and writes (see brax_env_step).
+struct EnvArgs {
+  const EnvT* env;   // per type
+  Fields reset;      // reset state of every environment
+  float* obs;        // [Omax][E]
+  float* reward;     // [E]
+  uint8_t* done;     // [E]
+  int Omax;
+};
+
 // TAPE: also write each substep's tape record (state before the kinematic
 // update, total torque, count of applied contacts) to the wavefront-major
 // tape[step][sub][work item w of n_work][TAPE_N][64], for the adjoint that
 // reads it instead of recomputing the step.
 // REGC: contact candidates of a body kept in registers (the rest are read
 // from the table inside the loop).
-template <int MAXDOF, bool TAPE, bool PAIRS, int REGC = REG_CONTACTS>
+// ENV: after the step(s), the environment layer on the state in registers
+// (reward, termination, reset of finished environments, observation of the
+// final state), so that an environment step is one launch.
+template <int MAXDOF, bool TAPE, bool PAIRS, int REGC = REG_CONTACTS, bool ENV = false>
 __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const WaveWork& wk,
                                           const int32_t* __restrict__ env_list, const int32_t* __restrict__ type_off,
                                           int E, int Bm, const Fields& in, const Fields& out,
                                           const float* __restrict__ acts, int Am, int T, int save_every,
                                           const Fields& traj, uint8_t* nonfinite, float* __restrict__ tape,
-                                          int smax, int w, int n_work, PairLanes* pl = nullptr) {
+                                          int smax, int w, int n_work, PairLanes* pl = nullptr,
+                                          const EnvArgs* ea = nullptr) {
   const int t = wk.type;
   const TypeT ty = tab->type[t];
   const int nb = ty.nb;
@@ -330,6 +344,7 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
 
   if (PAIRS && ty.np > 0) pair_lanes_load(tab, t, pl, lane);
   Body s = load_body(in, b, e, Bm, E);
+  const float x_before = s.p.x;  // the environment layer's root progress
   // frozen velocity components zeroed once; every update below keeps them zero
   s.v = keep(s.v, B.free_p);
   s.w = keep(s.w, B.free_r);
@@ -417,15 +432,68 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
       ++n_save;
     }
   }
-  if (live) {
-    store_body(out, 0, s, b, e, Bm, E);
-    // padded body slots of a smaller system are written as zeros
-    for (int pb = nb + b; pb < Bm; pb += nb) zero_body(out, pb, e, Bm, E);
-  }
   if (nonfinite) {
     const unsigned long long bad = __ballot(live && !finite_body(s));
     const unsigned long long group = (nb >= 64) ? ~0ull : ((1ull << nb) - 1ull);
     if (live && b == 0) nonfinite[e] = ((bad >> base) & group) ? 1 : 0;
+  }
+  bool finished = false;
+  if (ENV) {
+    // reward and termination from the stepped state (the root's lane holds it)
+    const EnvT P = ea->env[t];
+    const int rl = base + P.root;
+    const float x0 = shfl(x_before, rl), x1 = shfl(s.p.x, rl), z1 = shfl(s.p.z, rl);
+    const bool healthy = z1 >= P.z_min && z1 <= P.z_max;
+    finished = !healthy;
+    // control cost: the squared actions as passed, summed over the
+    // environment's lanes in body order
+    float sq = 0.f;
+    for (int x = 0; x < MAXDOF; ++x) sq += raw_next[x] * raw_next[x];
+    float ctrl = 0.f;
+    for (int i = 0; i < nb; ++i) ctrl += shfl(sq, base + i);
+    if (live && b == P.root) {
+      ea->reward[e] = P.forward_weight * (x1 - x0) / ty.dt + (healthy ? P.healthy_reward : 0.f) - P.ctrl_cost * ctrl;
+      ea->done[e] = healthy ? 0 : 1;
+    }
+    // a finished environment continues from its reset state
+    if (finished && live) s = load_body(ea->reset, b, e, Bm, E);
+    // observation of the final state: joint angles and relative angular
+    // velocity about each Euler axis on the child's lane (the parent's
+    // rotation and angular velocity read across lanes), the root's entries
+    // and the padding on the root's lane
+    const m3 Rf = quat_to_mat(s.q);
+    m3 RPf;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) RPf.m[i] = shfl(Rf.m[i], src_parent);
+    const v3 wP = V(shfl(s.w.x, src_parent), shfl(s.w.y, src_parent), shfl(s.w.z, src_parent));
+    const JointGeo g = joint_geo<MAXDOF>(J, RPf, joint_child<MAXDOF>(J, s, Rf));
+    const v3 wrel = s.w - wP;
+    const int D = ty.ndof;
+    if (live && has_joint) {
+      for (int k = 0; k < MAXDOF; ++k) {
+        if (k < J.dof) {
+          ea->obs[(size_t)(11 + J.dof0 + k) * E + e] = g.th[k];
+          ea->obs[(size_t)(11 + D + J.dof0 + k) * E + e] = dot(wrel, g.ax[k]);
+        }
+      }
+    }
+    if (live && b == P.root) {
+      const float head[11] = {s.p.z, s.q.w, s.q.x, s.q.y, s.q.z, s.v.x, s.v.y, s.v.z, s.w.x, s.w.y, s.w.z};
+#pragma unroll
+      for (int k = 0; k < 11; ++k) ea->obs[(size_t)k * E + e] = head[k];
+      for (int k = 11 + 2 * D; k < ea->Omax; ++k) ea->obs[(size_t)k * E + e] = 0.f;
+    }
+  }
+  if (live) {
+    store_body(out, 0, s, b, e, Bm, E);
+    // padded body slots of a smaller system are written as zeros (a finished
+    // environment's as its reset state's)
+    for (int pb = nb + b; pb < Bm; pb += nb) {
+      if (ENV && finished)
+        store_body(out, 0, load_body(ea->reset, pb, e, Bm, E), pb, e, Bm, E);
+      else
+        zero_body(out, pb, e, Bm, E);
+    }
   }
 }
 
@@ -500,6 +568,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                              tape, smax, w, n_work, pl);
 }
 
+// One environment step with the environment layer fused after it (T = 1):
+// kernels of their own so that the epilogue's registers do not weigh on the
+// rollout kernels. PAIRS: batches with body-body candidates.
+template <bool PAIRS, int REGC>
+__global__ __launch_bounds__(256) void k_fused_env(const Tables* __restrict__ tab, const WaveWork* __restrict__ work,
+                                                   int n_work, const int32_t* __restrict__ env_list,
+                                                   const int32_t* __restrict__ type_off, int E, int Bm, Fields in,
+                                                   Fields out, const float* __restrict__ acts, int Am,
+                                                   uint8_t* nonfinite, EnvArgs ea) {
+  extern __shared__ PairLanes env_pair_lds[];  // one per wavefront of the block (PAIRS only)
+  const int w = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (w >= n_work) return;
+  const WaveWork wk = work[w];
+  PairLanes* pl = PAIRS ? env_pair_lds + (threadIdx.x >> 6) : nullptr;
+  const Fields none{nullptr, nullptr, nullptr, nullptr};
+  if (tab->type[wk.type].max_dof <= 1)
+    fused_run<1, false, PAIRS, REGC, true>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, 1, 0, none,
+                                           nonfinite, nullptr, 0, w, n_work, pl, &ea);
+  else
+    fused_run<3, false, PAIRS, REGC, true>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, 1, 0, none,
+                                           nonfinite, nullptr, 0, w, n_work, pl, &ea);
+}
+
 // ------------------------------------------------------------------ small helpers
 __global__ void k_copy_state(int n3, int n4, Fields in, Fields out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -514,110 +605,27 @@ __global__ void k_copy_state(int n3, int n4, Fields in, Fields out) {
 static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
 // ------------------------------------------------------------------ environment layer
-// One thread per environment (SoA reads coalesce over environments).
-__global__ void k_env_pre(const Tables* __restrict__ tab, const EnvT* __restrict__ env,
-                          const int32_t* __restrict__ env_type, int E, int Bm, Fields in, float* __restrict__ x0) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= E) return;
-  const int root = env[env_type[e]].root;
-  x0[e] = in.pos[(size_t)root * E + e];
-}
-
-// Locomotion reward, termination, reset and observation (Section 4.2):
-//   reward = forward_weight (x_root' - x_root) / dt + healthy_reward [healthy]
-//            - ctrl_cost sum_k a_k^2,  healthy = z_min <= z_root' <= z_max,
-//   done = not healthy; a finished environment takes its reset state; the
-//   observation of the (reset) state is [z_root, q_root, v_root, w_root,
-//   joint angles (D), (w_child - w_parent) . Euler axis (D)], zero-padded.
-// Grid: x over environments (coalesced SoA access), y over rows: row j <
-// n_rows - 1 writes the observation entries of joint j, the last row the
-// reward, termination, root entries and padding. Each thread decides
-// `healthy` itself from the stepped state and reads bodies from the reset
-// state when the environment finished; `out` is not written here (the reset
-// copy follows in k_env_reset), so every thread sees the same stepped state.
-__global__ void k_env(const Tables* __restrict__ tab, const EnvT* __restrict__ env,
-                      const int32_t* __restrict__ env_type, int E, int Bm, int Am, int Omax, int n_rows,
-                      const float* __restrict__ x0, Fields out, const float* __restrict__ act, Fields reset,
-                      float* __restrict__ obs, float* __restrict__ reward, uint8_t* __restrict__ done) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= E) return;
-  const int row = blockIdx.y;
-  const int t = env_type[e];
-  const TypeT& ty = tab->type[t];
-  const EnvT P = env[t];
-  const size_t BE = (size_t)Bm * E;
-  const float z1 = out.pos[2 * BE + (size_t)P.root * E + e];
-  const bool healthy = z1 >= P.z_min && z1 <= P.z_max;
-  const Fields src = healthy ? out : reset;  // the state the observation is of
-  auto load = [&](int b) {
-    const size_t i = (size_t)b * E + e;
-    Body s;
-    s.p = V(src.pos[i], src.pos[BE + i], src.pos[2 * BE + i]);
-    s.q = q4{src.rot[i], src.rot[BE + i], src.rot[2 * BE + i], src.rot[3 * BE + i]};
-    s.v = V(src.vel[i], src.vel[BE + i], src.vel[2 * BE + i]);
-    s.w = V(src.ang[i], src.ang[BE + i], src.ang[2 * BE + i]);
-    return s;
-  };
-  const int D = ty.ndof;
-  if (row < n_rows - 1) {
-    if (row >= ty.nj) return;
-    const JointT& J = tab->joint[t][row];
-    const Body Pb = load(J.parent), Cb = load(J.child);
-    const JointGeo g = joint_geo<3>(J, quat_to_mat(Pb.q), quat_to_mat(Cb.q));
-    const v3 wrel = Cb.w - Pb.w;
-    for (int k = 0; k < J.dof; ++k) {
-      obs[(size_t)(11 + J.dof0 + k) * E + e] = g.th[k];
-      obs[(size_t)(11 + D + J.dof0 + k) * E + e] = dot(wrel, g.ax[k]);
-    }
-    return;
+hipError_t launch_env_step(const LaunchCtx& c, const WaveWork* work, int n_work, int waves_per_block,
+                           const EnvT* env, int Omax, Fields in, Fields out, const float* act, Fields reset, float* obs,
+                           float* reward, uint8_t* done, bool flags, hipStream_t s) {
+  if (n_work == 0) return hipSuccess;
+  bool pairs = false, many_contacts = false;
+  for (int t = 0; t < c.n_types; ++t) {
+    pairs = pairs || c.host_tab->type[t].np > 0;
+    many_contacts = many_contacts || c.host_tab->type[t].max_contacts > REG_CONTACTS;
   }
-  const float x1 = out.pos[(size_t)P.root * E + e];
-  float ctrl = 0.f;
-  for (int k = 0; k < ty.na; ++k) {
-    const float a = act[(size_t)k * E + e];
-    ctrl += a * a;
-  }
-  reward[e] = P.forward_weight * (x1 - x0[e]) / ty.dt + (healthy ? P.healthy_reward : 0.f) - P.ctrl_cost * ctrl;
-  done[e] = healthy ? 0 : 1;
-  const Body r = load(P.root);
-  const float head[11] = {r.p.z, r.q.w, r.q.x, r.q.y, r.q.z, r.v.x, r.v.y, r.v.z, r.w.x, r.w.y, r.w.z};
-  for (int k = 0; k < 11; ++k) obs[(size_t)k * E + e] = head[k];
-  for (int k = 11 + 2 * D; k < Omax; ++k) obs[(size_t)k * E + e] = 0.f;
-}
-
-// A finished environment takes its reset state: one thread per (body slot,
-// environment) element, after k_env.
-__global__ void k_env_reset(int E, int Bm, const uint8_t* __restrict__ done, Fields out, Fields reset) {
-  const size_t BE = (size_t)Bm * E;
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= BE) return;
-  const int e = (int)(i % E);
-  if (!done[e]) return;
-  for (int c = 0; c < 3; ++c) {
-    out.pos[c * BE + i] = reset.pos[c * BE + i];
-    out.vel[c * BE + i] = reset.vel[c * BE + i];
-    out.ang[c * BE + i] = reset.ang[c * BE + i];
-  }
-  for (int c = 0; c < 4; ++c) out.rot[c * BE + i] = reset.rot[c * BE + i];
-}
-
-hipError_t launch_env_pre(const LaunchCtx& c, const EnvT* env, Fields in, float* x0, hipStream_t s) {
-  if (c.E == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_env_pre, dim3(cdiv(c.E, 256)), dim3(256), 0, s, c.tab, env, c.env_type, c.E, c.Bm, in, x0);
-  return hipGetLastError();
-}
-
-hipError_t launch_env(const LaunchCtx& c, const EnvT* env, int Omax, const float* x0, Fields out, const float* act,
-                      Fields reset, float* obs, float* reward, uint8_t* done, hipStream_t s) {
-  if (c.E == 0) return hipSuccess;
-  int max_nj = 0;
-  for (int t = 0; t < c.n_types; ++t) max_nj = std::max(max_nj, (int)c.host_tab->type[t].nj);
-  const int n_rows = max_nj + 1;
-  hipLaunchKernelGGL(k_env, dim3(cdiv(c.E, 64), n_rows), dim3(64), 0, s, c.tab, env, c.env_type, c.E, c.Bm, c.Am,
-                     Omax, n_rows, x0, out, act, reset, obs, reward, done);
-  const hipError_t err = hipGetLastError();
-  if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_env_reset, dim3(cdiv((long)c.Bm * c.E, 256)), dim3(256), 0, s, c.E, c.Bm, done, out, reset);
+  const dim3 grid(cdiv(n_work, waves_per_block)), block(64 * waves_per_block);
+  uint8_t* nf = flags ? c.nonfinite : nullptr;
+  const EnvArgs ea{env, reset, obs, reward, done, Omax};
+  if (pairs)
+    hipLaunchKernelGGL((k_fused_env<true, REG_CONTACTS>), grid, block, sizeof(PairLanes) * waves_per_block, s, c.tab,
+                       work, n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, act, c.Am, nf, ea);
+  else if (many_contacts)
+    hipLaunchKernelGGL((k_fused_env<false, 8>), grid, block, 0, s, c.tab, work, n_work, c.env_list, c.type_off, c.E,
+                       c.Bm, in, out, act, c.Am, nf, ea);
+  else
+    hipLaunchKernelGGL((k_fused_env<false, REG_CONTACTS>), grid, block, 0, s, c.tab, work, n_work, c.env_list,
+                       c.type_off, c.E, c.Bm, in, out, act, c.Am, nf, ea);
   return hipGetLastError();
 }
 

@@ -45,8 +45,9 @@ def check_env(o, X, a, R, p, out, obs, rew, done, mg, nb, D, Dm):
            | (np.abs(rew - ref_r) >= 2e-3 * scale_r)          # forward term: a position difference over dt
            | (np.abs(obs[:, :11 + D] - ref_obs[:, :11 + D]).max(1) >= 1e-4 * (1 + lo))
            | (np.abs(obs[:, 11 + D:] - ref_obs[:, 11 + D:]).max(1) >= 1e-3 * (1 + hi)))
+    print(f"  excused (ambiguous, over tolerance): {int(bad.sum())} of {len(bad)}", flush=True)
     assert not (bad & ~amb).any(), np.flatnonzero(bad & ~amb)
-    assert bad.mean() <= 0.1
+    assert bad.sum() <= 0.01 * len(bad)
     return ref_d
 
 

@@ -38,12 +38,14 @@ def report(tag, r, amb):
           f"all {r.max(0)} non-ambiguous {r[~amb].max(0) if (~amb).any() else 'n/a'}", flush=True)
 
 
-def check(r, amb, tol, frac=0.02):
+def check(r, amb, tol, frac=0.01):
     """Every environment meets `tol` unless it is branch-ambiguous; those
-    excused must be at most `frac` of the batch."""
+    excused must be at most `frac` of the batch (1%: the bar for
+    branch-ambiguous environments)."""
     bad = r.max(1) >= tol
+    print(f"  excused (branch-ambiguous, over tolerance): {int(bad.sum())} of {len(bad)}", flush=True)
     assert not (bad & ~amb).any(), r[bad & ~amb].max(0)
-    assert bad.mean() <= frac, (bad.sum(), len(bad))
+    assert bad.sum() <= frac * len(bad), (bad.sum(), len(bad))
 
 
 @pytest.mark.parametrize("name", SYSTEMS)
@@ -79,6 +81,24 @@ def test_step_matches_oracle(name, flags):
     r = rel_err(from_dev(out, o.nb), Xo)
     amb = ambiguous(mg, STEP_AMB)
     report(f"step {name} flags={flags}", r, amb)
+    check(r, amb, STEP_TOL)
+
+
+@pytest.mark.parametrize("flags", [braxmi.BRAX_FUSED, braxmi.BRAX_PLAIN])
+@pytest.mark.parametrize("name", ["chain", "quadruped", "biped"])
+def test_step_with_torque_actions_beyond_the_clip(name, flags):
+    """Torque actions drawn from U(-2, 2): about half of them lie outside
+    [-1, 1] and are clipped (Sec. 3 actuators; the clip of the torque law)."""
+    E = 157
+    o, X, _ = make_states(name, E, seed=13, warm=25)
+    a = synth.actions(13, 1, E, o.na, 2.0)[0]
+    assert (np.abs(a) > 1).mean() > 0.4
+    Xo, mg = o.step(X, a.astype(np.float64), margins=True)
+    sysg = braxmi.System(synth.system_text(synth.WORKLOADS[name].system), E)
+    out = sysg.step(to_dev(X), acts_dev(a[None])[0].contiguous(), flags=flags)
+    r = rel_err(from_dev(out, o.nb), Xo)
+    amb = ambiguous(mg, STEP_AMB)
+    report(f"step beyond clip {name} flags={flags}", r, amb)
     check(r, amb, STEP_TOL)
 
 
@@ -153,7 +173,7 @@ def test_ragged_env_counts(E):
     sysg = braxmi.System(synth.system_text("quadruped"), E)
     out = sysg.step(to_dev(X), acts_dev(acts[:1])[0].contiguous())
     r = rel_err(from_dev(out, o.nb), Xo)
-    check(r, ambiguous(mg, STEP_AMB), STEP_TOL, frac=1.0 if E < 50 else 0.02)
+    check(r, ambiguous(mg, STEP_AMB), STEP_TOL)
 
 
 def test_zero_envs():

@@ -30,10 +30,13 @@ def reset_inputs(system, wl, seed=0):
     return angles, torch.from_numpy(np.ascontiguousarray(root.T)), ang, root
 
 
-def check(r, amb, tol, frac=0.05):
+def check(r, amb, tol, frac=0.01):
+    """As in the forward parity tests: non-ambiguous environments meet `tol`;
+    the excused ones are at most 1% of the sample."""
     bad = r.max(1) >= tol
+    print(f"  excused (branch-ambiguous, over tolerance): {int(bad.sum())} of {len(bad)}", flush=True)
     assert not (bad & ~amb).any(), r[bad & ~amb].max(0)
-    assert bad.mean() <= frac, (bad.sum(), len(bad))
+    assert bad.sum() <= frac * len(bad), (bad.sum(), len(bad))
 
 
 @pytest.mark.parametrize("name", ["quadruped", "biped", "grasp"])
@@ -45,7 +48,7 @@ def test_full_size_workload_sampled_parity(name):
     sysg.autotune()
     angles, root, ang, rootn = reset_inputs(sysg, wl)
     s0 = sysg.default_qp(angles.cuda(), root.cuda())
-    sample = np.random.default_rng(30).choice(wl.envs, size=64, replace=False)
+    sample = np.random.default_rng(30).choice(wl.envs, size=200, replace=False)
     # reset pose
     X0s = from_dev(s0, s.nb, sample)
     Xo0 = np.stack([o.default_qp(s.default_angles() + ang[e].astype(np.float64), rootn[e].astype(np.float64))
@@ -61,7 +64,7 @@ def test_full_size_workload_sampled_parity(name):
     X30 = from_dev(s20, s.nb, sample)
     s31 = sysg.step(s20, A[30])
     Xo31, mg1 = o.step(X30, acts[30, sample].astype(np.float64), margins=True)
-    check(rel_err(from_dev(s31, s.nb, sample), Xo31), ambiguous(mg1, 1e-6), 1e-4, frac=0.02)
+    check(rel_err(from_dev(s31, s.nb, sample), Xo31), ambiguous(mg1, 1e-6), 1e-4)
 
 
 def test_full_size_quadruped_rollout_properties():
@@ -97,16 +100,16 @@ def test_full_size_mixed_batch_sampled_parity():
     rng = np.random.default_rng(31)
     for t, name in enumerate(synth.MIXED_TYPES):
         o = oracle.Oracle(descs[t])
-        idx = rng.choice(np.flatnonzero(types == t), size=16, replace=False)
+        idx = rng.choice(np.flatnonzero(types == t), size=200, replace=False)
         X0 = from_dev(s0, sysg.b_max, idx)[:, :o.nb]
         Xo0 = np.broadcast_to(o.default_qp(), X0.shape)
         assert rel_err(X0, Xo0).max() < 2e-6, name
         Xo20, _, mg = o.rollout(X0, acts[:20, idx, :o.na].astype(np.float64), margins=True)
         X20 = from_dev(s20, sysg.b_max, idx)
-        check(rel_err(X20[:, :o.nb], Xo20), ambiguous(mg, 1e-5), 1e-3, frac=0.25)
+        check(rel_err(X20[:, :o.nb], Xo20), ambiguous(mg, 1e-5), 1e-3)
         assert not X20[:, o.nb:].any()
         Xo21, mg1 = o.step(X20[:, :o.nb], acts[20, idx, :o.na].astype(np.float64), margins=True)
-        check(rel_err(from_dev(s21, sysg.b_max, idx)[:, :o.nb], Xo21), ambiguous(mg1, 1e-6), 1e-4, frac=0.1)
+        check(rel_err(from_dev(s21, sysg.b_max, idx)[:, :o.nb], Xo21), ambiguous(mg1, 1e-6), 1e-4)
 
 
 def test_full_size_differentiation_step_vjp_sampled():

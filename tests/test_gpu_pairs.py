@@ -56,10 +56,12 @@ def report(tag, r, amb, hit):
           f"max rel err (pos, rot, vel, ang) non-ambiguous {r[~amb].max(0) if (~amb).any() else 'n/a'}", flush=True)
 
 
-def check(r, amb, tol, frac=0.02):
+def check(r, amb, tol, frac=0.01):
+    """Non-ambiguous environments meet `tol`; the excused ones are at most 1%."""
     bad = r.max(1) >= tol
+    print(f"  excused (branch-ambiguous, over tolerance): {int(bad.sum())} of {len(bad)}", flush=True)
     assert not (bad & ~amb).any(), r[bad & ~amb].max(0)
-    assert bad.mean() <= frac, (bad.sum(), len(bad))
+    assert bad.sum() <= frac * len(bad), (bad.sum(), len(bad))
 
 
 def step_case(text, nb, seed, flags):
@@ -103,7 +105,7 @@ def test_pair_rollout_20_steps_matches_oracle(text, nb, seed):
     r = rel_err(from_dev(out, nb), Xo)
     amb = ambiguous(mg, ROLL_AMB)
     report(f"pair rollout20 nb={nb}", r, amb, np.zeros(E, bool))
-    check(r, amb, ROLL_TOL, frac=0.03)
+    check(r, amb, ROLL_TOL)
 
 
 def test_pairs_in_a_mixed_batch():
@@ -143,7 +145,7 @@ def test_pairs_in_a_mixed_batch():
         r = rel_err(Xg[idx, :nbs[t]], Xo)
         amb = ambiguous(mg, STEP_AMB)
         print(f"mixed type {t}: max non-ambiguous {r[~amb].max(0) if (~amb).any() else 'n/a'}", flush=True)
-        check(r, amb, STEP_TOL, frac=0.05)
+        check(r, amb, STEP_TOL)
         assert np.abs(Xg[idx, nbs[t]:]).max(initial=0.0) == 0.0   # padded body slots are zero
 
 
@@ -159,10 +161,11 @@ def normwise(got, ref):
     return np.linalg.norm(got - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), 1e-30)
 
 
-def check_grad(err, amb, frac=0.05):
+def check_grad(err, amb, frac=0.01):
     bad = err >= GRAD_TOL
+    print(f"  excused (ambiguous, over tolerance): {int(bad.sum())} of {len(bad)}", flush=True)
     assert not (bad & ~amb).any(), err[bad & ~amb]
-    assert bad.mean() <= frac
+    assert bad.sum() <= frac * len(bad)
 
 
 @pytest.mark.parametrize("flags", [braxmi.BRAX_FUSED, braxmi.BRAX_PLAIN])
@@ -217,5 +220,5 @@ def test_pair_vjp_from_tape_and_parameters(case):
     amb = mg.min(1) < 1e-5
     print(f"pair parameter vjp nb={nb}: P {pv.shape[1]} max err {err.max():.2e} ambiguous {int(amb.sum())}/{n}",
           flush=True)
-    check_grad(err, amb, frac=0.1)
+    check_grad(err, amb)
     assert normwise(from_dev(g_in, nb), from_dev(gr, nb)).max() < 1e-5

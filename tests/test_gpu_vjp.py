@@ -16,6 +16,10 @@ pytestmark = pytest.mark.gpu
 SYSTEMS = ("chain", "quadruped", "biped", "manipulator", "cheetah", "grasp")
 MIXED = synth.MIXED_TYPES      # the four types of the mixed batch
 GRAD_TOL = 1e-3
+# environments of the differentiation test whose 100-step FP64 gradient moves
+# by less than GRAD_TOL under FP32-level perturbations of the trajectory
+# (measured; the test fails if fewer qualify)
+STABLE_ENVS = 12
 
 
 def to_dev(X, b_max=None):
@@ -55,8 +59,38 @@ def test_step_vjp_matches_oracle(name, flags):
     print(f"vjp {name} flags={flags}: max err {err.max():.2e} non-ambiguous {err[~amb].max() if (~amb).any() else 0:.2e} "
           f"ambiguous {int(amb.sum())}/{E}", flush=True)
     bad = err >= GRAD_TOL
+    print(f"  excused (ambiguous, over tolerance): {int(bad.sum())} of {len(bad)}", flush=True)
     assert not (bad & ~amb).any(), err[bad & ~amb]
-    assert bad.mean() <= 0.05
+    assert bad.sum() <= 0.01 * len(bad)
+
+
+@pytest.mark.parametrize("flags", [braxmi.BRAX_FUSED, braxmi.BRAX_PLAIN])
+@pytest.mark.parametrize("name", ["chain", "quadruped", "biped"])
+def test_step_vjp_with_clipped_torque_actions(name, flags):
+    """Torque actions from U(-2, 2): a clipped action's cotangent is exactly
+    zero (clip' = 0 outside [-1, 1]); the rest match the oracle."""
+    E = 40
+    o, X, _ = make_states(name, E, seed=14, warm=15)
+    a = synth.actions(14, 1, E, o.na, 2.0)[0]
+    clipped = np.abs(a) > 1
+    assert clipped.mean() > 0.4
+    g = np.random.default_rng(15).normal(size=X.shape).astype(np.float32).astype(np.float64)
+    gi_o, ga_o = o.step_vjp(X, a.astype(np.float64), g)
+    assert not ga_o[clipped].any()
+    _, mg = o.step(X, a.astype(np.float64), margins=True)
+    sysg = braxmi.System(synth.system_text(synth.WORKLOADS[name].system), E)
+    g_in, g_act = sysg.step_vjp(to_dev(X), acts_dev(a[None])[0].contiguous(), to_dev(g), flags=flags)
+    gi = from_dev(g_in, o.nb)
+    ga = g_act.cpu().numpy().T[:, :o.na]
+    assert not ga[clipped].any()
+    err = normwise(np.concatenate([gi.reshape(E, -1), ga], 1), np.concatenate([gi_o.reshape(E, -1), ga_o], 1))
+    amb = mg.min(1) < 1e-6
+    print(f"vjp beyond clip {name} flags={flags}: max err {err.max():.2e} ambiguous {int(amb.sum())}/{E}",
+          flush=True)
+    bad = err >= GRAD_TOL
+    print(f"  excused (ambiguous, over tolerance): {int(bad.sum())} of {len(bad)}", flush=True)
+    assert not (bad & ~amb).any(), err[bad & ~amb]
+    assert bad.sum() <= 0.01 * len(bad)
 
 
 @pytest.mark.parametrize("name", SYSTEMS)
@@ -85,8 +119,9 @@ def test_step_vjp_from_tape_matches_oracle_and_recompute(name):
     amb = mg.min(1) < 1e-6
     print(f"vjp from tape {name}: max err {err.max():.2e} ambiguous {int(amb.sum())}/{E}", flush=True)
     bad = err >= GRAD_TOL
+    print(f"  excused (ambiguous, over tolerance): {int(bad.sum())} of {len(bad)}", flush=True)
     assert not (bad & ~amb).any(), err[bad & ~amb]
-    assert bad.mean() <= 0.05
+    assert bad.sum() <= 0.01 * len(bad)
     g_in2, g_act2 = sysg.step_vjp(to_dev(X), A[0].contiguous(), to_dev(g))
     ref = np.concatenate([from_dev(g_in2, o.nb).reshape(E, -1), g_act2.cpu().numpy().T], 1)
     got = np.concatenate([gi.reshape(E, -1), g_act.cpu().numpy().T], 1)
@@ -228,8 +263,9 @@ def test_step_vjp_params_matches_oracle(name):
     print(f"parameter vjp {name}: P {P} max err {err.max():.2e} non-ambiguous "
           f"{err[~amb].max() if (~amb).any() else 0:.2e} ambiguous {int(amb.sum())}/{E}", flush=True)
     bad = err >= GRAD_TOL
+    print(f"  excused (ambiguous, over tolerance): {int(bad.sum())} of {len(bad)}", flush=True)
     assert not (bad & ~amb).any(), err[bad & ~amb]
-    assert bad.mean() <= 0.1
+    assert bad.sum() <= 0.01 * len(bad)
     g_in2, g_act2 = sysg.step_vjp(to_dev(X), A, to_dev(g))
     got = np.concatenate([from_dev(g_in, o.nb).reshape(E, -1), g_act.cpu().numpy().T], 1)
     ref = np.concatenate([from_dev(g_in2, o.nb).reshape(E, -1), g_act2.cpu().numpy().T], 1)
@@ -369,14 +405,16 @@ def test_rollout_gradient_differentiation_workload():
         first 20 steps (two checkpoint segments), within 1e-3 for every
         environment.
     (c) End to end over all 100 steps, within 1e-3 for every environment
-        whose FP64 gradient moves by less than 1e-4 (a tenth of the
-        tolerance) when the trajectory is perturbed at FP32 rounding level at
-        every step. Over 100 steps with ground contacts such perturbations
-        shift contact activations across substeps and move the FP64 gradient
-        itself by up to several percent in some environments; those are
-        ill-conditioned for any FP32 forward pass and only reported.
+        whose FP64 gradient moves by less than 1e-3 when the trajectory is
+        perturbed at FP32 rounding level at every step (its sensitivity), and
+        within 1e-3 + 2 x sensitivity for every environment. Over 100 steps
+        with ground contacts such perturbations shift contact activations
+        across substeps and move the FP64 gradient itself by up to several
+        percent in some environments; no FP32 forward pass can match the FP64
+        gradient closer than that there. The number of environments under the
+        1e-3 sensitivity bar is pinned to the measured one.
     """
-    name, E, T, k, T0 = "quadruped", 8, 100, 10, 20
+    name, E, T, k, T0 = "quadruped", 16, 100, 10, 20
     wl = synth.WORKLOADS["quadruped_diff"]
     o = oracle.Oracle(synth.system_text(name))
     s = o.system
@@ -386,7 +424,7 @@ def test_rollout_gradient_differentiation_workload():
     acts = synth.actions(0, T, E, s.na, wl.act_range)
     ga_o = _loss_grad_oracle(o, X0, acts)
     cond = _jittered_sensitivity(o, X0, acts, ga_o)
-    stable = cond < 0.1 * GRAD_TOL
+    stable = cond < GRAD_TOL
     ga_o20 = _loss_grad_oracle(o, X0, acts[:T0])
     cond20 = _jittered_sensitivity(o, X0, acts[:T0], ga_o20)
 
@@ -413,10 +451,12 @@ def test_rollout_gradient_differentiation_workload():
     print(f"rollout gradient k={k}: T={T0} vs oracle {p(err20)} (FP64 sensitivity {p(cond20)}); "
           f"T={T} vs oracle {p(err)} (FP64 sensitivity {p(cond)}); "
           f"T={T} vs oracle adjoint along GPU trajectory {p(err_along)}", flush=True)
+    print(f"  environments under the sensitivity bar: {int(stable.sum())} of {E}", flush=True)
     assert err_along.max() < GRAD_TOL
     assert cond20.max() < 0.1 * GRAD_TOL and err20.max() < GRAD_TOL
     assert (err[stable] < GRAD_TOL).all()
-    assert stable.sum() >= 2
+    assert (err < GRAD_TOL + 2 * cond).all()
+    assert stable.sum() >= STABLE_ENVS
 
     # checkpoint spacing changes memory, not the result
     assert torch.equal(grad, _gpu_loss_grad(sysg, s0, acts, 1))
