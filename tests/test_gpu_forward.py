@@ -3,7 +3,9 @@
 All calls go through the C ABI (libbraxmi.so) via the Python binding; inputs
 are seeded synthetic states and actions shared with the oracle as FP32 arrays.
 Tolerances: 1e-4 relative per step from identical state, 1e-3 over 20-step
-rollouts, for environments that are not branch-ambiguous (see helpers).
+rollouts; single steps excuse only branch-ambiguous environments (at most
+1%), rollouts only environments where the oracle itself is FP32-sensitive
+(see helpers).
 """
 import numpy as np
 import pytest
@@ -11,13 +13,13 @@ import torch
 
 import oracle
 from paper_2106_13281_amd import braxmi, synth
-from tests.helpers import ambiguous, make_states, rel_err
+from tests.helpers import ambiguous, check_rollout, fp32_sensitivity, make_states, rel_err
 
 pytestmark = pytest.mark.gpu
 SYSTEMS = ("chain", "quadruped", "biped", "manipulator", "cheetah", "grasp")
 MIXED = synth.MIXED_TYPES      # the four types of the mixed batch
 STEP_TOL, ROLL_TOL = 1e-4, 1e-3
-STEP_AMB, ROLL_AMB = 1e-6, 1e-5
+STEP_AMB = 1e-6
 
 
 def to_dev(X, b_max=None):
@@ -107,13 +109,12 @@ def test_rollout_20_steps_matches_oracle(name):
     E = 96
     o, X, acts = make_states(name, E, seed=2, warm=20)
     T = 20
-    Xo, _, mg = o.rollout(X, acts[:T].astype(np.float64), margins=True)
+    Xo = o.rollout(X, acts[:T].astype(np.float64))[0]
     sysg = braxmi.System(synth.system_text(synth.WORKLOADS[name].system), E)
     out, _ = sysg.rollout(to_dev(X), acts_dev(acts[:T]))
     r = rel_err(from_dev(out, o.nb), Xo)
-    amb = ambiguous(mg, ROLL_AMB)
-    report(f"rollout20 {name}", r, amb)
-    check(r, amb, ROLL_TOL)
+    print(f"rollout20 {name}: envs {len(r)}, max rel err (pos, rot, vel, ang) {r.max(0)}", flush=True)
+    check_rollout(r, fp32_sensitivity(o, X, acts[:T], Xo), ROLL_TOL)
 
 
 @pytest.mark.parametrize("name", SYSTEMS)

@@ -6,7 +6,8 @@ several candidates, once with a free and once with a frozen hub. States are
 taken from the oracle's own trajectories just before each environment's
 first impact, rounded to FP32. Tolerances as for the ground contacts: 1e-4
 relative per step, 1e-3 over 20 steps, for environments that are not
-branch-ambiguous (see helpers).
+branch-ambiguous (single steps) or where the oracle itself is FP32-sensitive
+(rollouts; see helpers).
 """
 import numpy as np
 import pytest
@@ -14,12 +15,12 @@ import torch
 
 import oracle
 from paper_2106_13281_amd import braxmi, synth
-from tests.helpers import ambiguous, rel_err
+from tests.helpers import ambiguous, check_rollout, fp32_sensitivity, rel_err
 from tests.pair_scenes import CLUSTER_BODIES, KIND_PAIRS, approach, cluster, two_body
 
 pytestmark = pytest.mark.gpu
 STEP_TOL, ROLL_TOL = 1e-4, 1e-3
-STEP_AMB, ROLL_AMB = 1e-6, 1e-5
+STEP_AMB = 1e-6
 E = 157          # several wavefronts and a ragged tail
 
 
@@ -99,13 +100,12 @@ def test_cluster_step_matches_oracle(frozen, flags):
                          [(cluster(False), 5, 7), (cluster(True), 5, 7)])
 def test_pair_rollout_20_steps_matches_oracle(text, nb, seed):
     o, X = scene(text, nb, seed)
-    Xo, _, mg = o.rollout(X, np.zeros((20, E, 0)), margins=True)
+    Xo = o.rollout(X, np.zeros((20, E, 0)))[0]
     sysg = braxmi.System(text, E)
     out, _ = sysg.rollout(to_dev(X), no_acts(20, E))
     r = rel_err(from_dev(out, nb), Xo)
-    amb = ambiguous(mg, ROLL_AMB)
-    report(f"pair rollout20 nb={nb}", r, amb, np.zeros(E, bool))
-    check(r, amb, ROLL_TOL)
+    print(f"pair rollout20 nb={nb}: max rel err (pos, rot, vel, ang) {r.max(0)}", flush=True)
+    check_rollout(r, fp32_sensitivity(o, X, np.zeros((20, E, 0)), Xo), ROLL_TOL)
 
 
 def test_pairs_in_a_mixed_batch():
