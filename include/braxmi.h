@@ -180,6 +180,22 @@ int brax_step(const brax_sys* sys, const brax_state* in, const float* act, brax_
 int brax_step_vjp(const brax_sys* sys, const brax_state* in, const float* act, const brax_state* g_out,
                   brax_state* g_in, float* g_act, int32_t flags, void* stream);
 
+/* brax_step_vjp for callers that cannot allocate device memory (code being
+ * captured into a HIP graph, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, results and kernel choice, but the call
+ * allocates nothing. Where brax_step_vjp takes the per-phase adjoint
+ * (BRAX_PLAIN, or an on-chip tape beyond lds_limit), its workspace is a
+ * fixed 64 MiB device array of the library, one per GPU, held until the
+ * process ends, instead of the handle's workspace grown on demand; the fused
+ * adjoint needs none. Every call on one GPU shares that GPU's array (which
+ * keeps the last call's contents; nothing in it needs to start at zero), so
+ * calls that overlap on one GPU, from any handles or streams, race: run
+ * them one at a time. Errors: as brax_step_vjp; BRAX_E_UNSUPPORTED when the
+ * per-phase workspace the batch needs exceeds the 64 MiB; BRAX_E_ARG for
+ * BRAX_GRAPH (capture the call yourself instead). */
+int brax_step_vjp_noalloc(const brax_sys* sys, const brax_state* in, const float* act, const brax_state* g_out,
+                          brax_state* g_in, float* g_act, int32_t flags, void* stream);
+
 /* T consecutive steps with acts [T][Amax][E]. With save_every > 0, the state
  * after steps save_every, 2*save_every, ... is written to traj (each field
  * [T/save_every][C][Bmax][E]); traj may be NULL when save_every == 0. The

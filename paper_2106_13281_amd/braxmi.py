@@ -60,7 +60,7 @@ EXPORTS = ("brax_sys_create", "brax_sys_destroy", "brax_sys_query", "brax_defaul
            "brax_step", "brax_step_vjp", "brax_step_vjp_params", "brax_rollout", "brax_rollout_tape",
            "brax_step_vjp_tape", "brax_rollout_vjp_tape",
            "brax_env_configure", "brax_env_step", "brax_autotune", "brax_schedule", "brax_set_schedule",
-           "brax_nonfinite", "brax_last_error")
+           "brax_nonfinite", "brax_last_error", "brax_step_vjp_noalloc")
 
 _lib = None
 
@@ -83,6 +83,8 @@ def lib():
         L.brax_step.argtypes = [C.c_void_p, P(_State), C.c_void_p, P(_State), C.c_int32, C.c_void_p]
         L.brax_step_vjp.argtypes = [C.c_void_p, P(_State), C.c_void_p, P(_State), P(_State), C.c_void_p, C.c_int32,
                                     C.c_void_p]
+        L.brax_step_vjp_noalloc.argtypes = [C.c_void_p, P(_State), C.c_void_p, P(_State), P(_State), C.c_void_p,
+                                            C.c_int32, C.c_void_p]
         L.brax_rollout.argtypes = [C.c_void_p, P(_State), C.c_void_p, C.c_int32, C.c_int32, P(_State), P(_State),
                                    C.c_int32, C.c_void_p]
         L.brax_step_vjp_params.argtypes = [C.c_void_p, P(_State), C.c_void_p, P(_State), P(_State), C.c_void_p,
@@ -249,6 +251,16 @@ class System:
         si, sg, sgi = state.struct(), g_out.struct(), g_in.struct()
         _check(lib().brax_step_vjp(self._h, C.byref(si), _ptr(act), C.byref(sg), C.byref(sgi), _ptr(g_act), flags,
                                    _stream(stream)))
+        return g_in, g_act
+
+    def step_vjp_noalloc(self, state, act, g_out, g_in, g_act, flags=0, stream=None):
+        """step_vjp through brax_step_vjp_noalloc: the library allocates nothing
+        (the caller passes every output; the per-phase adjoint's workspace is the
+        library's fixed per-GPU array)."""
+        act = self._act(act, (self.a_max, self.n_envs))
+        si, sg, sgi = state.struct(), g_out.struct(), g_in.struct()
+        _check(lib().brax_step_vjp_noalloc(self._h, C.byref(si), _ptr(act), C.byref(sg), C.byref(sgi), _ptr(g_act),
+                                           flags, _stream(stream)))
         return g_in, g_act
 
     def step_vjp_params(self, state, act, g_out, g_in=None, g_act=None, g_params=None, flags=0, stream=None):

@@ -356,6 +356,8 @@ int brax_sys_create(const char* const* descs, int32_t n_descs, const int32_t* en
       return rc;
   }
   if ((rc = upload_work(s.get()))) return rc;
+  // the fixed workspace of brax_step_vjp_noalloc: its device address, once per device
+  if (noalloc_init(device) != 0) return fail(BRAX_E_DEVICE, "no device address for the fixed adjoint workspace");
   {
     int full[MAXT];
     for (int t = 0; t < n_descs; ++t) full[t] = std::max(1, 64 / s->host_tab.type[t].nb);
@@ -756,19 +758,35 @@ int brax_autotune(brax_sys* s, void* stream) {
   return rc;
 }
 
-int brax_step_vjp(const brax_sys* sys, const brax_state* in, const float* act, const brax_state* g_out,
-                  brax_state* g_in, float* g_act, int32_t flags, void* stream) {
-  brax_sys* s = const_cast<brax_sys*>(sys);
+namespace {
+
+// Argument checks shared by brax_step_vjp and brax_step_vjp_noalloc.
+int check_step_vjp(const brax_sys* s, const brax_state* in, const float* act, const brax_state* g_out,
+                   const brax_state* g_in, const float* g_act, int32_t flags) {
   if (!s) return fail(BRAX_E_ARG, "sys is NULL");
   if (const int frc = check_flags(flags)) return frc;
   if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
-  if (s->E == 0) return check_flags(flags);
+  if (s->E == 0) return BRAX_OK;
   if (!state_ok(in) || !state_ok(g_out) || !state_ok(g_in)) return fail(BRAX_E_ARG, "state has a NULL field");
   if (!act && s->Am > 0) return fail(BRAX_E_ARG, "act is NULL");
   if (!g_act && s->Am > 0) return fail(BRAX_E_ARG, "g_act is NULL");
   if (g_in->pos == in->pos || g_in->pos == g_out->pos) return fail(BRAX_E_ARG, "g_in may not alias in or g_out");
-  int rc = check_flags(flags);
-  if (rc) return rc;
+  return BRAX_OK;
+}
+
+// The adjoint takes the per-phase kernels (tape in a device workspace) for
+// BRAX_PLAIN or when the fused kernel's on-chip tape exceeds the device limit.
+bool vjp_takes_plain(const brax_sys* s, int32_t flags) {
+  return (flags & BRAX_PLAIN) || vjp_lds_bytes(s->host_tab, s->n_types, false) > s->lds_limit;
+}
+
+}  // namespace
+
+int brax_step_vjp(const brax_sys* sys, const brax_state* in, const float* act, const brax_state* g_out,
+                  brax_state* g_in, float* g_act, int32_t flags, void* stream) {
+  brax_sys* s = const_cast<brax_sys*>(sys);
+  int rc = check_step_vjp(s, in, act, g_out, g_in, g_act, flags);
+  if (rc || s->E == 0) return rc;
   DeviceGuard g(s->device);
   hipStream_t st = (hipStream_t)stream;
   if ((rc = vjp_reserve(s->vjp, s->host_tab, s->n_types, s->type_cnt, s->E, s->Bm)))
@@ -778,11 +796,34 @@ int brax_step_vjp(const brax_sys* sys, const brax_state* in, const float* act, c
   return run_maybe_graph(s, flags & BRAX_GRAPH, key, st, [&](hipStream_t cs) -> int {
     LaunchCtx c = s->ctx();
     VjpSched sched{s->d_vjp_work, (int)s->vjp_work.size(), 1, s->d_jslot, s->d_cslot};
-    // a tape that does not fit on chip: the per-phase adjoint, tape in the workspace
-    const bool plain = (flags & BRAX_PLAIN) || vjp_lds_bytes(s->host_tab, s->n_types, false) > s->lds_limit;
-    HIP_TRY(launch_vjp(c, s->vjp, sched, F(in), act, F(g_out), F(g_in), g_act, plain, cs));
+    HIP_TRY(launch_vjp(c, s->vjp, sched, F(in), act, F(g_out), F(g_in), g_act, vjp_takes_plain(s, flags), cs));
     return BRAX_OK;
   });
+}
+
+int brax_step_vjp_noalloc(const brax_sys* sys, const brax_state* in, const float* act, const brax_state* g_out,
+                          brax_state* g_in, float* g_act, int32_t flags, void* stream) {
+  const brax_sys* s = sys;
+  int rc = check_step_vjp(s, in, act, g_out, g_in, g_act, flags);
+  if (rc || s->E == 0) return rc;
+  if (flags & BRAX_GRAPH)
+    return fail(BRAX_E_ARG, "BRAX_GRAPH is not taken here (capturing allocates); capture the call yourself");
+  const bool plain = vjp_takes_plain(s, flags);
+  VjpWork w{};
+  if (plain) {
+    const size_t need = vjp_workspace_bytes(s->host_tab, s->n_types, s->type_cnt, s->E, s->Bm);
+    if (need > NOALLOC_WORKSPACE_BYTES)
+      return fail(BRAX_E_UNSUPPORTED, "the per-phase adjoint of this batch needs %zu bytes of workspace, more than "
+                  "the fixed %zu", need, NOALLOC_WORKSPACE_BYTES);
+    w.buf = noalloc_workspace(s->device);
+    if (!w.buf) return fail(BRAX_E_DEVICE, "no fixed adjoint workspace on device %d", s->device);
+    w.bytes = NOALLOC_WORKSPACE_BYTES;
+  }
+  DeviceGuard g(s->device);
+  LaunchCtx c = s->ctx();
+  VjpSched sched{s->d_vjp_work, (int)s->vjp_work.size(), 1, s->d_jslot, s->d_cslot};
+  HIP_TRY(launch_vjp(c, w, sched, F(in), act, F(g_out), F(g_in), g_act, plain, (hipStream_t)stream));
+  return BRAX_OK;
 }
 
 int brax_step_vjp_params(const brax_sys* sys, const brax_state* in, const float* act, const brax_state* g_out,

@@ -30,9 +30,18 @@ size_t vjp_lds_bytes(const Tables& tab, int n_types, bool params);
 // a host-only handle reports.
 constexpr size_t LDS_LIMIT_GFX950 = 160 * 1024;
 
+// Bytes of device workspace the per-phase adjoint of a batch needs.
+size_t vjp_workspace_bytes(const Tables& tab, int n_types, const int* type_cnt, int E, int Bm);
 // 0 or BRAX_E_NOMEM.
 int vjp_reserve(VjpWork& w, const Tables& tab, int n_types, const int* type_cnt, int E, int Bm);
 void vjp_free(VjpWork& w);
+// The fixed device workspace of brax_step_vjp_noalloc (64 MiB per GPU).
+constexpr size_t NOALLOC_WORKSPACE_BYTES = size_t(64) << 20;
+// With `device` current: look up (once per device) the device address of the
+// fixed workspace. 0, or -1 when the lookup fails.
+int noalloc_init(int device);
+// That address (nullptr before noalloc_init succeeded on the device).
+float* noalloc_workspace(int device);
 // g_in <- d(step)/d(in)^T g_out, g_act <- d(step)/d(act)^T g_out (both overwritten).
 hipError_t launch_vjp(const LaunchCtx& c, VjpWork& w, const VjpSched& sched, Fields in, const float* act,
                       Fields g_out, Fields g_in, float* g_act, bool plain, hipStream_t s);

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "bx_access.h"
 #include "bx_adj.h"
@@ -673,7 +674,7 @@ bool many_contacts(const LaunchCtx& c) {
       hipLaunchKernelGGL((K<PAIRS, false, REG_CONTACTS>), __VA_ARGS__); \
   } while (0)
 
-int vjp_reserve(VjpWork& w, const Tables& tab, int n_types, const int* type_cnt, int E, int Bm) {
+size_t vjp_workspace_bytes(const Tables& tab, int n_types, const int* type_cnt, int E, int Bm) {
   size_t smax = 1;
   size_t per_type = 0;
   for (int t = 0; t < n_types; ++t) {
@@ -683,7 +684,11 @@ int vjp_reserve(VjpWork& w, const Tables& tab, int n_types, const int* type_cnt,
                       26 * (size_t)tab.type[t].np);
   }
   const size_t nbe = (size_t)Bm * std::max(E, 1);
-  const size_t need = (smax * TAPE_N + 13 + 13 + 6 + 6) * nbe + per_type + 64;
+  return ((smax * TAPE_N + 13 + 13 + 6 + 6) * nbe + per_type + 64) * sizeof(float);
+}
+
+int vjp_reserve(VjpWork& w, const Tables& tab, int n_types, const int* type_cnt, int E, int Bm) {
+  const size_t need = vjp_workspace_bytes(tab, n_types, type_cnt, E, Bm) / sizeof(float);
   if (w.buf && w.bytes >= need * sizeof(float)) return 0;
   vjp_free(w);
   if (hipMalloc(&w.buf, need * sizeof(float)) != hipSuccess) {
@@ -693,6 +698,38 @@ int vjp_reserve(VjpWork& w, const Tables& tab, int n_types, const int* type_cnt,
   }
   w.bytes = need * sizeof(float);
   return 0;
+}
+
+// Workspace of the adjoint for callers that cannot allocate
+// (brax_step_vjp_noalloc): a device array of fixed size in the library's code
+// object, one copy per GPU, held until the process ends. Host code never
+// passes `scratch` itself to a kernel (on the host the name stands for a
+// host-side shadow, not a device address): noalloc_init looks up the
+// device's own address once per device and every use goes through it.
+static __device__ __align__(256) float scratch[NOALLOC_WORKSPACE_BYTES / sizeof(float)];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[MAX_DEVICES] = {nullptr};
+}  // namespace
+
+int noalloc_init(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return -1;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return 0;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != device) return -1;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return -1;
+  g_scratch_ptr[device] = static_cast<float*>(p);
+  return 0;
+}
+
+float* noalloc_workspace(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
 }
 
 void vjp_free(VjpWork& w) {
