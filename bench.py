@@ -309,7 +309,8 @@ def main():
     ms_g = time_calls(lambda: gsys.rollout(g0, gacts, out=gout), args.steps, args.warmup)
     extra["grasp_fwd_env_steps_per_s"] = wg.envs * wg.steps / (ms_g / 1e3)
     extra["grasp_fwd_frac"] = algorithmic_flops("grasp") * wg.envs * wg.steps / (ms_g / 1e3) / 1e12 / PEAK_FP32_TFLOPS
-    extra["grasp_workload"] = (f"manipulator with four finger-box body-body candidates, box within reach, "
+    extra["grasp_workload"] = (f"manipulator with six finger-box body-body candidates (each finger capsule's two ends "
+                               f"and axis segment), box within reach, "
                                f"{wg.envs} environments x {wg.steps} steps, actions U(-1,1)")
     log(f"grasp forward: {ms_g:.2f} ms per {wg.envs}x{wg.steps} rollout")
 

@@ -125,7 +125,10 @@ typedef struct {
  *   collide with each other: each collider is reduced to a core feature (a
  *   sphere's centre, a capsule's axis segment, a box) plus a radius, every
  *   collider of the first body is paired with every one of the second, and
- *   a capsule against a box contributes its two end spheres.
+ *   a capsule against a box contributes its two end spheres and its axis
+ *   segment, the segment a candidate only where its point nearest the box
+ *   (the deepest one where the axis passes through the box) lies strictly
+ *   between its ends.
  * env_desc: host [n_envs] index of each environment's description, or NULL
  *   (all use descs[0]). Environments of one type need not be contiguous.
  * device: HIP device ordinal, or -1 to parse and validate only (no device

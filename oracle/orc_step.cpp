@@ -46,7 +46,7 @@ thread_local int64_t g_flops = 0;
 thread_local std::vector<TraceNode>* g_trace = nullptr;
 
 enum { MAXB = 16, MAXJ = 16, MAXC = 96, MAXA = 48, MAXP = 32 };
-enum { PP, PS, SP, SS, PB, BP };  // body-body candidate: first body's feature vs the second's
+enum { PP, PS, SP, SS, PB, BP, SB, BS };  // body-body candidate: first body's feature vs the second's
 
 // Flat system description filled by the Python side of the oracle
 // (oracle/__init__.py mirrors this struct field by field).
@@ -448,6 +448,149 @@ template <class T> T point_box(const V3<T>& p, const V3<T>& c, const M3<T>& R, c
   n = matvec(R, ek);
   return T(-1.0) * (T(h[k]) - (sg > 0 ? qa[k] : T(-1.0) * qa[k]));
 }
+// Segment a0-a1 against a box (centre c, rotation R box to world, half
+// extents h): the parameter s* in [0, 1] of the segment point nearest the
+// box, or of the deepest one where the segment passes through the box. In
+// box coordinates the segment is q(s) = q0 + s dq. It passes through the box
+// where the parameters with every |q_k(s)| < h_k form an interval of
+// positive length. Outside, the squared distance sum_k max(|q_k| - h_k, 0)^2
+// is convex and quadratic between the parameters where some |q_k(s)| = h_k:
+// the candidates are the two ends, those parameters and each piece's
+// stationary point inside its piece. Through the box, the deepest point
+// minimises the signed distance max_k (|q_k| - h_k), linear between the
+// parameters where two of the six lines +-q_k(s) - h_k cross: the candidates
+// are the two ends and those crossings. The smallest value wins (the
+// smallest s among equal ones).
+// act: how far (in m) the point is from switching between an end and the
+// interior (the distance of an interior point from the nearer end, or of
+// the first or last piece's stationary point beyond an end).
+template <class T> T segment_box(const V3<T>& a0, const V3<T>& a1, const V3<T>& c, const M3<T>& R, const double* h,
+                                 double& act, Margins* mg) {
+  const M3<T> Rt = transpose(R);
+  const V3<T> q0v = matvec(Rt, sub(a0, c)), dqv = matvec(Rt, sub(a1, a0));
+  const T q0[3] = {q0v.x, q0v.y, q0v.z}, dq[3] = {dqv.x, dqv.y, dqv.z};
+  const double L = std::sqrt(val(dot(dqv, dqv)));
+  auto qat = [&](const T& s, int k) { return q0[k] + s * dq[k]; };
+  auto best_of = [&](const std::vector<T>& cs, auto fn, double& second) {
+    size_t bi = 0;
+    double bv = 1e300;
+    second = 1e300;
+    for (size_t i = 0; i < cs.size(); ++i) {
+      const double v = val(fn(cs[i]));
+      if (v < bv || (v == bv && val(cs[i]) < val(cs[bi]))) {
+        if (i) second = std::min(second, bv);
+        bv = v;
+        bi = i;
+      } else {
+        second = std::min(second, v);
+      }
+    }
+    return bi;
+  };
+  // the interval of parameters strictly inside every slab |q_k| < h_k
+  double te = 0.0, tx = 1.0;
+  for (int k = 0; k < 3; ++k) {
+    if (val(dq[k]) != 0) {
+      const double t1 = (-h[k] - val(q0[k])) / val(dq[k]), t2 = (h[k] - val(q0[k])) / val(dq[k]);
+      te = std::max(te, std::min(t1, t2));
+      tx = std::min(tx, std::max(t1, t2));
+    } else if (!(std::fabs(val(q0[k])) < h[k])) {
+      te = 1.0;
+      tx = 0.0;
+    }
+  }
+  if (mg) mg->feature_gap = std::min(mg->feature_gap, std::fabs(tx - te) * L);
+  double second = 0;
+  T s;
+  if (te < tx) {
+    // through the box: the deepest point
+    auto inside_sd = [&](const T& t) {
+      T g = T(-1e300);
+      for (int k = 0; k < 3; ++k) {
+        const T qk = qat(t, k);
+        const T ex = val(qk) >= 0 ? qk - T(h[k]) : T(-1.0) * qk - T(h[k]);
+        if (val(ex) > val(g)) g = ex;
+      }
+      return g;
+    };
+    std::vector<T> ic = {T(0.0), T(1.0)};
+    for (int i = 0; i < 6; ++i)
+      for (int j = i + 1; j < 6; ++j) {
+        const double si = (i & 1) ? -1.0 : 1.0, sj = (j & 1) ? -1.0 : 1.0;
+        const int ki = i / 2, kj = j / 2;
+        const T bi_ = T(si) * dq[ki], bj_ = T(sj) * dq[kj];
+        if (val(bi_) == val(bj_)) continue;
+        const T ai = T(si) * q0[ki] - T(h[ki]), aj = T(sj) * q0[kj] - T(h[kj]);
+        const T sc = (aj - ai) / (bi_ - bj_);
+        if (val(sc) > 0 && val(sc) < 1) ic.push_back(sc);
+      }
+    const size_t bi = best_of(ic, inside_sd, second);
+    s = ic[bi];
+    if (mg) mg->feature_gap = std::min(mg->feature_gap, std::fabs(second - val(inside_sd(s))));
+  } else {
+    auto outside_sq = [&](const T& t) {
+      T f = T(0.0);
+      for (int k = 0; k < 3; ++k) {
+        const T qk = qat(t, k);
+        const T ex = val(qk) >= 0 ? qk - T(h[k]) : T(-1.0) * qk - T(h[k]);
+        if (val(ex) > 0) f = f + ex * ex;
+      }
+      return f;
+    };
+    // the parameters where |q_k(s)| = h_k, inside (0, 1), sorted
+    std::vector<T> cuts;
+    for (int k = 0; k < 3; ++k)
+      for (double sg : {-1.0, 1.0})
+        if (val(dq[k]) != 0) {
+          const T sc = (T(sg * h[k]) - q0[k]) / dq[k];
+          if (val(sc) > 0 && val(sc) < 1) cuts.push_back(sc);
+        }
+    std::sort(cuts.begin(), cuts.end(), [](const T& x, const T& y) { return val(x) < val(y); });
+    std::vector<T> cand = {T(0.0), T(1.0)};
+    for (const T& x : cuts) cand.push_back(x);
+    // each piece's stationary point: active coordinates and their sides fixed
+    std::vector<double> ends = {0.0};
+    for (const T& x : cuts) ends.push_back(val(x));
+    ends.push_back(1.0);
+    for (size_t i = 0; i + 1 < ends.size(); ++i) {
+      const double mid = 0.5 * (ends[i] + ends[i + 1]);
+      T num = T(0.0), den = T(0.0);
+      for (int k = 0; k < 3; ++k) {
+        const double qm = val(q0[k]) + mid * val(dq[k]);
+        if (std::fabs(qm) > h[k]) {
+          const double sg = qm >= 0 ? 1.0 : -1.0;
+          num = num + (q0[k] - T(sg * h[k])) * dq[k];
+          den = den + dq[k] * dq[k];
+        }
+      }
+      if (val(den) > 0) {
+        const T st = T(-1.0) * num / den;
+        if (val(st) > ends[i] && val(st) < ends[i + 1]) cand.push_back(st);
+      }
+    }
+    const size_t bi = best_of(cand, outside_sq, second);
+    s = cand[bi];
+    if (mg)
+      for (int k = 0; k < 3; ++k)  // a coordinate reaching its face: the piece switches
+        mg->feature_gap = std::min(mg->feature_gap, std::fabs(std::fabs(val(qat(s, k))) - h[k]));
+    if (val(s) == 0.0 || val(s) == 1.0) {
+      // the stationary point of the end's piece, beyond that end
+      const double mid = val(s) == 0.0 ? 0.5 * ends[1] : 0.5 * (ends[ends.size() - 2] + 1.0);
+      double num = 0, den = 0;
+      for (int k = 0; k < 3; ++k) {
+        const double qm = val(q0[k]) + mid * val(dq[k]);
+        if (std::fabs(qm) > h[k]) {
+          num += (val(q0[k]) - (qm >= 0 ? 1.0 : -1.0) * h[k]) * val(dq[k]);
+          den += val(dq[k]) * val(dq[k]);
+        }
+      }
+      act = den > 0 ? std::fabs(-num / den - val(s)) * L : 0.0;
+      return s;
+    }
+  }
+  act = std::min(val(s), 1.0 - val(s)) * L;
+  return s;
+}
 // One body-body contact candidate (the paper's collisions between colliders,
 // Section 7.2, with the impulse of the ground contact): closest features,
 // normal n from the second body to the first, depth; the velocity-level
@@ -465,7 +608,37 @@ void pair_apply(const OrcSys& s, int c, const Body<T>* B, const Derived<T>* D, d
   V3<T> ca, cb, n;
   T dist;
   const double ra = s.p_ra[c], rb = s.p_rb[c];
-  if (kind == PB || kind == BP) {
+  if (kind == SB || kind == BS) {
+    // a capsule's axis against a box: a candidate only where the segment's
+    // nearest point lies strictly between its ends (the two ends are the
+    // capsule's end-sphere candidates)
+    const bool box_b = kind == SB;
+    const Body<T>& sb = box_b ? A : Bb;            // the segment's body
+    const Body<T>& xb = box_b ? Bb : A;            // the box's body
+    const Derived<T>& sdr = box_b ? D[ia] : D[ib];
+    const Derived<T>& xd = box_b ? D[ib] : D[ia];
+    const V3<T> a0 = wpt(sb, sdr, box_b ? s.p_a0[c] : s.p_b0[c]), a1 = wpt(sb, sdr, box_b ? s.p_a1[c] : s.p_b1[c]);
+    const V3<T> bc = wpt(xb, xd, box_b ? s.p_b0[c] : s.p_a0[c]);
+    const M3<T> R = matmul(xd.R, const_mat<T>(box_b ? s.p_bR[c] : s.p_aR[c]));
+    // the branch margins of the closest features count only where the
+    // candidate is (or, at an end, would be) in contact
+    Margins loc;
+    double act = 0;
+    const T sst = segment_box(a0, a1, bc, R, box_b ? s.p_bh[c] : s.p_ah[c], act, mg ? &loc : nullptr);
+    const bool interior = val(sst) > 0 && val(sst) < 1;
+    if (!interior && !mg) return;
+    // that segment point against the box
+    const V3<T> ps = add(a0, scale(sst, sub(a1, a0)));
+    V3<T> cbox, nb;
+    const T sd = point_box(ps, bc, R, box_b ? s.p_bh[c] : s.p_ah[c], cbox, nb, mg ? &loc : nullptr);
+    if (mg && val(sd) < ra + rb) mg->feature_gap = std::min(mg->feature_gap, std::min(loc.feature_gap, act));
+    if (!interior) return;
+    if (box_b) {
+      ca = ps; cb = cbox; n = nb; dist = sd;
+    } else {
+      ca = cbox; cb = ps; n = scale(T(-1.0), nb); dist = sd;
+    }
+  } else if (kind == PB || kind == BP) {
     const bool box_b = kind == PB;
     const Body<T>& pb = box_b ? A : Bb;            // the point's body
     const Body<T>& xb = box_b ? Bb : A;            // the box's body

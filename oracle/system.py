@@ -34,7 +34,7 @@ MAXB, MAXJ, MAXC, MAXA, MAXP = 16, 16, 96, 48, 32
 
 # body-body contact candidate kinds: the core feature of the first body
 # (point, segment or box) against that of the second
-PP, PS, SP, SS, PB, BP = range(6)
+PP, PS, SP, SS, PB, BP, SB, BS = range(8)
 
 
 # ----------------------------------------------------------------- parsing
@@ -231,7 +231,9 @@ def _feature(col):
 def pair_candidates(a, ca, b, cb):
     """Contact candidates between collider ca of body a and cb of body b:
     sphere-sphere, sphere-capsule, capsule-capsule, sphere-box; a capsule
-    against a box contributes its two end spheres; box-box is not modelled."""
+    against a box contributes its two end spheres and its axis segment, the
+    latter only where the segment's point nearest the box lies strictly
+    between its ends; box-box is not modelled."""
     ka, ga, ra = _feature(ca)
     kb, gb, rb = _feature(cb)
     z3, eye = np.zeros(3), np.eye(3)
@@ -250,9 +252,15 @@ def pair_candidates(a, ca, b, cb):
         return [rec(SS, ga[0], ga[1], ra, gb[0], gb[1], rb)]
     if kb == "box":
         pts = [ga] if ka == "point" else list(ga)
-        return [rec(PB, p, p, ra, gb[0], gb[0], 0.0, bh=gb[2], bR=gb[1]) for p in pts]
+        out = [rec(PB, p, p, ra, gb[0], gb[0], 0.0, bh=gb[2], bR=gb[1]) for p in pts]
+        if ka == "segment":
+            out.append(rec(SB, ga[0], ga[1], ra, gb[0], gb[0], 0.0, bh=gb[2], bR=gb[1]))
+        return out
     pts = [gb] if kb == "point" else list(gb)
-    return [rec(BP, ga[0], ga[0], 0.0, p, p, rb, ah=ga[2], aR=ga[1]) for p in pts]
+    out = [rec(BP, ga[0], ga[0], 0.0, p, p, rb, ah=ga[2], aR=ga[1]) for p in pts]
+    if kb == "segment":
+        out.append(rec(BS, ga[0], ga[0], 0.0, gb[0], gb[1], rb, ah=ga[2], aR=ga[1]))
+    return out
 
 
 # ----------------------------------------------------------------- the system

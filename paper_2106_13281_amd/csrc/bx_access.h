@@ -100,6 +100,15 @@ __device__ __forceinline__ int xcd_block(int b, int n) {
   return g0 + x * q + (x < r ? x : r) + i / NXCD;
 }
 
+// Index of this wavefront's work item in a launch of blocks of whole
+// wavefronts. It is the same on every lane of the wavefront; readfirstlane
+// makes that visible to the compiler, so the work item, its system type and
+// the type's constants are held in scalar registers and tests on them are
+// scalar branches rather than per-lane masks.
+__device__ __forceinline__ int wave_index() {
+  return __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6));
+}
+
 // Action of joint axis x, clipped to its range ([-1, 1] for a torque,
 // the joint's range for a target angle); 0 for an axis without actuator.
 __device__ __forceinline__ float act_of(const float* act, const JointT& J, int x, int e, int E) {

@@ -196,12 +196,15 @@ BXF Bar contact_adj(const ContactT& c, const TypeT& ty, const BodyT& B, const Bo
   applied = true;
   float jn = num / kn;
   v3 J = V(0.f, 0.f, jn);
-  float sp = sqrtf(u.x * u.x + u.y * u.y);
+  // the forward's friction branch and normalisation (contact_eval)
+  const float sp2 = u.x * u.x + u.y * u.y;
+  const bool slip = sp2 > 0.f;
   v3 t = V(0.f, 0.f, 0.f), zt = V(0.f, 0.f, 0.f), b = V(0.f, 0.f, 0.f);
-  float kt = 0.f, stop = 0.f, cap = 0.f, jt = 0.f, isp = 0.f;
+  float kt = 0.f, stop = 0.f, cap = 0.f, jt = 0.f, isp = 0.f, sp = 0.f;
   bool use_cap = false;
-  if (sp > 0.f) {
-    isp = 1.f / sp;
+  if (slip) {
+    isp = 1.f / sqrtf(sp2);
+    sp = sp2 * isp;
     t = V(u.x * isp, u.y * isp, 0.f);
     zt = cross(rr, t);
     b = mul(f.Iwinv, zt);
@@ -222,7 +225,7 @@ BXF Bar contact_adj(const ContactT& c, const TypeT& ty, const BodyT& B, const Bo
   cross_adj(rr, J, yb, rb, Jb);
   float jnb = Jb.z;
   v3 ub = V(0.f, 0.f, 0.f);
-  if (sp > 0.f) {
+  if (slip) {
     float jtb = -(Jb.x * t.x + Jb.y * t.y);
     v3 tb = V(-jt * Jb.x, -jt * Jb.y, 0.f);
     float capb = use_cap ? jtb : 0.f, stopb = use_cap ? 0.f : jtb;

@@ -377,48 +377,46 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
       for (int i = 0; i < 9; ++i) RP.m[i] = shfl(R.m[i], src_parent);
       Frame f = derive_inv(B, R);
       JointChild jc = joint_child<MAXDOF>(J, s, R);
+      // the contact candidates while the parent's state is in flight (they
+      // need none of it): the first REGC from registers (no dynamic indexing;
+      // a slot no body of the type has is skipped by the whole wave), the
+      // rest from the table
+      v3 dv = V(0.f, 0.f, 0.f), dw = V(0.f, 0.f, 0.f);
+      int cnt = 0;
+#pragma unroll
+      for (int k = 0; k < REGC; ++k)
+        if (k < ty.max_contacts && n_con > k) cnt += contact_eval(Creg[k], ty, B, s, f, dv, dw) ? 1 : 0;
+      for (int c = REGC; c < n_con; ++c) cnt += contact_eval(tab->contact[t][B.c0 + c], ty, B, s, f, dv, dw) ? 1 : 0;
       // joint evaluated on every lane (a root uses its own state as the
-      // parent and its result is discarded), so that it interleaves with the
-      // contacts below
-      // (a root's fp, tp are never read: its parent gather has no such child)
+      // parent and its result is discarded)
       JointOut jo = joint_eval<MAXDOF>(J, P, RP, s, jc, a);
-      // children's reactions: all cross-lane reads issued before the contact
-      // phase and consumed after it (child order)
+      // children's reactions (child order); a child's reaction on its parent
+      // is the opposite of its (F, rP x F + tau), read as is and subtracted
       v3 cf[GATHER], ct[GATHER];
 #pragma unroll
       for (int i = 0; i < GATHER; ++i) {
         if (i < ty.max_children) {
           const int src = base + (i < B.nch ? (int)((B.ch_packed >> (4 * i)) & 15u) : b);
-          cf[i] = V(shfl(jo.fp.x, src), shfl(jo.fp.y, src), shfl(jo.fp.z, src));
-          ct[i] = V(shfl(jo.tp.x, src), shfl(jo.tp.y, src), shfl(jo.tp.z, src));
+          cf[i] = V(shfl(jo.fc.x, src), shfl(jo.fc.y, src), shfl(jo.fc.z, src));
+          ct[i] = V(shfl(jo.tpn.x, src), shfl(jo.tpn.y, src), shfl(jo.tpn.z, src));
         }
       }
-      v3 dv = V(0.f, 0.f, 0.f), dw = V(0.f, 0.f, 0.f);
-      int cnt = 0;
-      // the first REGC candidates from registers (no dynamic indexing; a slot
-      // no body of the type has is skipped by the whole wave), the rest from
-      // the table; a candidate is skipped by the whole wave when it touches
-      // the ground on no lane
-#pragma unroll
-      for (int k = 0; k < REGC; ++k)
-        if (k < ty.max_contacts && n_con > k) cnt += contact_eval(Creg[k], ty, B, s, f, dv, dw) ? 1 : 0;
-      for (int c = REGC; c < n_con; ++c) cnt += contact_eval(tab->contact[t][B.c0 + c], ty, B, s, f, dv, dw) ? 1 : 0;
       const v3 z3 = V(0.f, 0.f, 0.f);
       v3 force = has_joint ? jo.fc : z3, torque = has_joint ? jo.tc : z3;
 #pragma unroll
       for (int i = 0; i < GATHER; ++i) {
         if (i < B.nch) {
-          force += cf[i];
-          torque += ct[i];
+          force -= cf[i];
+          torque -= ct[i];
         }
       }
       for (int i = GATHER; i < ty.max_children; ++i) {
         const int src = base + (i < B.nch ? (int)((B.ch_packed >> (4 * i)) & 15u) : b);
-        v3 fp = V(shfl(jo.fp.x, src), shfl(jo.fp.y, src), shfl(jo.fp.z, src));
-        v3 tq = V(shfl(jo.tp.x, src), shfl(jo.tp.y, src), shfl(jo.tp.z, src));
+        v3 fc = V(shfl(jo.fc.x, src), shfl(jo.fc.y, src), shfl(jo.fc.z, src));
+        v3 tq = V(shfl(jo.tpn.x, src), shfl(jo.tpn.y, src), shfl(jo.tpn.z, src));
         if (i < B.nch) {
-          force += fp;
-          torque += tq;
+          force -= fc;
+          torque -= tq;
         }
       }
       // body-body contacts after the joint sums, where fewer values are live
@@ -508,7 +506,7 @@ __global__ __launch_bounds__(256) void k_fused(const Tables* __restrict__ tab, c
                                                Fields out, const float* __restrict__ acts, int Am, int T,
                                                int save_every, Fields traj, uint8_t* nonfinite, float* tape,
                                                int smax) {
-  const int w = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int w = wave_index();
   if (w >= n_work) return;
   const WaveWork wk = work[w];
   // wave-uniform: joints of at most one axis take the shorter path
@@ -533,7 +531,7 @@ __global__ __launch_bounds__(256) void k_fused_tape(const Tables* __restrict__ t
                                                     Fields out, const float* __restrict__ acts, int Am, int T,
                                                     int save_every, Fields traj, uint8_t* nonfinite, float* tape,
                                                     int smax) {
-  const int w = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int w = wave_index();
   if (w >= n_work) return;
   const WaveWork wk = work[w];
   if (tab->type[wk.type].max_dof <= 1)
@@ -546,8 +544,10 @@ __global__ __launch_bounds__(256) void k_fused_tape(const Tables* __restrict__ t
 
 // The same for batches with body-body contacts: kernels of their own (with
 // and without the tape), so that the registers the body-body phase needs do
-// not lower the occupancy of the kernel above.
-template <bool TAPE, bool ONE_AXIS>
+// not lower the occupancy of the kernel above. REGC as for k_fused (8 for a
+// batch with a box, whose corners are otherwise read from the table in the
+// substep loop).
+template <bool TAPE, bool ONE_AXIS, int REGC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_pairs(const Tables* __restrict__ tab,
                                                      const WaveWork* __restrict__ work, int n_work,
                                                      const int32_t* __restrict__ env_list,
@@ -556,16 +556,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                                                      int save_every, Fields traj, uint8_t* nonfinite, float* tape,
                                                      int smax) {
   extern __shared__ PairLanes pair_lds[];  // one per wavefront of the block
-  const int w = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int w = wave_index();
   if (w >= n_work) return;
   const WaveWork wk = work[w];
   PairLanes* pl = pair_lds + (threadIdx.x >> 6);
   if (ONE_AXIS || tab->type[wk.type].max_dof <= 1)
-    fused_run<1, TAPE, true>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
-                             tape, smax, w, n_work, pl);
+    fused_run<1, TAPE, true, REGC>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj,
+                                   nonfinite, tape, smax, w, n_work, pl);
   else
-    fused_run<3, TAPE, true>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj, nonfinite,
-                             tape, smax, w, n_work, pl);
+    fused_run<3, TAPE, true, REGC>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj,
+                                   nonfinite, tape, smax, w, n_work, pl);
 }
 
 // One environment step with the environment layer fused after it (T = 1):
@@ -578,7 +578,7 @@ __global__ __launch_bounds__(256) void k_fused_env(const Tables* __restrict__ ta
                                                    Fields out, const float* __restrict__ acts, int Am,
                                                    uint8_t* nonfinite, EnvArgs ea) {
   extern __shared__ PairLanes env_pair_lds[];  // one per wavefront of the block (PAIRS only)
-  const int w = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int w = wave_index();
   if (w >= n_work) return;
   const WaveWork wk = work[w];
   PairLanes* pl = PAIRS ? env_pair_lds + (threadIdx.x >> 6) : nullptr;
@@ -658,15 +658,19 @@ hipError_t launch_fused(const LaunchCtx& c, const WaveWork* work, int n_work, in
     const size_t lds = sizeof(PairLanes) * waves_per_block;
     const dim3 grid(cdiv(n_work, waves_per_block)), block(64 * waves_per_block);
     uint8_t* nf = flags ? c.nonfinite : nullptr;
+    // the tape kernel keeps two register candidates (the tape rows take the registers)
     if (tape)
-      hipLaunchKernelGGL((k_fused_pairs<true, false>), grid, block, lds, s, c.tab, work, n_work, c.env_list, c.type_off,
-                         c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, tape, smax);
-    else if (one_axis)
-      hipLaunchKernelGGL((k_fused_pairs<false, true>), grid, block, lds, s, c.tab, work, n_work, c.env_list, c.type_off,
-                         c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0);
-    else
-      hipLaunchKernelGGL((k_fused_pairs<false, false>), grid, block, lds, s, c.tab, work, n_work, c.env_list,
+      hipLaunchKernelGGL((k_fused_pairs<true, false, REG_CONTACTS>), grid, block, lds, s, c.tab, work, n_work,
+                         c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, tape, smax);
+    else if (one_axis && many_contacts)
+      hipLaunchKernelGGL((k_fused_pairs<false, true, 8>), grid, block, lds, s, c.tab, work, n_work, c.env_list,
                          c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0);
+    else if (one_axis)
+      hipLaunchKernelGGL((k_fused_pairs<false, true, REG_CONTACTS>), grid, block, lds, s, c.tab, work, n_work,
+                         c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0);
+    else
+      hipLaunchKernelGGL((k_fused_pairs<false, false, REG_CONTACTS>), grid, block, lds, s, c.tab, work, n_work,
+                         c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0);
     return hipGetLastError();
   }
   if (tape && many_contacts)

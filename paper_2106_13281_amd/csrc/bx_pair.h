@@ -53,6 +53,15 @@ struct PairGeo {
   m3 Rb;                 // box rotation (box to world)
   int face;              // -1: p outside the box, else the nearest face's axis
   float sg;              // that face's side (+1 / -1)
+  // segment-box kinds: the segment a0 + s da in box coordinates q0s + s dqs,
+  // the parameter of its point nearest the box and how it was found
+  v3 q0s, dqs;
+  float sst;             // that parameter
+  int sbin;              // 0: the segment stays outside the box, 1: it reaches it
+  int act;               // outside: coordinates beyond their face at the minimiser (bit k)
+  v3 sig;                // their sides (+1 / -1)
+  float sD;              // outside: sum of dqs_k^2 over those coordinates
+  int li, lj;            // inside: the two lines +-q_k - h_k crossing at the parameter (-1: an end)
 };
 
 // Parameter in [0, 1] of the point of segment a + u d closest to p; 0 for a
@@ -147,11 +156,152 @@ BXF float point_box(v3 p, v3 c, const m3& Rb, const float* h, PairGeo& g) {
   return -gk;
 }
 
+// The parameter s in [0, 1] of the point of segment a0 + s da nearest the
+// box (centre c, rotation Rb box to world, half extents h); in box
+// coordinates the segment is q(s) = q0 + s dq. Outside the box the squared
+// distance sum_k max(|q_k| - h_k, 0)^2 is convex: its smallest minimiser is
+// the smallest candidate (the ends and the parameters where some |q_k| =
+// h_k) where half its slope, sum_k (q_k - clamp q_k) dq_k, is >= 0, or the
+// zero of that slope on the piece before it, where the coordinates beyond
+// their faces are fixed and the slope is linear: s = -N / D with
+// N = sum (q0_k - sg_k h_k) dq_k, D = sum dq_k^2 over them. Where the
+// segment passes through the box (the parameters with every |q_k| < h_k
+// form an interval of positive length) the deepest point is taken instead:
+// the smallest of max_k (|q_k| - h_k) over the ends and the crossings of two
+// of the six lines +-q_k(s) - h_k (the smallest s on ties).
+BXF float seg_box_param(v3 a0, v3 da, v3 c, const m3& Rb, const float* h, PairGeo& g) {
+  const v3 q0 = mul_t(Rb, a0 - c), dq = mul_t(Rb, da);
+  g.q0s = q0;
+  g.dqs = dq;
+  const float qa[3] = {q0.x, q0.y, q0.z}, qd[3] = {dq.x, dq.y, dq.z};
+  float sL = -1.f, fL = 0.f, sR = 2.f;
+  auto consider = [&](float s) {
+    float f = 0.f;
+    for (int k = 0; k < 3; ++k) {
+      const float q = qa[k] + s * qd[k];
+      f += (q - clampf(q, -h[k], h[k])) * qd[k];
+    }
+    if (f >= 0.f) {
+      sR = fminf(sR, s);
+    } else if (s > sL) {
+      sL = s;
+      fL = f;
+    }
+  };
+  consider(0.f);
+  consider(1.f);
+  for (int k = 0; k < 3; ++k)
+    if (qd[k] != 0.f) {
+      consider(clampf((h[k] - qa[k]) / qd[k], 0.f, 1.f));
+      consider(clampf((-h[k] - qa[k]) / qd[k], 0.f, 1.f));
+    }
+  (void)fL;
+  g.act = 0;
+  g.sig = V(0.f, 0.f, 0.f);
+  g.sD = 0.f;
+  g.sbin = 0;
+  g.li = g.lj = -1;
+  float s;
+  if (sR > 1.f) {
+    s = 1.f;
+  } else if (sL < 0.f) {
+    s = sR;
+  } else {
+    const float mid = 0.5f * (sL + sR);
+    float N = 0.f, D = 0.f, sg[3] = {0.f, 0.f, 0.f};
+    for (int k = 0; k < 3; ++k) {
+      const float q = qa[k] + mid * qd[k];
+      if (fabsf(q) > h[k]) {
+        sg[k] = q >= 0.f ? 1.f : -1.f;
+        N += (qa[k] - sg[k] * h[k]) * qd[k];
+        D += qd[k] * qd[k];
+        g.act |= 1 << k;
+      }
+    }
+    g.sig = V(sg[0], sg[1], sg[2]);
+    g.sD = D;
+    s = D > 0.f ? clampf(-N / D, sL, sR) : sR;
+  }
+  // does the segment pass through the box? (the parameters with every
+  // |q_k(s)| < h_k form an interval of positive length)
+  float te = 0.f, tx = 1.f;
+  for (int k = 0; k < 3; ++k) {
+    if (qd[k] != 0.f) {
+      const float t1 = (-h[k] - qa[k]) / qd[k], t2 = (h[k] - qa[k]) / qd[k];
+      te = fmaxf(te, fminf(t1, t2));
+      tx = fminf(tx, fmaxf(t1, t2));
+    } else if (!(fabsf(qa[k]) < h[k])) {
+      te = 1.f;
+      tx = 0.f;
+    }
+  }
+  if (!(te < tx)) return s;
+  // it does: its deepest point
+  g.sbin = 1;
+  g.act = 0;
+  auto depth_at = [&](float t) {
+    float m = fabsf(qa[0] + t * qd[0]) - h[0];
+    m = fmaxf(m, fabsf(qa[1] + t * qd[1]) - h[1]);
+    return fmaxf(m, fabsf(qa[2] + t * qd[2]) - h[2]);
+  };
+  float bs = 0.f, bv = depth_at(0.f);
+  {
+    const float v1 = depth_at(1.f);
+    if (v1 < bv) {
+      bs = 1.f;
+      bv = v1;
+    }
+  }
+  for (int i = 0; i < 6; ++i)
+    for (int j = i + 1; j < 6; ++j) {
+      const float si = (i & 1) ? -1.f : 1.f, sj = (j & 1) ? -1.f : 1.f;
+      const float bi = si * qd[i >> 1], bj = sj * qd[j >> 1];
+      if (bi == bj) continue;
+      const float ai = si * qa[i >> 1] - h[i >> 1], aj = sj * qa[j >> 1] - h[j >> 1];
+      const float t = (aj - ai) / (bi - bj);
+      if (!(t > 0.f && t < 1.f)) continue;
+      const float v = depth_at(t);
+      if (v < bv || (v == bv && t < bs)) {
+        bs = t;
+        bv = v;
+        g.li = i;
+        g.lj = j;
+      }
+    }
+  if (bs == 0.f || bs == 1.f) g.li = g.lj = -1;
+  return bs;
+}
+
 // Closest points of a candidate's features: ca on the first body, cb on the
 // second, unit normal n from cb towards ca, and their distance along n
 // (signed for a point against a box). Returns false where the normal is
 // undefined (coincident core points).
 BXF bool pair_geometry(const PairT& c, const PairSide& A, const PairSide& B, PairGeo& g) {
+  if (c.kind >= PK_SB) {
+    // a capsule's axis segment against a box: a candidate only where the
+    // segment's point nearest the box lies strictly between its ends (the
+    // ends are the capsule's end-sphere candidates); that point against the
+    // box as a point candidate
+    const bool box_b = c.kind == PK_SB;
+    const m3 SR = sel(box_b, A.R, B.R), XR = sel(box_b, B.R, A.R);
+    g.a0 = sel(box_b, A.p, B.p) + mul(SR, ld3(box_b ? c.a0 : c.b0));
+    g.da = mul(SR, ld3(box_b ? c.a1 : c.b1) - ld3(box_b ? c.a0 : c.b0));
+    g.bc = sel(box_b, B.p, A.p) + mul(XR, ld3(box_b ? c.b0 : c.a0));
+    if (c.box_rot)
+      g.Rb = mul(XR, box_b ? c.bR : c.aR);
+    else
+      g.Rb = XR;
+    const float* h = box_b ? c.bh : c.ah;
+    g.sst = seg_box_param(g.a0, g.da, g.bc, g.Rb, h, g);
+    if (!(g.sst > 0.f && g.sst < 1.f)) return false;
+    g.p = g.a0 + g.sst * g.da;
+    g.dist = point_box(g.p, g.bc, g.Rb, h, g);
+    const v3 cbox = g.cb;
+    g.ca = sel(box_b, g.p, cbox);
+    g.cb = sel(box_b, cbox, g.p);
+    g.n = sel(box_b, g.nbx, -g.nbx);
+    return true;
+  }
   if (c.kind >= PK_PB) {
     const bool box_b = c.kind == PK_PB;
     // the point's body (first for PB) and the box's body

@@ -139,10 +139,79 @@ BXF void point_box_adj(const PairGeo& g, const float* h, v3 cboxb, v3 nbxb, floa
   cb -= wb;
 }
 
+// seg_box_param -> cotangents of the segment's box coordinates q0s, dqs from
+// that of the parameter: outside, s = -N / D over the coordinates beyond
+// their faces; inside, the crossing s = (a_j - a_i) / (b_i - b_j) of lines
+// a_m + b_m s = sg_m q_{k_m}(s) - h_{k_m}. An end (s = 0 or 1) passes nothing.
+BXF void seg_box_param_adj(const PairGeo& g, const float* h, float sb, v3& q0b, v3& dqb) {
+  const float qa[3] = {g.q0s.x, g.q0s.y, g.q0s.z}, qd[3] = {g.dqs.x, g.dqs.y, g.dqs.z};
+  const float sg[3] = {g.sig.x, g.sig.y, g.sig.z};
+  float a[3] = {0.f, 0.f, 0.f}, d[3] = {0.f, 0.f, 0.f};
+  if (g.sbin == 0) {
+    if (g.sD > 0.f)
+      for (int k = 0; k < 3; ++k)
+        if (g.act & (1 << k)) {
+          a[k] -= sb * qd[k] / g.sD;
+          d[k] -= sb * (qa[k] - sg[k] * h[k] + 2.f * g.sst * qd[k]) / g.sD;
+        }
+  } else if (g.li >= 0) {
+    const int ki = g.li >> 1, kj = g.lj >> 1;
+    const float si = (g.li & 1) ? -1.f : 1.f, sj = (g.lj & 1) ? -1.f : 1.f;
+    const float den = si * qd[ki] - sj * qd[kj];
+    const float w = sb / den;
+    for (int k = 0; k < 3; ++k) {
+      a[k] += (k == kj ? sj * w : 0.f) - (k == ki ? si * w : 0.f);
+      d[k] += (k == kj ? sj * g.sst * w : 0.f) - (k == ki ? si * g.sst * w : 0.f);
+    }
+  }
+  q0b += V(a[0], a[1], a[2]);
+  dqb += V(d[0], d[1], d[2]);
+}
+
 // Closest features -> side cotangents, given those of cb (through the
 // contact point), n and dist.
 BXF void pair_geometry_adj(const PairT& c, const PairGeo& g, v3 cbb, v3 nb, float distb, PairSideBar& Ab,
                            PairSideBar& Bb) {
+  if (c.kind >= PK_SB) {
+    const bool box_b = c.kind == PK_SB;
+    const float* h = box_b ? c.bh : c.ah;
+    // SB: cb = cbox, n = nbx; BS: cb = p, n = -nbx; p = a0 + s da
+    const v3 z3 = V(0.f, 0.f, 0.f);
+    v3 pb = sel(box_b, z3, cbb), ccb = z3;
+    m3 Rbb = m3_zero();
+    point_box_adj(g, h, sel(box_b, cbb, z3), sel(box_b, nb, -nb), distb, pb, ccb, Rbb);
+    v3 a0b = pb, dab = g.sst * pb;
+    const float sb = dot(pb, g.da);
+    v3 q0b = z3, dqb = z3;
+    seg_box_param_adj(g, h, sb, q0b, dqb);
+    // q0s = Rb^T (a0 - c), dqs = Rb^T da
+    outer_add(Rbb, g.a0 - g.bc, q0b);
+    const v3 wb = mul(g.Rb, q0b);
+    a0b += wb;
+    ccb -= wb;
+    outer_add(Rbb, g.da, dqb);
+    dab += mul(g.Rb, dqb);
+    // a0 = S.p + S.R l0, da = S.R (l1 - l0) (the segment's body); bc = X.p + X.R lc, Rb = X.R bR (the box's)
+    m3 SRb = m3_zero(), XRb = m3_zero();
+    const v3 l0 = ld3(box_b ? c.a0 : c.b0), l1 = ld3(box_b ? c.a1 : c.b1);
+    outer_add(SRb, a0b, l0);
+    outer_add(SRb, dab, l1 - l0);
+    outer_add(XRb, ccb, ld3(box_b ? c.b0 : c.a0));
+    if (c.box_rot) {
+      const float* bR = box_b ? c.bR : c.aR;
+      for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k)
+          XRb.m[3 * i + k] +=
+              Rbb.m[3 * i] * bR[3 * k] + Rbb.m[3 * i + 1] * bR[3 * k + 1] + Rbb.m[3 * i + 2] * bR[3 * k + 2];
+    } else {
+      add_to(XRb, Rbb);
+    }
+    Ab.p += sel(box_b, a0b, ccb);
+    Bb.p += sel(box_b, ccb, a0b);
+    add_to(Ab.R, sel(box_b, SRb, XRb));
+    add_to(Bb.R, sel(box_b, XRb, SRb));
+    return;
+  }
   if (c.kind >= PK_PB) {
     const bool box_b = c.kind == PK_PB;
     // PB: cb = cbox, n = nbx; BP: cb = p, n = -nbx

@@ -484,8 +484,9 @@ int build_system(const char* text, SystemDesc& d, std::string& err) {
     // declared pair against every collider of the second; each collider is
     // reduced to a core feature plus a radius: a sphere to its centre, a
     // capsule to its axis segment, a box to itself (radius 0). A capsule
-    // against a box becomes its two end spheres; box against box is not
-    // modelled.
+    // against a box becomes its two end spheres and its axis segment (the
+    // latter a candidate only where its point nearest the box lies strictly
+    // between the ends); box against box is not modelled.
     std::vector<int> involved(d.bodies.size(), 0);
     for (const Val* pv : top.all("body_contacts")) {
       View pm = top.sub(pv);
@@ -537,6 +538,28 @@ int build_system(const char* text, SystemDesc& d, std::string& err) {
             double* bR = box_b ? Q.bR : Q.aR;
             for (int i = 0; i < 3; ++i) {
               pt0[i] = pt1[i] = e[k][i];
+              bx0[i] = bx1[i] = bc.pos[i];
+              bh[i] = bc.half[i];
+            }
+            for (int i = 0; i < 9; ++i) bR[i] = bc.R[i];
+            (box_b ? Q.ra : Q.rb) = pc.radius;
+            (box_b ? Q.rb : Q.ra) = 0.0;
+            d.pairs.push_back(Q);
+          }
+          if (pc.kind == 1) {
+            // and the capsule's axis segment, a candidate where its point
+            // nearest the box lies strictly between the two ends
+            PairD Q = P;
+            Q.kind = box_b ? PK_SB : PK_BS;
+            double* s0 = box_b ? Q.a0 : Q.b0;
+            double* s1 = box_b ? Q.a1 : Q.b1;
+            double* bx0 = box_b ? Q.b0 : Q.a0;
+            double* bx1 = box_b ? Q.b1 : Q.a1;
+            double* bh = box_b ? Q.bh : Q.ah;
+            double* bR = box_b ? Q.bR : Q.aR;
+            for (int i = 0; i < 3; ++i) {
+              s0[i] = e[0][i];
+              s1[i] = e[1][i];
               bx0[i] = bx1[i] = bc.pos[i];
               bh[i] = bc.half[i];
             }
@@ -690,7 +713,8 @@ void pack_type(const SystemDesc& d, Tables& tab, int t) {
     auto extent = [&](bool box, const double* p0, const double* p1, const double* half, double r) {
       return box ? norm(p0) + norm(half) : std::max(norm(p0), norm(p1)) + r;
     };
-    const double reach = extent(S.kind == PK_BP, S.a0, S.a1, S.ah, S.ra) + extent(S.kind == PK_PB, S.b0, S.b1, S.bh, S.rb);
+    const bool box_a = S.kind == PK_BP || S.kind == PK_BS, box_b = S.kind == PK_PB || S.kind == PK_SB;
+    const double reach = extent(box_a, S.a0, S.a1, S.ah, S.ra) + extent(box_b, S.b0, S.b1, S.bh, S.rb);
     // with a margin (0.01% and 0.1 mm) far above the FP32 rounding of positions and of the test
     P.reach = (float)(reach * (1.0 + 1e-4) + 1e-4);
     BodyT& A = tab.body[t][S.a];

@@ -146,7 +146,12 @@ struct Frame {
 // already zero (the integrators below keep them zero).
 BXF void kinematic_unmasked(Body& s, float h) {
   s.p = s.p + h * s.v;
-  q4 dq = qmul(q4{0.f, s.w.x, s.w.y, s.w.z}, s.q);
+  // (0, w) (x) q written out: the product with a pure quaternion has no
+  // terms in its zero real part
+  const v3 w = s.w;
+  const q4 a = s.q;
+  q4 dq{-(w.x * a.x + w.y * a.y + w.z * a.z), w.x * a.w + w.y * a.z - w.z * a.y,
+        w.y * a.w - w.x * a.z + w.z * a.x, w.z * a.w + w.x * a.y - w.y * a.x};
   float hh = 0.5f * h;
   q4 q{s.q.w + hh * dq.w, s.q.x + hh * dq.x, s.q.y + hh * dq.y, s.q.z + hh * dq.z};
   float inv = 1.f / sqrtf(q.w * q.w + q.x * q.x + q.y * q.y + q.z * q.z);
@@ -242,6 +247,28 @@ BXF JointGeo joint_geo(const JointT& J, const m3& RP, const JointChild& c) {
   return g;
 }
 
+// The geometry the step itself needs (joint_eval). For one-axis joints only
+// e1P, the angle th1 and its axis are used: m12 = e2P.e3C and m22 = e3P.e3C
+// are taken as the parent joint frame's y and z columns against RP^T e3C,
+// without forming e2P and e3P. The fields the step does not read are left
+// unset on that path (the adjoint takes joint_geo).
+template <int MAXDOF>
+BXF JointGeo joint_geo_step(const JointT& J, const m3& RP, const JointChild& c) {
+  if (MAXDOF > 1) return joint_geo<MAXDOF>(J, RP, c);
+  JointGeo g;
+  g.rP = mul(RP, ld3(J.ap));
+  g.rC = c.rC;
+  g.e1P = mul(RP, V(J.FP[0], J.FP[3], J.FP[6]));
+  g.e1C = c.e1C;
+  g.e3C = c.e3C;
+  const v3 v = mul_t(RP, c.e3C);
+  g.m12 = J.FP[1] * v.x + J.FP[4] * v.y + J.FP[7] * v.z;
+  g.m22 = J.FP[2] * v.x + J.FP[5] * v.y + J.FP[8] * v.z;
+  g.th[0] = atan2_poly(-g.m12, g.m22);
+  g.ax[0] = g.e1P;
+  return g;
+}
+
 template <int MAXDOF>
 BXF JointGeo joint_geo(const JointT& J, const m3& RP, const m3& RC) {
   Body none;
@@ -258,6 +285,7 @@ BXF JointGeo joint_geo(const JointT& J, const m3& RP, const m3& RC) {
 //   limit springs         -k_lim (th_k - clamp(th_k)) about Euler axis k < dof.
 struct JointOut {
   v3 fc, tc, fp, tp;
+  v3 tpn;  // -tp: a gather that subtracts it needs no negation
 };
 
 template <int MAXDOF>
@@ -287,9 +315,9 @@ BXF v3 joint_spring(const JointT& J, const Body& P, const Body& C, const JointGe
 // target-angle actuator gear_k (a_k - theta_k); act_pd selects the second.
 template <int MAXDOF>
 BXF v3 joint_actuator(const JointT& J, const JointGeo& g, const float* a) {
-  v3 tau = V(0.f, 0.f, 0.f);
-  for (int k = 0; k < MAXDOF; ++k)
-    if (MAXDOF == 1 || k < J.dof) tau += (J.gear[k] * (a[k] - J.act_pd[k] * g.th[k])) * g.ax[k];
+  v3 tau = (J.gear[0] * (a[0] - J.act_pd[0] * g.th[0])) * g.ax[0];
+  for (int k = 1; k < MAXDOF; ++k)
+    if (k < J.dof) tau += (J.gear[k] * (a[k] - J.act_pd[k] * g.th[k])) * g.ax[k];
   return tau;
 }
 
@@ -298,14 +326,15 @@ BXF v3 joint_actuator(const JointT& J, const JointGeo& g, const float* a) {
 template <int MAXDOF>
 BXF JointOut joint_eval(const JointT& J, const Body& P, const m3& RP, const Body& C, const JointChild& c,
                         const float* a /* clipped actions per axis, 0 if none */) {
-  JointGeo g = joint_geo<MAXDOF>(J, RP, c);
+  JointGeo g = joint_geo_step<MAXDOF>(J, RP, c);
   v3 F;
   v3 tau = joint_spring<MAXDOF>(J, P, C, g, c.uC, F) + joint_actuator<MAXDOF>(J, g, a);
   JointOut o;
   o.fc = F;
   o.tc = cross(g.rC, F) + tau;
   o.fp = -F;
-  o.tp = -(cross(g.rP, F) + tau);
+  o.tpn = cross(g.rP, F) + tau;
+  o.tp = -o.tpn;
   return o;
 }
 template <int MAXDOF>
@@ -330,21 +359,27 @@ BXF bool contact_eval(const ContactT& c, const TypeT& ty, const BodyT& B, const 
   float num = ty.beta_h * depth - ty.one_plus_e * u.z;
   if (!(num > 0.f)) return false;
   float jn = num / kn;
+  // J = jn z - jt t, so Iwinv (r x J) = jn Iwinv (r x z) - jt Iwinv (r x t):
+  // both products are already formed for kn and kt
   v3 J = V(0.f, 0.f, jn);
-  float sp = sqrtf(u.x * u.x + u.y * u.y);
-  if (sp > 0.f) {
-    float isp = 1.f / sp;
+  v3 dwc = jn * a;
+  const float sp2 = u.x * u.x + u.y * u.y;
+  if (sp2 > 0.f) {
+    const float isp = 1.f / sqrtf(sp2);
+    const float sp = sp2 * isp;
     v3 t = V(u.x * isp, u.y * isp, 0.f);
     v3 z = cross(r, t);
-    float kt = B.inv_m + dot(z, mul(f.Iwinv, z));  // t.((Iwinv (r x t)) x r) = (r x t).Iwinv (r x t)
+    v3 bz = mul(f.Iwinv, z);
+    float kt = B.inv_m + dot(z, bz);  // t.((Iwinv (r x t)) x r) = (r x t).Iwinv (r x t)
     float stop = sp / kt;
     float cap = ty.mu * jn;
     float jt = cap <= stop ? cap : stop;
     J.x = -jt * t.x;
     J.y = -jt * t.y;
+    dwc = dwc - jt * bz;
   }
   dv += B.inv_m * J;
-  dw += mul(f.Iwinv, cross(r, J));
+  dw += dwc;
   return true;
 }
 

@@ -19,7 +19,7 @@ constexpr int MAXPI = 16;  // body-body candidates one body takes part in
 constexpr int MAXH = 8;    // body-body candidates one lane evaluates (fused kernels)
 constexpr int MAXR = 8;    // shares of one side one body collects per evaluation slot
 // body-body candidate kinds: the first body's core feature against the second's
-enum PairKind : int32_t { PK_PP = 0, PK_PS = 1, PK_SP = 2, PK_SS = 3, PK_PB = 4, PK_BP = 5 };
+enum PairKind : int32_t { PK_PP = 0, PK_PS = 1, PK_SP = 2, PK_SS = 3, PK_PB = 4, PK_BP = 5, PK_SB = 6, PK_BS = 7 };
 
 struct TypeT {
   int32_t nb, nj, nc, na, ndof, substeps;

@@ -368,14 +368,15 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
     JointChild jc = joint_child<MAXDOF>(J, s, R);
     const v3 z3 = V(0.f, 0.f, 0.f);
     JointOut jo = joint_eval<MAXDOF>(J, P, RP, s, jc, a);
-    if (!has_joint) jo.fc = jo.tc = jo.fp = jo.tp = z3;
+    if (!has_joint) jo.fc = jo.tc = jo.fp = jo.tp = jo.tpn = z3;
+    // children's reactions read un-negated and subtracted (as in the forward)
     v3 cf[GATHER], ct[GATHER];
 #pragma unroll
     for (int i = 0; i < GATHER; ++i) {
       if (i < ty.max_children) {
         const int src = base + (i < B.nch ? (int)((B.ch_packed >> (4 * i)) & 15u) : b);
-        cf[i] = shfl3(jo.fp, src);
-        ct[i] = shfl3(jo.tp, src);
+        cf[i] = shfl3(jo.fc, src);
+        ct[i] = shfl3(jo.tpn, src);
       }
     }
     v3 dv = z3, dw = z3;
@@ -390,16 +391,16 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
 #pragma unroll
     for (int i = 0; i < GATHER; ++i) {
       if (i < B.nch) {
-        force += cf[i];
-        torque += ct[i];
+        force -= cf[i];
+        torque -= ct[i];
       }
     }
     for (int i = GATHER; i < ty.max_children; ++i) {
       const int src = base + (i < B.nch ? (int)((B.ch_packed >> (4 * i)) & 15u) : b);
-      v3 fp = shfl3(jo.fp, src), tq = shfl3(jo.tp, src);
+      v3 fc = shfl3(jo.fc, src), tq = shfl3(jo.tpn, src);
       if (i < B.nch) {
-        force += fp;
-        torque += tq;
+        force -= fc;
+        torque -= tq;
       }
     }
     if (PAIRS && ty.np > 0) pair_phase(tab, t, *pl, b, base, s, f, dv, dw, cnt);

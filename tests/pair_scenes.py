@@ -93,3 +93,48 @@ def approach(E, nb, seed, speed=2.0, dist=0.5, z=0.9):
             X[:, i, 7:10] = -speed * d + rng.normal(0, 0.3, (E, 3))
     X[:, :, 10:13] = rng.normal(0, 3.0, (E, nb, 3))
     return X.astype(np.float32).astype(np.float64)
+
+
+def edge_box(frozen_box, box_first=False, r=0.05, L=0.6):
+    """A capsule "cap" and a box "box" (half extents 0.2, 0.15, 0.1), declared
+    as a contact pair (capsule first, or box first), no gravity."""
+    frozen = 'frozen { position { x: 1 y: 1 z: 1 } rotation { x: 1 y: 1 z: 1 } }' if frozen_box else ""
+    first, second = ("box", "cap") if box_first else ("cap", "box")
+    return f"""substeps: 4
+dt: 0.004
+friction: 0.6
+elasticity: 0.2
+baumgarte: 0.2
+bodies {{ name: "cap" mass: 2 inertia {{ x: 0.05 y: 0.04 z: 0.03 }}
+  colliders {{ capsule {{ radius: {r} length: {L} }} }} }}
+bodies {{ name: "box" mass: 3 inertia {{ x: 0.07 y: 0.06 z: 0.05 }} {frozen}
+  colliders {{ box {{ halfsize {{ x: 0.2 y: 0.15 z: 0.1 }} }} }} }}
+body_contacts {{ first: "{first}" second: "{second}" }}
+"""
+
+
+def edge_states(E, seed, frozen_box, r=0.05):
+    """[E][2][13]: the capsule lying across the box's edge y = 0.15, z = 0.1
+    (its axis about perpendicular to the edge and to the edge's bisector
+    n = (0, 1, 1)/sqrt 2, tilted by a few degrees), its axis within r of the
+    edge (in contact there, its ends clear of the box), moving towards the
+    box; the box unrotated; its centre 1 m above the ground (its ends and
+    the capsule clear of it)."""
+    rng = np.random.default_rng(seed)
+    lift = np.array([0.0, 0.0, 1.0])
+    n = np.array([0.0, 1.0, 1.0]) / np.sqrt(2.0)
+    base = Rotation.from_euler("x", -135.0, degrees=True)
+    X = np.zeros((E, 2, 13))
+    for e in range(E):
+        edge = np.array([rng.uniform(-0.15, 0.15), 0.15, 0.1])
+        rot = Rotation.from_rotvec(rng.normal(0.0, 0.1, 3)) * base
+        X[e, 0, 0:3] = lift + edge + rng.uniform(0.2, 0.8) * r * n
+        X[e, 0, 3:7] = rot.as_quat()[[3, 0, 1, 2]]
+        X[e, 0, 7:10] = -0.2 * n + rng.normal(0.0, 0.1, 3)
+        X[e, 0, 10:13] = rng.normal(0.0, 1.0, 3)
+        X[e, 1, 0:3] = lift
+        X[e, 1, 3] = 1.0
+        if not frozen_box:
+            X[e, 1, 7:10] = rng.normal(0.0, 0.05, 3)
+            X[e, 1, 10:13] = rng.normal(0.0, 0.3, 3)
+    return X.astype(np.float32).astype(np.float64)

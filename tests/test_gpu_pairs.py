@@ -16,7 +16,7 @@ import torch
 import oracle
 from paper_2106_13281_amd import braxmi, synth
 from tests.helpers import ambiguous, check_rollout, fp32_sensitivity, rel_err
-from tests.pair_scenes import CLUSTER_BODIES, KIND_PAIRS, approach, cluster, two_body
+from tests.pair_scenes import CLUSTER_BODIES, KIND_PAIRS, approach, cluster, edge_box, edge_states, two_body
 
 pytestmark = pytest.mark.gpu
 STEP_TOL, ROLL_TOL = 1e-4, 1e-3
@@ -222,3 +222,68 @@ def test_pair_vjp_from_tape_and_parameters(case):
           flush=True)
     check_grad(err, amb)
     assert normwise(from_dev(g_in, nb), from_dev(gr, nb)).max() < 1e-5
+
+
+EDGE_CASES = [(frozen, box_first) for frozen in (True, False) for box_first in (False, True)]
+EDGE_IDS = [f"{'frozen' if f else 'free'}-box-{'first' if b else 'second'}" for f, b in EDGE_CASES]
+
+
+@pytest.mark.parametrize("flags", [braxmi.BRAX_FUSED, braxmi.BRAX_PLAIN])
+@pytest.mark.parametrize("frozen,box_first", EDGE_CASES, ids=EDGE_IDS)
+def test_capsule_across_box_edge_matches_oracle(frozen, box_first, flags):
+    """A capsule lying across a box edge, its axis within its radius of the
+    edge and its ends clear of the box: every impulse comes from the axis
+    segment's nearest point (a capsule taken as its two end spheres would
+    pass through the edge). One step within 1e-4, 20 steps within 1e-3."""
+    text = edge_box(frozen, box_first)
+    o = oracle.Oracle(text)
+    X = edge_states(E, 3, frozen)
+    z = np.zeros((E, 0))
+    Xo, mg = o.step(X, z, margins=True)
+    hit = np.abs(Xo[:, :, 7:10] - X[:, :, 7:10]).max((1, 2)) > 1e-6
+    assert hit.all()
+    sysg = braxmi.System(text, E)
+    out = sysg.step(to_dev(X), torch.zeros((0, E), dtype=torch.float32, device="cuda"), flags=flags)
+    r = rel_err(from_dev(out, 2), Xo)
+    amb = ambiguous(mg, STEP_AMB)
+    report(f"capsule across box edge {EDGE_IDS[EDGE_CASES.index((frozen, box_first))]} flags={flags}", r, amb, hit)
+    check(r, amb, STEP_TOL)
+    Xo20 = o.rollout(X, np.zeros((20, E, 0)))[0]
+    out20, _ = sysg.rollout(to_dev(X), no_acts(20, E), flags=flags)
+    r20 = rel_err(from_dev(out20, 2), Xo20)
+    print(f"  20 steps: max rel err {r20.max(0)}", flush=True)
+    check_rollout(r20, fp32_sensitivity(o, X, np.zeros((20, E, 0)), Xo20), ROLL_TOL)
+
+
+@pytest.mark.parametrize("flags", [braxmi.BRAX_FUSED, braxmi.BRAX_PLAIN])
+@pytest.mark.parametrize("frozen,box_first", EDGE_CASES, ids=EDGE_IDS)
+def test_capsule_across_box_edge_vjp_matches_oracle(frozen, box_first, flags):
+    """The adjoint through the axis segment's nearest point (its parameter
+    moves with both bodies' states) against the oracle's dual-number
+    adjoint; with a free box also the tape adjoint and the parameter
+    cotangents."""
+    text = edge_box(frozen, box_first)
+    o = oracle.Oracle(text)
+    n = 64
+    X = edge_states(n, 4, frozen)
+    z = np.zeros((n, 0))
+    g = np.random.default_rng(14).normal(size=X.shape).astype(np.float32).astype(np.float64)
+    gi_o, _ = o.step_vjp(X, z, g)
+    _, mg = o.step(X, z, margins=True)
+    sysg = braxmi.System(text, n)
+    a0 = torch.zeros((0, n), dtype=torch.float32, device="cuda")
+    g_in, _ = sysg.step_vjp(to_dev(X), a0, to_dev(g), flags=flags)
+    err = normwise(from_dev(g_in, 2), gi_o)
+    amb = mg.min(1) < 1e-6
+    print(f"edge vjp {EDGE_IDS[EDGE_CASES.index((frozen, box_first))]} flags={flags}: max err {err.max():.2e} "
+          f"ambiguous {int(amb.sum())}/{n}", flush=True)
+    check_grad(err, amb)
+    if flags == braxmi.BRAX_FUSED and not frozen:
+        _, tape = sysg.rollout_tape(to_dev(X), torch.zeros((1, 0, n), dtype=torch.float32, device="cuda"))
+        gt, _ = sysg.step_vjp_tape(tape[0], a0, to_dev(g))
+        assert (normwise(from_dev(gt, 2), from_dev(g_in, 2))[~amb] < 1e-4).all()
+        pv = o.param_vjp(X, z, g)
+        _, _, g_par = sysg.step_vjp_params(to_dev(X), a0, to_dev(g))
+        perr = normwise(g_par.cpu().numpy().T, pv)
+        print(f"  parameter vjp: max err {perr.max():.2e}", flush=True)
+        check_grad(perr, mg.min(1) < 1e-5)

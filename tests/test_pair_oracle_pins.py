@@ -4,7 +4,11 @@ Geometry: the oracle reports |r_a + r_b - distance| of every candidate as a
 branch margin; with two bodies far from the ground and at rest its minimum
 is the smallest |gap| between the candidates' surfaces, which is checked
 against a convex minimisation of the distance between the core features
-(scipy; a capsule against a box is its two end spheres). Dynamics: equal and
+(scipy; a capsule against a box is its two end spheres plus its axis
+segment where the segment's point nearest the box lies between the ends).
+A capsule lying across a box edge takes the impulse of its nearest point
+in closed form, and a capsule axis reaching into a box its deepest point's
+depth (scipy's bounded minimisation of the signed distance). Dynamics: equal and
 opposite impulses conserve total linear and angular momentum exactly
 (isotropic bodies, no gravity); a head-on elastic frictionless collision of
 equal spheres exchanges their velocities exactly.
@@ -77,13 +81,16 @@ def test_pair_depth_matches_convex_distance(ka, kb):
     o = oracle.Oracle(two_body(ka, kb))
     rng = np.random.default_rng(3)
     checked = 0
-    for trial in range(40):
+    for trial in range(60):
         X = np.zeros((1, 2, 13))
         X[0, :, 3:7] = Rotation.random(2, random_state=trial).as_quat()[:, [3, 0, 1, 2]]
         X[0, 0, 0:3] = [0.0, 0.0, 5.0]
         X[0, 1, 0:3] = [0.0, 0.0, 5.0] + rng.uniform(-0.4, 0.4, 3)
         fa, fb = features(o, X[0])
-        # a capsule against a box is modelled by its two end spheres
+        # a capsule against a box: its two end spheres, and its axis segment
+        # where the segment's point nearest the box lies between the ends
+        # (then the segment's gap is the smallest; where it lies at an end it
+        # is that end's gap, so it can be listed in either case)
         split = lambda f: [("point", g, f[2]) for g in f[1]] if f[0] == "segment" else [f]
         has_box = ka.startswith("box") or kb.startswith("box")
         if has_box:
@@ -91,7 +98,12 @@ def test_pair_depth_matches_convex_distance(ka, kb):
         else:
             fas, fbs = [fa], [fb]
         gaps = [surface_gap(x, y) for x in fas for y in fbs]
-        if not has_box or min(gaps) > -0.02:  # deep box penetrations: the nearest-face rule
+        axis_clear = True
+        if has_box and "segment" in (fa[0], fb[0]):
+            full = surface_gap(fa, fb)
+            gaps.append(full)
+            axis_clear = full > -min(fa[2], fb[2]) + 1e-6   # the axis itself stays outside the box
+        if not has_box or (min(gaps) > -0.02 and axis_clear):  # deep box penetrations: the nearest-face rule
             _, mg = o.step(X, np.zeros((1, 0)), margins=True)
             assert abs(mg[0, 0] - min(abs(g) for g in gaps)) < 1e-7, (trial, mg[0, 0], gaps)
             checked += 1
@@ -290,3 +302,87 @@ def test_sphere_sliding_on_a_frozen_box_rolls_at_the_lever_arm_speed():
     # the normal direction stays at the fixed point; the table never moves
     assert abs(Xs[0, 0, 2] - X[0, 0, 2]) < 1e-12 and abs(Xs[0, 0, 9]) < 1e-12
     assert np.array_equal(Xs[0, 1], X[0, 1])
+
+
+CAPSULE_ON_FROZEN_BOX = """substeps: 1
+dt: 0.002
+friction: 0.7
+elasticity: 0.0
+baumgarte: 0.2
+bodies {{ name: "cap" mass: 2 inertia {{ x: 0.05 y: 0.04 z: 0.03 }}
+  colliders {{ capsule {{ radius: {r} length: {L} }} }} }}
+bodies {{ name: "box" mass: 3 inertia {{ x: 0.07 y: 0.07 z: 0.07 }}
+  frozen {{ position {{ x: 1 y: 1 z: 1 }} rotation {{ x: 1 y: 1 z: 1 }} }}
+  colliders {{ box {{ halfsize {{ x: 0.2 y: 0.15 z: 0.1 }} }} }} }}
+body_contacts {{ first: "cap" second: "box" }}
+"""
+
+
+LIFT = np.array([0.0, 0.0, 5.0])   # far above the ground plane (no gravity in these scenes)
+
+
+def _capsule_state(centre, axis_rot):
+    """[1][2][13]: the capsule at `centre` (relative to the box) with rotation
+    `axis_rot` (its local z is the axis), at rest; the box, unrotated and at
+    rest, 5 m above the ground."""
+    X = np.zeros((1, 2, 13))
+    X[0, 0, 0:3] = LIFT + centre
+    X[0, 0, 3:7] = axis_rot.as_quat()[[3, 0, 1, 2]]
+    X[0, 1, 0:3] = LIFT
+    X[0, 1, 3] = 1.0
+    return X
+
+
+@pytest.mark.parametrize("d", [0.01, 0.03])
+def test_capsule_across_a_box_edge_takes_the_impulse_of_its_nearest_point(d):
+    """A capsule lying across the box's edge y = 0.15, z = 0.1 at distance d
+    (< r) from it, its axis perpendicular to the edge and to the edge's
+    bisector n = (0, 1, 1)/sqrt 2: the nearest point is the capsule's middle,
+    the ends are clear of the box. One substep at rest, no gravity, box
+    frozen: the only impulse acts along n at a lever arm parallel to n, so
+    v' = beta (r - d) / h n exactly and w' = 0. (A capsule taken as its two
+    end spheres would pass through the edge.)"""
+    r, L, h, beta = 0.05, 0.6, 0.002, 0.2
+    o = oracle.Oracle(CAPSULE_ON_FROZEN_BOX.format(r=r, L=L))
+    n = np.array([0.0, 1.0, 1.0]) / np.sqrt(2.0)
+    edge = np.array([0.05, 0.15, 0.1])
+    rot = Rotation.from_euler("x", -135.0, degrees=True)      # local z -> (0, 1, -1)/sqrt 2
+    assert np.allclose(rot.apply([0, 0, 1]), [0.0, 1 / np.sqrt(2), -1 / np.sqrt(2)])
+    X = _capsule_state(edge + d * n, rot)
+    Xn, mg = o.step(X, np.zeros((1, 0)), margins=True)
+    assert np.abs(Xn[0, 0, 7:10] - beta * (r - d) / h * n).max() < 1e-12
+    assert np.abs(Xn[0, 0, 10:13]).max() < 1e-12
+    assert abs(mg[0, 0] - (r - d)) < 1e-12           # the smallest |depth| is the middle's
+    assert np.abs(Xn[0, 1, 7:13]).max() == 0.0         # the frozen box does not move
+
+
+def _signed_box_distance(p, half):
+    q = np.abs(p) - half
+    return np.linalg.norm(np.maximum(q, 0.0)) + min(q.max(), 0.0)
+
+
+@pytest.mark.parametrize("trial", range(6))
+def test_capsule_axis_reaching_into_a_box_takes_its_deepest_point(trial):
+    """A long thin capsule whose axis passes through the box while both ends
+    stay clear of it: the only candidate in contact is the axis segment, and
+    its depth is r minus the smallest signed distance of an axis point from
+    the box (a convex function of the axis parameter), found here by
+    scipy's bounded scalar minimisation."""
+    from scipy.optimize import minimize_scalar
+    r, L = 0.02, 1.4
+    o = oracle.Oracle(CAPSULE_ON_FROZEN_BOX.format(r=r, L=L))
+    half = np.array([0.2, 0.15, 0.1])
+    rng = np.random.default_rng(50 + trial)
+    while True:
+        rot = Rotation.random(random_state=1000 * trial + int(rng.integers(1 << 30)))
+        centre = rng.uniform(-0.5, 0.5) * half
+        axis = rot.apply([0, 0, 1])
+        hh = L / 2 - r
+        ends = [centre + hh * axis, centre - hh * axis]
+        sd = lambda s: _signed_box_distance(ends[0] + s * (ends[1] - ends[0]), half)
+        if min(sd(0.0), sd(1.0)) > r + 0.05:
+            break
+    best = minimize_scalar(sd, bounds=(0.0, 1.0), method="bounded", options=dict(xatol=1e-12))
+    assert best.fun < 0.0                                # the axis reaches into the box
+    _, mg = o.step(_capsule_state(centre, rot), np.zeros((1, 0)), margins=True)
+    assert abs(mg[0, 0] - (r - best.fun)) < 1e-7, (mg[0, 0], r - best.fun)
