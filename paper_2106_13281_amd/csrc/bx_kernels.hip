@@ -422,8 +422,14 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
       // body-body contacts after the joint sums, where fewer values are live
       if (PAIRS && ty.np > 0) pair_phase(tab, t, *pl, b, base, s, f, dv, dw, cnt);
       if (TAPE) wtape_rest(tp, torque, cnt, lane);
-      potential(B, ty, s, f, force, torque);
-      collision(B, s, dv, dw, cnt);
+      // without frozen axes in the type (wave-uniform) the integrators skip the masks
+      if (ty.frozen) {
+        potential(B, ty, s, f, force, torque);
+        collision(B, s, dv, dw, cnt);
+      } else {
+        potential<false>(B, ty, s, f, force, torque);
+        collision<false>(B, s, dv, dw, cnt);
+      }
     }
     if (save_every > 0 && (step + 1) % save_every == 0) {
       if (live) store_snapshot(traj, (size_t)n_save, s, b, e, Bm, E);

@@ -627,6 +627,10 @@ void pack_type(const SystemDesc& d, Tables& tab, int t) {
   ty.mu = (float)d.mu;
   ty.clearance = (float)d.clearance;
   for (int k = 0; k < 3; ++k) ty.g[k] = (float)d.g[k];
+  ty.frozen = 0;
+  for (const BodyD& bd : d.bodies)
+    for (int k = 0; k < 3; ++k)
+      if (bd.free_p[k] == 0 || bd.free_r[k] == 0) ty.frozen = 1;
 
   std::vector<int> joint_of(ty.nb, -1);
   for (int j = 0; j < ty.nj; ++j) joint_of[d.joints[j].child] = j;

@@ -66,13 +66,15 @@ BXF q4 qmul(q4 a, q4 b) {
 
 // Rotation matrix of a unit quaternion (body to world).
 BXF m3 quat_to_mat(q4 q) {
-  float xx = q.x * q.x, yy = q.y * q.y, zz = q.z * q.z;
-  float xy = q.x * q.y, xz = q.x * q.z, yz = q.y * q.z;
-  float wx = q.w * q.x, wy = q.w * q.y, wz = q.w * q.z;
+  // products with the doubled components (exact doubling)
+  const float x2 = q.x + q.x, y2 = q.y + q.y, z2 = q.z + q.z;
+  const float xx = q.x * x2, yy = q.y * y2, zz = q.z * z2;
+  const float xy = q.x * y2, xz = q.x * z2, yz = q.y * z2;
+  const float wx = q.w * x2, wy = q.w * y2, wz = q.w * z2;
   m3 R;
-  R.m[0] = 1.f - 2.f * (yy + zz); R.m[1] = 2.f * (xy - wz);       R.m[2] = 2.f * (xz + wy);
-  R.m[3] = 2.f * (xy + wz);       R.m[4] = 1.f - 2.f * (xx + zz); R.m[5] = 2.f * (yz - wx);
-  R.m[6] = 2.f * (xz - wy);       R.m[7] = 2.f * (yz + wx);       R.m[8] = 1.f - 2.f * (xx + yy);
+  R.m[0] = 1.f - (yy + zz); R.m[1] = xy - wz;         R.m[2] = xz + wy;
+  R.m[3] = xy + wz;         R.m[4] = 1.f - (xx + zz); R.m[5] = yz - wx;
+  R.m[6] = xz - wy;         R.m[7] = yz + wx;         R.m[8] = 1.f - (xx + yy);
   return R;
 }
 
@@ -148,12 +150,11 @@ BXF void kinematic_unmasked(Body& s, float h) {
   s.p = s.p + h * s.v;
   // (0, w) (x) q written out: the product with a pure quaternion has no
   // terms in its zero real part
-  const v3 w = s.w;
+  const float hh = 0.5f * h;
+  const v3 w = V(hh * s.w.x, hh * s.w.y, hh * s.w.z);
   const q4 a = s.q;
-  q4 dq{-(w.x * a.x + w.y * a.y + w.z * a.z), w.x * a.w + w.y * a.z - w.z * a.y,
-        w.y * a.w - w.x * a.z + w.z * a.x, w.z * a.w + w.x * a.y - w.y * a.x};
-  float hh = 0.5f * h;
-  q4 q{s.q.w + hh * dq.w, s.q.x + hh * dq.x, s.q.y + hh * dq.y, s.q.z + hh * dq.z};
+  const q4 q{a.w - (w.x * a.x + w.y * a.y + w.z * a.z), a.x + (w.x * a.w + w.y * a.z - w.z * a.y),
+             a.y + (w.y * a.w - w.x * a.z + w.z * a.x), a.z + (w.z * a.w + w.x * a.y - w.y * a.x)};
   float inv = 1.f / sqrtf(q.w * q.w + q.x * q.x + q.y * q.y + q.z * q.z);
   s.q = q4{q.w * inv, q.x * inv, q.y * inv, q.z * inv};
 }
@@ -386,22 +387,36 @@ BXF bool contact_eval(const ContactT& c, const TypeT& ty, const BodyT& B, const 
 // Potential integrator: v += h (g + f/m); w += h Iwinv (t - w x (Iw w)).
 // Iw w is formed in the body frame, R (I o (R^T w)), which needs no world
 // inertia matrix.
+// MASKED = false: for a system type without frozen axes (the same result,
+// without the per-axis selects).
+template <bool MASKED = true>
 BXF void potential(const BodyT& B, const TypeT& ty, Body& s, const Frame& f, v3 force, v3 torque) {
   v3 acc = ld3(ty.g) + B.inv_m * force;
-  s.v = keep_fma(s.v, ty.h, acc, B.free_p);
   v3 wb = mul_t(f.R, s.w);
   v3 gyro = cross(s.w, mul(f.R, V(B.I[0] * wb.x, B.I[1] * wb.y, B.I[2] * wb.z)));
   v3 alpha = mul(f.Iwinv, torque - gyro);
-  s.w = keep_fma(s.w, ty.h, alpha, B.free_r);
+  if (MASKED) {
+    s.v = keep_fma(s.v, ty.h, acc, B.free_p);
+    s.w = keep_fma(s.w, ty.h, alpha, B.free_r);
+  } else {
+    s.v = V(fmaf(ty.h, acc.x, s.v.x), fmaf(ty.h, acc.y, s.v.y), fmaf(ty.h, acc.z, s.v.z));
+    s.w = V(fmaf(ty.h, alpha.x, s.w.x), fmaf(ty.h, alpha.y, s.w.y), fmaf(ty.h, alpha.z, s.w.z));
+  }
 }
 
 // Collision integrator: the body's contact impulses averaged over the n
 // candidates that applied one.
+template <bool MASKED = true>
 BXF void collision(const BodyT& B, Body& s, v3 dv, v3 dw, int n) {
   if (n > 0) {
     float inv = 1.f / (float)n;
-    s.v = keep_fma(s.v, inv, dv, B.free_p);
-    s.w = keep_fma(s.w, inv, dw, B.free_r);
+    if (MASKED) {
+      s.v = keep_fma(s.v, inv, dv, B.free_p);
+      s.w = keep_fma(s.w, inv, dw, B.free_r);
+    } else {
+      s.v = V(fmaf(inv, dv.x, s.v.x), fmaf(inv, dv.y, s.v.y), fmaf(inv, dv.z, s.v.z));
+      s.w = V(fmaf(inv, dw.x, s.w.x), fmaf(inv, dw.y, s.w.y), fmaf(inv, dw.z, s.w.z));
+    }
   }
 }
 

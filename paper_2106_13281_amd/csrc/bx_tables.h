@@ -36,7 +36,7 @@ struct TypeT {
   float mu;                // Coulomb friction
   float clearance;         // reset height of the lowest contact point (m)
   float g[3];              // gravity (m/s^2)
-  float pad1;
+  int32_t frozen;          // 1 if some body of the type has a frozen axis
 };
 
 struct BodyT {
