@@ -290,7 +290,10 @@ int brax_env_step(const brax_sys* sys, const brax_state* in, const float* act, c
                   brax_state* out, float* obs, float* reward, uint8_t* done, int32_t flags, void* stream);
 
 /* Time the fused kernel's launch shapes on `stream` and keep the fastest
- * for later calls (the result does not depend on the shape). */
+ * for later calls (the result does not depend on the shape). Shapes are
+ * tried from full wavefronts down and from one wavefront per block up; a
+ * later shape replaces the best so far only if it is more than 1% faster,
+ * so that repeated tunings of one batch settle on the same shape. */
 int brax_autotune(brax_sys* sys, void* stream);
 
 /* Launch shape in use: environments per wavefront (of the first system type)

@@ -711,7 +711,9 @@ int brax_autotune(brax_sys* s, void* stream) {
           acc = std::min(acc, ms);
         }
         for (int u = 0; u < s->n_types; ++u) s->envs_per_wave[u] = saved[u];
-        if (acc < best_t) {
+        // a later (emptier) shape must be faster by more than the timing
+        // noise (1%), so that repeated tunings settle on the same shape
+        if (acc < 0.99f * best_t) {
           best_t = acc;
           best_epw[t] = epw;
         }
@@ -734,7 +736,7 @@ int brax_autotune(brax_sys* s, void* stream) {
       }
       acc = std::min(acc, ms);
     }
-    if (!rc && acc < best_total) {
+    if (!rc && acc < 0.99f * best_total) {
       best_total = acc;
       best_wpb = wpb;
     }
