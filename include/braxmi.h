@@ -290,11 +290,22 @@ int brax_env_step(const brax_sys* sys, const brax_state* in, const float* act, c
                   brax_state* out, float* obs, float* reward, uint8_t* done, int32_t flags, void* stream);
 
 /* Time the fused kernel's launch shapes on `stream` and keep the fastest
- * for later calls (the result does not depend on the shape). Shapes are
- * tried from full wavefronts down and from one wavefront per block up; a
- * later shape replaces the best so far only if it is more than 1% faster,
- * so that repeated tunings of one batch settle on the same shape. */
+ * for later calls (the result does not depend on the shape). Per system
+ * type, the environments per wavefront that give about one wavefront per
+ * SIMD are tried first, then from full wavefronts down; wavefronts per
+ * block from one up. A later shape replaces the best so far only if it is
+ * more than 1% faster, so that repeated tunings of one batch settle on the
+ * same shape. */
 int brax_autotune(brax_sys* sys, void* stream);
+
+/* brax_autotune with trials on the caller's workload: each trial is a
+ * T-step rollout from `in` with actions `act` ([T][A_max][E], as
+ * brax_rollout), so that the shapes are compared on the states and actions
+ * of use (trials from the reset pose miss how contacts and body-body
+ * candidates come and go). Device pointers, caller owned, read only; the
+ * trials' output goes to the library's own scratch state. BRAX_E_ARG for
+ * T < 1 or a NULL field. */
+int brax_autotune_on(brax_sys* sys, const brax_state* in, const float* act, int32_t T, void* stream);
 
 /* Launch shape in use: environments per wavefront (of the first system type)
  * and wavefronts per block. */

@@ -59,7 +59,8 @@ class _Layout(C.Structure):
 EXPORTS = ("brax_sys_create", "brax_sys_destroy", "brax_sys_query", "brax_default_angles", "brax_default_qp",
            "brax_step", "brax_step_vjp", "brax_step_vjp_params", "brax_rollout", "brax_rollout_tape",
            "brax_step_vjp_tape", "brax_rollout_vjp_tape",
-           "brax_env_configure", "brax_env_step", "brax_autotune", "brax_schedule", "brax_set_schedule",
+           "brax_env_configure", "brax_env_step", "brax_autotune", "brax_autotune_on", "brax_schedule",
+           "brax_set_schedule",
            "brax_nonfinite", "brax_last_error", "brax_step_vjp_noalloc")
 
 _lib = None
@@ -99,6 +100,7 @@ def lib():
         L.brax_env_step.argtypes = [C.c_void_p, P(_State), C.c_void_p, P(_State), P(_State), C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_int32, C.c_void_p]
         L.brax_autotune.argtypes = [C.c_void_p, C.c_void_p]
+        L.brax_autotune_on.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
         L.brax_schedule.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32)]
         L.brax_set_schedule.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
         L.brax_nonfinite.argtypes = [C.c_void_p, P(C.c_uint8)]
@@ -370,6 +372,15 @@ class System:
 
     def autotune(self, stream=None):
         _check(lib().brax_autotune(self._h, _stream(stream)))
+        return self.schedule()
+
+    def autotune_on(self, state, acts, stream=None):
+        """autotune with trials on the caller's workload: T-step rollouts from
+        `state` with `acts` [T][A_max][E] (T = acts.shape[0])."""
+        T = acts.shape[0]
+        acts = self._act(acts, (T, self.a_max, self.n_envs))
+        si = state.struct()
+        _check(lib().brax_autotune_on(self._h, C.byref(si), _ptr(acts), T, _stream(stream)))
         return self.schedule()
 
     def schedule(self):

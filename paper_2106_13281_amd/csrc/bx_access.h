@@ -210,6 +210,72 @@ __device__ __forceinline__ void pin_consts(BodyT& B, JointT& J, bool has_joint, 
   }
 }
 
+// A wavefront's exchange rows in LDS, one per lane, through which lanes read
+// one another's values (a parent's state and rotation, a child's reaction or
+// cotangent) in a few 16-byte accesses, where cross-lane permutes take one
+// instruction per value. A wavefront's LDS operations complete in program
+// order: a read that follows a write sees it, and a write that follows a
+// read leaves that read intact, so a row is rewritten as soon as its last
+// reader has been issued and no barrier is needed. Rows of 20 floats keep
+// the 16-byte accesses of eight consecutive lanes on distinct banks.
+struct XchRows {
+  float4 r[64][5];
+};
+
+// Position and velocities (columns 0-7), then the rotation matrix (8-15)
+// with the last angular velocity component beside its last entry (16, 17):
+// written in two parts so that the first is on its way while R is formed.
+__device__ __forceinline__ void xch_put_pvw(XchRows* X, int lane, const Body& s) {
+  X->r[lane][0] = make_float4(s.p.x, s.p.y, s.p.z, s.v.x);
+  X->r[lane][1] = make_float4(s.v.y, s.v.z, s.w.x, s.w.y);
+}
+__device__ __forceinline__ void xch_put_rot(XchRows* X, int lane, float wz, const m3& R) {
+  X->r[lane][2] = make_float4(R.m[0], R.m[1], R.m[2], R.m[3]);
+  X->r[lane][3] = make_float4(R.m[4], R.m[5], R.m[6], R.m[7]);
+  *reinterpret_cast<float2*>(&X->r[lane][4]) = make_float2(wz, R.m[8]);
+}
+// Position, velocities and rotation of the body on lane src (P.q is not set).
+__device__ __forceinline__ void xch_get_pvw_rot(const XchRows* X, int src, Body& P, m3& RP) {
+  const float4 a0 = X->r[src][0], a1 = X->r[src][1], r0 = X->r[src][2], r1 = X->r[src][3];
+  const float2 a2 = *reinterpret_cast<const float2*>(&X->r[src][4]);
+  P.p = V(a0.x, a0.y, a0.z);
+  P.v = V(a0.w, a1.x, a1.y);
+  P.w = V(a1.z, a1.w, a2.x);
+  RP.m[0] = r0.x; RP.m[1] = r0.y; RP.m[2] = r0.z; RP.m[3] = r0.w;
+  RP.m[4] = r1.x; RP.m[5] = r1.y; RP.m[6] = r1.z; RP.m[7] = r1.w;
+  RP.m[8] = a2.y;
+}
+// Two 3-vectors (columns 0-5).
+__device__ __forceinline__ void xch_put2(XchRows* X, int lane, v3 a, v3 b) {
+  X->r[lane][0] = make_float4(a.x, a.y, a.z, b.x);
+  *reinterpret_cast<float2*>(&X->r[lane][1]) = make_float2(b.y, b.z);
+}
+__device__ __forceinline__ void xch_get2(const XchRows* X, int src, v3& a, v3& b) {
+  const float4 x0 = X->r[src][0];
+  const float2 x1 = *reinterpret_cast<const float2*>(&X->r[src][1]);
+  a = V(x0.x, x0.y, x0.z);
+  b = V(x0.w, x1.x, x1.y);
+}
+// A full body state or its cotangent (p, q, v, w: columns 0-12).
+template <class S>
+__device__ __forceinline__ void xch_put_body(XchRows* X, int lane, const S& s) {
+  X->r[lane][0] = make_float4(s.p.x, s.p.y, s.p.z, s.q.w);
+  X->r[lane][1] = make_float4(s.q.x, s.q.y, s.q.z, s.v.x);
+  X->r[lane][2] = make_float4(s.v.y, s.v.z, s.w.x, s.w.y);
+  X->r[lane][3].x = s.w.z;
+}
+template <class S>
+__device__ __forceinline__ S xch_get_body(const XchRows* X, int src) {
+  const float4 a0 = X->r[src][0], a1 = X->r[src][1], a2 = X->r[src][2];
+  const float a3 = X->r[src][3].x;
+  S s;
+  s.p = V(a0.x, a0.y, a0.z);
+  s.q = q4{a0.w, a1.x, a1.y, a1.z};
+  s.v = V(a1.w, a2.x, a2.y);
+  s.w = V(a2.z, a2.w, a3);
+  return s;
+}
+
 // Contact candidates of a body kept in registers (more are read from the table).
 constexpr int REG_CONTACTS = 2;
 // Children whose reactions are gathered with all cross-lane reads in flight at once.

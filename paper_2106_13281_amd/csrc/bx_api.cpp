@@ -636,38 +636,42 @@ int brax_set_schedule(brax_sys* s, int32_t envs_per_wave, int32_t waves_per_bloc
   return BRAX_OK;
 }
 
-int brax_autotune(brax_sys* s, void* stream) {
-  if (!s) return fail(BRAX_E_ARG, "sys is NULL");
-  if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
+// Times the launch shapes from state `in` with T steps of actions `act`
+// (both caller-owned, read only), or, with in = NULL, from the reset pose
+// after 32 steps of zero actions with 8 steps of zero actions.
+static int autotune_impl(brax_sys* s, const brax_state* in, const float* act, int T_in, hipStream_t st) {
   if (s->E == 0) return BRAX_OK;
   DeviceGuard g(s->device);
-  hipStream_t st = (hipStream_t)stream;
-  // scratch state and zero actions; timing runs use the reset pose
   const size_t n3 = (size_t)3 * s->Bm * s->E, n4 = (size_t)4 * s->Bm * s->E;
-  const int T = 8;
+  const bool own = in == nullptr;
+  const int T = own ? 8 : T_in;
+  // scratch: the trials' output state and, without a caller's state, the
+  // reset state and zero actions
   float* buf = nullptr;
-  size_t nbuf = 2 * (3 * n3 + n4) + (size_t)std::max(s->Am, 1) * s->E * T;
+  size_t nbuf = (3 * n3 + n4) + (own ? (3 * n3 + n4) + (size_t)std::max(s->Am, 1) * s->E * T : 0);
   HIP_TRY(hipMalloc(&buf, sizeof(float) * nbuf));
   HIP_TRY(hipMemsetAsync(buf, 0, sizeof(float) * nbuf, st));
-  Fields a{buf, buf + n3, buf + n3 + n4, buf + 2 * n3 + n4};
-  float* b0 = buf + 3 * n3 + n4;
-  Fields b{b0, b0 + n3, b0 + n3 + n4, b0 + 2 * n3 + n4};
-  float* acts = buf + 2 * (3 * n3 + n4);
+  Fields b{buf, buf + n3, buf + n3 + n4, buf + 2 * n3 + n4};
+  float* a0 = buf + 3 * n3 + n4;
+  Fields a = own ? Fields{a0, a0 + n3, a0 + n3 + n4, a0 + 2 * n3 + n4} : F(in);
+  const float* acts = own ? buf + 2 * (3 * n3 + n4) : act;
   LaunchCtx c = s->ctx();
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   int rc = BRAX_OK;
-  // timing state: the reset pose after 32 steps of zero actions, so that the
-  // bodies have dropped onto the ground and contacts are active as in use
-  if (launch_default_qp(c, nullptr, nullptr, b, st) != hipSuccess ||
-      launch_fused(c, s->d_work, (int)s->work.size(), s->waves_per_block, b, a, acts, 1, 0, Fields{}, false, st) !=
-          hipSuccess)
-    rc = fail(BRAX_E_DEVICE, "autotune reset failed");
-  for (int k = 1; k < 32 && !rc; ++k)
-    if (launch_fused(c, s->d_work, (int)s->work.size(), s->waves_per_block, a, a, acts, 1, 0, Fields{}, false, st) !=
-        hipSuccess)
+  // own timing state: the reset pose after 32 steps of zero actions, so that
+  // the bodies have dropped onto the ground and contacts are active as in use
+  if (own) {
+    if (launch_default_qp(c, nullptr, nullptr, b, st) != hipSuccess ||
+        launch_fused(c, s->d_work, (int)s->work.size(), s->waves_per_block, b, a, acts, 1, 0, Fields{}, false, st) !=
+            hipSuccess)
       rc = fail(BRAX_E_DEVICE, "autotune reset failed");
+    for (int k = 1; k < 32 && !rc; ++k)
+      if (launch_fused(c, s->d_work, (int)s->work.size(), s->waves_per_block, a, a, acts, 1, 0, Fields{}, false,
+                       st) != hipSuccess)
+        rc = fail(BRAX_E_DEVICE, "autotune reset failed");
+  }
   int n_cu = 0;
   if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, s->device) != hipSuccess || n_cu <= 0)
     n_cu = 256;
@@ -683,14 +687,20 @@ int brax_autotune(brax_sys* s, void* stream) {
     if (rc) break;
     for (int t = 0; t < s->n_types; ++t) {
       // from a full wavefront down to half of one, at most 6 values evenly
-      // spaced, plus the value that gives about one wavefront per SIMD
+      // spaced, after the value that gives about one wavefront per SIMD; that
+      // one is timed first, so that it stays unless another is clearly
+      // faster (fewer environments per wavefront skip more contact and
+      // body-body slots that no lane of the wavefront needs, which a short
+      // trial may not show)
       const int full = std::max(1, 64 / s->host_tab.type[t].nb);
       const int low = std::max(1, full / 2);
-      epw_c.clear();
-      const int span = full - low + 1, nc = std::min(span, 6);
-      for (int i = 0; i < nc; ++i) epw_c.push_back(full - (nc > 1 ? (i * (span - 1)) / (nc - 1) : 0));
       const int fill = std::min(full, std::max(1, (s->type_cnt[t] + n_simd - 1) / n_simd));
-      if (std::find(epw_c.begin(), epw_c.end(), fill) == epw_c.end()) epw_c.push_back(fill);
+      epw_c.assign(1, fill);
+      const int span = full - low + 1, nc = std::min(span, 6);
+      for (int i = 0; i < nc; ++i) {
+        const int epw = full - (nc > 1 ? (i * (span - 1)) / (nc - 1) : 0);
+        if (epw != fill) epw_c.push_back(epw);
+      }
       float best_t = 1e30f;
       for (int epw : epw_c) {
         // time this type alone with the others at their current best
@@ -758,6 +768,22 @@ int brax_autotune(brax_sys* s, void* stream) {
   }
   s->graphs.clear();
   return rc;
+}
+
+int brax_autotune(brax_sys* s, void* stream) {
+  if (!s) return fail(BRAX_E_ARG, "sys is NULL");
+  if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
+  return autotune_impl(s, nullptr, nullptr, 0, (hipStream_t)stream);
+}
+
+int brax_autotune_on(brax_sys* s, const brax_state* in, const float* act, int32_t T, void* stream) {
+  if (!s) return fail(BRAX_E_ARG, "sys is NULL");
+  if (s->device < 0) return fail(BRAX_E_ARG, "host-only handle (created with device -1)");
+  if (T < 1) return fail(BRAX_E_ARG, "T must be >= 1");
+  if (s->E == 0) return BRAX_OK;
+  if (!state_ok(in)) return fail(BRAX_E_ARG, "state has a NULL field");
+  if (!act && s->Am > 0) return fail(BRAX_E_ARG, "act is NULL");
+  return autotune_impl(s, in, act, T, (hipStream_t)stream);
 }
 
 namespace {

@@ -290,9 +290,9 @@ __global__ void k_plain_collision(const Tables* __restrict__ tab, int t, const i
 // ------------------------------------------------------------------ fused path
 // One lane per body, floor(64 / nb) environments per wavefront; the lane of
 // body b also evaluates the joint whose child is b (with its actuators) and
-// b's own contact candidates. Neighbour data moves by cross-lane permutes
-// (ds_bpermute): the child lane fetches its parent's state; the parent lane
-// fetches each child's reaction (fp, tp) in child order. State stays in
+// b's own contact candidates. Neighbour data moves through the wavefront's
+// exchange rows in LDS: the child lane reads its parent's state; the parent
+// lane reads each child's reaction (fp, tp) in child order. State stays in
 // registers across all substeps and steps; only actions are read per step.
 
 // What the environment epilogue reads and writes (see brax_env_step).
@@ -304,6 +304,20 @@ struct EnvArgs {
   uint8_t* done;     // [E]
   int Omax;
 };
+
+// LDS bytes of one wavefront of the fused kernels: its exchange rows and,
+// for batches with body-body candidates, its copy of their tables (placed
+// after the exchange rows of all wavefronts of the block).
+static inline size_t fused_lds_per_wave(bool pairs) {
+  return sizeof(XchRows) + (pairs ? sizeof(PairLanes) : 0);
+}
+
+__device__ __forceinline__ XchRows* xch_lanes(float4* lds) {
+  return reinterpret_cast<XchRows*>(lds) + (threadIdx.x >> 6);
+}
+__device__ __forceinline__ PairLanes* pair_lanes(float4* lds) {
+  return reinterpret_cast<PairLanes*>(reinterpret_cast<XchRows*>(lds) + (blockDim.x >> 6)) + (threadIdx.x >> 6);
+}
 
 // TAPE: also write each substep's tape record (state before the kinematic
 // update, total torque, count of applied contacts) to the wavefront-major
@@ -320,7 +334,7 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
                                           int E, int Bm, const Fields& in, const Fields& out,
                                           const float* __restrict__ acts, int Am, int T, int save_every,
                                           const Fields& traj, uint8_t* nonfinite, float* __restrict__ tape,
-                                          int smax, int w, int n_work, PairLanes* pl = nullptr,
+                                          int smax, int w, int n_work, XchRows* X, PairLanes* pl = nullptr,
                                           const EnvArgs* ea = nullptr) {
   const int t = wk.type;
   const TypeT ty = tab->type[t];
@@ -363,18 +377,16 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
       float* tp = TAPE ? tape + (((size_t)step * smax + sub) * n_work + w) * TAPE_N * 64 : nullptr;
       if (TAPE) wtape_state(tp, s, lane);
       kinematic_unmasked(s, h);
-      // parent's post-kinematic state: the cross-lane reads are issued first
-      // and this body's rotation is formed while they are in flight; the
-      // parent's rotation matrix is read from the parent lane's own
-      Body P;
-      P.p = V(shfl(s.p.x, src_parent), shfl(s.p.y, src_parent), shfl(s.p.z, src_parent));
-      P.q = s.q;  // unused: the joint reads the parent's orientation as RP
-      P.v = V(shfl(s.v.x, src_parent), shfl(s.v.y, src_parent), shfl(s.v.z, src_parent));
-      P.w = V(shfl(s.w.x, src_parent), shfl(s.w.y, src_parent), shfl(s.w.z, src_parent));
+      // parent's post-kinematic state through the exchange rows: this body's
+      // state is written first and its rotation formed while that is in
+      // flight; the parent's rotation matrix is read from the parent lane's
+      xch_put_pvw(X, lane, s);
       const m3 R = quat_to_mat(s.q);
+      xch_put_rot(X, lane, s.w.z, R);
+      Body P;
       m3 RP;
-#pragma unroll
-      for (int i = 0; i < 9; ++i) RP.m[i] = shfl(R.m[i], src_parent);
+      xch_get_pvw_rot(X, src_parent, P, RP);
+      P.q = s.q;  // unused: the joint reads the parent's orientation as RP
       Frame f = derive_inv(B, R);
       JointChild jc = joint_child<MAXDOF>(J, s, R);
       // the contact candidates while the parent's state is in flight (they
@@ -393,12 +405,12 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
       // children's reactions (child order); a child's reaction on its parent
       // is the opposite of its (F, rP x F + tau), read as is and subtracted
       v3 cf[GATHER], ct[GATHER];
+      xch_put2(X, lane, jo.fc, jo.tpn);
 #pragma unroll
       for (int i = 0; i < GATHER; ++i) {
         if (i < ty.max_children) {
           const int src = base + (i < B.nch ? (int)((B.ch_packed >> (4 * i)) & 15u) : b);
-          cf[i] = V(shfl(jo.fc.x, src), shfl(jo.fc.y, src), shfl(jo.fc.z, src));
-          ct[i] = V(shfl(jo.tpn.x, src), shfl(jo.tpn.y, src), shfl(jo.tpn.z, src));
+          xch_get2(X, src, cf[i], ct[i]);
         }
       }
       const v3 z3 = V(0.f, 0.f, 0.f);
@@ -412,8 +424,8 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
       }
       for (int i = GATHER; i < ty.max_children; ++i) {
         const int src = base + (i < B.nch ? (int)((B.ch_packed >> (4 * i)) & 15u) : b);
-        v3 fc = V(shfl(jo.fc.x, src), shfl(jo.fc.y, src), shfl(jo.fc.z, src));
-        v3 tq = V(shfl(jo.tpn.x, src), shfl(jo.tpn.y, src), shfl(jo.tpn.z, src));
+        v3 fc, tq;
+        xch_get2(X, src, fc, tq);
         if (i < B.nch) {
           force -= fc;
           torque -= tq;
@@ -512,16 +524,18 @@ __global__ __launch_bounds__(256) void k_fused(const Tables* __restrict__ tab, c
                                                Fields out, const float* __restrict__ acts, int Am, int T,
                                                int save_every, Fields traj, uint8_t* nonfinite, float* tape,
                                                int smax) {
+  extern __shared__ float4 fused_lds[];  // exchange rows, one set per wavefront of the block
   const int w = wave_index();
   if (w >= n_work) return;
   const WaveWork wk = work[w];
+  XchRows* X = xch_lanes(fused_lds);
   // wave-uniform: joints of at most one axis take the shorter path
   if (ONE_AXIS || tab->type[wk.type].max_dof <= 1)
     fused_run<1, false, false, REGC>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj,
-                                     nonfinite, nullptr, 0, w, n_work);
+                                     nonfinite, nullptr, 0, w, n_work, X);
   else
     fused_run<3, false, false, REGC>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj,
-                                     nonfinite, nullptr, 0, w, n_work);
+                                     nonfinite, nullptr, 0, w, n_work, X);
 }
 
 // The same with the forward tape: a kernel of its own, so that the tape
@@ -537,15 +551,17 @@ __global__ __launch_bounds__(256) void k_fused_tape(const Tables* __restrict__ t
                                                     Fields out, const float* __restrict__ acts, int Am, int T,
                                                     int save_every, Fields traj, uint8_t* nonfinite, float* tape,
                                                     int smax) {
+  extern __shared__ float4 fused_lds[];
   const int w = wave_index();
   if (w >= n_work) return;
   const WaveWork wk = work[w];
+  XchRows* X = xch_lanes(fused_lds);
   if (tab->type[wk.type].max_dof <= 1)
     fused_run<1, true, false, REGC>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj,
-                                    nonfinite, tape, smax, w, n_work);
+                                    nonfinite, tape, smax, w, n_work, X);
   else
     fused_run<3, true, false, REGC>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj,
-                                    nonfinite, tape, smax, w, n_work);
+                                    nonfinite, tape, smax, w, n_work, X);
 }
 
 // The same for batches with body-body contacts: kernels of their own (with
@@ -561,17 +577,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                                                      Fields out, const float* __restrict__ acts, int Am, int T,
                                                      int save_every, Fields traj, uint8_t* nonfinite, float* tape,
                                                      int smax) {
-  extern __shared__ PairLanes pair_lds[];  // one per wavefront of the block
+  extern __shared__ float4 fused_lds[];  // exchange rows, then body-body tables, one set per wavefront
   const int w = wave_index();
   if (w >= n_work) return;
   const WaveWork wk = work[w];
-  PairLanes* pl = pair_lds + (threadIdx.x >> 6);
+  XchRows* X = xch_lanes(fused_lds);
+  PairLanes* pl = pair_lanes(fused_lds);
   if (ONE_AXIS || tab->type[wk.type].max_dof <= 1)
     fused_run<1, TAPE, true, REGC>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj,
-                                   nonfinite, tape, smax, w, n_work, pl);
+                                   nonfinite, tape, smax, w, n_work, X, pl);
   else
     fused_run<3, TAPE, true, REGC>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj,
-                                   nonfinite, tape, smax, w, n_work, pl);
+                                   nonfinite, tape, smax, w, n_work, X, pl);
 }
 
 // One environment step with the environment layer fused after it (T = 1):
@@ -583,18 +600,19 @@ __global__ __launch_bounds__(256) void k_fused_env(const Tables* __restrict__ ta
                                                    const int32_t* __restrict__ type_off, int E, int Bm, Fields in,
                                                    Fields out, const float* __restrict__ acts, int Am,
                                                    uint8_t* nonfinite, EnvArgs ea) {
-  extern __shared__ PairLanes env_pair_lds[];  // one per wavefront of the block (PAIRS only)
+  extern __shared__ float4 fused_lds[];  // exchange rows, then body-body tables (PAIRS), per wavefront
   const int w = wave_index();
   if (w >= n_work) return;
   const WaveWork wk = work[w];
-  PairLanes* pl = PAIRS ? env_pair_lds + (threadIdx.x >> 6) : nullptr;
+  XchRows* X = xch_lanes(fused_lds);
+  PairLanes* pl = PAIRS ? pair_lanes(fused_lds) : nullptr;
   const Fields none{nullptr, nullptr, nullptr, nullptr};
   if (tab->type[wk.type].max_dof <= 1)
     fused_run<1, false, PAIRS, REGC, true>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, 1, 0, none,
-                                           nonfinite, nullptr, 0, w, n_work, pl, &ea);
+                                           nonfinite, nullptr, 0, w, n_work, X, pl, &ea);
   else
     fused_run<3, false, PAIRS, REGC, true>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, 1, 0, none,
-                                           nonfinite, nullptr, 0, w, n_work, pl, &ea);
+                                           nonfinite, nullptr, 0, w, n_work, X, pl, &ea);
 }
 
 // ------------------------------------------------------------------ small helpers
@@ -623,14 +641,15 @@ hipError_t launch_env_step(const LaunchCtx& c, const WaveWork* work, int n_work,
   const dim3 grid(cdiv(n_work, waves_per_block)), block(64 * waves_per_block);
   uint8_t* nf = flags ? c.nonfinite : nullptr;
   const EnvArgs ea{env, reset, obs, reward, done, Omax};
+  const size_t lds = fused_lds_per_wave(pairs) * waves_per_block;
   if (pairs)
-    hipLaunchKernelGGL((k_fused_env<true, REG_CONTACTS>), grid, block, sizeof(PairLanes) * waves_per_block, s, c.tab,
-                       work, n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, act, c.Am, nf, ea);
+    hipLaunchKernelGGL((k_fused_env<true, REG_CONTACTS>), grid, block, lds, s, c.tab, work, n_work, c.env_list,
+                       c.type_off, c.E, c.Bm, in, out, act, c.Am, nf, ea);
   else if (many_contacts)
-    hipLaunchKernelGGL((k_fused_env<false, 8>), grid, block, 0, s, c.tab, work, n_work, c.env_list, c.type_off, c.E,
-                       c.Bm, in, out, act, c.Am, nf, ea);
+    hipLaunchKernelGGL((k_fused_env<false, 8>), grid, block, lds, s, c.tab, work, n_work, c.env_list, c.type_off,
+                       c.E, c.Bm, in, out, act, c.Am, nf, ea);
   else
-    hipLaunchKernelGGL((k_fused_env<false, REG_CONTACTS>), grid, block, 0, s, c.tab, work, n_work, c.env_list,
+    hipLaunchKernelGGL((k_fused_env<false, REG_CONTACTS>), grid, block, lds, s, c.tab, work, n_work, c.env_list,
                        c.type_off, c.E, c.Bm, in, out, act, c.Am, nf, ea);
   return hipGetLastError();
 }
@@ -660,8 +679,8 @@ hipError_t launch_fused(const LaunchCtx& c, const WaveWork* work, int n_work, in
     one_axis = one_axis && c.host_tab->type[t].max_dof <= 1;
     many_contacts = many_contacts || c.host_tab->type[t].max_contacts > REG_CONTACTS;
   }
+  const size_t lds = fused_lds_per_wave(pairs) * waves_per_block;
   if (pairs) {
-    const size_t lds = sizeof(PairLanes) * waves_per_block;
     const dim3 grid(cdiv(n_work, waves_per_block)), block(64 * waves_per_block);
     uint8_t* nf = flags ? c.nonfinite : nullptr;
     // the tape kernel keeps two register candidates (the tape rows take the registers)
@@ -680,27 +699,27 @@ hipError_t launch_fused(const LaunchCtx& c, const WaveWork* work, int n_work, in
     return hipGetLastError();
   }
   if (tape && many_contacts)
-    hipLaunchKernelGGL((k_fused_tape<8>), dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block), 0, s,
+    hipLaunchKernelGGL((k_fused_tape<8>), dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block), lds, s,
                        c.tab, work, n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every,
                        traj, flags ? c.nonfinite : nullptr, tape, smax);
   else if (tape)
     hipLaunchKernelGGL((k_fused_tape<REG_CONTACTS>), dim3(cdiv(n_work, waves_per_block)), dim3(64 * waves_per_block),
-                       0, s, c.tab, work, n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T,
+                       lds, s, c.tab, work, n_work, c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T,
                        save_every, traj, flags ? c.nonfinite : nullptr, tape, smax);
   else {
     const dim3 grid(cdiv(n_work, waves_per_block)), block(64 * waves_per_block);
     uint8_t* nf = flags ? c.nonfinite : nullptr;
     if (one_axis && many_contacts)
-      hipLaunchKernelGGL((k_fused<true, 8>), grid, block, 0, s, c.tab, work, n_work, c.env_list, c.type_off, c.E,
+      hipLaunchKernelGGL((k_fused<true, 8>), grid, block, lds, s, c.tab, work, n_work, c.env_list, c.type_off, c.E,
                          c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0);
     else if (one_axis)
-      hipLaunchKernelGGL((k_fused<true, REG_CONTACTS>), grid, block, 0, s, c.tab, work, n_work, c.env_list,
+      hipLaunchKernelGGL((k_fused<true, REG_CONTACTS>), grid, block, lds, s, c.tab, work, n_work, c.env_list,
                          c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0);
     else if (many_contacts)
-      hipLaunchKernelGGL((k_fused<false, 8>), grid, block, 0, s, c.tab, work, n_work, c.env_list, c.type_off, c.E,
+      hipLaunchKernelGGL((k_fused<false, 8>), grid, block, lds, s, c.tab, work, n_work, c.env_list, c.type_off, c.E,
                          c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0);
     else
-      hipLaunchKernelGGL((k_fused<false, REG_CONTACTS>), grid, block, 0, s, c.tab, work, n_work, c.env_list,
+      hipLaunchKernelGGL((k_fused<false, REG_CONTACTS>), grid, block, lds, s, c.tab, work, n_work, c.env_list,
                          c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0);
   }
   return hipGetLastError();

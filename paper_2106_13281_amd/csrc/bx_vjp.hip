@@ -274,26 +274,9 @@ __global__ void k_adj_kinematic(const Tables* __restrict__ tab, int t, const int
 // first with their tape in LDS ([substep][TAPE_N][64 lanes] per wavefront,
 // lane fastest); then the substeps run backwards, each lane computing its
 // body's integrate, joint (+ actuator) and contact adjoints. The parent's
-// post-kinematic state and force/torque cotangents come by cross-lane reads;
-// each child's cotangent for its parent is read by the parent lane in child
-// order.
-__device__ __forceinline__ Body shfl_body(const Body& s, int src) {
-  Body r;
-  r.p = V(shfl(s.p.x, src), shfl(s.p.y, src), shfl(s.p.z, src));
-  r.q = q4{shfl(s.q.w, src), shfl(s.q.x, src), shfl(s.q.y, src), shfl(s.q.z, src)};
-  r.v = V(shfl(s.v.x, src), shfl(s.v.y, src), shfl(s.v.z, src));
-  r.w = V(shfl(s.w.x, src), shfl(s.w.y, src), shfl(s.w.z, src));
-  return r;
-}
-__device__ __forceinline__ Bar shfl_bar(const Bar& s, int src) {
-  Bar r;
-  r.p = V(shfl(s.p.x, src), shfl(s.p.y, src), shfl(s.p.z, src));
-  r.q = q4{shfl(s.q.w, src), shfl(s.q.x, src), shfl(s.q.y, src), shfl(s.q.z, src)};
-  r.v = V(shfl(s.v.x, src), shfl(s.v.y, src), shfl(s.v.z, src));
-  r.w = V(shfl(s.w.x, src), shfl(s.w.y, src), shfl(s.w.z, src));
-  return r;
-}
-__device__ __forceinline__ v3 shfl3(v3 a, int src) { return V(shfl(a.x, src), shfl(a.y, src), shfl(a.z, src)); }
+// post-kinematic state and force/torque cotangents come through the
+// wavefront's exchange rows; each child's cotangent for its parent is read
+// by the parent lane in child order.
 
 // FROM_TAPE: the forward substeps are not recomputed; their tape records are
 // read from the wavefront-major hbm_tape[step][sub][work item w of n_work][TAPE_N][64]
@@ -311,7 +294,7 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
                                               const int32_t* __restrict__ type_off, int E, int Bm, int Am,
                                               const Fields& in, const float* __restrict__ act, const Fields& g_out,
                                               const Fields& g_in, float* __restrict__ g_act, float* lds,
-                                              const float* __restrict__ hbm_tape, int w, int n_work,
+                                              XchRows* X, const float* __restrict__ hbm_tape, int w, int n_work,
                                               float* __restrict__ g_params = nullptr, int p_max = 0,
                                               PairLanes* pl = nullptr, int T = 1, size_t tstride = 0) {
   constexpr int TN = PARAMS ? TAPE_N + 3 : TAPE_N;  // LDS tape rows per substep
@@ -353,17 +336,15 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
     tp[448] = s.v.x; tp[512] = s.v.y; tp[576] = s.v.z;
     tp[640] = s.w.x; tp[704] = s.w.y; tp[768] = s.w.z;
     kinematic(B, s, h);
-    // as in the forward kernel: parent reads first, the parent's rotation
-    // matrix read from the parent lane
-    Body P;
-    P.p = shfl3(s.p, src_parent);
-    P.q = s.q;  // unused: the joint reads the parent's orientation as RP
-    P.v = shfl3(s.v, src_parent);
-    P.w = shfl3(s.w, src_parent);
+    // as in the forward kernel: this body's state written first, the
+    // parent's rotation matrix read from the parent lane's row
+    xch_put_pvw(X, lane, s);
     const m3 R = quat_to_mat(s.q);
+    xch_put_rot(X, lane, s.w.z, R);
+    Body P;
     m3 RP;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) RP.m[i] = shfl(R.m[i], src_parent);
+    xch_get_pvw_rot(X, src_parent, P, RP);
+    P.q = s.q;  // unused: the joint reads the parent's orientation as RP
     Frame f = derive_inv(B, R);
     JointChild jc = joint_child<MAXDOF>(J, s, R);
     const v3 z3 = V(0.f, 0.f, 0.f);
@@ -371,12 +352,12 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
     if (!has_joint) jo.fc = jo.tc = jo.fp = jo.tp = jo.tpn = z3;
     // children's reactions read un-negated and subtracted (as in the forward)
     v3 cf[GATHER], ct[GATHER];
+    xch_put2(X, lane, jo.fc, jo.tpn);
 #pragma unroll
     for (int i = 0; i < GATHER; ++i) {
       if (i < ty.max_children) {
         const int src = base + (i < B.nch ? (int)((B.ch_packed >> (4 * i)) & 15u) : b);
-        cf[i] = shfl3(jo.fc, src);
-        ct[i] = shfl3(jo.tpn, src);
+        xch_get2(X, src, cf[i], ct[i]);
       }
     }
     v3 dv = z3, dw = z3;
@@ -397,7 +378,8 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
     }
     for (int i = GATHER; i < ty.max_children; ++i) {
       const int src = base + (i < B.nch ? (int)((B.ch_packed >> (4 * i)) & 15u) : b);
-      v3 fc = shfl3(jo.fc, src), tq = shfl3(jo.tpn, src);
+      v3 fc, tq;
+      xch_get2(X, src, fc, tq);
       if (i < B.nch) {
         force -= fc;
         torque -= tq;
@@ -456,14 +438,17 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
       }
       Body post = pre;
       kinematic(B, post, h);
-      Body P = shfl_body(post, src_parent);
+      xch_put_body(X, lane, post);
+      Body P = xch_get_body<Body>(X, src_parent);
       Frame f = derive(B, post);
       v3 fb, tb, dvb, dwb;
       // this body's frame cotangents from every item of the substep, turned
       // into its quaternion cotangent once at the end
       FrameBar fr = framebar_zero();
       Bar tot = integrate_adj(B, ty, post, f, ttot, n, G, fb, tb, dvb, dwb, fr, ftot, invm_bar);
-      v3 fbP = shfl3(fb, src_parent), tbP = shfl3(tb, src_parent);
+      xch_put2(X, lane, fb, tb);
+      v3 fbP, tbP;
+      xch_get2(X, src_parent, fbP, tbP);
       Bar bP = bar_zero(), bC = bar_zero();
       {
         // evaluated on every lane so that it interleaves with the contacts; a
@@ -478,11 +463,12 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
       }
       // children's cotangents for this body: reads in flight during the contact adjoints
       Bar cb[GATHER];
+      xch_put_body(X, lane, bP);
 #pragma unroll
       for (int i = 0; i < GATHER; ++i) {
         if (i < ty.max_children) {
           const int src = base + (i < B.nch ? (int)((B.ch_packed >> (4 * i)) & 15u) : b);
-          cb[i] = shfl_bar(bP, src);
+          cb[i] = xch_get_body<Bar>(X, src);
         }
       }
       auto contact_back = [&](const ContactT& C) {
@@ -515,7 +501,7 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
         if (i < B.nch) bar_add(tot, cb[i]);
       for (int i = GATHER; i < ty.max_children; ++i) {
         const int src = base + (i < B.nch ? (int)((B.ch_packed >> (4 * i)) & 15u) : b);
-        Bar x = shfl_bar(bP, src);
+        Bar x = xch_get_body<Bar>(X, src);
         if (i < B.nch) bar_add(tot, x);
       }
       G = kinematic_adj(B, pre, h, tot);
@@ -569,19 +555,20 @@ __global__ __launch_bounds__(64) void k_fused_vjp(const Tables* __restrict__ tab
                                                   const int32_t* __restrict__ type_off, int E, int Bm, int Am,
                                                   int smax, Fields in, const float* __restrict__ act, Fields g_out,
                                                   Fields g_in, float* __restrict__ g_act) {
-  extern __shared__ float lds_tape[];  // [body-body tables (PAIRS)] [substep tape]
+  extern __shared__ float4 lds_tape[];  // [exchange rows] [body-body tables (PAIRS)] [substep tape]
   const int w = xcd_block(blockIdx.x, gridDim.x);
   if (w >= n_work) return;
   const WaveWork wk = work[w];
-  PairLanes* pl = PAIRS ? reinterpret_cast<PairLanes*>(lds_tape) : nullptr;
-  float* lds = lds_tape + (PAIRS ? sizeof(PairLanes) / 4 : 0);
+  XchRows* X = reinterpret_cast<XchRows*>(lds_tape);
+  PairLanes* pl = PAIRS ? reinterpret_cast<PairLanes*>(X + 1) : nullptr;
+  float* lds = reinterpret_cast<float*>(X + 1) + (PAIRS ? sizeof(PairLanes) / 4 : 0);
   (void)smax;
   if (ONE_AXIS || tab->type[wk.type].max_dof <= 1)
     fused_vjp_run<1, false, false, PAIRS, REGC>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds,
-        nullptr, w, n_work, nullptr, 0, pl);
+        X, nullptr, w, n_work, nullptr, 0, pl);
   else
     fused_vjp_run<3, false, false, PAIRS, REGC>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds,
-        nullptr, w, n_work, nullptr, 0, pl);
+        X, nullptr, w, n_work, nullptr, 0, pl);
 }
 
 // The adjoint of one step with the cotangents of the system parameters.
@@ -593,22 +580,24 @@ __global__ __launch_bounds__(64) void k_fused_vjp_params(const Tables* __restric
                                                          Fields in, const float* __restrict__ act, Fields g_out,
                                                          Fields g_in, float* __restrict__ g_act,
                                                          float* __restrict__ g_params, int p_max) {
-  extern __shared__ float lds_tape[];  // [body-body tables (PAIRS)] [substep tape]
+  extern __shared__ float4 lds_tape[];  // [exchange rows] [body-body tables (PAIRS)] [substep tape]
   const int w = xcd_block(blockIdx.x, gridDim.x);
   if (w >= n_work) return;
   const WaveWork wk = work[w];
-  PairLanes* pl = PAIRS ? reinterpret_cast<PairLanes*>(lds_tape) : nullptr;
-  float* lds = lds_tape + (PAIRS ? sizeof(PairLanes) / 4 : 0);
+  XchRows* X = reinterpret_cast<XchRows*>(lds_tape);
+  PairLanes* pl = PAIRS ? reinterpret_cast<PairLanes*>(X + 1) : nullptr;
+  float* lds = reinterpret_cast<float*>(X + 1) + (PAIRS ? sizeof(PairLanes) / 4 : 0);
   if (ONE_AXIS || tab->type[wk.type].max_dof <= 1)
     fused_vjp_run<1, false, true, PAIRS, REGC>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds,
-                                         nullptr, w, n_work, g_params, p_max, pl);
+                                         X, nullptr, w, n_work, g_params, p_max, pl);
   else
     fused_vjp_run<3, false, true, PAIRS, REGC>(tab, wk, env_list, type_off, E, Bm, Am, in, act, g_out, g_in, g_act, lds,
-                                         nullptr, w, n_work, g_params, p_max, pl);
+                                         X, nullptr, w, n_work, g_params, p_max, pl);
 }
 
 // The adjoint of T consecutive steps from their forward tape in HBM (no
-// recompute, no LDS), the last step first.
+// recompute; LDS holds only the exchange rows and body-body tables), the
+// last step first.
 template <bool PAIRS, bool ONE_AXIS, int REGC>
 __global__ __launch_bounds__(64) void k_fused_vjp_tape(const Tables* __restrict__ tab,
                                                        const WaveWork* __restrict__ work, int n_work,
@@ -617,18 +606,19 @@ __global__ __launch_bounds__(64) void k_fused_vjp_tape(const Tables* __restrict_
                                                        const float* __restrict__ tape, size_t tstride, int T,
                                                        const float* __restrict__ act, Fields g_out, Fields g_in,
                                                        float* __restrict__ g_act) {
-  extern __shared__ float lds_pairs[];  // body-body tables (PAIRS)
+  extern __shared__ float4 lds_xch[];  // [exchange rows] [body-body tables (PAIRS)]
   const int w = xcd_block(blockIdx.x, gridDim.x);
   if (w >= n_work) return;
   const WaveWork wk = work[w];
   const Fields none{nullptr, nullptr, nullptr, nullptr};
-  PairLanes* pl = PAIRS ? reinterpret_cast<PairLanes*>(lds_pairs) : nullptr;
+  XchRows* X = reinterpret_cast<XchRows*>(lds_xch);
+  PairLanes* pl = PAIRS ? reinterpret_cast<PairLanes*>(X + 1) : nullptr;
   if (ONE_AXIS || tab->type[wk.type].max_dof <= 1)
     fused_vjp_run<1, true, false, PAIRS, REGC>(tab, wk, env_list, type_off, E, Bm, Am, none, act, g_out, g_in, g_act,
-        nullptr, tape, w, n_work, nullptr, 0, pl, T, tstride);
+        nullptr, X, tape, w, n_work, nullptr, 0, pl, T, tstride);
   else
     fused_vjp_run<3, true, false, PAIRS, REGC>(tab, wk, env_list, type_off, E, Bm, Am, none, act, g_out, g_in, g_act,
-        nullptr, tape, w, n_work, nullptr, 0, pl, T, tstride);
+        nullptr, X, tape, w, n_work, nullptr, 0, pl, T, tstride);
 }
 
 // Whether a type of the batch has body-body contact candidates: the kernels
@@ -746,7 +736,7 @@ size_t vjp_lds_bytes(const Tables& tab, int n_types, bool params) {
     smax = std::max(smax, (size_t)tab.type[t].substeps);
     pairs = pairs || tab.type[t].np > 0;
   }
-  return smax * (TAPE_N + (params ? 3 : 0)) * 64 * sizeof(float) + (pairs ? sizeof(PairLanes) : 0);
+  return sizeof(XchRows) + smax * (TAPE_N + (params ? 3 : 0)) * 64 * sizeof(float) + (pairs ? sizeof(PairLanes) : 0);
 }
 
 hipError_t launch_vjp_params(const LaunchCtx& c, const VjpSched& sched, Fields in, const float* act, Fields g_out,
@@ -754,7 +744,7 @@ hipError_t launch_vjp_params(const LaunchCtx& c, const VjpSched& sched, Fields i
   if (sched.n_work == 0) return hipSuccess;
   size_t smax = 1;
   for (int t = 0; t < c.n_types; ++t) smax = std::max(smax, (size_t)c.host_tab->type[t].substeps);
-  const size_t lds = smax * (TAPE_N + 3) * 64 * sizeof(float);
+  const size_t lds = sizeof(XchRows) + smax * (TAPE_N + 3) * 64 * sizeof(float);
   if (any_pairs(c))
     LAUNCH_AXES(k_fused_vjp_params, true, dim3(sched.n_work), dim3(64), lds + sizeof(PairLanes), s, c.tab, sched.work,
                 sched.n_work, c.env_list, c.type_off, c.E, c.Bm, c.Am, in, act, g_out, g_in, g_act, g_params, p_max);
@@ -768,10 +758,10 @@ hipError_t launch_vjp_tape(const LaunchCtx& c, const VjpSched& sched, const floa
                            const float* act, Fields g_out, Fields g_in, float* g_act, hipStream_t s) {
   if (sched.n_work == 0 || T <= 0) return hipSuccess;
   if (any_pairs(c))
-    LAUNCH_AXES(k_fused_vjp_tape, true, dim3(sched.n_work), dim3(64), sizeof(PairLanes), s, c.tab, sched.work,
+    LAUNCH_AXES(k_fused_vjp_tape, true, dim3(sched.n_work), dim3(64), sizeof(XchRows) + sizeof(PairLanes), s, c.tab, sched.work,
                 sched.n_work, c.env_list, c.type_off, c.E, c.Bm, c.Am, tape, tstride, T, act, g_out, g_in, g_act);
   else
-    LAUNCH_AXES(k_fused_vjp_tape, false, dim3(sched.n_work), dim3(64), 0, s, c.tab, sched.work, sched.n_work,
+    LAUNCH_AXES(k_fused_vjp_tape, false, dim3(sched.n_work), dim3(64), sizeof(XchRows), s, c.tab, sched.work, sched.n_work,
                 c.env_list, c.type_off, c.E, c.Bm, c.Am, tape, tstride, T, act, g_out, g_in, g_act);
   return hipGetLastError();
 }
@@ -794,7 +784,7 @@ hipError_t launch_vjp(const LaunchCtx& c, VjpWork& w, const VjpSched& sched, Fie
   p += 6 * nbe;
   if (!plain) {
     // one wavefront per block; its tape lives in LDS
-    const size_t lds = smax * TAPE_N * 64 * sizeof(float);
+    const size_t lds = sizeof(XchRows) + smax * TAPE_N * 64 * sizeof(float);
     if (sched.n_work == 0) return hipSuccess;
     if (any_pairs(c))
       LAUNCH_AXES(k_fused_vjp, true, dim3(sched.n_work), dim3(64), lds + sizeof(PairLanes), s, c.tab, sched.work,

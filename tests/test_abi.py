@@ -124,6 +124,9 @@ def test_argument_errors():
     assert L.brax_rollout(s._h, C.byref(st), None, -1, 0, None, C.byref(st), 0, None) == -1
     assert L.brax_rollout_vjp_tape(s._h, None, None, 1, C.byref(st), C.byref(st), None, 0, None) == -1
     assert b"host-only" in L.brax_last_error()
+    assert L.brax_autotune_on(s._h, C.byref(st), None, 8, None) == -1
+    assert b"host-only" in L.brax_last_error()
+    assert L.brax_autotune_on(None, C.byref(st), None, 8, None) == -1
     assert L.brax_sys_query(None, None) == -1
     L.brax_sys_destroy(None)  # no-op
 
@@ -191,18 +194,20 @@ def test_flag_values_and_combinations():
 
 def test_adjoint_tape_size_is_reported_against_the_lds_limit():
     """The fused adjoint keeps each substep's tape on chip: 17 floats per lane
-    (20 with parameter cotangents) x 64 lanes per substep; the query reports
-    it beside the per-workgroup limit (160 KiB for a host-only handle), so a
+    (20 with parameter cotangents) x 64 lanes per substep, beside the
+    wavefront's exchange rows (20 floats per lane); the query reports it
+    beside the per-workgroup limit (160 KiB for a host-only handle), so a
     system with many substeps is seen to exceed it (such batches take the
     per-phase adjoint; the parameter adjoint refuses them)."""
     few = "substeps: 10\n" + BODY.format(n="a")
     many = "substeps: 200\n" + BODY.format(n="a")
     s10, s200 = host(few), host(many)
-    assert s10.vjp_lds_bytes == 10 * 17 * 64 * 4
-    assert s10.vjp_params_lds_bytes == 10 * 20 * 64 * 4
+    xch = 20 * 64 * 4
+    assert s10.vjp_lds_bytes == 10 * 17 * 64 * 4 + xch
+    assert s10.vjp_params_lds_bytes == 10 * 20 * 64 * 4 + xch
     assert s10.lds_limit == 160 * 1024
     assert s10.vjp_lds_bytes <= s10.lds_limit
-    assert s200.vjp_lds_bytes == 200 * 17 * 64 * 4 > s200.lds_limit
+    assert s200.vjp_lds_bytes == 200 * 17 * 64 * 4 + xch > s200.lds_limit
     # the bench and test systems all fit
     for name in SYSTEMS:
         s = host(synth.system_text(name))

@@ -7,6 +7,8 @@ rollouts; single steps excuse only branch-ambiguous environments (at most
 1%), rollouts only environments where the oracle itself is FP32-sensitive
 (see helpers).
 """
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -265,6 +267,19 @@ def test_autotune_keeps_results():
     after, _ = sysg.rollout(to_dev(X), a)
     for x, y in zip(before.fields(), after.fields()):
         assert torch.equal(x, y)
+    # tuned on the caller's state and actions: the inputs are left as they
+    # were, and the results again do not depend on the shape chosen
+    inp, acts20 = to_dev(X), acts_dev(acts[:20])
+    keep = [x.clone() for x in inp.fields()] + [acts20.clone()]
+    epw, wpb = sysg.autotune_on(inp, acts20)
+    assert 1 <= epw <= 7 and wpb in (1, 2, 4)
+    for x, y in zip(list(inp.fields()) + [acts20], keep):
+        assert torch.equal(x, y)
+    after, _ = sysg.rollout(to_dev(X), a)
+    for x, y in zip(before.fields(), after.fields()):
+        assert torch.equal(x, y)
+    st = inp.struct()
+    assert braxmi.lib().brax_autotune_on(sysg._h, ctypes.byref(st), None, 0, None) == -1  # T < 1
 
 
 def test_graph_cache_tells_apart_every_buffer():
