@@ -10,6 +10,7 @@ roofline of the dominant kernel and the FP64 oracle timed on the host cores.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -91,16 +92,23 @@ def make_inputs(system, wl, seed=0):
 
 
 def time_calls(fn, reps, warmup):
-    """Average ms per call with HIP events on torch's current stream (the one the library uses)."""
+    """Average ms per call with HIP events on torch's current stream (the one the library uses).
+    Python's cyclic garbage collector is held off over the timed calls (as timeit does): a full
+    collection inside a loop of short calls stalls the host for tens of milliseconds."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        fn()
-    e1.record()
-    torch.cuda.synchronize()
+    gc.collect()
+    gc.disable()
+    try:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+    finally:
+        gc.enable()
     return e0.elapsed_time(e1) / reps
 
 

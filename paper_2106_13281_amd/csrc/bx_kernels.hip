@@ -432,7 +432,7 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
         }
       }
       // body-body contacts after the joint sums, where fewer values are live
-      if (PAIRS && ty.np > 0) pair_phase(tab, t, *pl, b, base, s, f, dv, dw, cnt);
+      if (PAIRS && ty.np > 0) pair_phase(tab, t, *pl, X, lane, b, base, s, f, dv, dw, cnt);
       if (TAPE) wtape_rest(tp, torque, cnt, lane);
       // without frozen axes in the type (wave-uniform) the integrators skip the masks
       if (ty.frozen) {

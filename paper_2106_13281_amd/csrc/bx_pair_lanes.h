@@ -3,15 +3,15 @@
 // Each candidate is evaluated on the lane of one body of the environment
 // (its handler, chosen when the tables are packed so that the candidates
 // spread over all of the environment's lanes); the two bodies' states and
-// frames come by cross-lane reads. The handler leaves both shares in
-// registers; in the same evaluation slot each body's lane collects its
-// shares from the handler lanes listed in its table row, first-body shares
-// and second-body shares in two passes. An evaluation slot in which no lane
-// of the wavefront has a candidate whose body origins are within reach is
-// skipped as a whole (no contact is possible there). The loops run to the
-// type's maxima so that every cross-lane read executes on the whole
-// wavefront; a lane without work in a slot reads its own values and
-// discards them.
+// frames come from the side rows every lane writes to LDS once per substep.
+// The handler writes both shares to its exchange row; in the same evaluation
+// slot each body's lane collects its shares from the handler lanes listed in
+// its table row, first-body shares and second-body shares in two passes. An
+// evaluation slot in which no lane of the wavefront has a candidate whose
+// body origins are within reach is skipped as a whole (no contact is
+// possible there). The loops run to the type's maxima, so that the
+// wavefront takes every read together; a lane without work in a slot reads
+// its own values and discards them.
 #pragma once
 #include "bx_access.h"
 #include "bx_pair_adj.h"
@@ -24,6 +24,11 @@ __device__ __forceinline__ v3 shfl_v3(v3 a, int src) { return V(shfl(a.x, src), 
 // lanes read them at lane-varying indices every substep, which from LDS
 // costs a fraction of the latency of the device-memory tables.
 struct PairLanes {
+  // each lane's post-kinematic state and frame for the handlers, rewritten
+  // every substep: p.xyz v.x | v.yz w.xy | w.z R0-2 | R3-6 | R7-8 Iwinv.xx yy |
+  // Iwinv.zz xy xz yz (rows of 28 floats: 16-byte reads of eight consecutive
+  // lanes fall on distinct banks)
+  float4 side[64][7];
   PairT pair[MAXP];
   int32_t nh[MAXB];
   int32_t hp[MAXB][MAXH];
@@ -68,44 +73,75 @@ __device__ __forceinline__ PairSide shfl_side(const PairSide& s, int src, v3 p) 
   return o;
 }
 
+__device__ __forceinline__ void side_put(PairLanes& L, int lane, const Body& s, const Frame& f) {
+  float4* r = L.side[lane];
+  const m3& R = f.R;
+  const s3& I = f.Iwinv;
+  r[0] = make_float4(s.p.x, s.p.y, s.p.z, s.v.x);
+  r[1] = make_float4(s.v.y, s.v.z, s.w.x, s.w.y);
+  r[2] = make_float4(s.w.z, R.m[0], R.m[1], R.m[2]);
+  r[3] = make_float4(R.m[3], R.m[4], R.m[5], R.m[6]);
+  r[4] = make_float4(R.m[7], R.m[8], I.xx, I.yy);
+  r[5] = make_float4(I.zz, I.xy, I.xz, I.yz);
+}
+
+// The side of the body on lane src, whose first row r0 was read already.
+__device__ __forceinline__ PairSide side_get(const PairLanes& L, int src, float4 r0) {
+  const float4* r = L.side[src];
+  const float4 r1 = r[1], r2 = r[2], r3 = r[3], r4 = r[4], r5 = r[5];
+  PairSide o;
+  o.p = V(r0.x, r0.y, r0.z);
+  o.v = V(r0.w, r1.x, r1.y);
+  o.w = V(r1.z, r1.w, r2.x);
+  o.R.m[0] = r2.y; o.R.m[1] = r2.z; o.R.m[2] = r2.w;
+  o.R.m[3] = r3.x; o.R.m[4] = r3.y; o.R.m[5] = r3.z; o.R.m[6] = r3.w;
+  o.R.m[7] = r4.x; o.R.m[8] = r4.y;
+  o.Iwinv = s3{r4.z, r4.w, r5.x, r5.y, r5.z, r5.w};
+  return o;
+}
+
 // Whether any lane of the wavefront has a candidate within reach in this
-// slot; the two body origins come by cross-lane reads.
+// slot.
 __device__ __forceinline__ bool pair_near(const PairT& P, bool mine, v3 pA, v3 pB) {
   const v3 d = pA - pB;
   return mine && dot(d, d) <= P.reach * P.reach;
 }
 
 // Forward: adds this body's body-body velocity changes to dv, dw and the
-// applied candidates to cnt (post-kinematic state s, frame f).
-__device__ __forceinline__ void pair_phase(const Tables* __restrict__ tab, int t, const PairLanes& L, int b,
-                                           int base, const Body& s, const Frame& f, v3& dv, v3& dw, int& cnt) {
+// applied candidates to cnt (post-kinematic state s, frame f). The shares
+// travel through the wavefront's exchange rows X, free at this point of the
+// substep: dvA on | dwA on | dvB on | dwB on.
+__device__ __forceinline__ void pair_phase(const Tables* __restrict__ tab, int t, PairLanes& L, XchRows* X, int lane,
+                                           int b, int base, const Body& s, const Frame& f, v3& dv, v3& dw, int& cnt) {
   const TypeT& ty = tab->type[t];
   const int nh = L.nh[b];
-  const PairSide me{s.p, s.v, s.w, f.R, f.Iwinv};
+  side_put(L, lane, s, f);
   for (int i = 0; i < ty.max_handled; ++i) {
     const bool mine = i < nh;
     const PairT& P = L.pair[L.hp[b][i]];  // hp = 0 past nh: a valid candidate, unused
     const int sa = base + (mine ? P.a : b), sb = base + (mine ? P.b : b);
-    const v3 pA = shfl_v3(s.p, sa), pB = shfl_v3(s.p, sb);
-    const bool near = pair_near(P, mine, pA, pB);
+    const float4 ra = L.side[sa][0], rb = L.side[sb][0];
+    const bool near = pair_near(P, mine, V(ra.x, ra.y, ra.z), V(rb.x, rb.y, rb.z));
     if (__ballot(near) == 0ull) continue;  // wave-uniform
-    const PairSide A = shfl_side(me, sa, pA), B = shfl_side(me, sb, pB);
+    const PairSide A = side_get(L, sa, ra), B = side_get(L, sb, rb);
     v3 dvA = V(0.f, 0.f, 0.f), dwA = dvA, dvB = dvA, dwB = dvA;
     float on = 0.f;
     if (near && pair_eval(P, ty, A, B, dvA, dwA, dvB, dwB)) on = 1.f;
+    X->r[lane][0] = make_float4(dvA.x, dvA.y, dvA.z, on);
+    X->r[lane][1] = make_float4(dwA.x, dwA.y, dwA.z, on);
+    X->r[lane][2] = make_float4(dvB.x, dvB.y, dvB.z, on);
+    X->r[lane][3] = make_float4(dwB.x, dwB.y, dwB.z, on);
     // collect: first-body shares, then second-body shares
     for (int side = 0; side < 2; ++side) {
       const int nr = side == 0 ? L.nra[b][i] : L.nrb[b][i];
       const uint32_t rv = side == 0 ? L.recva[b][i] : L.recvb[b][i];
       const int kmax = side == 0 ? ty.recv_na[i] : ty.recv_nb[i];
-      const v3 xv = sel(side == 0, dvA, dvB), xw = sel(side == 0, dwA, dwB);
       for (int k = 0; k < kmax; ++k) {
         const int hsrc = base + (k < nr ? (int)((rv >> (4 * k)) & 15u) : b);
-        const v3 a = shfl_v3(xv, hsrc), w = shfl_v3(xw, hsrc);
-        const float got = shfl(on, hsrc);
-        if (k < nr && got != 0.f) {
-          dv += a;
-          dw += w;
+        const float4 a = X->r[hsrc][2 * side], w = X->r[hsrc][2 * side + 1];
+        if (k < nr && a.w != 0.f) {
+          dv += V(a.x, a.y, a.z);
+          dw += V(w.x, w.y, w.z);
           ++cnt;
         }
       }

@@ -385,7 +385,7 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
         torque -= tq;
       }
     }
-    if (PAIRS && ty.np > 0) pair_phase(tab, t, *pl, b, base, s, f, dv, dw, cnt);
+    if (PAIRS && ty.np > 0) pair_phase(tab, t, *pl, X, lane, b, base, s, f, dv, dw, cnt);
     tp[832] = torque.x; tp[896] = torque.y; tp[960] = torque.z;
     tp[1024] = (float)cnt;
     if (PARAMS) {
