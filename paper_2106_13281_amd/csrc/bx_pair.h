@@ -174,67 +174,56 @@ BXF float seg_box_param(v3 a0, v3 da, v3 c, const m3& Rb, const float* h, PairGe
   g.q0s = q0;
   g.dqs = dq;
   const float qa[3] = {q0.x, q0.y, q0.z}, qd[3] = {dq.x, dq.y, dq.z};
-  float sL = -1.f, fL = 0.f, sR = 2.f;
+  // straight-line code (selects, no branches) up to the through-box test:
+  // the lanes of a wavefront take it together
+  float sL = -1.f, sR = 2.f;
   auto consider = [&](float s) {
     float f = 0.f;
     for (int k = 0; k < 3; ++k) {
       const float q = qa[k] + s * qd[k];
       f += (q - clampf(q, -h[k], h[k])) * qd[k];
     }
-    if (f >= 0.f) {
-      sR = fminf(sR, s);
-    } else if (s > sL) {
-      sL = s;
-      fL = f;
-    }
+    const bool up = f >= 0.f;
+    sR = up ? fminf(sR, s) : sR;
+    sL = (!up && s > sL) ? s : sL;
   };
   consider(0.f);
   consider(1.f);
-  for (int k = 0; k < 3; ++k)
-    if (qd[k] != 0.f) {
-      consider(clampf((h[k] - qa[k]) / qd[k], 0.f, 1.f));
-      consider(clampf((-h[k] - qa[k]) / qd[k], 0.f, 1.f));
-    }
-  (void)fL;
-  g.act = 0;
-  g.sig = V(0.f, 0.f, 0.f);
-  g.sD = 0.f;
-  g.sbin = 0;
-  g.li = g.lj = -1;
-  float s;
-  if (sR > 1.f) {
-    s = 1.f;
-  } else if (sL < 0.f) {
-    s = sR;
-  } else {
-    const float mid = 0.5f * (sL + sR);
-    float N = 0.f, D = 0.f, sg[3] = {0.f, 0.f, 0.f};
-    for (int k = 0; k < 3; ++k) {
-      const float q = qa[k] + mid * qd[k];
-      if (fabsf(q) > h[k]) {
-        sg[k] = q >= 0.f ? 1.f : -1.f;
-        N += (qa[k] - sg[k] * h[k]) * qd[k];
-        D += qd[k] * qd[k];
-        g.act |= 1 << k;
-      }
-    }
-    g.sig = V(sg[0], sg[1], sg[2]);
-    g.sD = D;
-    s = D > 0.f ? clampf(-N / D, sL, sR) : sR;
-  }
-  // does the segment pass through the box? (the parameters with every
-  // |q_k(s)| < h_k form an interval of positive length)
+  // the face crossings t1, t2 of each coordinate; one that does not move
+  // (dq_k = 0) gives infinite or undefined crossings, which clamp to an end
+  // already considered or fail every comparison (no change), and leave the
+  // through-box interval below unbounded (|q_k| < h_k) or empty
   float te = 0.f, tx = 1.f;
   for (int k = 0; k < 3; ++k) {
-    if (qd[k] != 0.f) {
-      const float t1 = (-h[k] - qa[k]) / qd[k], t2 = (h[k] - qa[k]) / qd[k];
-      te = fmaxf(te, fminf(t1, t2));
-      tx = fminf(tx, fmaxf(t1, t2));
-    } else if (!(fabsf(qa[k]) < h[k])) {
-      te = 1.f;
-      tx = 0.f;
-    }
+    const float t1 = (-h[k] - qa[k]) / qd[k], t2 = (h[k] - qa[k]) / qd[k];
+    consider(clampf(t2, 0.f, 1.f));
+    consider(clampf(t1, 0.f, 1.f));
+    te = fmaxf(te, fminf(t1, t2));
+    tx = fminf(tx, fmaxf(t1, t2));
   }
+  g.sbin = 0;
+  g.li = g.lj = -1;
+  // outside: the minimiser on the bracket [sL, sR], from the coordinates
+  // beyond their faces at its middle
+  const float mid = 0.5f * (sL + sR);
+  float N = 0.f, D = 0.f, sg[3];
+  int act = 0;
+  for (int k = 0; k < 3; ++k) {
+    const float q = qa[k] + mid * qd[k];
+    const bool out = fabsf(q) > h[k];
+    const float sk = q >= 0.f ? 1.f : -1.f;
+    sg[k] = out ? sk : 0.f;
+    N += out ? (qa[k] - sk * h[k]) * qd[k] : 0.f;
+    D += out ? qd[k] * qd[k] : 0.f;
+    act |= out ? 1 << k : 0;
+  }
+  const bool bracket = !(sR > 1.f) && !(sL < 0.f);
+  const float s = sR > 1.f ? 1.f : (sL < 0.f ? sR : (D > 0.f ? clampf(-N / D, sL, sR) : sR));
+  g.act = bracket ? act : 0;
+  g.sig = bracket ? V(sg[0], sg[1], sg[2]) : V(0.f, 0.f, 0.f);
+  g.sD = bracket ? D : 0.f;
+  // does the segment pass through the box? (the parameters with every
+  // |q_k(s)| < h_k form an interval of positive length)
   if (!(te < tx)) return s;
   // it does: its deepest point
   g.sbin = 1;
@@ -277,42 +266,31 @@ BXF float seg_box_param(v3 a0, v3 da, v3 c, const m3& Rb, const float* h, PairGe
 // (signed for a point against a box). Returns false where the normal is
 // undefined (coincident core points).
 BXF bool pair_geometry(const PairT& c, const PairSide& A, const PairSide& B, PairGeo& g) {
-  if (c.kind >= PK_SB) {
-    // a capsule's axis segment against a box: a candidate only where the
-    // segment's point nearest the box lies strictly between its ends (the
-    // ends are the capsule's end-sphere candidates); that point against the
-    // box as a point candidate
-    const bool box_b = c.kind == PK_SB;
+  if (c.kind >= PK_PB) {
+    // a point (PB, BP) or a capsule's axis segment (SB, BS) against a box,
+    // whose body is the second for PB and SB: the segment is a candidate
+    // only where its point nearest the box lies strictly between its ends
+    // (the ends are the capsule's end-sphere candidates), and that point is
+    // then taken as a point candidate; both kinds share the point-box part
+    const bool seg = c.kind >= PK_SB;
+    const bool box_b = c.kind == PK_PB || c.kind == PK_SB;
     const m3 SR = sel(box_b, A.R, B.R), XR = sel(box_b, B.R, A.R);
-    g.a0 = sel(box_b, A.p, B.p) + mul(SR, ld3(box_b ? c.a0 : c.b0));
-    g.da = mul(SR, ld3(box_b ? c.a1 : c.b1) - ld3(box_b ? c.a0 : c.b0));
+    const v3 o0 = ld3(box_b ? c.a0 : c.b0);
+    g.a0 = sel(box_b, A.p, B.p) + mul(SR, o0);
     g.bc = sel(box_b, B.p, A.p) + mul(XR, ld3(box_b ? c.b0 : c.a0));
     if (c.box_rot)
       g.Rb = mul(XR, box_b ? c.bR : c.aR);
     else
       g.Rb = XR;
     const float* h = box_b ? c.bh : c.ah;
-    g.sst = seg_box_param(g.a0, g.da, g.bc, g.Rb, h, g);
-    if (!(g.sst > 0.f && g.sst < 1.f)) return false;
-    g.p = g.a0 + g.sst * g.da;
+    g.p = g.a0;
+    if (seg) {
+      g.da = mul(SR, ld3(box_b ? c.a1 : c.b1) - o0);
+      g.sst = seg_box_param(g.a0, g.da, g.bc, g.Rb, h, g);
+      if (!(g.sst > 0.f && g.sst < 1.f)) return false;
+      g.p = g.a0 + g.sst * g.da;
+    }
     g.dist = point_box(g.p, g.bc, g.Rb, h, g);
-    const v3 cbox = g.cb;
-    g.ca = sel(box_b, g.p, cbox);
-    g.cb = sel(box_b, cbox, g.p);
-    g.n = sel(box_b, g.nbx, -g.nbx);
-    return true;
-  }
-  if (c.kind >= PK_PB) {
-    const bool box_b = c.kind == PK_PB;
-    // the point's body (first for PB) and the box's body
-    g.p = sel(box_b, A.p, B.p) + mul(sel(box_b, A.R, B.R), ld3(box_b ? c.a0 : c.b0));
-    const m3 XR = sel(box_b, B.R, A.R);
-    g.bc = sel(box_b, B.p, A.p) + mul(XR, ld3(box_b ? c.b0 : c.a0));
-    if (c.box_rot)
-      g.Rb = mul(XR, box_b ? c.bR : c.aR);
-    else
-      g.Rb = XR;
-    g.dist = point_box(g.p, g.bc, g.Rb, box_b ? c.bh : c.ah, g);
     const v3 cbox = g.cb;
     g.ca = sel(box_b, g.p, cbox);
     g.cb = sel(box_b, cbox, g.p);
