@@ -112,6 +112,10 @@ typedef struct {
   int64_t vjp_lds_bytes;               /* on-chip memory per wavefront of the fused brax_step_vjp */
   int64_t vjp_params_lds_bytes;        /* the same for brax_step_vjp_params */
   int64_t lds_limit;                   /* the device's per-workgroup limit (160 KiB for a host-only handle) */
+  int32_t lanes_per_env[BRAX_MAX_TYPES]; /* lanes per environment of the fused forward without a tape: one
+                                            per body, plus one per two further ground-contact candidates of
+                                            a body with more than two (copies of its state that each
+                                            evaluate two of its candidates) */
 } brax_layout;
 
 /* Build a batch of n_envs environments from n_descs system descriptions.

@@ -53,7 +53,8 @@ class _Layout(C.Structure):
                 ("device", C.c_int32), ("nonfinite", C.c_void_p), ("tape_step_floats", C.c_int64),
                 ("n_params", C.c_int32 * MAX_TYPES), ("p_max", C.c_int32),
                 ("n_pairs", C.c_int32 * MAX_TYPES),
-                ("vjp_lds_bytes", C.c_int64), ("vjp_params_lds_bytes", C.c_int64), ("lds_limit", C.c_int64)]
+                ("vjp_lds_bytes", C.c_int64), ("vjp_params_lds_bytes", C.c_int64), ("lds_limit", C.c_int64),
+                ("lanes_per_env", C.c_int32 * MAX_TYPES)]
 
 
 EXPORTS = ("brax_sys_create", "brax_sys_destroy", "brax_sys_query", "brax_default_angles", "brax_default_qp",
@@ -199,6 +200,7 @@ class System:
         self.vjp_lds_bytes = lay.vjp_lds_bytes                     # on-chip tape of the fused adjoint
         self.vjp_params_lds_bytes = lay.vjp_params_lds_bytes
         self.lds_limit = lay.lds_limit
+        self.lanes_per_env = list(lay.lanes_per_env[:nt])          # fused forward: bodies + contact lanes
         self.dt = list(lay.dt[:nt])
         self.device = torch.device("cuda", device) if device >= 0 else None
         self._side = None  # second stream of the checkpointed backward (created on first use)

@@ -306,7 +306,8 @@ int brax_sys_create(const char* const* descs, int32_t n_descs, const int32_t* en
     for (int t = 0; t < n_descs; ++t) fill[t] = s->type_off[t];
     for (int e = 0; e < n_envs; ++e) s->env_list[fill[s->env_type[e]]++] = e;
   }
-  for (int t = 0; t < n_descs; ++t) s->envs_per_wave[t] = std::max(1, 64 / s->host_tab.type[t].nb);
+  // forward work list: lanes per environment include contact lanes
+  for (int t = 0; t < n_descs; ++t) s->envs_per_wave[t] = std::max(1, 64 / s->host_tab.type[t].nl);
   for (int t = 0; t < n_descs; ++t) s->smax = std::max(s->smax, s->host_tab.type[t].substeps);
   s->waves_per_block = 1;
   build_work(s.get());
@@ -390,6 +391,7 @@ int brax_sys_query(const brax_sys* s, brax_layout* out) {
     const TypeT& ty = s->host_tab.type[t];
     out->n_params[t] = 4 * ty.nb + 5 * ty.nj + ty.na + 1;
     out->n_pairs[t] = ty.np;
+    out->lanes_per_env[t] = ty.nl;
     out->p_max = std::max(out->p_max, out->n_params[t]);
   }
   for (int t = 0; t < s->n_types; ++t) {
@@ -618,7 +620,7 @@ int brax_set_schedule(brax_sys* s, int32_t envs_per_wave, int32_t waves_per_bloc
   if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
     return fail(BRAX_E_ARG, "waves_per_block must be 1, 2 or 4");
   for (int t = 0; t < s->n_types; ++t) {
-    const int full = std::max(1, 64 / s->host_tab.type[t].nb);
+    const int full = std::max(1, 64 / s->host_tab.type[t].nl);
     s->envs_per_wave[t] = envs_per_wave <= 0 ? full : std::min(envs_per_wave, full);
   }
   s->waves_per_block = waves_per_block;
@@ -692,7 +694,7 @@ static int autotune_impl(brax_sys* s, const brax_state* in, const float* act, in
       // faster (fewer environments per wavefront skip more contact and
       // body-body slots that no lane of the wavefront needs, which a short
       // trial may not show)
-      const int full = std::max(1, 64 / s->host_tab.type[t].nb);
+      const int full = std::max(1, 64 / s->host_tab.type[t].nl);
       const int low = std::max(1, full / 2);
       const int fill = std::min(full, std::max(1, (s->type_cnt[t] + n_simd - 1) / n_simd));
       epw_c.assign(1, fill);

@@ -339,25 +339,38 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
   const int t = wk.type;
   const TypeT ty = tab->type[t];
   const int nb = ty.nb;
+  // without a tape, a body with many contact candidates has contact lanes
+  // (lanes nb .. nl-1 of the environment) that hold copies of its state;
+  // the tape kernels keep one lane per body (their tape is read lane by lane)
+  constexpr bool LANES = !TAPE;
+  const int nl = LANES ? ty.nl : nb;
   const int lane = threadIdx.x & 63;
-  const int slot = lane / nb;
-  const int b = lane - slot * nb;
-  const int base = slot * nb;
-  const bool live = slot < wk.count;
+  // lanes past the wavefront's last environment slot shadow the first
+  // slot's lanes: every row they read lies within the wavefront's 64, and
+  // they store nothing
+  const int per_wave = 64 / nl;
+  const bool spare = lane >= per_wave * nl;
+  const int slot = spare ? 0 : lane / nl;
+  const int b = spare ? lane - per_wave * nl : lane - slot * nl;
+  const int base = slot * nl;
+  const bool live = !spare && slot < wk.count;
   const int e = env_list[type_off[t] + wk.k0 + (live ? slot : 0)];
   BodyT B = tab->body[t][b];
+  const int bs = LANES ? B.body_of : b;  // the body whose state this lane holds
   const bool has_joint = B.joint >= 0;
   JointT J = tab->joint[t][has_joint ? B.joint : 0];
   const int src_parent = base + (has_joint ? J.parent : b);
-  const int n_con = B.c1 - B.c0;
+  const int cfirst = LANES ? B.l0 : B.c0;
+  const int n_con = LANES ? B.l1 - B.l0 : B.c1 - B.c0;
+  const int max_con = LANES ? ty.max_lc : ty.max_contacts;
   ContactT Creg[REGC];
 #pragma unroll
-  for (int k = 0; k < REGC; ++k) Creg[k] = tab->contact[t][B.c0 + (n_con > k ? k : 0)];
+  for (int k = 0; k < REGC; ++k) Creg[k] = tab->contact[t][cfirst + (n_con > k ? k : 0)];
   pin_consts<MAXDOF>(B, J, has_joint, Creg, REGC);
   const float h = ty.h;
 
-  if (PAIRS && ty.np > 0) pair_lanes_load(tab, t, pl, lane);
-  Body s = load_body(in, b, e, Bm, E);
+  if (PAIRS && ty.np > 0) pair_lanes_load(tab, t, pl, lane, nl);
+  Body s = load_body(in, bs, e, Bm, E);
   const float x_before = s.p.x;  // the environment layer's root progress
   // frozen velocity components zeroed once; every update below keeps them zero
   s.v = keep(s.v, B.free_p);
@@ -397,8 +410,8 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
       int cnt = 0;
 #pragma unroll
       for (int k = 0; k < REGC; ++k)
-        if (k < ty.max_contacts && n_con > k) cnt += contact_eval(Creg[k], ty, B, s, f, dv, dw) ? 1 : 0;
-      for (int c = REGC; c < n_con; ++c) cnt += contact_eval(tab->contact[t][B.c0 + c], ty, B, s, f, dv, dw) ? 1 : 0;
+        if (k < max_con && n_con > k) cnt += contact_eval(Creg[k], ty, B, s, f, dv, dw) ? 1 : 0;
+      for (int c = REGC; c < n_con; ++c) cnt += contact_eval(tab->contact[t][cfirst + c], ty, B, s, f, dv, dw) ? 1 : 0;
       // joint evaluated on every lane (a root uses its own state as the
       // parent and its result is discarded)
       JointOut jo = joint_eval<MAXDOF>(J, P, RP, s, jc, a);
@@ -431,6 +444,28 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
           torque -= tq;
         }
       }
+      // a body's contact candidates spread over its lane group: every lane of
+      // the group adds the group's sums in group order (the same total on
+      // each, so the copies of the state stay equal); the exchange rows are
+      // free once the children's reactions have been read
+      if (LANES && nl > nb) {
+        X->r[lane][0] = make_float4(dv.x, dv.y, dv.z, (float)cnt);
+        X->r[lane][1] = make_float4(dw.x, dw.y, dw.z, 0.f);
+        v3 sv = V(0.f, 0.f, 0.f), sw = sv;
+        int sc = 0;
+        for (int i = 0; i < ty.max_ng; ++i) {
+          const int src = base + (i < B.ng ? (int)((B.grp_packed >> (4 * i)) & 15u) : b);
+          const float4 gv = X->r[src][0], gw = X->r[src][1];
+          if (i < B.ng) {
+            sv += V(gv.x, gv.y, gv.z);
+            sw += V(gw.x, gw.y, gw.z);
+            sc += (int)gv.w;
+          }
+        }
+        dv = sv;
+        dw = sw;
+        cnt = sc;
+      }
       // body-body contacts after the joint sums, where fewer values are live
       if (PAIRS && ty.np > 0) pair_phase(tab, t, *pl, X, lane, b, base, s, f, dv, dw, cnt);
       if (TAPE) wtape_rest(tp, torque, cnt, lane);
@@ -444,7 +479,7 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
       }
     }
     if (save_every > 0 && (step + 1) % save_every == 0) {
-      if (live) store_snapshot(traj, (size_t)n_save, s, b, e, Bm, E);
+      if (live && b < nb) store_snapshot(traj, (size_t)n_save, s, b, e, Bm, E);
       ++n_save;
     }
   }
@@ -472,7 +507,7 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
       ea->done[e] = healthy ? 0 : 1;
     }
     // a finished environment continues from its reset state
-    if (finished && live) s = load_body(ea->reset, b, e, Bm, E);
+    if (finished && live) s = load_body(ea->reset, bs, e, Bm, E);
     // observation of the final state: joint angles and relative angular
     // velocity about each Euler axis on the child's lane (the parent's
     // rotation and angular velocity read across lanes), the root's entries
@@ -485,7 +520,7 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
     const JointGeo g = joint_geo<MAXDOF>(J, RPf, joint_child<MAXDOF>(J, s, Rf));
     const v3 wrel = s.w - wP;
     const int D = ty.ndof;
-    if (live && has_joint) {
+    if (live && has_joint && b < nb) {
       for (int k = 0; k < MAXDOF; ++k) {
         if (k < J.dof) {
           ea->obs[(size_t)(11 + J.dof0 + k) * E + e] = g.th[k];
@@ -500,7 +535,7 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
       for (int k = 11 + 2 * D; k < ea->Omax; ++k) ea->obs[(size_t)k * E + e] = 0.f;
     }
   }
-  if (live) {
+  if (live && b < nb) {
     store_body(out, 0, s, b, e, Bm, E);
     // padded body slots of a smaller system are written as zeros (a finished
     // environment's as its reset state's)
@@ -636,7 +671,7 @@ hipError_t launch_env_step(const LaunchCtx& c, const WaveWork* work, int n_work,
   bool pairs = false, many_contacts = false;
   for (int t = 0; t < c.n_types; ++t) {
     pairs = pairs || c.host_tab->type[t].np > 0;
-    many_contacts = many_contacts || c.host_tab->type[t].max_contacts > REG_CONTACTS;
+    many_contacts = many_contacts || c.host_tab->type[t].max_lc > REG_CONTACTS;  // per lane, contact lanes included
   }
   const dim3 grid(cdiv(n_work, waves_per_block)), block(64 * waves_per_block);
   uint8_t* nf = flags ? c.nonfinite : nullptr;
@@ -673,11 +708,14 @@ hipError_t launch_fused(const LaunchCtx& c, const WaveWork* work, int n_work, in
                         Fields out, const float* acts, int T, int save_every, Fields traj, bool flags,
                         hipStream_t s, float* tape, int smax) {
   if (n_work == 0) return hipSuccess;
-  bool pairs = false, one_axis = true, many_contacts = false;
+  bool pairs = false, one_axis = true, many_contacts = false, many_lane_contacts = false;
   for (int t = 0; t < c.n_types; ++t) {
     pairs = pairs || c.host_tab->type[t].np > 0;
     one_axis = one_axis && c.host_tab->type[t].max_dof <= 1;
+    // per lane: the tape kernels hold a body's candidates on its lane, the
+    // others spread them over contact lanes
     many_contacts = many_contacts || c.host_tab->type[t].max_contacts > REG_CONTACTS;
+    many_lane_contacts = many_lane_contacts || c.host_tab->type[t].max_lc > REG_CONTACTS;
   }
   const size_t lds = fused_lds_per_wave(pairs) * waves_per_block;
   if (pairs) {
@@ -687,7 +725,7 @@ hipError_t launch_fused(const LaunchCtx& c, const WaveWork* work, int n_work, in
     if (tape)
       hipLaunchKernelGGL((k_fused_pairs<true, false, REG_CONTACTS>), grid, block, lds, s, c.tab, work, n_work,
                          c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, tape, smax);
-    else if (one_axis && many_contacts)
+    else if (one_axis && many_lane_contacts)
       hipLaunchKernelGGL((k_fused_pairs<false, true, 8>), grid, block, lds, s, c.tab, work, n_work, c.env_list,
                          c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0);
     else if (one_axis)
@@ -709,13 +747,13 @@ hipError_t launch_fused(const LaunchCtx& c, const WaveWork* work, int n_work, in
   else {
     const dim3 grid(cdiv(n_work, waves_per_block)), block(64 * waves_per_block);
     uint8_t* nf = flags ? c.nonfinite : nullptr;
-    if (one_axis && many_contacts)
+    if (one_axis && many_lane_contacts)
       hipLaunchKernelGGL((k_fused<true, 8>), grid, block, lds, s, c.tab, work, n_work, c.env_list, c.type_off, c.E,
                          c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0);
     else if (one_axis)
       hipLaunchKernelGGL((k_fused<true, REG_CONTACTS>), grid, block, lds, s, c.tab, work, n_work, c.env_list,
                          c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0);
-    else if (many_contacts)
+    else if (many_lane_contacts)
       hipLaunchKernelGGL((k_fused<false, 8>), grid, block, lds, s, c.tab, work, n_work, c.env_list, c.type_off, c.E,
                          c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0);
     else

@@ -41,13 +41,15 @@ struct PairLanes {
 // All lanes of the wavefront copy type t's tables into L; the wavefront's
 // own later LDS reads see the writes (LDS operations of a wavefront are
 // performed in order).
-__device__ __forceinline__ void pair_lanes_load(const Tables* __restrict__ tab, int t, PairLanes* L, int lane) {
+// nl: lanes per environment (bodies, then contact lanes).
+__device__ __forceinline__ void pair_lanes_load(const Tables* __restrict__ tab, int t, PairLanes* L, int lane,
+                                                int nl) {
   const TypeT& ty = tab->type[t];
   const int n_words = ty.np * (int)(sizeof(PairT) / 4);
   const uint32_t* src = reinterpret_cast<const uint32_t*>(&tab->pair[t][0]);
   uint32_t* dst = reinterpret_cast<uint32_t*>(&L->pair[0]);
   for (int x = lane; x < n_words; x += 64) dst[x] = src[x];
-  for (int x = lane; x < ty.nb * MAXH; x += 64) {
+  for (int x = lane; x < nl * MAXH; x += 64) {
     const int b = x / MAXH, i = x - b * MAXH;
     const BodyT& B = tab->body[t][b];
     if (i == 0) L->nh[b] = B.nh;

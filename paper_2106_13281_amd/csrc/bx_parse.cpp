@@ -786,6 +786,60 @@ void pack_type(const SystemDesc& d, Tables& tab, int t) {
       J.act_pd[k] = 1.f;
     }
   }
+  // contact lanes of the fused forward without a tape: a body with more
+  // than two ground-contact candidates takes ceil(n / 2) - 1 extra lanes
+  // (copies of its entry, which integrate the same state), each evaluating
+  // two of its candidates, so that a wavefront evaluates at most two
+  // candidate slots per substep; a type whose contact lanes would not fit
+  // (MAXB lanes, 8 per group) keeps every candidate on its body's lane
+  ty.nl = ty.nb;
+  ty.max_lc = ty.max_contacts;
+  ty.max_ng = 1;
+  for (int b = 0; b < ty.nb; ++b) {
+    BodyT& B = tab.body[t][b];
+    B.l0 = B.c0;
+    B.l1 = B.c1;
+    B.body_of = b;
+    B.ng = 1;
+    B.grp_packed = (uint32_t)b;
+  }
+  {
+    int extra = 0, max_ng = 1;
+    for (int b = 0; b < ty.nb; ++b) {
+      const int n = tab.body[t][b].c1 - tab.body[t][b].c0;
+      const int g = n > 2 ? (n + 1) / 2 : 1;
+      extra += g - 1;
+      max_ng = std::max(max_ng, g);
+    }
+    if (extra > 0 && ty.nb + extra <= MAXB && max_ng <= 8) {
+      int lane = ty.nb;
+      ty.max_lc = 0;
+      for (int b = 0; b < ty.nb; ++b) {
+        BodyT& B = tab.body[t][b];
+        const int n = B.c1 - B.c0;
+        if (n > 2) {
+          const int g = (n + 1) / 2;
+          B.l1 = B.c0 + 2;
+          B.ng = g;
+          for (int i = 1; i < g; ++i) B.grp_packed |= (uint32_t)(lane + i - 1) << (4 * i);
+          for (int i = 1; i < g; ++i) {
+            BodyT& M = tab.body[t][lane + i - 1];
+            M = B;  // same constants, joint, children and body-body share lists
+            M.l0 = B.c0 + 2 * i;
+            M.l1 = std::min(B.c1, M.l0 + 2);
+            M.nh = 0;  // evaluates no body-body candidate
+            for (int k = 0; k < MAXH; ++k) M.hp[k] = 0;
+          }
+          lane += g - 1;
+        }
+        ty.max_lc = std::max(ty.max_lc, B.l1 - B.l0);
+      }
+      for (int m = ty.nb; m < lane; ++m) ty.max_lc = std::max(ty.max_lc, tab.body[t][m].l1 - tab.body[t][m].l0);
+      ty.nl = lane;
+      ty.max_ng = max_ng;
+    }
+  }
+
   // parent-before-child order
   int n = 0;
   std::vector<int> placed(ty.nb, 0);

@@ -37,6 +37,11 @@ struct TypeT {
   float clearance;         // reset height of the lowest contact point (m)
   float g[3];              // gravity (m/s^2)
   int32_t frozen;          // 1 if some body of the type has a frozen axis
+  // the fused forward without a tape spreads the contact candidates of a
+  // body with more than two over extra lanes that hold copies of its state
+  // (contact lanes): lanes per environment there, the largest count of
+  // candidates one such lane evaluates, and the largest lane group of a body
+  int32_t nl, max_lc, max_ng;
 };
 
 struct BodyT {
@@ -63,6 +68,15 @@ struct BodyT {
   uint32_t recva[MAXH];    // per slot: the handler bodies of those shares, 4 bits each
   int32_t nrb[MAXH];       // the same as a candidate's second body
   uint32_t recvb[MAXH];
+  // lanes of the fused forward without a tape: entries nb .. nl-1 are contact
+  // lanes, copies of their body's entry that evaluate candidates [l0, l1)
+  // (a body lane evaluates its first ones); body_of: the body whose state the
+  // lane holds; its group: the lanes holding that body (body lane first),
+  // 4 bits each, whose contact sums every lane of the group adds in order
+  int32_t l0, l1;
+  int32_t body_of;
+  int32_t ng;
+  uint32_t grp_packed;
 };
 
 struct JointT {

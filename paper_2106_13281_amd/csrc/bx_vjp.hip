@@ -302,10 +302,14 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
   const TypeT ty = tab->type[t];
   const int nb = ty.nb;
   const int lane = threadIdx.x & 63;
-  const int slot = lane / nb;
-  const int b = lane - slot * nb;
+  // lanes past the last environment slot shadow the first slot's lanes (as
+  // in the forward kernels: their reads stay within the wavefront's rows)
+  const int per_wave = 64 / nb;
+  const bool spare = lane >= per_wave * nb;
+  const int slot = spare ? 0 : lane / nb;
+  const int b = spare ? lane - per_wave * nb : lane - slot * nb;
   const int base = slot * nb;
-  const bool live = slot < wk.count;
+  const bool live = !spare && slot < wk.count;
   const int e = env_list[type_off[t] + wk.k0 + (live ? slot : 0)];
   BodyT B = tab->body[t][b];
   const bool has_joint = B.joint >= 0;
@@ -317,7 +321,7 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
   for (int k = 0; k < REGC; ++k) Creg[k] = tab->contact[t][B.c0 + (n_con > k ? k : 0)];
   pin_consts<MAXDOF>(B, J, has_joint, Creg, REGC);
   const float h = ty.h;
-  if (PAIRS && ty.np > 0) pair_lanes_load(tab, t, pl, lane);
+  if (PAIRS && ty.np > 0) pair_lanes_load(tab, t, pl, lane, nb);
   const size_t AE = (size_t)Am * E;
   // actions of the step being differentiated, the last one first
   float a[3] = {0.f, 0.f, 0.f}, raw[3] = {0.f, 0.f, 0.f};

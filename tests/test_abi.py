@@ -192,6 +192,22 @@ def test_flag_values_and_combinations():
         assert msg in L.brax_last_error(), (flags, L.brax_last_error())
 
 
+def test_contact_lanes_per_environment():
+    """A body with more than two ground-contact candidates takes contact lanes
+    in the fused forward (one per two further candidates): the manipulator's
+    box (8 corners) adds 3 lanes to its 7 bodies; capsules and spheres (at
+    most two candidates) add none."""
+    for name, nl in (("manipulator", 10), ("grasp", 10), ("quadruped", 9), ("biped", None), ("chain", None)):
+        s = host(synth.system_text(name))
+        want = nl if nl is not None else s.n_bodies[0]
+        assert s.lanes_per_env == [want], name
+    box = ('bodies { name: "a" mass: 1 inertia { x: 1 y: 1 z: 1 } '
+           'colliders { box { halfsize { x: 0.1 y: 0.1 z: 0.1 } } } '
+           'colliders { capsule { radius: 0.05 length: 0.4 } } }\n')
+    s = host(box)
+    assert s.n_contacts == [10] and s.lanes_per_env == [5]  # 10 candidates: the body lane and 4 contact lanes
+
+
 def test_adjoint_tape_size_is_reported_against_the_lds_limit():
     """The fused adjoint keeps each substep's tape on chip: 17 floats per lane
     (20 with parameter cotangents) x 64 lanes per substep, beside the
