@@ -328,7 +328,9 @@ __device__ __forceinline__ PairLanes* pair_lanes(float4* lds) {
 // ENV: after the step(s), the environment layer on the state in registers
 // (reward, termination, reset of finished environments, observation of the
 // final state), so that an environment step is one launch.
-template <int MAXDOF, bool TAPE, bool PAIRS, int REGC = REG_CONTACTS, bool ENV = false>
+// CL: the batch has contact lanes (see TypeT::nl); kernels for batches
+// without keep one lane per body and none of the lane-group code.
+template <int MAXDOF, bool TAPE, bool PAIRS, int REGC = REG_CONTACTS, bool ENV = false, bool CL = false>
 __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const WaveWork& wk,
                                           const int32_t* __restrict__ env_list, const int32_t* __restrict__ type_off,
                                           int E, int Bm, const Fields& in, const Fields& out,
@@ -342,7 +344,7 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
   // without a tape, a body with many contact candidates has contact lanes
   // (lanes nb .. nl-1 of the environment) that hold copies of its state;
   // the tape kernels keep one lane per body (their tape is read lane by lane)
-  constexpr bool LANES = !TAPE;
+  constexpr bool LANES = CL && !TAPE;
   const int nl = LANES ? ty.nl : nb;
   const int lane = threadIdx.x & 63;
   // lanes past the wavefront's last environment slot shadow the first
@@ -552,7 +554,7 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
 // that path is compiled in (fewer registers). REGC: contact candidates per
 // body held in registers (8 for batches with a body of more than two, such
 // as a box's eight corners; 2 otherwise, where more registers only cost).
-template <bool ONE_AXIS, int REGC>
+template <bool ONE_AXIS, int REGC, bool CL>
 __global__ __launch_bounds__(256) void k_fused(const Tables* __restrict__ tab, const WaveWork* __restrict__ work,
                                                int n_work, const int32_t* __restrict__ env_list,
                                                const int32_t* __restrict__ type_off, int E, int Bm, Fields in,
@@ -566,11 +568,11 @@ __global__ __launch_bounds__(256) void k_fused(const Tables* __restrict__ tab, c
   XchRows* X = xch_lanes(fused_lds);
   // wave-uniform: joints of at most one axis take the shorter path
   if (ONE_AXIS || tab->type[wk.type].max_dof <= 1)
-    fused_run<1, false, false, REGC>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj,
-                                     nonfinite, nullptr, 0, w, n_work, X);
+    fused_run<1, false, false, REGC, false, CL>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T,
+                                                save_every, traj, nonfinite, nullptr, 0, w, n_work, X);
   else
-    fused_run<3, false, false, REGC>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj,
-                                     nonfinite, nullptr, 0, w, n_work, X);
+    fused_run<3, false, false, REGC, false, CL>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T,
+                                                save_every, traj, nonfinite, nullptr, 0, w, n_work, X);
 }
 
 // The same with the forward tape: a kernel of its own, so that the tape
@@ -604,7 +606,7 @@ __global__ __launch_bounds__(256) void k_fused_tape(const Tables* __restrict__ t
 // not lower the occupancy of the kernel above. REGC as for k_fused (8 for a
 // batch with a box, whose corners are otherwise read from the table in the
 // substep loop).
-template <bool TAPE, bool ONE_AXIS, int REGC>
+template <bool TAPE, bool ONE_AXIS, int REGC, bool CL = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_pairs(const Tables* __restrict__ tab,
                                                      const WaveWork* __restrict__ work, int n_work,
                                                      const int32_t* __restrict__ env_list,
@@ -619,17 +621,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   XchRows* X = xch_lanes(fused_lds);
   PairLanes* pl = pair_lanes(fused_lds);
   if (ONE_AXIS || tab->type[wk.type].max_dof <= 1)
-    fused_run<1, TAPE, true, REGC>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj,
-                                   nonfinite, tape, smax, w, n_work, X, pl);
+    fused_run<1, TAPE, true, REGC, false, CL>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every,
+                                              traj, nonfinite, tape, smax, w, n_work, X, pl);
   else
-    fused_run<3, TAPE, true, REGC>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every, traj,
-                                   nonfinite, tape, smax, w, n_work, X, pl);
+    fused_run<3, TAPE, true, REGC, false, CL>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, T, save_every,
+                                              traj, nonfinite, tape, smax, w, n_work, X, pl);
 }
 
 // One environment step with the environment layer fused after it (T = 1):
 // kernels of their own so that the epilogue's registers do not weigh on the
 // rollout kernels. PAIRS: batches with body-body candidates.
-template <bool PAIRS, int REGC>
+template <bool PAIRS, int REGC, bool CL>
 __global__ __launch_bounds__(256) void k_fused_env(const Tables* __restrict__ tab, const WaveWork* __restrict__ work,
                                                    int n_work, const int32_t* __restrict__ env_list,
                                                    const int32_t* __restrict__ type_off, int E, int Bm, Fields in,
@@ -643,11 +645,11 @@ __global__ __launch_bounds__(256) void k_fused_env(const Tables* __restrict__ ta
   PairLanes* pl = PAIRS ? pair_lanes(fused_lds) : nullptr;
   const Fields none{nullptr, nullptr, nullptr, nullptr};
   if (tab->type[wk.type].max_dof <= 1)
-    fused_run<1, false, PAIRS, REGC, true>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, 1, 0, none,
-                                           nonfinite, nullptr, 0, w, n_work, X, pl, &ea);
+    fused_run<1, false, PAIRS, REGC, true, CL>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, 1, 0, none,
+                                               nonfinite, nullptr, 0, w, n_work, X, pl, &ea);
   else
-    fused_run<3, false, PAIRS, REGC, true>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, 1, 0, none,
-                                           nonfinite, nullptr, 0, w, n_work, X, pl, &ea);
+    fused_run<3, false, PAIRS, REGC, true, CL>(tab, wk, env_list, type_off, E, Bm, in, out, acts, Am, 1, 0, none,
+                                               nonfinite, nullptr, 0, w, n_work, X, pl, &ea);
 }
 
 // ------------------------------------------------------------------ small helpers
@@ -668,24 +670,31 @@ hipError_t launch_env_step(const LaunchCtx& c, const WaveWork* work, int n_work,
                            const EnvT* env, int Omax, Fields in, Fields out, const float* act, Fields reset, float* obs,
                            float* reward, uint8_t* done, bool flags, hipStream_t s) {
   if (n_work == 0) return hipSuccess;
-  bool pairs = false, many_contacts = false;
+  bool pairs = false, many_contacts = false, cl = false;
   for (int t = 0; t < c.n_types; ++t) {
     pairs = pairs || c.host_tab->type[t].np > 0;
     many_contacts = many_contacts || c.host_tab->type[t].max_lc > REG_CONTACTS;  // per lane, contact lanes included
+    cl = cl || c.host_tab->type[t].nl > c.host_tab->type[t].nb;
   }
   const dim3 grid(cdiv(n_work, waves_per_block)), block(64 * waves_per_block);
   uint8_t* nf = flags ? c.nonfinite : nullptr;
   const EnvArgs ea{env, reset, obs, reward, done, Omax};
   const size_t lds = fused_lds_per_wave(pairs) * waves_per_block;
-  if (pairs)
-    hipLaunchKernelGGL((k_fused_env<true, REG_CONTACTS>), grid, block, lds, s, c.tab, work, n_work, c.env_list,
-                       c.type_off, c.E, c.Bm, in, out, act, c.Am, nf, ea);
+#define BX_ENV(P, R, L)                                                                                            \
+  hipLaunchKernelGGL((k_fused_env<P, R, L>), grid, block, lds, s, c.tab, work, n_work, c.env_list, c.type_off, c.E, \
+                     c.Bm, in, out, act, c.Am, nf, ea)
+  // with contact lanes, candidates past a lane's first two are read from the table
+  if (pairs && cl)
+    BX_ENV(true, REG_CONTACTS, true);
+  else if (pairs)
+    BX_ENV(true, REG_CONTACTS, false);
+  else if (cl)
+    BX_ENV(false, REG_CONTACTS, true);
   else if (many_contacts)
-    hipLaunchKernelGGL((k_fused_env<false, 8>), grid, block, lds, s, c.tab, work, n_work, c.env_list, c.type_off,
-                       c.E, c.Bm, in, out, act, c.Am, nf, ea);
+    BX_ENV(false, 8, false);
   else
-    hipLaunchKernelGGL((k_fused_env<false, REG_CONTACTS>), grid, block, lds, s, c.tab, work, n_work, c.env_list,
-                       c.type_off, c.E, c.Bm, in, out, act, c.Am, nf, ea);
+    BX_ENV(false, REG_CONTACTS, false);
+#undef BX_ENV
   return hipGetLastError();
 }
 
@@ -708,7 +717,7 @@ hipError_t launch_fused(const LaunchCtx& c, const WaveWork* work, int n_work, in
                         Fields out, const float* acts, int T, int save_every, Fields traj, bool flags,
                         hipStream_t s, float* tape, int smax) {
   if (n_work == 0) return hipSuccess;
-  bool pairs = false, one_axis = true, many_contacts = false, many_lane_contacts = false;
+  bool pairs = false, one_axis = true, many_contacts = false, many_lane_contacts = false, cl = false;
   for (int t = 0; t < c.n_types; ++t) {
     pairs = pairs || c.host_tab->type[t].np > 0;
     one_axis = one_axis && c.host_tab->type[t].max_dof <= 1;
@@ -716,7 +725,11 @@ hipError_t launch_fused(const LaunchCtx& c, const WaveWork* work, int n_work, in
     // others spread them over contact lanes
     many_contacts = many_contacts || c.host_tab->type[t].max_contacts > REG_CONTACTS;
     many_lane_contacts = many_lane_contacts || c.host_tab->type[t].max_lc > REG_CONTACTS;
+    cl = cl || c.host_tab->type[t].nl > c.host_tab->type[t].nb;
   }
+  // kernels with contact lanes hold two candidates per lane in registers
+  // (further ones, of a type whose lanes did not fit, are read from the table)
+  if (cl) many_lane_contacts = false;
   const size_t lds = fused_lds_per_wave(pairs) * waves_per_block;
   if (pairs) {
     const dim3 grid(cdiv(n_work, waves_per_block)), block(64 * waves_per_block);
@@ -728,8 +741,14 @@ hipError_t launch_fused(const LaunchCtx& c, const WaveWork* work, int n_work, in
     else if (one_axis && many_lane_contacts)
       hipLaunchKernelGGL((k_fused_pairs<false, true, 8>), grid, block, lds, s, c.tab, work, n_work, c.env_list,
                          c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0);
+    else if (one_axis && cl)
+      hipLaunchKernelGGL((k_fused_pairs<false, true, REG_CONTACTS, true>), grid, block, lds, s, c.tab, work, n_work,
+                         c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0);
     else if (one_axis)
       hipLaunchKernelGGL((k_fused_pairs<false, true, REG_CONTACTS>), grid, block, lds, s, c.tab, work, n_work,
+                         c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0);
+    else if (cl)
+      hipLaunchKernelGGL((k_fused_pairs<false, false, REG_CONTACTS, true>), grid, block, lds, s, c.tab, work, n_work,
                          c.env_list, c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0);
     else
       hipLaunchKernelGGL((k_fused_pairs<false, false, REG_CONTACTS>), grid, block, lds, s, c.tab, work, n_work,
@@ -747,18 +766,22 @@ hipError_t launch_fused(const LaunchCtx& c, const WaveWork* work, int n_work, in
   else {
     const dim3 grid(cdiv(n_work, waves_per_block)), block(64 * waves_per_block);
     uint8_t* nf = flags ? c.nonfinite : nullptr;
-    if (one_axis && many_lane_contacts)
-      hipLaunchKernelGGL((k_fused<true, 8>), grid, block, lds, s, c.tab, work, n_work, c.env_list, c.type_off, c.E,
-                         c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0);
+#define BX_FUSED(A, R, L)                                                                                         \
+  hipLaunchKernelGGL((k_fused<A, R, L>), grid, block, lds, s, c.tab, work, n_work, c.env_list, c.type_off, c.E, c.Bm, \
+                     in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0)
+    if (one_axis && cl)
+      BX_FUSED(true, REG_CONTACTS, true);
+    else if (cl)
+      BX_FUSED(false, REG_CONTACTS, true);
+    else if (one_axis && many_lane_contacts)
+      BX_FUSED(true, 8, false);
     else if (one_axis)
-      hipLaunchKernelGGL((k_fused<true, REG_CONTACTS>), grid, block, lds, s, c.tab, work, n_work, c.env_list,
-                         c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0);
+      BX_FUSED(true, REG_CONTACTS, false);
     else if (many_lane_contacts)
-      hipLaunchKernelGGL((k_fused<false, 8>), grid, block, lds, s, c.tab, work, n_work, c.env_list, c.type_off, c.E,
-                         c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0);
+      BX_FUSED(false, 8, false);
     else
-      hipLaunchKernelGGL((k_fused<false, REG_CONTACTS>), grid, block, lds, s, c.tab, work, n_work, c.env_list,
-                         c.type_off, c.E, c.Bm, in, out, acts, c.Am, T, save_every, traj, nf, nullptr, 0);
+      BX_FUSED(false, REG_CONTACTS, false);
+#undef BX_FUSED
   }
   return hipGetLastError();
 }
