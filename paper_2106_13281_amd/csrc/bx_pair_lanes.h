@@ -102,6 +102,29 @@ __device__ __forceinline__ PairSide side_get(const PairLanes& L, int src, float4
   return o;
 }
 
+// Slot 0 of a lane's candidates, read once per launch: the lanes of its two
+// bodies and its squared reach (negative without a candidate), for the
+// early reach test on the positions in the exchange rows.
+struct PairSlot0 {
+  int sa, sb;
+  float r2;
+};
+__device__ __forceinline__ PairSlot0 pair_slot0(const PairLanes& L, int b, int base) {
+  PairSlot0 q{base + b, base + b, -1.f};
+  if (L.nh[b] > 0) {
+    const PairT& P = L.pair[L.hp[b][0]];
+    q = PairSlot0{base + P.a, base + P.b, P.reach * P.reach};
+  }
+  return q;
+}
+// The early reach test of slot 0, while row 0 of every lane's exchange row
+// holds its post-kinematic position (1 within reach, 0 not).
+__device__ __forceinline__ int pair_near0(const XchRows* X, const PairSlot0& q) {
+  const float4 a = X->r[q.sa][0], c = X->r[q.sb][0];
+  const v3 d = V(a.x, a.y, a.z) - V(c.x, c.y, c.z);
+  return (q.r2 >= 0.f && dot(d, d) <= q.r2) ? 1 : 0;
+}
+
 // Whether any lane of the wavefront has a candidate within reach in this
 // slot.
 __device__ __forceinline__ bool pair_near(const PairT& P, bool mine, v3 pA, v3 pB) {
@@ -112,20 +135,32 @@ __device__ __forceinline__ bool pair_near(const PairT& P, bool mine, v3 pA, v3 p
 // Forward: adds this body's body-body velocity changes to dv, dw and the
 // applied candidates to cnt (post-kinematic state s, frame f). The shares
 // travel through the wavefront's exchange rows X, free at this point of the
-// substep: dvA on | dwA on | dvB on | dwB on.
+// substep: dvA on | dwA on | dvB on | dwB on. near0: slot 0's early reach
+// test (pair_near0), or -1 to test it here; the side rows are written only
+// once some slot is to be evaluated or tested from them.
 __device__ __forceinline__ void pair_phase(const Tables* __restrict__ tab, int t, PairLanes& L, XchRows* X, int lane,
-                                           int b, int base, const Body& s, const Frame& f, v3& dv, v3& dw, int& cnt) {
+                                           int b, int base, const Body& s, const Frame& f, v3& dv, v3& dw, int& cnt,
+                                           int near0 = -1) {
   const TypeT& ty = tab->type[t];
   const int nh = L.nh[b];
-  side_put(L, lane, s, f);
+  bool sides = false;  // wave-uniform
   for (int i = 0; i < ty.max_handled; ++i) {
     const bool mine = i < nh;
     const PairT& P = L.pair[L.hp[b][i]];  // hp = 0 past nh: a valid candidate, unused
     const int sa = base + (mine ? P.a : b), sb = base + (mine ? P.b : b);
-    const float4 ra = L.side[sa][0], rb = L.side[sb][0];
-    const bool near = pair_near(P, mine, V(ra.x, ra.y, ra.z), V(rb.x, rb.y, rb.z));
+    bool near;
+    if (i == 0 && near0 >= 0) {
+      near = near0 != 0;
+    } else {
+      if (!sides) side_put(L, lane, s, f);
+      sides = true;
+      const float4 ra = L.side[sa][0], rb = L.side[sb][0];
+      near = pair_near(P, mine, V(ra.x, ra.y, ra.z), V(rb.x, rb.y, rb.z));
+    }
     if (__ballot(near) == 0ull) continue;  // wave-uniform
-    const PairSide A = side_get(L, sa, ra), B = side_get(L, sb, rb);
+    if (!sides) side_put(L, lane, s, f);
+    sides = true;
+    const PairSide A = side_get(L, sa, L.side[sa][0]), B = side_get(L, sb, L.side[sb][0]);
     v3 dvA = V(0.f, 0.f, 0.f), dwA = dvA, dvB = dvA, dwB = dvA;
     float on = 0.f;
     if (near && pair_eval(P, ty, A, B, dvA, dwA, dvB, dwB)) on = 1.f;
