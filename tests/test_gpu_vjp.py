@@ -110,8 +110,10 @@ def test_step_vjp_from_tape_matches_oracle_and_recompute(name):
     out_t, tape = sysg.rollout_tape(to_dev(X), A)
     out_r, _ = sysg.rollout(to_dev(X), A)
     # two kernels (with and without the tape) compiled separately: the same
-    # arithmetic up to the compiler's fused multiply-add choices, so the same
-    # bar as the plain and fused kernels' agreement
+    # arithmetic up to the compiler's fused multiply-add choices and, for a
+    # body with contact lanes in the kernel without the tape (the manipulator's
+    # and grasp system's box), the order in which its contact sums are added,
+    # so the same bar as the plain and fused kernels' agreement
     assert rel_err(from_dev(out_t, o.nb), from_dev(out_r, o.nb)).max() < 1e-5
     g_in, g_act = sysg.step_vjp_tape(tape[0], A[0].contiguous(), to_dev(g))
     gi = from_dev(g_in, o.nb)
