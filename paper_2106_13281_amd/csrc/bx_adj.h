@@ -70,23 +70,23 @@ BXF void quat_to_mat_adj(q4 q, const m3& Rb, q4& qb) {
                  q.x * b[6] + q.y * b[7]);
 }
 // Frame (R, Iw, Iwinv) cotangents -> q_bar
-BXF void frame_adj(const BodyT& B, const Body& s, const Frame& f, const m3& Rb_in, const s3& Iwb, const s3& Iwinvb,
-                   q4& qb) {
+BXF void frame_adj(const BodyT& B, const Body& s, const Frame& f, const m3& Rb_in, const s3& Iwinvb, q4& qb) {
   m3 Rb = Rb_in;
-  rot_diag_adj(f.R, B.I, Iwb, Rb);
   rot_diag_adj(f.R, B.Iinv, Iwinvb, Rb);
   quat_to_mat_adj(s.q, Rb, qb);
 }
-// Cotangents of a body's frame (R, Iw, Iwinv), summed over the items of a
+// Cotangents of a body's frame (R, Iwinv), summed over the items of a
 // substep that read it; frame_adj is linear in them, so one conversion to
-// q_bar per body and substep serves every item.
+// q_bar per body and substep serves every item. Ib: the cotangent of the
+// principal moments from the gyroscopic term (for parameter gradients).
 struct FrameBar {
   m3 Rb;
-  s3 Iwb, Iwinvb;
+  s3 Iwinvb;
+  v3 Ib;
 };
-BXF FrameBar framebar_zero() { return FrameBar{m3_zero(), s3_zero(), s3_zero()}; }
+BXF FrameBar framebar_zero() { return FrameBar{m3_zero(), s3_zero(), V(0.f, 0.f, 0.f)}; }
 BXF void frame_adj(const BodyT& B, const Body& s, const Frame& f, const FrameBar& fr, q4& qb) {
-  frame_adj(B, s, f, fr.Rb, fr.Iwb, fr.Iwinvb, qb);
+  frame_adj(B, s, f, fr.Rb, fr.Iwinvb, qb);
 }
 // c = a x b  ->  a_bar += b x c_bar, b_bar += c_bar x a
 BXF void cross_adj(v3 a, v3 b, v3 cb, v3& ab, v3& bb) {
@@ -152,7 +152,11 @@ BXF Bar integrate_adj(const BodyT& B, const TypeT& ty, const Body& post, const F
   fb = (h * B.inv_m) * keep(ob.v, B.free_p);
   invm_bar += h * dot(keep(ob.v, B.free_p), f_tot);
   v3 ab = h * keep(ob.w, B.free_r);           // cotangent of alpha = Iwinv x
-  v3 u = mul(f.Iw, post.w);
+  // the gyroscopic term in the body frame, as the forward forms it:
+  // wb = R^T w', y = I wb, u = R y (the world inertia times w'), gyro = w' x u
+  const v3 wb = mul_t(f.R, post.w);
+  const v3 y = V(B.I[0] * wb.x, B.I[1] * wb.y, B.I[2] * wb.z);
+  v3 u = mul(f.R, y);
   v3 x = t_tot - cross(post.w, u);
   sym_outer_add(fr.Iwinvb, ab, x);
   v3 xb = mul(f.Iwinv, ab);
@@ -160,8 +164,14 @@ BXF Bar integrate_adj(const BodyT& B, const TypeT& ty, const Body& post, const F
   v3 gb = -xb;                               // gyro = w' x u
   v3 ub = V(0.f, 0.f, 0.f);
   cross_adj(post.w, u, gb, r.w, ub);
-  r.w += mul(f.Iw, ub);
-  sym_outer_add(fr.Iwb, ub, post.w);
+  // u = R y: R_bar += ub y^T, y_bar = R^T ub; y = I wb: wb_bar = I y_bar,
+  // I_bar += y_bar wb; wb = R^T w': w'_bar += R wb_bar, R_bar += w' wb_bar^T
+  const v3 yb = mul_t(f.R, ub);
+  const v3 wbb = V(B.I[0] * yb.x, B.I[1] * yb.y, B.I[2] * yb.z);
+  r.w += mul(f.R, wbb);
+  outer_add(fr.Rb, ub, y);
+  outer_add(fr.Rb, post.w, wbb);
+  fr.Ib += V(yb.x * wb.x, yb.y * wb.y, yb.z * wb.z);
   return r;
 }
 BXF Bar integrate_adj(const BodyT& B, const TypeT& ty, const Body& post, const Frame& f, v3 t_tot, int n,

@@ -231,7 +231,7 @@ __global__ void k_adj_pair(const Tables* __restrict__ tab, int t, const int32_t*
       r.p = sb[i].p;
       r.v = sb[i].v;
       r.w = sb[i].w;
-      frame_adj(tab->body[t][ids[i]], post[i], f[i], FrameBar{sb[i].R, s3_zero(), sb[i].Iwinv}, r.q);
+      frame_adj(tab->body[t][ids[i]], post[i], f[i], FrameBar{sb[i].R, sb[i].Iwinv, V(0.f, 0.f, 0.f)}, r.q);
     }
     slot_store_bar(pbar, 13 * i, ty.np, c, n, k, r);
   }
@@ -444,7 +444,7 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
       kinematic(B, post, h);
       xch_put_body(X, lane, post);
       Body P = xch_get_body<Body>(X, src_parent);
-      Frame f = derive(B, post);
+      Frame f = derive_inv(B, quat_to_mat(post.q));  // the adjoint needs no world inertia
       v3 fb, tb, dvb, dwb;
       // this body's frame cotangents from every item of the substep, turned
       // into its quaternion cotangent once at the end
@@ -487,15 +487,19 @@ __device__ __forceinline__ void fused_vjp_run(const Tables* __restrict__ tab, co
       if (PAIRS && ty.np > 0) pair_phase_adj(tab, t, *pl, b, base, post, f, dvb, dwb, tot, fr, invm_bar, mu_bar);
       bar_add(tot, bC);
       if (PARAMS) {
-        // Iw = R diag(I) R^T, Iwinv = R diag(1/I) R^T: d/dI_k = r_k^T S_bar r_k (r_k column k of R;
-        // an off-diagonal cotangent already holds both of its entries)
+        // the principal moments' cotangent from the gyroscopic term (body
+        // frame, integrate_adj), and Iwinv = R diag(1/I) R^T: d/d(1/I_k) =
+        // r_k^T S_bar r_k (r_k column k of R; an off-diagonal cotangent
+        // already holds both of its entries)
+        Ib[0] += fr.Ib.x;
+        Ib[1] += fr.Ib.y;
+        Ib[2] += fr.Ib.z;
         for (int k = 0; k < 3; ++k) {
           const v3 r = col(f.R, k);
           auto quad = [&](const s3& S) {
             return S.xx * r.x * r.x + S.yy * r.y * r.y + S.zz * r.z * r.z + S.xy * r.x * r.y + S.xz * r.x * r.z +
                    S.yz * r.y * r.z;
           };
-          Ib[k] += quad(fr.Iwb);
           Iinvb[k] += quad(fr.Iwinvb);
         }
       }
