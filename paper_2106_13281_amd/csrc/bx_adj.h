@@ -475,12 +475,48 @@ BXF void joint_actuator_adj(const JointT& J, const Body& P, const m3& RP, const 
   joint_geo_adj<MAXDOF>(J, P, C, g, gb, bP.q, bC.q);
 }
 
+// Geometry adjoint of a one-axis joint on joint_geo_step's geometry: the
+// cotangents of rP, rC, e1P, e1C, th0 and ax0 (= e1P) into the parent's
+// quaternion (qbP) and the child's rotation (RbC_acc). There th0 =
+// atan2(-m12, m22) with m12, m22 the parent frame's y and z columns
+// against v = RP^T e3C.
+BXF void joint_geo1_adj(const JointT& J, const Body& P, const m3& RP, const JointGeo& g, GeoBar gb, q4& qbP,
+                        m3& RbC_acc) {
+  gb.e1P += gb.ax[0];
+  float m12b = 0.f, m22b = 0.f;
+  const float x = g.m22, yy = -g.m12, r2 = x * x + yy * yy;
+  if (r2 > 0.f) {
+    m22b = -gb.th[0] * yy / r2;
+    m12b = -(gb.th[0] * x / r2);
+  }
+  const v3 vb = m12b * V(J.FP[1], J.FP[4], J.FP[7]) + m22b * V(J.FP[2], J.FP[5], J.FP[8]);
+  m3 RbP = m3_zero();
+  outer_add(RbP, g.e3C, vb);  // v = RP^T e3C
+  const v3 e3Cb = mul(RP, vb);
+  outer_add(RbP, gb.e1P, V(J.FP[0], J.FP[3], J.FP[6]));  // e1P = RP fp1
+  outer_add(RbP, gb.rP, ld3(J.ap));                       // rP = RP ap
+  outer_add(RbC_acc, gb.e1C, V(J.FC[0], J.FC[3], J.FC[6]));
+  outer_add(RbC_acc, e3Cb, V(J.FC[2], J.FC[5], J.FC[8]));
+  outer_add(RbC_acc, gb.rC, ld3(J.ac));
+  quat_to_mat_adj(P.q, RbP, qbP);
+}
+
 // Spring and actuators together (the fused path): geometry computed once;
-// the child's rotation cotangent is added to its frame cotangents fr.
+// the child's rotation cotangent is added to its frame cotangents fr. A
+// one-axis joint takes the step's own geometry (joint_geo_step) and its
+// adjoint, without the Euler frame of the multi-axis joints.
 template <int MAXDOF>
 BXF void joint_eval_adj(const JointT& J, const Body& P, const m3& RP, const Body& C, const m3& RC, const float* a,
                         v3 fcb, v3 tcb, v3 fpb, v3 tpb, Bar& bP, Bar& bC, float* ab, FrameBar& fr,
                         float* jbar = nullptr, float* gbar = nullptr) {
+  if (MAXDOF == 1) {
+    const JointGeo g = joint_geo_step<1>(J, RP, joint_child<1>(J, C, RC));
+    GeoBar gb = geobar_zero();
+    spring_adj_core<1>(J, P, C, g, fcb, tcb, fpb, tpb, bP, bC, gb, jbar);
+    actuator_adj_core<1>(J, g, a, tcb, tpb, gb, ab, gbar);
+    joint_geo1_adj(J, P, RP, g, gb, bP.q, fr.Rb);
+    return;
+  }
   JointGeo g = joint_geo<MAXDOF>(J, RP, RC);
   GeoBar gb = geobar_zero();
   spring_adj_core<MAXDOF>(J, P, C, g, fcb, tcb, fpb, tpb, bP, bC, gb, jbar);
