@@ -295,11 +295,11 @@ int brax_env_step(const brax_sys* sys, const brax_state* in, const float* act, c
 
 /* Time the fused kernel's launch shapes on `stream` and keep the fastest
  * for later calls (the result does not depend on the shape). Per system
- * type, the environments per wavefront that give about one wavefront per
- * SIMD are tried first, then from full wavefronts down; wavefronts per
- * block from one up. A later shape replaces the best so far only if it is
- * more than 1% faster, so that repeated tunings of one batch settle on the
- * same shape. */
+ * type, environments per wavefront from full wavefronts down, and the
+ * value that gives the type about one wavefront per SIMD (tried first in a
+ * batch of one type, last otherwise); wavefronts per block from one up. A
+ * later shape replaces the best so far only if it is more than 1% faster,
+ * so that repeated tunings of one batch settle on the same shape. */
 int brax_autotune(brax_sys* sys, void* stream);
 
 /* brax_autotune with trials on the caller's workload: each trial is a

@@ -689,20 +689,23 @@ static int autotune_impl(brax_sys* s, const brax_state* in, const float* act, in
     if (rc) break;
     for (int t = 0; t < s->n_types; ++t) {
       // from a full wavefront down to half of one, at most 6 values evenly
-      // spaced, after the value that gives about one wavefront per SIMD; that
-      // one is timed first, so that it stays unless another is clearly
-      // faster (fewer environments per wavefront skip more contact and
-      // body-body slots that no lane of the wavefront needs, which a short
-      // trial may not show)
+      // spaced, and the value that gives the type about one wavefront per
+      // SIMD. A batch of one type times that one first, so that it stays
+      // unless another is clearly faster (fewer environments per wavefront
+      // skip more contact and body-body slots that no lane of the wavefront
+      // needs, which a short trial may not show); in a batch of several
+      // types, whose wavefronts share the SIMDs, it comes last
       const int full = std::max(1, 64 / s->host_tab.type[t].nl);
       const int low = std::max(1, full / 2);
       const int fill = std::min(full, std::max(1, (s->type_cnt[t] + n_simd - 1) / n_simd));
-      epw_c.assign(1, fill);
+      epw_c.clear();
+      if (s->n_types == 1) epw_c.push_back(fill);
       const int span = full - low + 1, nc = std::min(span, 6);
       for (int i = 0; i < nc; ++i) {
         const int epw = full - (nc > 1 ? (i * (span - 1)) / (nc - 1) : 0);
         if (epw != fill) epw_c.push_back(epw);
       }
+      if (s->n_types > 1) epw_c.push_back(fill);
       float best_t = 1e30f;
       for (int epw : epw_c) {
         // time this type alone with the others at their current best
