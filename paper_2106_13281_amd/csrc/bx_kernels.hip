@@ -372,7 +372,7 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
   const float h = ty.h;
 
   if (PAIRS && ty.np > 0) pair_lanes_load(tab, t, pl, lane, nl);
-  const PairSlot0 ps0 = (PAIRS && ty.np > 0) ? pair_slot0(*pl, b, base) : PairSlot0{lane, lane, -1.f};
+  const PairSlot0 ps0 = (PAIRS && ty.np > 0) ? pair_slot0(*pl, b, base) : PairSlot0{-1, lane, lane};
   Body s = load_body(in, bs, e, Bm, E);
   const float x_before = s.p.x;  // the environment layer's root progress
   // frozen velocity components zeroed once; every update below keeps them zero
@@ -402,8 +402,9 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
       Body P;
       m3 RP;
       xch_get_pvw_rot(X, src_parent, P, RP);
-      // body-body slot 0: its reach test on the positions in the rows now
-      const int near0 = (PAIRS && ty.np > 0) ? pair_near0(X, ps0) : 0;
+      // body-body slot 0: its bound test on the positions and rotations in
+      // the rows now
+      const int near0 = (PAIRS && ty.np > 0) ? pair_near0(X, *pl, ps0) : 0;
       P.q = s.q;  // unused: the joint reads the parent's orientation as RP
       Frame f = derive_inv(B, R);
       JointChild jc = joint_child<MAXDOF>(J, s, R);

@@ -7,9 +7,9 @@
 // The handler writes both shares to its exchange row; in the same evaluation
 // slot each body's lane collects its shares from the handler lanes listed in
 // its table row, first-body shares and second-body shares in two passes. An
-// evaluation slot in which no lane of the wavefront has a candidate whose
-// body origins are within reach is skipped as a whole (no contact is
-// possible there). The loops run to the type's maxima, so that the
+// evaluation slot in which no lane of the wavefront has a candidate that
+// passes its bound test (one feature's distance from a ball around the
+// other's: no contact is possible where it fails) is skipped as a whole. The loops run to the type's maxima, so that the
 // wavefront takes every read together; a lane without work in a slot reads
 // its own values and discards them.
 #pragma once
@@ -102,31 +102,70 @@ __device__ __forceinline__ PairSide side_get(const PairLanes& L, int src, float4
   return o;
 }
 
-// Slot 0 of a lane's candidates, read once per launch: the lanes of its two
-// bodies and its squared reach (negative without a candidate), for the
-// early reach test on the positions in the exchange rows.
+// The bound test of candidate P (see PairT::lo): the line feature of the
+// body at pL, RL against the ball around the feature of the body at pK, RK.
+__device__ __forceinline__ bool pair_bound(const PairT& P, v3 pL, const m3& RL, v3 pK, const m3& RK) {
+  const float4 lo = *reinterpret_cast<const float4*>(P.lo);
+  const float4 ld = *reinterpret_cast<const float4*>(P.ld);
+  const float4 kc = *reinterpret_cast<const float4*>(P.kc);
+  const v3 a = pL + mul(RL, V(lo.x, lo.y, lo.z));
+  const v3 d = mul(RL, V(ld.x, ld.y, ld.z));
+  const v3 r = (pK + mul(RK, V(kc.x, kc.y, kc.z))) - a;
+  const float dd = dot(d, d);
+  const float u = dd > 0.f ? clampf(dot(r, d) / dd, 0.f, 1.f) : 0.f;
+  const v3 q = r - u * d;
+  return dot(q, q) <= lo.w;
+}
+// The line body's and the other body's lanes of candidate P.
+__device__ __forceinline__ int pair_line_lane(const PairT& P, int base) { return base + (P.kc[3] != 0.f ? P.b : P.a); }
+__device__ __forceinline__ int pair_ball_lane(const PairT& P, int base) { return base + (P.kc[3] != 0.f ? P.a : P.b); }
+
+// Position and rotation of the body on lane src from the exchange rows
+// (while they hold every lane's post-kinematic state and rotation).
+__device__ __forceinline__ void xch_get_pR(const XchRows* X, int src, v3& p, m3& R) {
+  const float4 a0 = X->r[src][0], r0 = X->r[src][2], r1 = X->r[src][3];
+  const float2 a2 = *reinterpret_cast<const float2*>(&X->r[src][4]);
+  p = V(a0.x, a0.y, a0.z);
+  R.m[0] = r0.x; R.m[1] = r0.y; R.m[2] = r0.z; R.m[3] = r0.w;
+  R.m[4] = r1.x; R.m[5] = r1.y; R.m[6] = r1.z; R.m[7] = r1.w;
+  R.m[8] = a2.y;
+}
+// The same from the side rows.
+__device__ __forceinline__ void side_get_pR(const PairLanes& L, int src, v3& p, m3& R) {
+  const float4 r0 = L.side[src][0], r2 = L.side[src][2], r3 = L.side[src][3], r4 = L.side[src][4];
+  p = V(r0.x, r0.y, r0.z);
+  R.m[0] = r2.y; R.m[1] = r2.z; R.m[2] = r2.w;
+  R.m[3] = r3.x; R.m[4] = r3.y; R.m[5] = r3.z; R.m[6] = r3.w;
+  R.m[7] = r4.x; R.m[8] = r4.y;
+}
+
+// Slot 0 of a lane's candidates, read once per launch: its index (-1
+// without one) and the lanes of its line and ball bodies, for the early
+// bound test on the exchange rows.
 struct PairSlot0 {
-  int sa, sb;
-  float r2;
+  int pi, sl, sk;
 };
 __device__ __forceinline__ PairSlot0 pair_slot0(const PairLanes& L, int b, int base) {
-  PairSlot0 q{base + b, base + b, -1.f};
+  PairSlot0 q{-1, base + b, base + b};
   if (L.nh[b] > 0) {
-    const PairT& P = L.pair[L.hp[b][0]];
-    q = PairSlot0{base + P.a, base + P.b, P.reach * P.reach};
+    const int pi = L.hp[b][0];
+    q = PairSlot0{pi, pair_line_lane(L.pair[pi], base), pair_ball_lane(L.pair[pi], base)};
   }
   return q;
 }
-// The early reach test of slot 0, while row 0 of every lane's exchange row
-// holds its post-kinematic position (1 within reach, 0 not).
-__device__ __forceinline__ int pair_near0(const XchRows* X, const PairSlot0& q) {
-  const float4 a = X->r[q.sa][0], c = X->r[q.sb][0];
-  const v3 d = V(a.x, a.y, a.z) - V(c.x, c.y, c.z);
-  return (q.r2 >= 0.f && dot(d, d) <= q.r2) ? 1 : 0;
+// The early bound test of slot 0 (1 passed, 0 not), while every lane's
+// exchange row holds its post-kinematic position and its rotation.
+__device__ __forceinline__ int pair_near0(const XchRows* X, const PairLanes& L, const PairSlot0& q) {
+  v3 pL, pK;
+  m3 RL, RK;
+  xch_get_pR(X, q.sl, pL, RL);
+  xch_get_pR(X, q.sk, pK, RK);
+  const bool near = pair_bound(L.pair[q.pi < 0 ? 0 : q.pi], pL, RL, pK, RK);
+  return (q.pi >= 0 && near) ? 1 : 0;
 }
 
-// Whether any lane of the wavefront has a candidate within reach in this
-// slot.
+// The adjoint's test: whether the candidate's body origins are within its
+// reach (no contact beyond it; looser than the bound test).
 __device__ __forceinline__ bool pair_near(const PairT& P, bool mine, v3 pA, v3 pB) {
   const v3 d = pA - pB;
   return mine && dot(d, d) <= P.reach * P.reach;
@@ -154,8 +193,11 @@ __device__ __forceinline__ void pair_phase(const Tables* __restrict__ tab, int t
     } else {
       if (!sides) side_put(L, lane, s, f);
       sides = true;
-      const float4 ra = L.side[sa][0], rb = L.side[sb][0];
-      near = pair_near(P, mine, V(ra.x, ra.y, ra.z), V(rb.x, rb.y, rb.z));
+      v3 pL, pK;
+      m3 RL, RK;
+      side_get_pR(L, mine ? pair_line_lane(P, base) : base + b, pL, RL);
+      side_get_pR(L, mine ? pair_ball_lane(P, base) : base + b, pK, RK);
+      near = mine && pair_bound(P, pL, RL, pK, RK);
     }
     if (__ballot(near) == 0ull) continue;  // wave-uniform
     if (!sides) side_put(L, lane, s, f);

@@ -721,6 +721,39 @@ void pack_type(const SystemDesc& d, Tables& tab, int t) {
     const double reach = extent(box_a, S.a0, S.a1, S.ah, S.ra) + extent(box_b, S.b0, S.b1, S.bh, S.rb);
     // with a margin (0.01% and 0.1 mm) far above the FP32 rounding of positions and of the test
     P.reach = (float)(reach * (1.0 + 1e-4) + 1e-4);
+    // the bound test: a segment side is the line (the first body's when both
+    // are), the other side a ball around its feature's centre: a box's centre
+    // with its half diagonal, a segment's midpoint with its half length, or
+    // a point; a contact needs the line within both radii plus that extent
+    {
+      const bool seg_a = S.kind == PK_SP || S.kind == PK_SS || S.kind == PK_SB;
+      const bool seg_b = S.kind == PK_PS || S.kind == PK_BS;
+      const bool line_b = seg_b || S.kind == PK_BP;  // otherwise the first body's feature is the line
+      const double* l0 = line_b ? S.b0 : S.a0;
+      const double* l1 = line_b ? S.b1 : S.a1;
+      const bool lseg = line_b ? seg_b : seg_a;
+      const bool kbox = line_b ? box_a : box_b;
+      const double* k0 = line_b ? S.a0 : S.b0;
+      const double* k1 = line_b ? S.a1 : S.b1;
+      const double* kh = line_b ? S.ah : S.bh;
+      const bool kseg = line_b ? (S.kind == PK_SS) : (S.kind == PK_PS || S.kind == PK_SS);
+      double kcen[3], ext = 0.0;
+      for (int k = 0; k < 3; ++k) kcen[k] = kseg ? 0.5 * (k0[k] + k1[k]) : k0[k];
+      if (kbox) ext = norm(kh);
+      if (kseg) {
+        const double dk[3] = {k1[0] - k0[0], k1[1] - k0[1], k1[2] - k0[2]};
+        ext = 0.5 * norm(dk);
+      }
+      const double rt = (S.ra + S.rb + ext) * (1.0 + 1e-4) + 1e-4;
+      for (int k = 0; k < 3; ++k) {
+        P.lo[k] = (float)l0[k];
+        P.ld[k] = lseg ? (float)(l1[k] - l0[k]) : 0.f;
+        P.kc[k] = (float)kcen[k];
+      }
+      P.lo[3] = (float)(rt * rt);
+      P.ld[3] = 0.f;
+      P.kc[3] = line_b ? 1.f : 0.f;
+    }
     BodyT& A = tab.body[t][S.a];
     BodyT& Bb = tab.body[t][S.b];
     A.pairs[A.npair++] = c;

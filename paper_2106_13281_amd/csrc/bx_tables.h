@@ -4,6 +4,7 @@
 // description (bodies, joints, actuators, colliders of Appendix A plus the
 // engine constants). Everything here is immutable during stepping.
 #pragma once
+#include <cstddef>
 #include <cstdint>
 
 namespace bx {
@@ -108,12 +109,24 @@ struct PairT {
   int32_t box_rot;         // the box collider is rotated in its body (aR / bR not the identity)
   int32_t pad;
   float reach;             // no contact while the two body origins are farther apart than this
+  // the bound test of the fused forward: the line feature lo + u ld (u in
+  // [0, 1]; a segment, or a point with ld = 0) in the frame of the body
+  // named by kc[3] (1: b, 0: a) against the ball around kc in the other
+  // body's frame; no contact while the line's distance from kc exceeds
+  // sqrt(lo[3]) (the radii, the other feature's extent from kc, a margin).
+  // 16-byte aligned within the struct (offset 32; the size is a multiple of 16)
+  float lo[4], ld[4], kc[4];
   float a0[3], a1[3], ra;
   float b0[3], b1[3], rb;
   float ah[3], bh[3];
   float aR[9], bR[9];
   float im_a, im_b;
 };
+
+// the fused kernels read lo, ld and kc as 16-byte vectors from their LDS copy
+static_assert(offsetof(PairT, lo) % 16 == 0 && offsetof(PairT, ld) % 16 == 0 && offsetof(PairT, kc) % 16 == 0 &&
+                  sizeof(PairT) % 16 == 0,
+              "PairT layout");
 
 struct Tables {
   TypeT type[MAXT];
