@@ -193,16 +193,27 @@ BXF float seg_box_param(v3 a0, v3 da, v3 c, const m3& Rb, const float* h, PairGe
   // (dq_k = 0) gives infinite or undefined crossings, which clamp to an end
   // already considered or fail every comparison (no change), and leave the
   // through-box interval below unbounded (|q_k| < h_k) or empty
+  float t1[3], t2[3];
   float te = 0.f, tx = 1.f;
   for (int k = 0; k < 3; ++k) {
-    const float t1 = (-h[k] - qa[k]) / qd[k], t2 = (h[k] - qa[k]) / qd[k];
-    consider(clampf(t2, 0.f, 1.f));
-    consider(clampf(t1, 0.f, 1.f));
-    te = fmaxf(te, fminf(t1, t2));
-    tx = fminf(tx, fmaxf(t1, t2));
+    t1[k] = (-h[k] - qa[k]) / qd[k];
+    t2[k] = (h[k] - qa[k]) / qd[k];
+    te = fmaxf(te, fminf(t1[k], t2[k]));
+    tx = fminf(tx, fmaxf(t1[k], t2[k]));
   }
   g.sbin = 0;
   g.li = g.lj = -1;
+  g.act = 0;
+  g.sig = V(0.f, 0.f, 0.f);
+  g.sD = 0.f;
+  // the slope's signs at the ends decide an end as the minimiser (it is
+  // >= 0 at 0, or < 0 at 1), unless the segment passes through the box;
+  // the other candidates then change neither sL nor sR
+  if (!(te < tx) && (sL < 0.f || sR > 1.f)) return sR > 1.f ? 1.f : sR;
+  for (int k = 0; k < 3; ++k) {
+    consider(clampf(t2[k], 0.f, 1.f));
+    consider(clampf(t1[k], 0.f, 1.f));
+  }
   // outside: the minimiser on the bracket [sL, sR], from the coordinates
   // beyond their faces at its middle
   const float mid = 0.5f * (sL + sR);
