@@ -459,13 +459,23 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
         X->r[lane][1] = make_float4(dw.x, dw.y, dw.z, 0.f);
         v3 sv = V(0.f, 0.f, 0.f), sw = sv;
         int sc = 0;
-        for (int i = 0; i < ty.max_ng; ++i) {
-          const int src = base + (i < B.ng ? (int)((B.grp_packed >> (4 * i)) & 15u) : b);
-          const float4 gv = X->r[src][0], gw = X->r[src][1];
-          if (i < B.ng) {
-            sv += V(gv.x, gv.y, gv.z);
-            sw += V(gw.x, gw.y, gw.z);
-            sc += (int)gv.w;
+        // four rows read together, then added in order (a group has at most 8 lanes)
+        for (int i0 = 0; i0 < ty.max_ng; i0 += 4) {
+          float4 gv[4], gw[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int i = i0 + j;
+            const int src = base + (i < B.ng ? (int)((B.grp_packed >> (4 * (i & 7))) & 15u) : b);
+            gv[j] = X->r[src][0];
+            gw[j] = X->r[src][1];
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (i0 + j < B.ng) {
+              sv += V(gv[j].x, gv[j].y, gv[j].z);
+              sw += V(gw[j].x, gw[j].y, gw[j].z);
+              sc += (int)gv[j].w;
+            }
           }
         }
         dv = sv;

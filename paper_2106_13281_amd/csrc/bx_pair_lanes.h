@@ -215,13 +215,23 @@ __device__ __forceinline__ void pair_phase(const Tables* __restrict__ tab, int t
       const int nr = side == 0 ? L.nra[b][i] : L.nrb[b][i];
       const uint32_t rv = side == 0 ? L.recva[b][i] : L.recvb[b][i];
       const int kmax = side == 0 ? ty.recv_na[i] : ty.recv_nb[i];
-      for (int k = 0; k < kmax; ++k) {
-        const int hsrc = base + (k < nr ? (int)((rv >> (4 * k)) & 15u) : b);
-        const float4 a = X->r[hsrc][2 * side], w = X->r[hsrc][2 * side + 1];
-        if (k < nr && a.w != 0.f) {
-          dv += V(a.x, a.y, a.z);
-          dw += V(w.x, w.y, w.z);
-          ++cnt;
+      // four rows read together, then added in order (at most MAXR = 8 shares)
+      for (int k0 = 0; k0 < kmax; k0 += 4) {
+        float4 a[4], w[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int k = k0 + j;
+          const int hsrc = base + (k < nr ? (int)((rv >> (4 * (k & 7))) & 15u) : b);
+          a[j] = X->r[hsrc][2 * side];
+          w[j] = X->r[hsrc][2 * side + 1];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (k0 + j < nr && a[j].w != 0.f) {
+            dv += V(a[j].x, a[j].y, a[j].z);
+            dw += V(w[j].x, w[j].y, w[j].z);
+            ++cnt;
+          }
         }
       }
     }
