@@ -414,9 +414,28 @@ __device__ __forceinline__ void fused_run(const Tables* __restrict__ tab, const 
       // rest from the table
       v3 dv = V(0.f, 0.f, 0.f), dw = V(0.f, 0.f, 0.f);
       int cnt = 0;
+      if (REGC == 2 && !TAPE && (!CL || PAIRS)) {
+        // the penetrating candidates first, in candidate order (the same
+        // sums), so that the second evaluation's impulse runs only where a
+        // lane has two penetrating candidates, not wherever one has its
+        // second (measured per kernel: biped 14.0 -> 13.0 ms, planar runner
+        // 10.3 -> 10.0, grasp 24.7 -> 24.2; the contact-lane kernels without
+        // body-body contacts lost 2-3% and keep the plain order)
+        const v3 rl0 = mul(f.R, ld3(Creg[0].l)), rl1 = mul(f.R, ld3(Creg[REGC - 1].l));
+        const float d0 = Creg[0].rho - (s.p.z + rl0.z), d1 = Creg[REGC - 1].rho - (s.p.z + rl1.z);
+        const bool p0 = 0 < max_con && n_con > 0 && d0 > 0.f;
+        const bool p1 = 1 < max_con && n_con > 1 && d1 > 0.f;
+        if (p0 || p1)
+          cnt += contact_apply(p0 ? Creg[0].rho : Creg[REGC - 1].rho, ty, B, s, f, sel(p0, rl0, rl1), p0 ? d0 : d1,
+                               dv, dw)
+                     ? 1
+                     : 0;
+        if (p0 && p1) cnt += contact_apply(Creg[REGC - 1].rho, ty, B, s, f, rl1, d1, dv, dw) ? 1 : 0;
+      } else {
 #pragma unroll
-      for (int k = 0; k < REGC; ++k)
-        if (k < max_con && n_con > k) cnt += contact_eval(Creg[k], ty, B, s, f, dv, dw) ? 1 : 0;
+        for (int k = 0; k < REGC; ++k)
+          if (k < max_con && n_con > k) cnt += contact_eval(Creg[k], ty, B, s, f, dv, dw) ? 1 : 0;
+      }
       for (int c = REGC; c < n_con; ++c) cnt += contact_eval(tab->contact[t][cfirst + c], ty, B, s, f, dv, dw) ? 1 : 0;
       // joint evaluated on every lane (a root uses its own state as the
       // parent and its result is discarded)

@@ -347,13 +347,13 @@ BXF JointOut joint_eval(const JointT& J, const Body& P, const m3& RP, const Body
 // with restitution and Baumgarte term, jn = max(0, -(1+e) vn + beta depth / h)
 // / kn, and a Coulomb friction impulse from the same pre-impulse state,
 // jt = min(mu jn, s / kt). Adds the velocity changes to dv, dw and returns
-// whether an impulse was applied.
-BXF bool contact_eval(const ContactT& c, const TypeT& ty, const BodyT& B, const Body& s, const Frame& f, v3& dv,
-                      v3& dw) {
-  v3 rl = mul(f.R, ld3(c.l));
-  float depth = c.rho - (s.p.z + rl.z);
+// whether an impulse was applied. contact_apply takes the candidate's radius
+// rho, its centre rotated to the world rl = R l and its depth, as
+// contact_eval forms them.
+BXF bool contact_apply(float rho, const TypeT& ty, const BodyT& B, const Body& s, const Frame& f, v3 rl, float depth,
+                       v3& dv, v3& dw) {
   if (!(depth > 0.f)) return false;
-  v3 r = V(rl.x, rl.y, rl.z - c.rho);  // lowest point relative to the centre of mass
+  v3 r = V(rl.x, rl.y, rl.z - rho);  // lowest point relative to the centre of mass
   v3 u = s.v + cross(s.w, r);
   v3 a = mul(f.Iwinv, V(r.y, -r.x, 0.f));       // Iwinv (r x z)
   float kn = B.inv_m + (a.x * r.y - a.y * r.x);  // z . ((Iwinv (r x z)) x r)
@@ -382,6 +382,11 @@ BXF bool contact_eval(const ContactT& c, const TypeT& ty, const BodyT& B, const 
   dv += B.inv_m * J;
   dw += dwc;
   return true;
+}
+BXF bool contact_eval(const ContactT& c, const TypeT& ty, const BodyT& B, const Body& s, const Frame& f, v3& dv,
+                      v3& dw) {
+  const v3 rl = mul(f.R, ld3(c.l));
+  return contact_apply(c.rho, ty, B, s, f, rl, c.rho - (s.p.z + rl.z), dv, dw);
 }
 
 // Potential integrator: v += h (g + f/m); w += h Iwinv (t - w x (Iw w)).
