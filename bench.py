@@ -265,21 +265,27 @@ def main():
     env_rate = E * n_env_steps / (ms_env / 1e3)
     log(f"environment step: {ms_env / n_env_steps * 1e3:.1f} us per step of {E} environments")
 
-    # forward + VJP: the differentiation workload (1024 quadrupeds x 100 steps,
-    # checkpoints every 10 steps), gradient of a loss w.r.t. all actions
+    # forward + VJP: the differentiation workload (1024 quadrupeds x 100 steps),
+    # gradient of a loss w.r.t. all actions; the whole forward tape is kept in
+    # device memory (rollout_grad's default where it fits), and the same with
+    # checkpoints every 10 steps (each segment's tape recomputed)
     wd = synth.WORKLOADS["quadruped_diff"]
     dsys = braxmi.System(synth.system_text("quadruped"), wd.envs, device=0)
     d0, dacts = make_inputs(dsys, wd)
+    k_vjp = braxmi.checkpoint_interval(dsys, wd.steps)
 
-    def fwd_bwd():
+    def fwd_bwd(k):
         A = dacts.detach().clone().requires_grad_(True)
-        out_d = braxmi.rollout_grad(dsys, d0, A, k=10)
+        out_d = braxmi.rollout_grad(dsys, d0, A, k=k)
         loss = -(out_d.pos[0, 0] - d0.pos[0, 0]).sum() + 1e-3 * (A ** 2).sum()
         loss.backward()
         return A.grad
-    ms_vjp = time_calls(fwd_bwd, 5, 2)
+    ms_vjp = time_calls(lambda: fwd_bwd(k_vjp), 5, 2)
     fwd_vjp = wd.envs * wd.steps / (ms_vjp / 1e3)
-    log(f"forward+VJP: {ms_vjp:.2f} ms per {wd.envs}x{wd.steps} rollout gradient, {fwd_vjp:.3e} env-steps/s")
+    ms_vjp10 = time_calls(lambda: fwd_bwd(10), 5, 2)
+    tape_mb = wd.steps * dsys.tape_step_floats * 4 / 1e6
+    log(f"forward+VJP: {ms_vjp:.2f} ms per {wd.envs}x{wd.steps} rollout gradient, {fwd_vjp:.3e} env-steps/s "
+        f"(tape of {k_vjp} steps, {tape_mb:.0f} MB); checkpoints every 10 steps {ms_vjp10:.2f} ms")
 
     # the other workloads: biped forward; mixed batch (one persistent launch
     # over 8192 environments of four system types), direct and graph-replayed,
@@ -354,14 +360,15 @@ def main():
 
     def mixed_fwd_bwd():
         A = macts[:Tv].detach().clone().requires_grad_(True)
-        o2 = braxmi.rollout_grad(msys, m0, A, k=10)
+        o2 = braxmi.rollout_grad(msys, m0, A)
         (o2.pos.sum() + 1e-3 * (A ** 2).sum()).backward()
         return A.grad
     ms_mv = time_calls(mixed_fwd_bwd, 3, 1)
     extra["mixed_fwd_vjp_env_steps_per_s"] = len(types) * Tv / (ms_mv / 1e3)
     extra["mixed_workload"] = ("8192 environments: 2048 chains, 3277 quadrupeds, 2048 bipeds, 819 manipulators "
                                "(seeded permutation), reset pose, actions U(-1,1); forward 1000 steps, "
-                               "forward+VJP 100 steps with checkpoints every 10")
+                               f"forward+VJP 100 steps (checkpoint interval "
+                               f"{braxmi.checkpoint_interval(msys, Tv)} steps: the whole tape where it fits)")
     log(f"mixed forward: {ms_m:.2f} ms ({ms_mg:.2f} ms graph); step {ms_ms * 1e3:.1f} us "
         f"({ms_msg * 1e3:.1f} us graph); forward+VJP {ms_mv:.2f} ms")
 
@@ -394,9 +401,10 @@ def main():
         "fwd_vjp_env_steps_per_s": fwd_vjp,
         "fwd_vjp_frac": fwd_vjp * (fpe + vpe) / 1e12 / PEAK_FP32_TFLOPS,
         "fwd_vjp_flop_per_env_step": fpe + vpe,
-        "fwd_vjp_workload": f"quadruped {wd.envs} environments x {wd.steps} steps, checkpoints every 10 steps; "
-                            f"algorithmic work per env-step = forward {fpe:.0f} + one reverse sweep {vpe:.0f} "
-                            f"FLOP (the checkpointed recompute is not counted)",
+        "fwd_vjp_workload": f"quadruped {wd.envs} environments x {wd.steps} steps, the whole forward tape "
+                            f"({tape_mb:.0f} MB) kept in device memory; algorithmic work per env-step = forward "
+                            f"{fpe:.0f} + one reverse sweep {vpe:.0f} FLOP",
+        "fwd_vjp_ckpt10_env_steps_per_s": wd.envs * wd.steps / (ms_vjp10 / 1e3),
         "plain_fwd_gbs": plain_bytes / (ms_plain / 1e3) / 1e9,
         "plain_bytes_per_env_substep": plain_bytes_per_env_substep(system),
         "plain_us_per_launch": ms_plain * 1e3 / plain_launches,

@@ -540,7 +540,27 @@ def _contig(s):
     return State(*(t.contiguous() for t in s.fields()))
 
 
-def rollout_grad(system, state, acts, k=10, tape=True):
-    """Apply RolloutFn: returns the final State, differentiable w.r.t. state and acts."""
+# device memory a rollout's whole forward tape may take before rollout_grad
+# falls back to checkpoints (k=None)
+TAPE_BUDGET_BYTES = 8 << 30
+CHECKPOINT_EVERY = 10
+
+
+def checkpoint_interval(system, T, tape=True, budget=TAPE_BUDGET_BYTES):
+    """The checkpoint interval rollout_grad takes for k=None: the whole
+    rollout (T steps, so one taped forward launch, the tape kept and one
+    adjoint launch, with no recompute) when its tape fits `budget` bytes,
+    else CHECKPOINT_EVERY steps. The gradient is the same either way."""
+    T = int(T)
+    if tape and T * system.tape_step_floats * 4 <= budget:
+        return max(T, 1)
+    return CHECKPOINT_EVERY
+
+
+def rollout_grad(system, state, acts, k=None, tape=True):
+    """Apply RolloutFn: returns the final State, differentiable w.r.t. state and acts.
+    k: checkpoint interval in steps; None chooses it by checkpoint_interval."""
+    if k is None:
+        k = checkpoint_interval(system, acts.shape[0], tape)
     p, r, v, w = RolloutFn.apply(system, k, tape, state.pos, state.rot, state.vel, state.ang, acts)
     return State(p, r, v, w)

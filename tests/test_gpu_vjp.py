@@ -207,6 +207,28 @@ def test_rollout_vjp_tape_equals_step_by_step_mixed_batch():
     assert torch.equal(ga, torch.stack(steps[::-1]))
 
 
+def test_whole_tape_gradient_equals_checkpointed():
+    """rollout_grad with k=None keeps the whole forward tape when it fits the
+    budget (one taped forward launch, one adjoint launch): the same gradient,
+    bit for bit, as checkpoints every 10 steps and as a budget that forces
+    them; a budget below one step's tape falls back to the checkpoint
+    interval."""
+    name, E, T = "quadruped", 16, 37
+    o, X, _ = make_states(name, E, seed=43, warm=5)
+    acts = synth.actions(43, T, E, o.na, synth.WORKLOADS[name].act_range)
+    sysg = braxmi.System(synth.system_text(name), E)
+    assert braxmi.checkpoint_interval(sysg, T) == T
+    assert braxmi.checkpoint_interval(sysg, T, budget=4 * sysg.tape_step_floats) == braxmi.CHECKPOINT_EVERY
+    assert braxmi.checkpoint_interval(sysg, T, tape=False) == braxmi.CHECKPOINT_EVERY
+    grads = []
+    for k in (None, 10):
+        A = acts_dev(acts).requires_grad_(True)
+        out = braxmi.rollout_grad(sysg, to_dev(X), A, k=k)
+        (out.pos[0].sum() + 0.1 * out.vel.sum()).backward()
+        grads.append(A.grad.clone())
+    assert torch.equal(grads[0], grads[1])
+
+
 def test_overlapped_segment_backward_equals_serial_chain():
     """RolloutFn's backward (recompute of a segment on a second stream during
     the adjoint of the next, alternating tape buffers, the forward's last
