@@ -228,3 +228,20 @@ def test_adjoint_tape_size_is_reported_against_the_lds_limit():
     for name in SYSTEMS:
         s = host(synth.system_text(name))
         assert s.vjp_params_lds_bytes <= s.lds_limit, name
+
+
+def test_checkpoint_interval_keeps_the_whole_tape_within_the_budget():
+    """rollout_grad's default checkpoint interval: the whole rollout where its
+    forward tape (T x tape_step_floats x 4 bytes) fits the budget, else the
+    fixed interval; with tape=False always the fixed interval. The tape of
+    1024 quadrupeds takes 64 lanes x 17 floats x 10 substeps per wavefront
+    and step."""
+    s = host(synth.system_text("quadruped"), n=1024)
+    per_step = s.tape_step_floats * 4
+    assert s.tape_step_floats % (64 * 17 * 10) == 0
+    assert braxmi.checkpoint_interval(s, 100) == 100
+    assert braxmi.checkpoint_interval(s, 100, budget=100 * per_step) == 100
+    assert braxmi.checkpoint_interval(s, 100, budget=100 * per_step - 1) == braxmi.CHECKPOINT_EVERY
+    assert braxmi.checkpoint_interval(s, 100, tape=False) == braxmi.CHECKPOINT_EVERY
+    assert braxmi.checkpoint_interval(s, 0) == 1
+    assert 100 * per_step <= braxmi.TAPE_BUDGET_BYTES
